@@ -239,9 +239,11 @@ def config_graph(name: str) -> Graph:
     if name == "rmat22":
         return rmat(22, 8, 0.57, 0.19, 0.19, 1500, 4)
     if name.startswith("chunglu_"):
-        # scaled-down Chung-Lu of the same recipe: chunglu_<n>
+        # scaled-down Chung-Lu of the same recipe, chunglu_<n>: mean degree as above,
+        # weight clip and degree cap shrunk with sqrt(n / 1e6) so the hubs stay sparse
         n = int(name.split("_")[1])
-        return chung_lu(n, int(8.4 * n), 2.1, 1000.0, 0.2, 2000, 2)
+        wcap = max(8.0, 1000.0 * (n / 1e6) ** 0.5)
+        return chung_lu(n, int(8.4 * n), 2.1, wcap, 0.2, int(2 * wcap), 2)
     raise KeyError(name)
 
 

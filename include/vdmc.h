@@ -1,0 +1,179 @@
+/*
+ * vdmc.h -- C ABI of the MI355X (gfx950) per-vertex directed motif counter.
+ *
+ * The library computes, for every vertex v of a directed graph G and for k = 3
+ * or 4, the number of connected k-vertex induced subgraphs ("k-motifs") that
+ * contain v, split over the isomorphism classes of k-vertex weakly connected
+ * digraphs (13 classes for k = 3, 199 for k = 4).
+ *
+ * Definitions (paper: Levinas, Scherz, Louzoun, "BFS based distributed algorithm
+ * for parallel local directed sub-graph enumeration"):
+ *   - a k-motif is a set of k vertices connected in the undirected graph G_U
+ *     underneath G (Sec. 4.1);
+ *   - the motif index is the k x k adjacency matrix of the induced subgraph,
+ *     row = source, read row by row with the diagonal removed, first entry most
+ *     significant (Sec. 4.1, Fig. 1); isomorphic indices are merged into the
+ *     minimal one (Fig. 1, Sec. 4.2);
+ *   - every vertex of a motif gets one count in the motif's class (Sec. 4.2).
+ * Class ids: the minimal indices of connected classes in ascending order
+ * (vdmc_class_codes returns them).
+ *
+ * Conventions
+ *   - Every call returns a vdmc_status; on failure vdmc_last_error() returns a
+ *     thread-local message.  No C++ exception crosses this boundary.
+ *   - Device pointers are HIP device pointers on the current device; `stream` is
+ *     a hipStream_t passed as void* (NULL = the null stream).  Calls that take a
+ *     stream are asynchronous on it unless stated otherwise.
+ *   - Counts are uint64.  Output matrices are row-major uint64[n][C] with row =
+ *     ORIGINAL vertex id and column = class id; the caller owns them.
+ *   - Input arcs may contain self-loops (dropped) and repeated arcs (merged):
+ *     the paper works on a simple graph (Sec. 4.1).
+ */
+#ifndef VDMC_H
+#define VDMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vdmc_graph_s* vdmc_graph;     /* opaque; owns the device CSR; immutable */
+typedef struct vdmc_server_s* vdmc_server;   /* opaque; see vdmc_serve_* below */
+typedef int32_t vdmc_status;
+
+enum {
+    VDMC_OK = 0,
+    VDMC_ERR_INVALID_ARG = 1,   /* bad pointer, size, id or k */
+    VDMC_ERR_OUT_OF_MEMORY = 2, /* a device or host allocation failed */
+    VDMC_ERR_DEVICE = 3,        /* a HIP runtime call failed */
+    VDMC_ERR_UNSUPPORTED = 4,   /* valid request this library does not implement (e.g. k = 5) */
+    VDMC_ERR_BUSY = 5,          /* server has no free slot right now */
+    VDMC_ERR_NOT_FOUND = 6,     /* unknown request id */
+    VDMC_ERR_REJECTED = 7,      /* request can never fit the server's memory budget */
+    VDMC_ERR_TIMEOUT = 8        /* a wait ran out of time; the request is still running */
+};
+
+/* vdmc_build_graph flags */
+enum {
+    VDMC_INPUT_ON_DEVICE = 2u   /* src/dst are device pointers (else host pointers) */
+};
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* vdmc_last_error(void);
+
+/* Number of classes: 13 for k = 3, 199 for k = 4, -1 otherwise. */
+int32_t vdmc_num_classes(int32_t k);
+
+/* Minimal motif index (Sec. 4.1, Fig. 1) of every class, ascending by class id.
+ * codes_out: host array of vdmc_num_classes(k) entries.  Synchronous. */
+vdmc_status vdmc_class_codes(int32_t k, uint16_t* codes_out);
+
+/* Class id of every raw motif index: table_out is a host array of 2^(k(k-1))
+ * bytes; 0xFF marks a disconnected index.  Built once per device by a kernel that
+ * tries all k! relabellings (the "combine isomorphisms once" step, Sec. 2, 4.2).
+ * Synchronous. */
+vdmc_status vdmc_class_table(int32_t k, uint8_t* table_out);
+
+/*
+ * Build the device graph from arcs src[i] -> dst[i], i < m, vertex ids in [0, n).
+ *   - flags & VDMC_INPUT_ON_DEVICE: src/dst are device pointers, else host pointers;
+ *     the library copies them; the caller keeps ownership.
+ *   - Self-loops are dropped and repeated arcs merged; u->v and v->u together form
+ *     one undirected pair carrying both arc bits.
+ *   - Vertices are ranked by undirected degree, largest first, ties by original id
+ *     (the removal order of Sec. 2 and Sec. 6); the CSR is stored in rank space,
+ *     each row ascending, every entry (neighbour_rank << 2) | arc_bits with bit 0 =
+ *     row -> neighbour and bit 1 = neighbour -> row (Sec. 4.2 CSR).
+ * Errors: INVALID_ARG for n < 0, m < 0, n >= 2^30, NULL arrays with m > 0, or an id
+ * outside [0, n); OUT_OF_MEMORY; DEVICE.  Synchronises `stream` (the sizes of the
+ * result are needed on the host).  On success *out owns all device memory of the
+ * graph until vdmc_free_graph.
+ */
+vdmc_status vdmc_build_graph(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                             uint32_t flags, void* stream, vdmc_graph* out);
+
+/* Sizes of a built graph (any pointer may be NULL): vertices, distinct arcs,
+ * undirected pairs, largest undirected degree. */
+vdmc_status vdmc_graph_info(vdmc_graph g, int64_t* n, int64_t* arcs, int64_t* pairs,
+                            int32_t* max_deg);
+
+/* Rank-space CSR of a built graph, copied to host arrays (for tests): off[n+1],
+ * adj[2*pairs] entries (nbr_rank << 2 | arc_bits), perm[n] (rank -> original id).
+ * Any pointer may be NULL.  Synchronous. */
+vdmc_status vdmc_graph_export(vdmc_graph g, uint32_t* off, uint32_t* adj, int32_t* perm);
+
+/* Releases the graph's device memory.  NULL is a no-op.  The caller must make sure no
+ * count on the graph is still running. */
+vdmc_status vdmc_free_graph(vdmc_graph g);
+
+/*
+ * Per-vertex k-motif counts (Sec. 4.2): out is a caller-owned DEVICE buffer of
+ * n * vdmc_num_classes(k) uint64, fully overwritten (zeroed first, inside the call).
+ * Every connected k-set is enumerated exactly once from its lowest-rank vertex
+ * (Lemma 1) along the BFS shapes of Lemma 2 under the rules of Lemmas 3-4, encoded
+ * (Sec. 4.1), mapped to its class and credited to its k vertices.
+ * k in {3, 4}; k = 5 gives UNSUPPORTED, other k INVALID_ARG.  A graph with n < k
+ * gives an all-zero matrix.  Asynchronous on `stream`; `out` must not be in use by
+ * another call.  Uses library-owned scratch allocated at the graph's first count.
+ */
+vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream);
+
+/* Both k = 3 (out3: n x 13) and k = 4 (out4: n x 199) in one call; one staging of
+ * each root's neighbourhood feeds both. */
+vdmc_status vdmc_count34(vdmc_graph g, uint64_t* out3, uint64_t* out4, void* stream);
+
+/* Enumeration statistics of the last count on this graph (host, synchronous):
+ * number of k-sets per BFS shape, in the order k=3: (1,1), (1,2); k=4: (3,0,0),
+ * (2,1,0), (1,2,0), (1,1,1).  shape_counts: 6 entries. */
+vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
+
+/*
+ * Batched counts: num graphs, one k for all, outs[i] a DEVICE buffer of
+ * n_i * vdmc_num_classes(k) uint64 for graph gs[i].  All graphs are counted by one
+ * persistent launch whose work tiles come from a device-side cursor; the launch is
+ * captured in a HIP graph the first time a batch signature (same graphs, same
+ * outputs, same k) is seen and replayed afterwards.  Asynchronous on `stream`.
+ */
+vdmc_status vdmc_count_batch(const vdmc_graph* gs, int32_t num, int32_t k,
+                             uint64_t* const* outs, void* stream);
+
+/* Picks the batch launch parameters (tile size, workgroups per CU) by timing the
+ * candidates on the given batch; writes the choice to cache_path (NULL: keep in
+ * memory only).  Synchronous.  Results are bit-identical for every choice. */
+vdmc_status vdmc_tune(const vdmc_graph* gs, int32_t num, int32_t k, const char* cache_path);
+
+/*
+ * Serving: a request loop over resident graphs.
+ *   vdmc_serve_create: mem_budget_bytes caps the device memory held by in-flight
+ *     requests' scratch and outputs that the server allocates; max_inflight caps the
+ *     number of requests on the GPU at once.
+ *   vdmc_serve_submit: queue a count of graph g for k into the caller's DEVICE buffer
+ *     out (n x C uint64); returns a request id.  REJECTED if the request can never fit
+ *     the budget.  Requests are admitted in arrival order as slots and memory free up;
+ *     admitted requests run concurrently on the device.
+ *   vdmc_serve_poll: non-blocking; *done = 1 when the request's output is complete.
+ *   vdmc_serve_wait: blocks up to timeout_us (< 0: no limit); TIMEOUT if not done.
+ *   vdmc_serve_stats: latency percentiles (submit -> completion seen), throughput and
+ *     number of k-sets counted by completed requests.
+ *   vdmc_serve_destroy: waits for in-flight requests, then frees the server.
+ */
+typedef struct {
+    uint64_t mem_budget_bytes;
+    int32_t max_inflight;
+} vdmc_serve_config;
+
+vdmc_status vdmc_serve_create(const vdmc_serve_config* cfg, vdmc_server* out);
+vdmc_status vdmc_serve_submit(vdmc_server s, vdmc_graph g, int32_t k, uint64_t* out,
+                              uint64_t* req_id);
+vdmc_status vdmc_serve_poll(vdmc_server s, uint64_t req_id, int32_t* done);
+vdmc_status vdmc_serve_wait(vdmc_server s, uint64_t req_id, int64_t timeout_us);
+vdmc_status vdmc_serve_stats(vdmc_server s, double* p50_us, double* p99_us, double* req_per_s,
+                             uint64_t* sets);
+vdmc_status vdmc_serve_destroy(vdmc_server s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VDMC_H */

@@ -1,0 +1,19 @@
+"""MI355X-native per-vertex directed 3/4-motif counting (the VDMC method).
+
+The work runs in the HIP library ``libvdmc.so`` behind the C ABI of ``include/vdmc.h``;
+this package is its Python binding (``vdmc.py``) and build script (``build.py``).
+"""
+from .vdmc import (  # noqa: F401
+    Graph,
+    Server,
+    VdmcError,
+    class_codes,
+    class_table,
+    count,
+    count34,
+    count_batch,
+    load,
+    num_classes,
+    shape_counts,
+    tune,
+)

@@ -1,0 +1,199 @@
+// Isomorphism class table, built once per device by a kernel.
+//
+// Paper: the motif index is the induced adjacency matrix read row by row without
+// the diagonal, first entry most significant (Sec. 4.1, Fig. 1); isomorphs are
+// merged into their minimal index (Fig. 1; "combining isomorphisms only once",
+// Sec. 2; last step of Sec. 4.2).  The table maps every raw index to a class id
+// (ascending minimal index among connected classes) so that the merge happens in
+// the same instruction that credits a motif, with no post-processing pass.
+#include <map>
+
+#include "vdmc_internal.h"
+
+namespace vdmc {
+namespace {
+
+__host__ __device__ constexpr int factorial(int k) { return k <= 1 ? 1 : k * factorial(k - 1); }
+
+// weight of the off-diagonal entry (i, j) in a K-vertex index
+template <int K>
+__device__ inline int entry_shift(int i, int j) {
+    return K * (K - 1) - 1 - (i * (K - 1) + (j < i ? j : j - 1));
+}
+
+// Lehmer-code decoding of permutation number idx of {0..K-1}
+template <int K>
+__device__ inline void nth_permutation(int idx, int* p) {
+    int avail[K];
+    for (int i = 0; i < K; i++) avail[i] = i;
+    int left = K;
+    for (int i = 0; i < K; i++) {
+        int f = factorial(K - 1 - i);
+        int q = idx / f;
+        idx -= q * f;
+        p[i] = avail[q];
+        for (int t = q; t < left - 1; t++) avail[t] = avail[t + 1];
+        left--;
+    }
+}
+
+template <int K>
+__device__ inline int entry(uint32_t code, int i, int j) {
+    return (code >> entry_shift<K>(i, j)) & 1u;
+}
+
+template <int K>
+__device__ uint32_t minimal_relabelling(uint32_t code) {
+    uint32_t best = 0xffffffffu;
+    for (int pi = 0; pi < factorial(K); pi++) {
+        int p[K];
+        nth_permutation<K>(pi, p);
+        uint32_t c = 0;
+        for (int i = 0; i < K; i++)
+            for (int j = 0; j < K; j++)
+                if (i != j && entry<K>(code, p[i], p[j])) c |= 1u << entry_shift<K>(i, j);
+        best = c < best ? c : best;
+    }
+    return best;
+}
+
+template <int K>
+__device__ bool weakly_connected(uint32_t code) {
+    uint32_t reached = 1u, frontier = 1u;
+    while (frontier) {
+        uint32_t next = 0;
+        for (int x = 0; x < K; x++) {
+            if (!(frontier >> x & 1u)) continue;
+            for (int y = 0; y < K; y++)
+                if (x != y && (entry<K>(code, x, y) || entry<K>(code, y, x))) next |= 1u << y;
+        }
+        frontier = next & ~reached;
+        reached |= next;
+    }
+    return reached == (1u << K) - 1u;
+}
+
+constexpr int kTableThreads = 1024;
+
+template <int K>
+__global__ __launch_bounds__(kTableThreads) void k_class_table(uint8_t* table, uint16_t* class_codes,
+                                                               int* num_classes) {
+    constexpr int NC = 1 << (K * (K - 1));
+    constexpr int PER = (NC + kTableThreads - 1) / kTableThreads;
+    __shared__ uint16_t canon[NC];
+    __shared__ uint8_t conn[NC];
+    __shared__ uint16_t cid[NC];
+    __shared__ int scan[kTableThreads];
+    const int tid = threadIdx.x;
+    int mine = 0;
+    for (int t = 0; t < PER; t++) {
+        int c = tid * PER + t;
+        if (c < NC) {
+            canon[c] = (uint16_t)minimal_relabelling<K>((uint32_t)c);
+            conn[c] = weakly_connected<K>((uint32_t)c) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    for (int t = 0; t < PER; t++) {
+        int c = tid * PER + t;
+        if (c < NC && canon[c] == c && conn[c]) mine++;
+    }
+    scan[tid] = mine;
+    __syncthreads();
+    for (int s = 1; s < kTableThreads; s <<= 1) {   // inclusive Hillis-Steele scan
+        int v = tid >= s ? scan[tid - s] : 0;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    int next_id = scan[tid] - mine;
+    for (int t = 0; t < PER; t++) {
+        int c = tid * PER + t;
+        if (c < NC && canon[c] == c && conn[c]) {
+            cid[c] = (uint16_t)next_id;
+            class_codes[next_id] = (uint16_t)c;
+            next_id++;
+        }
+    }
+    if (tid == kTableThreads - 1) *num_classes = scan[tid];
+    __syncthreads();
+    for (int t = 0; t < PER; t++) {
+        int c = tid * PER + t;
+        if (c < NC) table[c] = conn[c] ? (uint8_t)cid[canon[c]] : (uint8_t)0xFF;
+    }
+}
+
+std::mutex g_tables_mu;
+std::map<int, ClassTables*> g_tables;
+
+template <int K>
+void build_one(uint8_t* d_table, std::vector<uint8_t>& host, std::vector<uint16_t>& codes) {
+    constexpr int NC = 1 << (K * (K - 1));
+    uint16_t* d_codes = nullptr;
+    int* d_num = nullptr;
+    VDMC_HIP(hipMalloc(&d_codes, NC * sizeof(uint16_t)));
+    VDMC_HIP(hipMalloc(&d_num, sizeof(int)));
+    hipLaunchKernelGGL(k_class_table<K>, dim3(1), dim3(kTableThreads), 0, 0, d_table, d_codes, d_num);
+    VDMC_HIP(hipGetLastError());
+    int num = 0;
+    host.resize(NC);
+    std::vector<uint16_t> all(NC);
+    VDMC_HIP(hipMemcpy(&num, d_num, sizeof(int), hipMemcpyDeviceToHost));
+    VDMC_HIP(hipMemcpy(host.data(), d_table, NC, hipMemcpyDeviceToHost));
+    VDMC_HIP(hipMemcpy(all.data(), d_codes, NC * sizeof(uint16_t), hipMemcpyDeviceToHost));
+    VDMC_HIP(hipFree(d_codes));
+    VDMC_HIP(hipFree(d_num));
+    VDMC_REQUIRE(num == num_classes(K), VDMC_ERR_DEVICE,
+                 "class table kernel produced " + std::to_string(num) + " classes for k=" +
+                     std::to_string(K));
+    codes.assign(all.begin(), all.begin() + num);
+}
+
+}  // namespace
+
+const ClassTables& class_tables() {
+    int dev = 0;
+    VDMC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_tables_mu);
+    auto it = g_tables.find(dev);
+    if (it != g_tables.end()) return *it->second;
+    auto* t = new ClassTables();
+    uint8_t* d = nullptr;
+    VDMC_HIP(hipMalloc(&d, 64 + 4096));
+    build_one<3>(d, t->host3, t->codes3);
+    build_one<4>(d + 64, t->host4, t->codes4);
+    t->t3 = d;
+    t->t4 = d + 64;
+    g_tables[dev] = t;   // kept for the life of the process
+    return *t;
+}
+
+}  // namespace vdmc
+
+extern "C" {
+
+int32_t vdmc_num_classes(int32_t k) { return vdmc::num_classes(k); }
+
+vdmc_status vdmc_class_codes(int32_t k, uint16_t* codes_out) {
+    return vdmc::guarded([&] {
+        VDMC_REQUIRE(codes_out != nullptr, VDMC_ERR_INVALID_ARG, "codes_out is NULL");
+        VDMC_REQUIRE(k == 3 || k == 4, k == 5 ? VDMC_ERR_UNSUPPORTED : VDMC_ERR_INVALID_ARG,
+                     "k must be 3 or 4");
+        const auto& t = vdmc::class_tables();
+        const auto& c = k == 3 ? t.codes3 : t.codes4;
+        std::copy(c.begin(), c.end(), codes_out);
+    });
+}
+
+vdmc_status vdmc_class_table(int32_t k, uint8_t* table_out) {
+    return vdmc::guarded([&] {
+        VDMC_REQUIRE(table_out != nullptr, VDMC_ERR_INVALID_ARG, "table_out is NULL");
+        VDMC_REQUIRE(k == 3 || k == 4, k == 5 ? VDMC_ERR_UNSUPPORTED : VDMC_ERR_INVALID_ARG,
+                     "k must be 3 or 4");
+        const auto& t = vdmc::class_tables();
+        const auto& h = k == 3 ? t.host3 : t.host4;
+        std::copy(h.begin(), h.end(), table_out);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/vdmc.h"
+
+namespace vdmc {
+
+// ----------------------------------------------------------------------------- errors
+
+void set_error(const std::string& msg);
+void clear_error();
+const char* last_error_cstr();
+
+struct Error {
+    vdmc_status code;
+    std::string msg;
+};
+
+#define VDMC_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            throw ::vdmc::Error{e_ == hipErrorOutOfMemory ? VDMC_ERR_OUT_OF_MEMORY       \
+                                                          : VDMC_ERR_DEVICE,             \
+                                std::string(#call) + ": " + hipGetErrorString(e_)};      \
+        }                                                                                \
+    } while (0)
+
+#define VDMC_REQUIRE(cond, code, msg)                        \
+    do {                                                     \
+        if (!(cond)) throw ::vdmc::Error{(code), (msg)};     \
+    } while (0)
+
+// Runs f() and converts exceptions into a status + thread-local message.
+template <class F>
+vdmc_status guarded(F&& f) {
+    try {
+        clear_error();
+        f();
+        return VDMC_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return VDMC_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return VDMC_ERR_DEVICE;
+    } catch (...) {
+        set_error("unknown failure");
+        return VDMC_ERR_DEVICE;
+    }
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ----------------------------------------------------------------------------- classes
+
+constexpr int kClasses3 = 13;
+constexpr int kClasses4 = 199;
+constexpr int kShapes = 6;   // (1,1) (1,2) | (3,0,0) (2,1,0) (1,2,0) (1,1,1)
+
+inline int num_classes(int k) { return k == 3 ? kClasses3 : (k == 4 ? kClasses4 : -1); }
+
+// Device-resident class tables of the current device: code -> class id (0xFF =
+// disconnected).  Built on first use by a kernel; cached per device.
+struct ClassTables {
+    const uint8_t* t3;   // 64 entries
+    const uint8_t* t4;   // 4096 entries
+    std::vector<uint8_t> host3, host4;
+    std::vector<uint16_t> codes3, codes4;
+};
+const ClassTables& class_tables();   // for the current device
+
+// ----------------------------------------------------------------------------- graph
+
+struct DeviceScratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace vdmc
+
+struct vdmc_graph_s {
+    int device = 0;
+    int64_t n = 0;
+    int64_t arcs = 0;
+    int64_t pairs = 0;
+    int32_t max_deg = 0;
+    uint32_t* off = nullptr;     // n + 1 row offsets (rank space)
+    uint32_t* adj = nullptr;     // 2 * pairs entries: (nbr_rank << 2) | arc bits
+    uint32_t* split = nullptr;   // n: index of the first entry with nbr_rank > row
+    int32_t* perm = nullptr;     // n: rank -> original id
+    // per-root work description used by the schedulers (built with the graph)
+    uint32_t* roots = nullptr;   // roots with a non-empty higher neighbourhood
+    int64_t nroots = 0;
+    unsigned long long* stats = nullptr;  // kShapes shape counters of the last count
+    std::mutex mu;
+};
+
+namespace vdmc {
+// launches (count.hip)
+void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
+                  hipStream_t stream);
+void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t stream);
+}  // namespace vdmc
