@@ -232,30 +232,33 @@ void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t st) {
 
 void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st) {
     const ClassTables& t = class_tables();
+    ensure_bins(g, hub_min_default(), st);
     if (k3) launch_fill_u64(out3, (size_t)g->n * kClasses3, 0, st);
     if (k4) launch_fill_u64(out4, (size_t)g->n * kClasses4, 0, st);
     launch_fill_u64((uint64_t*)g->stats, kShapes, 0, st);
-    if (g->nroots == 0) return;
-    Args a;
-    a.off = g->off;
-    a.adj = g->adj;
-    a.split = g->split;
-    a.perm = g->perm;
-    a.roots = g->roots;
-    a.nroots = g->nroots;
-    a.t3 = t.t3;
-    a.t4 = t.t4;
-    a.out3 = (unsigned long long*)out3;
-    a.out4 = (unsigned long long*)out4;
-    a.stats = g->stats;
-    int64_t blocks = g->nroots < 65536 ? g->nroots : 65536;
-    if (k3 && k4)
-        hipLaunchKernelGGL((k_count_roots<true, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
-    else if (k3)
-        hipLaunchKernelGGL((k_count_roots<true, false>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_count_roots<false, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
-    VDMC_HIP(hipGetLastError());
+    if (g->nlight > 0) {
+        Args a;
+        a.off = g->off;
+        a.adj = g->adj;
+        a.split = g->split;
+        a.perm = g->perm;
+        a.roots = g->light;
+        a.nroots = g->nlight;
+        a.t3 = t.t3;
+        a.t4 = t.t4;
+        a.out3 = (unsigned long long*)out3;
+        a.out4 = (unsigned long long*)out4;
+        a.stats = g->stats;
+        int64_t blocks = g->nlight < 65536 ? g->nlight : 65536;
+        if (k3 && k4)
+            hipLaunchKernelGGL((k_count_roots<true, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
+        else if (k3)
+            hipLaunchKernelGGL((k_count_roots<true, false>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_count_roots<false, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
+        VDMC_HIP(hipGetLastError());
+    }
+    launch_hub(g, k3, k4, out3, out4, st);
 }
 
 }  // namespace vdmc

@@ -1,0 +1,884 @@
+// Hub-root motif kernel: one workgroup per root with a large higher neighbourhood.
+//
+// The sets enumerated are exactly those of the per-set kernel (count.hip): every
+// connected k-set once, from its lowest-rank vertex r, along the BFS shapes of
+// Lemma 2 with the duplicate rules of Lemmas 3-4 (Sec. 5).  What changes is how the
+// work is laid out on the CU and how the per-vertex counters are raised:
+//
+//   * N+(r) (the depth-1 candidates, "slots" in rank order) is staged in LDS, and
+//     a 2-bit adjacency matrix M over the slots is built once per root in global
+//     scratch (L2-resident), so that every depth-1/depth-1 test is one load;
+//   * depth-2 vertices c are grouped: the entry (a, c) whose a is the lowest-rank
+//     neighbour of c in N+(r) leads the group and records A(c) = N(c) n N+(r);
+//     the depth-1 rule of (2,1,0) (c hangs under its lowest-rank parent) and the
+//     (1,1,1) paths through c are then enumerated group by group;
+//   * every loop keeps one member of the set fixed per lane and one fixed per wave
+//     step; the class of a set whose remaining pairs are non-adjacent ("pure") is a
+//     function of a few 2-bit codes, so lanes count such sets in packed register
+//     fields and waves count them with ballots; the counts are flushed into LDS or
+//     L2-resident per-slot counters and, once per root, into the output.  Sets with
+//     extra edges take a direct path (table lookup of the full index, atomics).
+// Every set is still visited by exactly one lane; only the increments are summed
+// before they reach memory, which leaves the integer result unchanged.
+#include "motif_device.h"
+#include "vdmc_internal.h"
+
+#include <hipcub/hipcub.hpp>
+
+namespace vdmc {
+namespace {
+
+constexpr int HT = 512;             // threads per hub workgroup
+constexpr int NW = HT / 64;         // waves per workgroup
+constexpr uint32_t PMAX = 2048;     // largest |N+(r)| on the hub path
+constexpr uint32_t NCHMAX = PMAX / 64;
+constexpr uint32_t F21 = (1u << 21) - 1u;
+constexpr size_t M_WORDS = (size_t)PMAX * NCHMAX * 4;   // 2-bit matrix, 16 codes per word
+
+struct HubArgs {
+    const uint32_t* off;
+    const uint32_t* adj;
+    const uint32_t* split;
+    const int32_t* perm;
+    const uint32_t* hubs;
+    uint32_t nhub;
+    unsigned* queue;
+    const uint8_t* t3;
+    const uint8_t* t4;
+    unsigned long long* out3;
+    unsigned long long* out4;
+    unsigned long long* stats;
+    int k3, k4;
+    // per-workgroup scratch
+    uint32_t* scratch;
+    size_t wg_words;        // u32 words per workgroup slice
+    size_t o_spar, o_s111, o_s3x, o_groups, o_alist, o_wlist, o_c120, o_eflag;
+    uint32_t wl_cap;        // per-wave list capacity (>= max degree)
+};
+
+// ----------------------------------------------------------------------------- helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ size_t mword(uint32_t d, uint32_t row, uint32_t col) {
+    return (((size_t)(col >> 6) * d + row) << 2) + ((col & 63u) >> 4);
+}
+__device__ __forceinline__ uint32_t mshift(uint32_t col) { return (col & 15u) << 1; }
+// arc bits of (P[row], P[col]) seen from P[row]
+__device__ __forceinline__ uint32_t mget(const uint32_t* M, uint32_t d, uint32_t row, uint32_t col) {
+    return (M[mword(d, row, col)] >> mshift(col)) & 3u;
+}
+
+// slot of rank x in the sorted list sP[0..d), or -1
+__device__ __forceinline__ int find_slot(const uint32_t* sP, uint32_t d, uint32_t x) {
+    uint32_t lo = 0, hi = d, key = x << 2;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (sP[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return (lo < d && (sP[lo] >> 2) == x) ? (int)lo : -1;
+}
+
+// largest i in [0, n) with pre[i] <= q
+__device__ __forceinline__ uint32_t slot_of(const uint32_t* pre, uint32_t n, uint32_t q) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// index of the multiset {x, y}, x, y in {1,2,3}: 11 12 13 22 23 33 -> 0..5
+__device__ __forceinline__ uint32_t pair_sig(uint32_t x, uint32_t y) {
+    uint32_t lo = min(x, y) - 1u, hi = max(x, y) - 1u;
+    return lo * 3u - (lo * (lo - 1u)) / 2u + (hi - lo);
+}
+__device__ __forceinline__ void sig_pair(uint32_t s, uint32_t& x, uint32_t& y) {
+    const uint8_t tx[6] = {1, 1, 1, 2, 2, 3};
+    const uint8_t ty[6] = {1, 2, 3, 2, 3, 3};
+    x = tx[s];
+    y = ty[s];
+}
+
+__device__ __forceinline__ void add_out(unsigned long long* out, const int32_t* perm, uint32_t C, uint32_t v,
+                                        uint32_t cls, unsigned long long cnt) {
+    if (cls < C && cnt) atomicAdd(&out[(size_t)perm[v] * C + cls], cnt);
+}
+
+// Inclusive scan of sPre[1..n] (counts) into prefix sums, sPre[0] = 0.  n <= 4*HT.
+__device__ void block_prefix(uint32_t* sPre, uint32_t n, uint32_t* sScan) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t base = 1 + tid * 4;
+    uint32_t loc[4], sum = 0;
+    for (int k = 0; k < 4; k++) {
+        uint32_t idx = base + k;
+        sum += idx <= n ? sPre[idx] : 0u;
+        loc[k] = sum;
+    }
+    sScan[tid] = sum;
+    __syncthreads();
+    for (uint32_t o = 1; o < HT; o <<= 1) {
+        uint32_t v = tid >= o ? sScan[tid - o] : 0u;
+        __syncthreads();
+        sScan[tid] += v;
+        __syncthreads();
+    }
+    const uint32_t excl = sScan[tid] - sum;
+    for (int k = 0; k < 4; k++) {
+        uint32_t idx = base + k;
+        if (idx <= n) sPre[idx] = excl + loc[k];
+    }
+    if (tid == 0) sPre[0] = 0;
+    __syncthreads();
+}
+
+__device__ __forceinline__ int wave_next(unsigned* sTask) {
+    int t = 0;
+    if (lane_id() == 0) t = (int)atomicAdd(sTask, 1u);
+    return __shfl(t, 0);
+}
+
+// ----------------------------------------------------------------------------- kernel
+
+__global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
+    __shared__ uint32_t sP[PMAX];
+    __shared__ uint32_t sPre[PMAX + 1];
+    __shared__ uint32_t sLo[PMAX];
+    __shared__ uint32_t sCnt[9 * PMAX];
+    __shared__ uint8_t sT4[4096];
+    __shared__ uint8_t sT3[64];
+    __shared__ unsigned long long sRoot4[kClasses4];
+    __shared__ unsigned long long sRoot3[kClasses3];
+    __shared__ uint32_t sScan[HT];
+    __shared__ uint32_t sCw[NW][27 + 27 + kClasses3];   // per-wave group accumulators
+    __shared__ unsigned sTask;
+    __shared__ unsigned sGroups;
+    __shared__ unsigned sAlloc;
+    __shared__ unsigned sRootIdx;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wid = tid >> 6;
+    uint32_t* W = A.scratch + (size_t)blockIdx.x * A.wg_words;
+    uint32_t* M = W;
+    uint32_t* spar = W + A.o_spar;     // [9][PMAX]  (2,1,0) parent-role counters
+    uint32_t* s111 = W + A.o_s111;     // [9][PMAX]  (1,1,1) depth-1 counters
+    uint32_t* s3x = W + A.o_s3x;       // [3][PMAX]  k=3 (1,2) depth-1 counters
+    uint32_t* grp = W + A.o_groups;    // 4 words per group: c, p, alist offset, row start
+    uint32_t* alist = W + A.o_alist;   // A(c) lists: slot << 2 | arc bits seen from the slot
+    uint32_t* wlist = W + A.o_wlist + (size_t)wid * A.wl_cap;
+    uint32_t* c120 = W + A.o_c120 + (size_t)wid * 3 * A.wl_cap;
+    uint8_t* eflag = reinterpret_cast<uint8_t*>(W + A.o_eflag);
+    unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
+
+    for (uint32_t i = tid; i < 4096; i += HT) sT4[i] = A.t4[i];
+    for (uint32_t i = tid; i < 64; i += HT) sT3[i] = A.t3[i];
+    for (uint32_t i = tid; i < 9 * PMAX; i += HT) { spar[i] = 0; s111[i] = 0; }
+    for (uint32_t i = tid; i < 3 * PMAX; i += HT) s3x[i] = 0;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) sRootIdx = atomicAdd(A.queue, 1u);
+        __syncthreads();
+        const uint32_t ri = sRootIdx;
+        if (ri >= A.nhub) break;
+        const uint32_t r = A.hubs[ri];
+        const uint32_t s0 = A.split[r];
+        const uint32_t d = A.off[r + 1] - s0;
+        const uint32_t nch = (d + 63) >> 6;
+
+        // ---------------------------------------------------------------- stage
+        for (uint32_t i = tid; i < d; i += HT) {
+            const uint32_t e = A.adj[s0 + i];
+            sP[i] = e;
+            const uint32_t a = e >> 2;
+            const uint32_t lo = lower_bound_rank(A.adj, A.off[a], A.off[a + 1], r + 1);
+            sLo[i] = lo;
+            sPre[i + 1] = A.off[a + 1] - lo;
+        }
+        for (uint32_t i = tid; i < kClasses4; i += HT) sRoot4[i] = 0;
+        for (uint32_t i = tid; i < kClasses3; i += HT) sRoot3[i] = 0;
+        for (uint32_t i = tid; i < 9 * d; i += HT) sCnt[i] = 0;
+        const size_t mwords = (size_t)d * nch * 4;
+        for (size_t i = tid; i < mwords; i += HT) M[i] = 0;
+        if (tid == 0) { sGroups = 0; sAlloc = 0; sTask = 0; }
+        __syncthreads();
+        block_prefix(sPre, d, sScan);
+        const uint32_t scan2 = sPre[d];
+        __threadfence();
+        __syncthreads();
+
+        // ---------------------------------------------------------------- local matrix + depth-2 flags
+        for (uint32_t q = tid; q < scan2; q += HT) {
+            const uint32_t i = slot_of(sPre, d, q);
+            const uint32_t e = A.adj[sLo[i] + (q - sPre[i])];
+            const int j = find_slot(sP, d, e >> 2);
+            if (j >= 0) {
+                atomicOr(&M[mword(d, i, (uint32_t)j)], (e & 3u) << mshift((uint32_t)j));
+                eflag[q] = 0;
+            } else {
+                eflag[q] = 1;
+            }
+        }
+        __threadfence();
+        __syncthreads();
+
+        // ---------------------------------------------------------------- k=3 (1,1): pairs of slots
+        if (A.k3) {
+            // tasks (ch, j): lanes are slots i = 64 ch + lane < j
+            uint32_t total = 0;
+            for (uint32_t ch = 0; ch < nch; ch++) total += (d > 64 * ch + 1) ? d - 1 - 64 * ch : 0;
+            for (int t = wave_next(&sTask); t < (int)total; t = wave_next(&sTask)) {
+                uint32_t ch = 0, rem = (uint32_t)t;
+                while (true) {
+                    uint32_t c = d - 1 - 64 * ch;
+                    if (rem < c) break;
+                    rem -= c;
+                    ch++;
+                }
+                const uint32_t j = 64 * ch + 1 + rem;
+                const uint32_t i = 64 * ch + lane;
+                const bool va = i < j;
+                const uint32_t ra = va ? (sP[i] & 3u) : 0u, rb = sP[j] & 3u;
+                const uint32_t ab = va ? swap_arc_bits(mget(M, d, j, i)) : 0u;
+                const bool pure = va && ab == 0;
+                if (pure) atomicAdd(&sCnt[(rb - 1) * d + i], 1u);
+                if (va && !pure) {
+                    const uint32_t cls = sT3[motif_index3(ra, rb, ab)];
+                    atomicAdd(&sRoot3[cls], 1ull);
+                    add_out(A.out3, A.perm, kClasses3, sP[i] >> 2, cls, 1);
+                    add_out(A.out3, A.perm, kClasses3, sP[j] >> 2, cls, 1);
+                }
+                if (va) shape[0]++;
+                for (uint32_t k = 1; k <= 3; k++) {
+                    const uint32_t nk = __popcll(__ballot(pure && ra == k));
+                    if (lane == k - 1 && nk) {
+                        atomicAdd(&sCnt[(k - 1) * d + j], nk);
+                        atomicAdd(&sRoot3[sT3[motif_index3(k, rb, 0u)]], (unsigned long long)nk);
+                    }
+                }
+            }
+            __syncthreads();
+            for (uint32_t q = tid; q < 3 * d; q += HT) {
+                const uint32_t cnt = sCnt[q];
+                if (!cnt) continue;
+                const uint32_t s = q % d, g = q / d;
+                add_out(A.out3, A.perm, kClasses3, sP[s] >> 2, sT3[motif_index3(sP[s] & 3u, g + 1, 0u)], cnt);
+                sCnt[q] = 0;
+            }
+            if (tid == 0) sTask = 0;
+            __syncthreads();
+        }
+
+        // ---------------------------------------------------------------- depth-2 groups
+        // Each depth-2 entry (a, c) scans row(c) above r; it leads the group of c iff a
+        // is the first neighbour of c in N+(r).  The leader records A(c).
+        for (int t = wave_next(&sTask); t < (int)scan2; t = wave_next(&sTask)) {
+            if (!eflag[t]) continue;
+            const uint32_t i = slot_of(sPre, d, (uint32_t)t);
+            const uint32_t c = A.adj[sLo[i] + ((uint32_t)t - sPre[i])] >> 2;
+            const uint32_t clo = lower_bound_rank(A.adj, A.off[c], A.off[c + 1], r + 1);
+            const uint32_t chi = A.off[c + 1];
+            int first = -1;
+            uint32_t p = 0;
+            for (uint32_t base = clo; base < chi; base += 64) {
+                const uint32_t tt = base + lane;
+                const int sl = tt < chi ? find_slot(sP, d, A.adj[tt] >> 2) : -1;
+                const unsigned long long mk = __ballot(sl >= 0);
+                if (first < 0 && mk) {
+                    first = __shfl(sl, (int)__ffsll((long long)mk) - 1);
+                    if (first != (int)i) break;
+                }
+                p += __popcll(mk);
+            }
+            if (first != (int)i) continue;
+            unsigned aoff = 0, g = 0;
+            if (lane == 0) {
+                aoff = atomicAdd(&sAlloc, p);
+                g = atomicAdd(&sGroups, 1u);
+            }
+            aoff = __shfl(aoff, 0);
+            g = __shfl(g, 0);
+            uint32_t pos = 0;
+            for (uint32_t base = clo; base < chi; base += 64) {
+                const uint32_t tt = base + lane;
+                uint32_t e = 0;
+                int sl = -1;
+                if (tt < chi) {
+                    e = A.adj[tt];
+                    sl = find_slot(sP, d, e >> 2);
+                }
+                const unsigned long long mk = __ballot(sl >= 0);
+                const uint32_t before = __popcll(mk & ((1ull << lane) - 1ull));
+                if (sl >= 0) alist[aoff + pos + before] = ((uint32_t)sl << 2) | swap_arc_bits(e & 3u);
+                pos += __popcll(mk);
+            }
+            if (lane == 0) {
+                grp[4 * g + 0] = c;
+                grp[4 * g + 1] = p;
+                grp[4 * g + 2] = aoff;
+                grp[4 * g + 3] = clo;
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) sTask = 0;
+        __syncthreads();
+
+        // ---------------------------------------------------------------- k=4 (3,0,0): slot triples
+        if (A.k4) {
+            uint32_t total = 0;
+            for (uint32_t ch = 0; ch < nch; ch++) total += (d > 64 * ch + 1) ? d - 1 - 64 * ch : 0;
+            for (int t = wave_next(&sTask); t < (int)total; t = wave_next(&sTask)) {
+                uint32_t ch = 0, rem = (uint32_t)t;
+                while (true) {
+                    uint32_t cc = d - 1 - 64 * ch;
+                    if (rem < cc) break;
+                    rem -= cc;
+                    ch++;
+                }
+                const uint32_t j = 64 * ch + 1 + rem;    // b
+                const uint32_t i = 64 * ch + lane;       // a (lane)
+                const bool va = i < j;
+                const uint32_t ra = va ? (sP[i] & 3u) : 0u, rb = sP[j] & 3u;
+                const uint32_t ab = va ? swap_arc_bits(mget(M, d, j, i)) : 0u;
+                unsigned long long acc = 0;                  // lane a: fields by rc
+                unsigned long long bacc1 = 0, bacc2 = 0, bacc3 = 0;  // b and r: by ra, fields by rc
+                for (uint32_t l = j + 1; l < d; l++) {
+                    const uint32_t rc = sP[l] & 3u;
+                    const uint32_t bc = mget(M, d, j, l);
+                    const uint32_t ac = va ? swap_arc_bits(mget(M, d, l, i)) : 0u;
+                    const bool pure = va && ((ab | ac | bc) == 0u);
+                    const uint32_t sh = 21u * (rc - 1u);
+                    if (pure) acc += 1ull << sh;
+                    const uint32_t n1 = __popcll(__ballot(pure && ra == 1u));
+                    const uint32_t n2 = __popcll(__ballot(pure && ra == 2u));
+                    const uint32_t n3 = __popcll(__ballot(pure && ra == 3u));
+                    bacc1 += (unsigned long long)n1 << sh;
+                    bacc2 += (unsigned long long)n2 << sh;
+                    bacc3 += (unsigned long long)n3 << sh;
+                    if (lane < 3) {
+                        const uint32_t nk = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
+                        if (nk) atomicAdd(&sCnt[pair_sig(lane + 1u, rb) * d + l], nk);
+                    }
+                    if (va && !pure) {
+                        const uint32_t cls = sT4[motif_index4(ra, rb, rc, ab, ac, bc)];
+                        atomicAdd(&sRoot4[cls], 1ull);
+                        add_out(A.out4, A.perm, kClasses4, sP[i] >> 2, cls, 1);
+                        add_out(A.out4, A.perm, kClasses4, sP[j] >> 2, cls, 1);
+                        add_out(A.out4, A.perm, kClasses4, sP[l] >> 2, cls, 1);
+                    }
+                    shape[2] += va ? 1 : 0;
+                }
+                if (va) {
+                    for (uint32_t rc = 1; rc <= 3; rc++) {
+                        const uint32_t cnt = (uint32_t)(acc >> (21u * (rc - 1u))) & F21;
+                        if (cnt) atomicAdd(&sCnt[pair_sig(rb, rc) * d + i], cnt);
+                    }
+                }
+                if (lane < 9) {
+                    const uint32_t ka = lane / 3 + 1, rc = lane % 3 + 1;
+                    const unsigned long long bw = ka == 1 ? bacc1 : (ka == 2 ? bacc2 : bacc3);
+                    const uint32_t cnt = (uint32_t)(bw >> (21u * (rc - 1u))) & F21;
+                    if (cnt) {
+                        atomicAdd(&sCnt[pair_sig(ka, rc) * d + j], cnt);
+                        atomicAdd(&sRoot4[sT4[motif_index4(ka, rb, rc, 0u, 0u, 0u)]], (unsigned long long)cnt);
+                    }
+                }
+            }
+            __syncthreads();
+            for (uint32_t q = tid; q < 6 * d; q += HT) {
+                const uint32_t cnt = sCnt[q];
+                if (!cnt) continue;
+                const uint32_t s = q % d, g = q / d;
+                uint32_t x, y;
+                sig_pair(g, x, y);
+                add_out(A.out4, A.perm, kClasses4, sP[s] >> 2, sT4[motif_index4(sP[s] & 3u, x, y, 0u, 0u, 0u)], cnt);
+                sCnt[q] = 0;
+            }
+            if (tid == 0) sTask = 0;
+            __syncthreads();
+        }
+
+        // ---------------------------------------------------------------- groups: (2,1,0), (1,1,1), k=3 (1,2)
+        const uint32_t ngroups = sGroups;
+        uint32_t* cw = sCw[wid];
+        for (uint32_t q = lane; q < 27 + 27 + kClasses3; q += 64) cw[q] = 0;
+        for (int t = wave_next(&sTask); t < (int)ngroups; t = wave_next(&sTask)) {
+            const uint32_t c = grp[4 * t + 0];
+            const uint32_t p = grp[4 * t + 1];
+            const uint32_t* Ac = alist + grp[4 * t + 2];
+            const uint32_t clo = grp[4 * t + 3];
+            const uint32_t chi = A.off[c + 1];
+            if (A.k3) {
+                for (uint32_t u = lane; u < p; u += 64) {
+                    const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = sP[x] & 3u;
+                    const uint32_t cls = sT3[motif_index3(rx, 0u, xc)];
+                    atomicAdd(&sRoot3[cls], 1ull);
+                    atomicAdd(&s3x[(xc - 1) * PMAX + x], 1u);
+                    atomicAdd(&cw[54 + cls], 1u);
+                    shape[1]++;
+                }
+            }
+            if (A.k4) {
+                // (2,1,0) with y outside A(c): lanes are y, the parent x runs over A(c)
+                for (uint32_t ch = 0; ch < nch; ch++) {
+                    const uint32_t y = 64 * ch + lane;
+                    const bool yv = y < d;
+                    const uint32_t ry = yv ? (sP[y] & 3u) : 0u;
+                    bool inA = false;
+                    if (yv) {
+                        uint32_t lo = 0, hi = p;
+                        while (lo < hi) {
+                            uint32_t mid = (lo + hi) >> 1;
+                            if ((Ac[mid] >> 2) < y) lo = mid + 1; else hi = mid;
+                        }
+                        inA = lo < p && (Ac[lo] >> 2) == y;
+                    }
+                    const bool lv = yv && !inA;
+                    unsigned long long acc1 = 0, acc2 = 0, acc3 = 0;   // by rx, fields by xc
+                    for (uint32_t u = 0; u < p; u++) {
+                        const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = sP[x] & 3u;
+                        const uint32_t xy = lv ? mget(M, d, x, y) : 0u;
+                        const bool pure = lv && xy == 0u;
+                        const unsigned long long inc = pure ? (1ull << (21u * (xc - 1u))) : 0ull;
+                        if (rx == 1) acc1 += inc; else if (rx == 2) acc2 += inc; else acc3 += inc;
+                        for (uint32_t k = 1; k <= 3; k++) {
+                            const uint32_t nk = __popcll(__ballot(pure && ry == k));
+                            if (lane == k - 1 && nk) {
+                                atomicAdd(&spar[((xc - 1) * 3 + (k - 1)) * PMAX + x], nk);
+                                cw[(rx - 1) * 9 + (xc - 1) * 3 + (k - 1)] += nk;
+                            }
+                        }
+                        if (lv && !pure) {
+                            const uint32_t cls = sT4[motif_index4(rx, ry, 0u, xy, xc, 0u)];
+                            atomicAdd(&sRoot4[cls], 1ull);
+                            add_out(A.out4, A.perm, kClasses4, sP[x] >> 2, cls, 1);
+                            add_out(A.out4, A.perm, kClasses4, sP[y] >> 2, cls, 1);
+                            add_out(A.out4, A.perm, kClasses4, c, cls, 1);
+                        }
+                        shape[3] += lv ? 1 : 0;
+                    }
+                    if (lv) {
+                        for (uint32_t q = 0; q < 9; q++) {
+                            const unsigned long long w = q < 3 ? acc1 : (q < 6 ? acc2 : acc3);
+                            const uint32_t cnt = (uint32_t)(w >> (21u * (q % 3))) & F21;
+                            if (cnt) atomicAdd(&sCnt[q * d + y], cnt);   // q = (rx-1)*3 + (xc-1)
+                        }
+                    }
+                }
+                // (2,1,0) with both depth-1 vertices in A(c): pairs u < v of A(c)
+                for (uint32_t v0 = 0; v0 < p; v0 += 64) {
+                    const uint32_t vpos = v0 + lane;
+                    const bool vv = vpos < p;
+                    const uint32_t ey = vv ? Ac[vpos] : 0u;
+                    const uint32_t y = ey >> 2, yc = ey & 3u, ry = vv ? (sP[y] & 3u) : 0u;
+                    const uint32_t umax = min(p, v0 + 64);
+                    for (uint32_t u = 0; u + 1 < umax; u++) {
+                        const bool valid = vv && u < vpos;
+                        if (!__ballot(valid)) continue;
+                        const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = sP[x] & 3u;
+                        if (valid) {
+                            const uint32_t xy = mget(M, d, x, y);
+                            const uint32_t cls = sT4[motif_index4(rx, ry, 0u, xy, xc, yc)];
+                            atomicAdd(&sRoot4[cls], 1ull);
+                            add_out(A.out4, A.perm, kClasses4, sP[x] >> 2, cls, 1);
+                            add_out(A.out4, A.perm, kClasses4, sP[y] >> 2, cls, 1);
+                            add_out(A.out4, A.perm, kClasses4, c, cls, 1);
+                            shape[3]++;
+                        }
+                    }
+                }
+                // (1,1,1): paths r - x - c - e, e above r, not in N(r), not adjacent to x
+                for (uint32_t base = clo; base < chi; base += 64) {
+                    const uint32_t tt = base + lane;
+                    uint32_t ee = 0;
+                    bool ev = tt < chi;
+                    if (ev) {
+                        ee = A.adj[tt];
+                        ev = find_slot(sP, d, ee >> 2) < 0;
+                    }
+                    const uint32_t e = ee >> 2, ce = ee & 3u;
+                    unsigned long long acc1 = 0, acc2 = 0, acc3 = 0;
+                    for (uint32_t u = 0; u < p; u++) {
+                        const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = sP[x] & 3u;
+                        const bool valid = ev && arc_bits(A.off, A.adj, sP[x] >> 2, e) == 0u;
+                        const unsigned long long inc = valid ? (1ull << (21u * (xc - 1u))) : 0ull;
+                        if (rx == 1) acc1 += inc; else if (rx == 2) acc2 += inc; else acc3 += inc;
+                        for (uint32_t k = 1; k <= 3; k++) {
+                            const uint32_t nk = __popcll(__ballot(valid && ce == k));
+                            if (lane == k - 1 && nk) {
+                                atomicAdd(&s111[((xc - 1) * 3 + (k - 1)) * PMAX + x], nk);
+                                cw[27 + (rx - 1) * 9 + (xc - 1) * 3 + (k - 1)] += nk;
+                            }
+                        }
+                        shape[5] += valid ? 1 : 0;
+                    }
+                    if (ev) {
+                        for (uint32_t q = 0; q < 9; q++) {
+                            const unsigned long long w = q < 3 ? acc1 : (q < 6 ? acc2 : acc3);
+                            const uint32_t cnt = (uint32_t)(w >> (21u * (q % 3))) & F21;
+                            if (cnt)
+                                add_out(A.out4, A.perm, kClasses4, e,
+                                        sT4[motif_index4(q / 3 + 1, 0u, 0u, q % 3 + 1, 0u, ce)], cnt);
+                        }
+                    }
+                }
+            }
+            // flush the group's depth-2 vertex (and the root, which is in every one of its sets)
+            for (uint32_t q = lane; q < 27 + 27 + kClasses3; q += 64) {
+                const uint32_t cnt = cw[q];
+                if (!cnt) continue;
+                cw[q] = 0;
+                if (q < 54) {
+                    const uint32_t qq = q % 27, rx = qq / 9 + 1, xc = (qq / 3) % 3 + 1, z = qq % 3 + 1;
+                    const uint32_t code = q < 27 ? motif_index4(rx, z, 0u, 0u, xc, 0u)      // (2,1,0): z = ry
+                                                 : motif_index4(rx, 0u, 0u, xc, 0u, z);    // (1,1,1): z = ce
+                    const uint32_t cls = sT4[code];
+                    add_out(A.out4, A.perm, kClasses4, c, cls, cnt);
+                    atomicAdd(&sRoot4[cls], (unsigned long long)cnt);
+                } else {
+                    add_out(A.out3, A.perm, kClasses3, c, q - 54, cnt);
+                }
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        if (A.k4) {
+            for (uint32_t q = tid; q < 9 * d; q += HT) {
+                const uint32_t cnt = sCnt[q];
+                if (!cnt) continue;
+                const uint32_t s = q % d, g = q / d, rx = g / 3 + 1, xc = g % 3 + 1;
+                add_out(A.out4, A.perm, kClasses4, sP[s] >> 2,
+                        sT4[motif_index4(rx, sP[s] & 3u, 0u, 0u, xc, 0u)], cnt);
+            }
+        }
+        if (tid == 0) sTask = 0;
+        __syncthreads();
+
+        // ---------------------------------------------------------------- k=4 (1,2,0): two depth-2 children of one slot
+        if (A.k4) {
+            for (int t = wave_next(&sTask); t < (int)d; t = wave_next(&sTask)) {
+                const uint32_t a = (uint32_t)t;
+                const uint32_t q0 = sPre[a], q1 = sPre[a + 1];
+                if (q1 - q0 < 2) continue;
+                uint32_t m = 0;
+                for (uint32_t qb = q0; qb < q1; qb += 64) {
+                    const uint32_t q = qb + lane;
+                    const bool f = q < q1 && eflag[q];
+                    const unsigned long long mk = __ballot(f);
+                    if (f) wlist[m + __popcll(mk & ((1ull << lane) - 1ull))] = A.adj[sLo[a] + (q - q0)];
+                    m += __popcll(mk);
+                }
+                if (m < 2) continue;
+                for (uint32_t q = lane; q < 3 * m; q += 64) c120[q] = 0;
+                __threadfence_block();
+                const uint32_t ra = sP[a] & 3u, va = sP[a] >> 2;
+                unsigned long long a6lo = 0, a6mid = 0, a6hi = 0;   // 6 signatures, 32-bit fields
+                for (uint32_t u0 = 1; u0 < m; u0 += 64) {
+                    const uint32_t u = u0 + lane;
+                    const bool uv = u < m;
+                    const uint32_t e2 = uv ? wlist[u] : 0u, c2 = e2 >> 2, ac2 = e2 & 3u;
+                    unsigned long long acc = 0;
+                    const uint32_t tmax = min(m, u0 + 64) - 1;
+                    for (uint32_t tt = 0; tt < tmax; tt++) {
+                        const uint32_t e1 = wlist[tt], c1 = e1 >> 2, ac = e1 & 3u;
+                        const bool valid = uv && tt < u;
+                        const uint32_t cc = valid ? arc_bits(A.off, A.adj, c1, c2) : 0u;
+                        const bool pure = valid && cc == 0u;
+                        if (pure) acc += 1ull << (21u * (ac - 1u));
+                        for (uint32_t k = 1; k <= 3; k++) {
+                            const uint32_t nk = __popcll(__ballot(pure && ac2 == k));
+                            if (nk) {
+                                if (lane == k - 1) atomicAdd(&c120[tt * 3 + (k - 1)], nk);
+                                const uint32_t sg = pair_sig(ac, k);
+                                const unsigned long long addv = (unsigned long long)nk << (32u * (sg & 1u));
+                                if (sg < 2) a6lo += addv; else if (sg < 4) a6mid += addv; else a6hi += addv;
+                            }
+                        }
+                        if (valid && !pure) {
+                            const uint32_t cls = sT4[motif_index4(ra, 0u, 0u, ac, ac2, cc)];
+                            atomicAdd(&sRoot4[cls], 1ull);
+                            add_out(A.out4, A.perm, kClasses4, va, cls, 1);
+                            add_out(A.out4, A.perm, kClasses4, c1, cls, 1);
+                            add_out(A.out4, A.perm, kClasses4, c2, cls, 1);
+                        }
+                        shape[4] += valid ? 1 : 0;
+                    }
+                    if (uv) {
+                        for (uint32_t g = 0; g < 3; g++) {
+                            const uint32_t cnt = (uint32_t)(acc >> (21u * g)) & F21;
+                            if (cnt) atomicAdd(&c120[u * 3 + g], cnt);
+                        }
+                    }
+                }
+                __threadfence_block();
+                for (uint32_t q = lane; q < 3 * m; q += 64) {
+                    const uint32_t cnt = atomicAdd(&c120[q], 0u);
+                    if (!cnt) continue;
+                    const uint32_t u = q / 3, g = q % 3;
+                    const uint32_t eu = wlist[u];
+                    add_out(A.out4, A.perm, kClasses4, eu >> 2,
+                            sT4[motif_index4(ra, 0u, 0u, eu & 3u, g + 1, 0u)], cnt);
+                }
+                if (lane < 6) {
+                    const unsigned long long w = lane < 2 ? a6lo : (lane < 4 ? a6mid : a6hi);
+                    const uint32_t cnt = (uint32_t)(w >> (32u * (lane & 1u)));
+                    if (cnt) {
+                        uint32_t x, y;
+                        sig_pair(lane, x, y);
+                        const uint32_t cls = sT4[motif_index4(ra, 0u, 0u, x, y, 0u)];
+                        add_out(A.out4, A.perm, kClasses4, va, cls, cnt);
+                        atomicAdd(&sRoot4[cls], (unsigned long long)cnt);
+                    }
+                }
+            }
+        }
+        __threadfence();
+        __syncthreads();
+
+        // ---------------------------------------------------------------- per-root flush
+        const uint32_t row = (uint32_t)A.perm[r];
+        if (A.k4)
+            for (uint32_t q = tid; q < kClasses4; q += HT)
+                if (sRoot4[q]) atomicAdd(&A.out4[(size_t)row * kClasses4 + q], sRoot4[q]);
+        if (A.k3)
+            for (uint32_t q = tid; q < kClasses3; q += HT)
+                if (sRoot3[q]) atomicAdd(&A.out3[(size_t)row * kClasses3 + q], sRoot3[q]);
+        for (uint32_t q = tid; q < 9 * d; q += HT) {
+            const uint32_t s = q % d, g = q / d, rs = sP[s] & 3u, vs = sP[s] >> 2;
+            const uint32_t a = spar[g * PMAX + s], b = s111[g * PMAX + s];
+            if (a) {   // (2,1,0) parent: g = (xc-1)*3 + (ry-1)
+                add_out(A.out4, A.perm, kClasses4, vs, sT4[motif_index4(rs, g % 3 + 1, 0u, 0u, g / 3 + 1, 0u)], a);
+                spar[g * PMAX + s] = 0;
+            }
+            if (b) {   // (1,1,1) depth-1: g = (xc-1)*3 + (ce-1)
+                add_out(A.out4, A.perm, kClasses4, vs, sT4[motif_index4(rs, 0u, 0u, g / 3 + 1, 0u, g % 3 + 1)], b);
+                s111[g * PMAX + s] = 0;
+            }
+            if (g < 3) {
+                const uint32_t x3 = s3x[g * PMAX + s];
+                if (x3) {
+                    add_out(A.out3, A.perm, kClasses3, vs, sT3[motif_index3(rs, 0u, g + 1)], x3);
+                    s3x[g * PMAX + s] = 0;
+                }
+            }
+        }
+    }
+    for (int s = 0; s < kShapes; s++) {
+        unsigned long long v = shape[s];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+        if (lane == 0 && v) atomicAdd(&A.stats[s], v);
+    }
+}
+
+// ----------------------------------------------------------------------------- binning
+
+constexpr int BT = 256;
+
+__global__ void k_root_work(const uint32_t* __restrict__ off, const uint32_t* __restrict__ adj,
+                            const uint32_t* __restrict__ split, const uint32_t* __restrict__ roots, int64_t nroots,
+                            uint32_t hub_min, uint32_t* __restrict__ is_hub, unsigned long long* __restrict__ wkey,
+                            unsigned long long* __restrict__ max_s2, unsigned* __restrict__ max_hi) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nroots; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t r = roots[i];
+        const uint32_t s = split[r], e = off[r + 1], d = e - s;
+        atomicMax(max_hi, d);
+        const bool hub = d >= hub_min && d <= PMAX;
+        is_hub[i] = hub ? 1u : 0u;
+        if (!hub) {
+            wkey[i] = ~0ull;
+            continue;
+        }
+        unsigned long long s2 = 0;
+        for (uint32_t t = s; t < e; t++) {
+            const uint32_t a = adj[t] >> 2;
+            s2 += off[a + 1] - lower_bound_rank(adj, off[a], off[a + 1], r + 1);
+        }
+        atomicMax(max_s2, s2);
+        const unsigned long long dd = d;
+        const unsigned long long w = dd * (dd - 1) * (dd - 2) / 6 + s2 * dd + s2 + 1;
+        wkey[i] = ~w;   // ascending sort of ~w = largest work first; non-hubs (~0) last
+    }
+}
+
+__global__ void k_split_bins(const uint32_t* __restrict__ roots, const uint32_t* __restrict__ is_hub,
+                             const uint32_t* __restrict__ pos, int64_t nroots, uint32_t* __restrict__ light) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nroots; i += (int64_t)gridDim.x * blockDim.x)
+        if (!is_hub[i]) light[i - pos[i]] = roots[i];
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+int g_num_cu = -1;
+
+int hub_workgroups() {
+    if (g_num_cu < 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            g_num_cu = prop.multiProcessorCount;
+        else
+            g_num_cu = 256;
+    }
+    return g_num_cu;
+}
+
+}  // namespace
+
+int hub_min_default() {
+    const char* e = getenv("VDMC_HUB_MIN");
+    if (e && *e) return atoi(e);
+    return 48;
+}
+
+void free_hub(vdmc_graph_s* g) {
+    (void)hipFree(g->light);
+    (void)hipFree(g->hubs);
+    (void)hipFree(g->hub_scratch);
+    (void)hipFree(g->hub_queue);
+    g->light = g->hubs = nullptr;
+    g->hub_scratch = nullptr;
+    g->hub_queue = nullptr;
+    g->bins_hub_min = -1;
+}
+
+void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
+    if (g->bins_hub_min == hub_min) return;
+    free_hub(g);
+    const int64_t nr = g->nroots;
+    std::vector<void*> tmp;
+    auto alloc = [&](size_t bytes) {
+        void* p = nullptr;
+        VDMC_HIP(hipMalloc(&p, bytes ? bytes : 16));
+        tmp.push_back(p);
+        return p;
+    };
+    struct Free {
+        std::vector<void*>& v;
+        ~Free() {
+            for (void* p : v) (void)hipFree(p);
+        }
+    } guard{tmp};
+    uint32_t* is_hub = (uint32_t*)alloc((nr + 1) * sizeof(uint32_t));
+    uint32_t* pos = (uint32_t*)alloc((nr + 1) * sizeof(uint32_t));
+    unsigned long long* wkey = (unsigned long long*)alloc((nr + 1) * sizeof(unsigned long long));
+    unsigned long long* wkey_s = (unsigned long long*)alloc((nr + 1) * sizeof(unsigned long long));
+    uint32_t* roots_s = (uint32_t*)alloc((nr + 1) * sizeof(uint32_t));
+    unsigned long long* d_max = (unsigned long long*)alloc(2 * sizeof(unsigned long long));
+    VDMC_HIP(hipMemsetAsync(d_max, 0, 2 * sizeof(unsigned long long), st));
+    unsigned* d_maxhi = (unsigned*)(d_max + 1);
+    int64_t nhub = 0, nlight = 0;
+    unsigned long long max_s2 = 0;
+    unsigned maxhi = 0;
+    if (nr > 0) {
+        unsigned blocks = (unsigned)std::min<int64_t>((nr + BT - 1) / BT, 65536);
+        hipLaunchKernelGGL(k_root_work, dim3(blocks), dim3(BT), 0, st, g->off, g->adj, g->split, g->roots, nr,
+                           (uint32_t)hub_min, is_hub, wkey, d_max, d_maxhi);
+        VDMC_HIP(hipGetLastError());
+        VDMC_HIP(hipMemsetAsync(is_hub + nr, 0, sizeof(uint32_t), st));
+        size_t tb = 0;
+        int n1 = (int)(nr + 1);
+        VDMC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, is_hub, pos, n1, st));
+        void* t1 = alloc(tb);
+        VDMC_HIP(hipcub::DeviceScan::ExclusiveSum(t1, tb, is_hub, pos, n1, st));
+        uint32_t h = 0;
+        VDMC_HIP(hipMemcpyAsync(&h, pos + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        VDMC_HIP(hipMemcpyAsync(&max_s2, d_max, sizeof(max_s2), hipMemcpyDeviceToHost, st));
+        VDMC_HIP(hipMemcpyAsync(&maxhi, d_maxhi, sizeof(maxhi), hipMemcpyDeviceToHost, st));
+        VDMC_HIP(hipStreamSynchronize(st));
+        nhub = h;
+        nlight = nr - nhub;
+        VDMC_HIP(hipMalloc(&g->light, (nlight + 1) * sizeof(uint32_t)));
+        VDMC_HIP(hipMalloc(&g->hubs, (nhub + 1) * sizeof(uint32_t)));
+        if (nlight > 0)
+            hipLaunchKernelGGL(k_split_bins, dim3(blocks), dim3(BT), 0, st, g->roots, is_hub, pos, nr, g->light);
+        VDMC_HIP(hipGetLastError());
+        if (nhub > 0) {
+            // sort all roots by work key (non-hubs carry ~0 and land at the end)
+            size_t sb = 0;
+            int ni = (int)nr;
+            VDMC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sb, wkey, wkey_s, g->roots, roots_s, ni, 0, 64, st));
+            void* t2 = alloc(sb);
+            VDMC_HIP(hipcub::DeviceRadixSort::SortPairs(t2, sb, wkey, wkey_s, g->roots, roots_s, ni, 0, 64, st));
+            VDMC_HIP(hipMemcpyAsync(g->hubs, roots_s, nhub * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+        }
+        VDMC_HIP(hipStreamSynchronize(st));
+    } else {
+        VDMC_HIP(hipMalloc(&g->light, sizeof(uint32_t)));
+        VDMC_HIP(hipMalloc(&g->hubs, sizeof(uint32_t)));
+    }
+    g->nhub = nhub;
+    g->nlight = nlight;
+    g->max_scan2 = (int64_t)max_s2;
+    g->max_hi = (int32_t)maxhi;
+    VDMC_HIP(hipMalloc(&g->hub_queue, 16));
+    if (nhub > 0) {
+        const int wgs = hub_workgroups();
+        const size_t s2 = (size_t)max_s2 + 64;
+        const size_t wl = (size_t)std::max<int32_t>(g->max_deg, 1) + 64;
+        size_t o = M_WORDS;
+        const size_t o_spar = o; o += 9 * PMAX;
+        const size_t o_s111 = o; o += 9 * PMAX;
+        const size_t o_s3x = o; o += 3 * PMAX;
+        const size_t o_groups = o; o += 4 * s2;
+        const size_t o_alist = o; o += s2;
+        const size_t o_wlist = o; o += NW * wl;
+        const size_t o_c120 = o; o += 3 * NW * wl;
+        const size_t o_eflag = o; o += (s2 + 3) / 4;
+        o = (o + 63) & ~(size_t)63;
+        g->hub_scratch_bytes = o * sizeof(uint32_t) * (size_t)wgs;
+        VDMC_HIP(hipMalloc(&g->hub_scratch, g->hub_scratch_bytes));
+        g->hub_layout[0] = o;
+        g->hub_layout[1] = o_spar;
+        g->hub_layout[2] = o_s111;
+        g->hub_layout[3] = o_s3x;
+        g->hub_layout[4] = o_groups;
+        g->hub_layout[5] = o_alist;
+        g->hub_layout[6] = o_wlist;
+        g->hub_layout[7] = o_c120;
+        g->hub_layout[8] = o_eflag;
+        g->hub_layout[9] = wl;
+    }
+    g->bins_hub_min = hub_min;
+}
+
+void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st) {
+    if (g->nhub == 0) return;
+    const ClassTables& t = class_tables();
+    HubArgs a;
+    a.off = g->off;
+    a.adj = g->adj;
+    a.split = g->split;
+    a.perm = g->perm;
+    a.hubs = g->hubs;
+    a.nhub = (uint32_t)g->nhub;
+    a.queue = g->hub_queue;
+    a.t3 = t.t3;
+    a.t4 = t.t4;
+    a.out3 = (unsigned long long*)out3;
+    a.out4 = (unsigned long long*)out4;
+    a.stats = g->stats;
+    a.k3 = k3;
+    a.k4 = k4;
+    a.scratch = (uint32_t*)g->hub_scratch;
+    a.wg_words = g->hub_layout[0];
+    a.o_spar = g->hub_layout[1];
+    a.o_s111 = g->hub_layout[2];
+    a.o_s3x = g->hub_layout[3];
+    a.o_groups = g->hub_layout[4];
+    a.o_alist = g->hub_layout[5];
+    a.o_wlist = g->hub_layout[6];
+    a.o_c120 = g->hub_layout[7];
+    a.o_eflag = g->hub_layout[8];
+    a.wl_cap = (uint32_t)g->hub_layout[9];
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 4);
+    const int wgs = hub_workgroups();
+    hipLaunchKernelGGL(k_hub, dim3(wgs), dim3(HT), 0, st, a);
+    VDMC_HIP(hipGetLastError());
+}
+
+}  // namespace vdmc

@@ -105,6 +105,19 @@ struct vdmc_graph_s {
     int64_t nroots = 0;
     unsigned long long* stats = nullptr;  // kShapes shape counters of the last count
     std::mutex mu;
+    // root bins (built at the first count for a given hub threshold)
+    int bins_hub_min = -1;
+    uint32_t* light = nullptr;   // roots handled by the per-set kernel
+    int64_t nlight = 0;
+    uint32_t* hubs = nullptr;    // roots handled by the hub kernel, largest work first
+    int64_t nhub = 0;
+    int64_t max_scan2 = 0;       // largest depth-2 scan over hub roots (scratch sizing)
+    int32_t max_hi = 0;          // largest |N+(r)|
+    // hub-kernel scratch (per workgroup slices), sized for this graph
+    void* hub_scratch = nullptr;
+    size_t hub_scratch_bytes = 0;
+    unsigned* hub_queue = nullptr;
+    size_t hub_layout[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace vdmc {
@@ -112,4 +125,9 @@ namespace vdmc {
 void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
                   hipStream_t stream);
 void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t stream);
+// hub path (count_hub.hip)
+void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t stream);
+void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t stream);
+int hub_min_default();
+void free_hub(vdmc_graph_s* g);
 }  // namespace vdmc
