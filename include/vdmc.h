@@ -128,6 +128,13 @@ vdmc_status vdmc_count34(vdmc_graph g, uint64_t* out3, uint64_t* out4, void* str
  * (2,1,0), (1,2,0), (1,1,1).  shape_counts: 6 entries. */
 vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
 
+/* Diagnostic counters of the last count on this graph (host, synchronous): entries 0-5
+ * are the shape counts above; entries 8-15 the device cycles the hub workgroups spent
+ * per phase (stage, local matrix, k=3 pairs, depth-2 groups, (3,0,0), group shapes,
+ * (1,2,0), flush), summed over workgroups; entries 16-23 the numbers of sets that took
+ * the direct (unaggregated) crediting path per shape.  Copies min(n, 32) entries. */
+vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n);
+
 /*
  * Batched counts: num graphs, one k for all, outs[i] a DEVICE buffer of
  * n_i * vdmc_num_classes(k) uint64 for graph gs[i].  All graphs are counted by one

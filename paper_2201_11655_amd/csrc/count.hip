@@ -26,7 +26,7 @@ namespace vdmc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint32_t kStage = 2048;   // entries of N+(r) staged in LDS
+constexpr uint32_t kStage = 2048;   // entries of N+(r) staged in LDS (single-graph launch)
 
 struct Args {
     const uint32_t* off;
@@ -57,161 +57,212 @@ __device__ __forceinline__ void credit(unsigned long long* out, const int32_t* p
     if (cls < (uint32_t)C) atomicAdd(&out[(size_t)perm[v] * C + cls], 1ull);   // 0xFF never credited
 }
 
-template <bool K3, bool K4>
-__global__ __launch_bounds__(kThreads) void k_count_roots(Args a) {
-    __shared__ uint32_t sP[kStage];
-    __shared__ uint32_t sLo[kStage + 1];     // first entry of row P[i] above r
-    __shared__ uint32_t sPre[kStage + 1];    // prefix sums of the D2 scan lengths
-    __shared__ unsigned long long sRoot3[kClasses3];
-    __shared__ unsigned long long sRoot4[kClasses4];
+template <uint32_t STAGE>
+struct RootLds {
+    uint32_t P[STAGE];
+    uint32_t lo[STAGE + 1];     // first entry of row P[i] above r
+    uint32_t pre[STAGE + 1];    // prefix sums of the depth-2 scan lengths
+    unsigned long long root3[kClasses3];
+    unsigned long long root4[kClasses4];
+};
+
+// All k-sets whose lowest-rank vertex is r, by one workgroup of BS threads, every set
+// credited to its non-root members with one atomic each (the root is summed in LDS).
+template <int BS, uint32_t STAGE, bool K3, bool K4>
+__device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8_t* t4, uint32_t r,
+                             RootLds<STAGE>& S, unsigned long long* shape) {
     const uint32_t tid = threadIdx.x;
-    unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
+    const uint32_t s = gv.split[r];
+    const uint32_t d = gv.off[r + 1] - s;
+    const bool staged = d <= STAGE;
+    __syncthreads();
+    if (staged)
+        for (uint32_t i = tid; i < d; i += BS) S.P[i] = gv.adj[s + i];
+    if (K3)
+        for (uint32_t i = tid; i < kClasses3; i += BS) S.root3[i] = 0;
+    if (K4)
+        for (uint32_t i = tid; i < kClasses4; i += BS) S.root4[i] = 0;
+    __syncthreads();
+    const uint32_t* P = staged ? S.P : gv.adj + s;
 
-    for (int64_t ri = blockIdx.x; ri < a.nroots; ri += gridDim.x) {
-        const uint32_t r = a.roots[ri];
-        const uint32_t s = a.split[r];
-        const uint32_t d = a.off[r + 1] - s;
-        const bool staged = d <= kStage;
-        __syncthreads();
-        if (staged)
-            for (uint32_t i = tid; i < d; i += kThreads) sP[i] = a.adj[s + i];
-        if (K3)
-            for (uint32_t i = tid; i < kClasses3; i += kThreads) sRoot3[i] = 0;
-        if (K4)
-            for (uint32_t i = tid; i < kClasses4; i += kThreads) sRoot4[i] = 0;
-        __syncthreads();
-        const uint32_t* P = staged ? sP : a.adj + s;
+    // ---- depth-1 shapes: pairs (i < j) of N+(r); k=4 extends each by l > j
+    const uint64_t npairs = (uint64_t)d * (d - 1) / 2;
+    for (uint64_t q = tid; q < npairs; q += BS) {
+        uint32_t j = (uint32_t)((1.0 + sqrt(1.0 + 8.0 * (double)q)) * 0.5);
+        while ((uint64_t)j * (j - 1) / 2 > q) j--;
+        while ((uint64_t)(j + 1) * j / 2 <= q) j++;
+        const uint32_t i = (uint32_t)(q - (uint64_t)j * (j - 1) / 2);
+        const uint32_t ea = P[i], eb = P[j];
+        const uint32_t va = ea >> 2, vb = eb >> 2, ra = ea & 3u, rb = eb & 3u;
+        const uint32_t ab = arc_bits(gv.off, gv.adj, va, vb);
+        if (K3) {
+            const uint32_t cls = t3[motif_index3(ra, rb, ab)];
+            if (cls < kClasses3) atomicAdd(&S.root3[cls], 1ull);
+            credit(gv.out3, gv.perm, kClasses3, va, cls);
+            credit(gv.out3, gv.perm, kClasses3, vb, cls);
+            shape[0]++;
+        }
+        if (K4) {
+            for (uint32_t l = j + 1; l < d; l++) {
+                const uint32_t ec = P[l];
+                const uint32_t vc = ec >> 2, rc = ec & 3u;
+                const uint32_t ac = arc_bits(gv.off, gv.adj, va, vc);
+                const uint32_t bc = arc_bits(gv.off, gv.adj, vb, vc);
+                const uint32_t cls = t4[motif_index4(ra, rb, rc, ab, ac, bc)];
+                if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
+                credit(gv.out4, gv.perm, kClasses4, va, cls);
+                credit(gv.out4, gv.perm, kClasses4, vb, cls);
+                credit(gv.out4, gv.perm, kClasses4, vc, cls);
+                shape[2]++;
+            }
+        }
+    }
 
-        // ---- depth-1 shapes: pairs (i < j) of N+(r); k=4 extends each by l > j
-        const uint64_t npairs = (uint64_t)d * (d - 1) / 2;
-        for (uint64_t q = tid; q < npairs; q += kThreads) {
-            uint32_t j = (uint32_t)((1.0 + sqrt(1.0 + 8.0 * (double)q)) * 0.5);
-            while ((uint64_t)j * (j - 1) / 2 > q) j--;
-            while ((uint64_t)(j + 1) * j / 2 <= q) j++;
-            const uint32_t i = (uint32_t)(q - (uint64_t)j * (j - 1) / 2);
-            const uint32_t ea = P[i], eb = P[j];
-            const uint32_t va = ea >> 2, vb = eb >> 2, ra = ea & 3u, rb = eb & 3u;
-            const uint32_t ab = arc_bits(a.off, a.adj, va, vb);
+    // ---- depth-2 candidates: entries (a, c) of rows of N+(r) with c > r, c not in N(r)
+    for (uint32_t c0 = 0; c0 < d; c0 += STAGE) {
+        const uint32_t cn = min(STAGE, d - c0);
+        __syncthreads();
+        for (uint32_t i = tid; i < cn; i += BS) {
+            const uint32_t va = P[c0 + i] >> 2;
+            S.lo[i] = lower_bound_rank(gv.adj, gv.off[va], gv.off[va + 1], r + 1);
+            S.pre[i + 1] = gv.off[va + 1] - S.lo[i];
+        }
+        __syncthreads();
+        if (tid == 0) {   // short serial scan: light roots have few depth-1 vertices
+            S.pre[0] = 0;
+            for (uint32_t i = 1; i <= cn; i++) S.pre[i] += S.pre[i - 1];
+        }
+        __syncthreads();
+        const uint32_t total = S.pre[cn];
+        for (uint32_t q = tid; q < total; q += BS) {
+            uint32_t lo = 0, hi = cn;   // slot with pre[i] <= q < pre[i+1]
+            while (hi - lo > 1) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (S.pre[mid] <= q) lo = mid; else hi = mid;
+            }
+            const uint32_t i = c0 + lo;
+            const uint32_t ea = P[i];
+            const uint32_t va = ea >> 2, ra = ea & 3u;
+            const uint32_t t = S.lo[lo] + (q - S.pre[lo]);
+            const uint32_t ecn = gv.adj[t];
+            const uint32_t vc = ecn >> 2, ac = ecn & 3u;
+            if (in_list(P, d, vc)) continue;   // c adjacent to r: depth 1, not 2
             if (K3) {
-                const uint32_t cls = a.t3[motif_index3(ra, rb, ab)];
-                if (cls < kClasses3) atomicAdd(&sRoot3[cls], 1ull);
-                credit(a.out3, a.perm, kClasses3, va, cls);
-                credit(a.out3, a.perm, kClasses3, vb, cls);
-                shape[0]++;
+                const uint32_t cls = t3[motif_index3(ra, 0u, ac)];
+                if (cls < kClasses3) atomicAdd(&S.root3[cls], 1ull);
+                credit(gv.out3, gv.perm, kClasses3, va, cls);
+                credit(gv.out3, gv.perm, kClasses3, vc, cls);
+                shape[1]++;
             }
             if (K4) {
-                for (uint32_t l = j + 1; l < d; l++) {
-                    const uint32_t ec = P[l];
-                    const uint32_t vc = ec >> 2, rc = ec & 3u;
-                    const uint32_t ac = arc_bits(a.off, a.adj, va, vc);
-                    const uint32_t bc = arc_bits(a.off, a.adj, vb, vc);
-                    const uint32_t cls = a.t4[motif_index4(ra, rb, rc, ab, ac, bc)];
-                    if (cls < kClasses4) atomicAdd(&sRoot4[cls], 1ull);
-                    credit(a.out4, a.perm, kClasses4, va, cls);
-                    credit(a.out4, a.perm, kClasses4, vb, cls);
-                    credit(a.out4, a.perm, kClasses4, vc, cls);
-                    shape[2]++;
+                // (2,1,0): second depth-1 vertex b
+                for (uint32_t j = 0; j < d; j++) {
+                    if (j == i) continue;
+                    const uint32_t eb = P[j];
+                    const uint32_t vb = eb >> 2, rb = eb & 3u;
+                    const uint32_t bc = arc_bits(gv.off, gv.adj, vb, vc);
+                    if (bc && j < i) continue;   // c hangs under the lower-rank parent b
+                    const uint32_t ab = arc_bits(gv.off, gv.adj, va, vb);
+                    const uint32_t cls = t4[motif_index4(ra, rb, 0u, ab, ac, bc)];
+                    if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
+                    credit(gv.out4, gv.perm, kClasses4, va, cls);
+                    credit(gv.out4, gv.perm, kClasses4, vb, cls);
+                    credit(gv.out4, gv.perm, kClasses4, vc, cls);
+                    shape[3]++;
+                }
+                // (1,2,0): a second depth-2 child c' > c of a
+                const uint32_t ha = gv.off[va + 1];
+                for (uint32_t t2 = t + 1; t2 < ha; t2++) {
+                    const uint32_t e2 = gv.adj[t2];
+                    const uint32_t vc2 = e2 >> 2;
+                    if (in_list(P, d, vc2)) continue;
+                    const uint32_t cc2 = arc_bits(gv.off, gv.adj, vc, vc2);
+                    const uint32_t cls = t4[motif_index4(ra, 0u, 0u, ac, e2 & 3u, cc2)];
+                    if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
+                    credit(gv.out4, gv.perm, kClasses4, va, cls);
+                    credit(gv.out4, gv.perm, kClasses4, vc, cls);
+                    credit(gv.out4, gv.perm, kClasses4, vc2, cls);
+                    shape[4]++;
+                }
+                // (1,1,1): path r - a - c - e, e not adjacent to r nor to a
+                const uint32_t hc = gv.off[vc + 1];
+                for (uint32_t t3i = lower_bound_rank(gv.adj, gv.off[vc], hc, r + 1); t3i < hc; t3i++) {
+                    const uint32_t e3 = gv.adj[t3i];
+                    const uint32_t ve = e3 >> 2;
+                    if (in_list(P, d, ve)) continue;                // also excludes a itself
+                    if (arc_bits(gv.off, gv.adj, va, ve)) continue; // e adjacent to a: depth 2
+                    const uint32_t cls = t4[motif_index4(ra, 0u, 0u, ac, 0u, e3 & 3u)];
+                    if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
+                    credit(gv.out4, gv.perm, kClasses4, va, cls);
+                    credit(gv.out4, gv.perm, kClasses4, vc, cls);
+                    credit(gv.out4, gv.perm, kClasses4, ve, cls);
+                    shape[5]++;
                 }
             }
         }
-
-        // ---- depth-2 candidates: entries (a, c) of rows of N+(r) with c > r, c not in N(r)
-        for (uint32_t c0 = 0; c0 < d; c0 += kStage) {
-            const uint32_t cn = min(kStage, d - c0);
-            __syncthreads();
-            for (uint32_t i = tid; i < cn; i += kThreads) {
-                const uint32_t va = P[c0 + i] >> 2;
-                sLo[i] = lower_bound_rank(a.adj, a.off[va], a.off[va + 1], r + 1);
-                sPre[i + 1] = a.off[va + 1] - sLo[i];
-            }
-            __syncthreads();
-            if (tid == 0) {   // short serial scan; v1 keeps this simple
-                sPre[0] = 0;
-                for (uint32_t i = 1; i <= cn; i++) sPre[i] += sPre[i - 1];
-            }
-            __syncthreads();
-            const uint32_t total = sPre[cn];
-            for (uint32_t q = tid; q < total; q += kThreads) {
-                uint32_t lo = 0, hi = cn;   // slot with sPre[i] <= q < sPre[i+1]
-                while (hi - lo > 1) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (sPre[mid] <= q) lo = mid; else hi = mid;
-                }
-                const uint32_t i = c0 + lo;
-                const uint32_t ea = P[i];
-                const uint32_t va = ea >> 2, ra = ea & 3u;
-                const uint32_t t = sLo[lo] + (q - sPre[lo]);
-                const uint32_t ecn = a.adj[t];
-                const uint32_t vc = ecn >> 2, ac = ecn & 3u;
-                if (in_list(P, d, vc)) continue;   // c adjacent to r: depth 1, not 2
-                if (K3) {
-                    const uint32_t cls = a.t3[motif_index3(ra, 0u, ac)];
-                    if (cls < kClasses3) atomicAdd(&sRoot3[cls], 1ull);
-                    credit(a.out3, a.perm, kClasses3, va, cls);
-                    credit(a.out3, a.perm, kClasses3, vc, cls);
-                    shape[1]++;
-                }
-                if (K4) {
-                    // (2,1,0): second depth-1 vertex b
-                    for (uint32_t j = 0; j < d; j++) {
-                        if (j == i) continue;
-                        const uint32_t eb = P[j];
-                        const uint32_t vb = eb >> 2, rb = eb & 3u;
-                        const uint32_t bc = arc_bits(a.off, a.adj, vb, vc);
-                        if (bc && j < i) continue;   // c hangs under the lower-rank parent b
-                        const uint32_t ab = arc_bits(a.off, a.adj, va, vb);
-                        uint32_t code;
-                        if (i < j) code = motif_index4(ra, rb, 0u, ab, ac, bc);
-                        else code = motif_index4(rb, ra, 0u, swap_arc_bits(ab), bc, ac);
-                        const uint32_t cls = a.t4[code];
-                        if (cls < kClasses4) atomicAdd(&sRoot4[cls], 1ull);
-                        credit(a.out4, a.perm, kClasses4, va, cls);
-                        credit(a.out4, a.perm, kClasses4, vb, cls);
-                        credit(a.out4, a.perm, kClasses4, vc, cls);
-                        shape[3]++;
-                    }
-                    // (1,2,0): a second depth-2 child c' > c of a
-                    const uint32_t ha = a.off[va + 1];
-                    for (uint32_t t2 = t + 1; t2 < ha; t2++) {
-                        const uint32_t e2 = a.adj[t2];
-                        const uint32_t vc2 = e2 >> 2;
-                        if (in_list(P, d, vc2)) continue;
-                        const uint32_t cc2 = arc_bits(a.off, a.adj, vc, vc2);
-                        const uint32_t cls = a.t4[motif_index4(ra, 0u, 0u, ac, e2 & 3u, cc2)];
-                        if (cls < kClasses4) atomicAdd(&sRoot4[cls], 1ull);
-                        credit(a.out4, a.perm, kClasses4, va, cls);
-                        credit(a.out4, a.perm, kClasses4, vc, cls);
-                        credit(a.out4, a.perm, kClasses4, vc2, cls);
-                        shape[4]++;
-                    }
-                    // (1,1,1): path r - a - c - e, e not adjacent to r nor to a
-                    const uint32_t hc = a.off[vc + 1];
-                    for (uint32_t t3 = lower_bound_rank(a.adj, a.off[vc], hc, r + 1); t3 < hc; t3++) {
-                        const uint32_t e3 = a.adj[t3];
-                        const uint32_t ve = e3 >> 2;
-                        if (in_list(P, d, ve)) continue;               // also excludes a itself
-                        if (arc_bits(a.off, a.adj, va, ve)) continue;  // e adjacent to a: depth 2
-                        const uint32_t cls = a.t4[motif_index4(ra, 0u, 0u, ac, 0u, e3 & 3u)];
-                        if (cls < kClasses4) atomicAdd(&sRoot4[cls], 1ull);
-                        credit(a.out4, a.perm, kClasses4, va, cls);
-                        credit(a.out4, a.perm, kClasses4, vc, cls);
-                        credit(a.out4, a.perm, kClasses4, ve, cls);
-                        shape[5]++;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        const size_t row = (size_t)a.perm[r];
-        if (K3)
-            for (uint32_t i = tid; i < kClasses3; i += kThreads)
-                if (sRoot3[i]) atomicAdd(&a.out3[row * kClasses3 + i], sRoot3[i]);
-        if (K4)
-            for (uint32_t i = tid; i < kClasses4; i += kThreads)
-                if (sRoot4[i]) atomicAdd(&a.out4[row * kClasses4 + i], sRoot4[i]);
     }
+    __syncthreads();
+    const size_t row = (size_t)gv.perm[r];
+    if (K3)
+        for (uint32_t i = tid; i < kClasses3; i += BS)
+            if (S.root3[i]) atomicAdd(&gv.out3[row * kClasses3 + i], S.root3[i]);
+    if (K4)
+        for (uint32_t i = tid; i < kClasses4; i += BS)
+            if (S.root4[i]) atomicAdd(&gv.out4[row * kClasses4 + i], S.root4[i]);
+}
+
+template <bool K3, bool K4>
+__global__ __launch_bounds__(kThreads) void k_count_roots(Args a) {
+    __shared__ RootLds<kStage> S;
+    unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
+    GraphView gv{a.off, a.adj, a.split, a.perm, a.out3, a.out4, a.stats};
+    for (int64_t ri = blockIdx.x; ri < a.nroots; ri += gridDim.x)
+        process_root<kThreads, kStage, K3, K4>(gv, a.t3, a.t4, a.roots[ri], S, shape);
     for (int s = 0; s < kShapes; s++)
         if (shape[s]) atomicAdd(&a.stats[s], shape[s]);
+}
+
+// Batched launch: a root table of (graph, root) pairs over many graphs, consumed in
+// tiles from a device-side cursor by a persistent grid.
+template <int BS, uint32_t STAGE, bool K3, bool K4>
+__global__ __launch_bounds__(BS) void k_count_batch(BatchArgs b) {
+    __shared__ RootLds<STAGE> S;
+    __shared__ unsigned long long tile_start;
+    unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
+    int cur_graph = -1;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) tile_start = atomicAdd(b.cursor, (unsigned long long)b.tile);
+        __syncthreads();
+        const unsigned long long t0 = tile_start;
+        if (t0 >= b.nentries) break;
+        const unsigned long long t1 = min(t0 + b.tile, b.nentries);
+        for (unsigned long long e = t0; e < t1; e++) {
+            const uint2 ent = b.table[e];   // x = graph index, y = root rank
+            if ((int)ent.x != cur_graph) {
+                if (cur_graph >= 0)
+                    for (int s = 0; s < kShapes; s++)
+                        if (shape[s]) { atomicAdd(&b.graphs[cur_graph].stats[s], shape[s]); shape[s] = 0; }
+                cur_graph = (int)ent.x;
+            }
+            process_root<BS, STAGE, K3, K4>(b.graphs[ent.x], b.t3, b.t4, ent.y, S, shape);
+        }
+    }
+    if (cur_graph >= 0)
+        for (int s = 0; s < kShapes; s++)
+            if (shape[s]) atomicAdd(&b.graphs[cur_graph].stats[s], shape[s]);
+}
+
+// zero every graph's output(s) and shape counters; one workgroup per graph
+__global__ void k_batch_zero(BatchArgs b, int k3, int k4) {
+    const GraphView& g = b.graphs[blockIdx.x];
+    const size_t n = b.nvert[blockIdx.x];
+    if (k3)
+        for (size_t i = threadIdx.x; i < n * kClasses3; i += blockDim.x) g.out3[i] = 0;
+    if (k4)
+        for (size_t i = threadIdx.x; i < n * kClasses4; i += blockDim.x) g.out4[i] = 0;
+    for (int i = threadIdx.x; i < kStatSlots; i += blockDim.x) g.stats[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *b.cursor = 0;
 }
 
 __global__ void k_fill(unsigned long long* p, size_t n, unsigned long long v) {
@@ -220,6 +271,33 @@ __global__ void k_fill(unsigned long long* p, size_t n, unsigned long long v) {
 }
 
 }  // namespace
+
+void launch_batch(const BatchArgs& b, int variant, int k3, int k4, int num_graphs, int wgs_per_cu, hipStream_t st) {
+    static int ncu = -1;
+    if (ncu < 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        VDMC_HIP(hipGetDevice(&dev));
+        VDMC_HIP(hipGetDeviceProperties(&prop, dev));
+        ncu = prop.multiProcessorCount;
+    }
+    hipLaunchKernelGGL(k_batch_zero, dim3(num_graphs), dim3(256), 0, st, b, k3, k4);
+    VDMC_HIP(hipGetLastError());
+    const unsigned grid = (unsigned)(ncu * wgs_per_cu);
+#define VDMC_BATCH_LAUNCH(BS, STG)                                                                           \
+    do {                                                                                                    \
+        if (k3 && k4) hipLaunchKernelGGL((k_count_batch<BS, STG, true, true>), dim3(grid), dim3(BS), 0, st, b); \
+        else if (k3) hipLaunchKernelGGL((k_count_batch<BS, STG, true, false>), dim3(grid), dim3(BS), 0, st, b); \
+        else hipLaunchKernelGGL((k_count_batch<BS, STG, false, true>), dim3(grid), dim3(BS), 0, st, b);         \
+    } while (0)
+    switch (variant) {
+        case 0: VDMC_BATCH_LAUNCH(64, 256); break;
+        case 1: VDMC_BATCH_LAUNCH(128, 256); break;
+        default: VDMC_BATCH_LAUNCH(256, 512); break;
+    }
+#undef VDMC_BATCH_LAUNCH
+    VDMC_HIP(hipGetLastError());
+}
 
 void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t st) {
     if (n == 0) return;
@@ -235,7 +313,7 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
     ensure_bins(g, hub_min_default(), st);
     if (k3) launch_fill_u64(out3, (size_t)g->n * kClasses3, 0, st);
     if (k4) launch_fill_u64(out4, (size_t)g->n * kClasses4, 0, st);
-    launch_fill_u64((uint64_t*)g->stats, kShapes, 0, st);
+    launch_fill_u64((uint64_t*)g->stats, kStatSlots, 0, st);
     if (g->nlight > 0) {
         Args a;
         a.off = g->off;
@@ -284,6 +362,16 @@ vdmc_status vdmc_count34(vdmc_graph g, uint64_t* out3, uint64_t* out4, void* str
         VDMC_REQUIRE(out3 != out4 || g->n == 0, VDMC_ERR_INVALID_ARG, "out3 and out4 alias");
         VDMC_HIP(hipSetDevice(g->device));
         vdmc::launch_count(g, 1, 1, out3, out4, vdmc::as_stream(stream));
+    });
+}
+
+vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n) {
+    return vdmc::guarded([&] {
+        VDMC_REQUIRE(g != nullptr && counters != nullptr && n >= 0, VDMC_ERR_INVALID_ARG, "bad argument");
+        VDMC_HIP(hipSetDevice(g->device));
+        VDMC_HIP(hipDeviceSynchronize());
+        const int k = n < vdmc::kStatSlots ? n : vdmc::kStatSlots;
+        VDMC_HIP(hipMemcpy(counters, g->stats, k * sizeof(uint64_t), hipMemcpyDeviceToHost));
     });
 }
 

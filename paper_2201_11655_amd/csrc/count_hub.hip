@@ -28,7 +28,7 @@
 namespace vdmc {
 namespace {
 
-constexpr int HT = 512;             // threads per hub workgroup
+constexpr int HT = 1024;            // threads per hub workgroup
 constexpr int NW = HT / 64;         // waves per workgroup
 constexpr uint32_t PMAX = 2048;     // largest |N+(r)| on the hub path
 constexpr uint32_t NCHMAX = PMAX / 64;
@@ -52,7 +52,7 @@ struct HubArgs {
     // per-workgroup scratch
     uint32_t* scratch;
     size_t wg_words;        // u32 words per workgroup slice
-    size_t o_spar, o_s111, o_s3x, o_groups, o_alist, o_wlist, o_c120, o_eflag;
+    size_t o_spar, o_s111, o_s3x, o_groups, o_alist, o_wlist, o_c120, o_eflag, o_llist;
     uint32_t wl_cap;        // per-wave list capacity (>= max degree)
 };
 
@@ -141,47 +141,116 @@ __device__ __forceinline__ int wave_next(unsigned* sTask) {
 
 // ----------------------------------------------------------------------------- kernel
 
-__global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
-    __shared__ uint32_t sP[PMAX];
-    __shared__ uint32_t sPre[PMAX + 1];
-    __shared__ uint32_t sLo[PMAX];
-    __shared__ uint32_t sCnt[9 * PMAX];
-    __shared__ uint8_t sT4[4096];
-    __shared__ uint8_t sT3[64];
-    __shared__ unsigned long long sRoot4[kClasses4];
-    __shared__ unsigned long long sRoot3[kClasses3];
-    __shared__ uint32_t sScan[HT];
-    __shared__ uint32_t sCw[NW][27 + 27 + kClasses3];   // per-wave group accumulators
-    __shared__ unsigned sTask;
-    __shared__ unsigned sGroups;
-    __shared__ unsigned sAlloc;
-    __shared__ unsigned sRootIdx;
+// P membership filter: one bit per hash bucket of a rank; a clear bit proves absence.
+constexpr uint32_t kBloomWords = 1024;   // 32768 bits
+__device__ __forceinline__ uint32_t bloom_bit(uint32_t x) { return (x * 2654435761u) >> 17; }
 
+struct Lds {
+    uint32_t P[PMAX];
+    uint32_t pre[PMAX + 1];
+    uint32_t lo[PMAX];
+    uint32_t cnt[9 * PMAX];
+    uint32_t bloom[kBloomWords];
+    uint32_t scan[HT];
+    uint32_t cw[NW][27 + 27 + kClasses3];      // per-wave group accumulators (c and r credits)
+    uint32_t inA[NW][PMAX / 32];               // per-wave membership bitmap of A(c)
+    uint32_t xacc[NW][64 * 3];                 // per-wave (1,1,1) depth-1 credits by A(c) position
+    unsigned long long root4[kClasses4];
+    unsigned long long root3[kClasses3];
+    unsigned long long stat[kStatSlots];       // shape counts, phase ticks, direct-path counts
+    uint16_t lcnt[PMAX];                       // local (in-N+(r)) degree of every slot
+    uint8_t t4[4096];
+    uint8_t t3[64];
+    unsigned task, groups, alloc, rootidx;
+};
+
+__device__ __forceinline__ int find_slot_f(const Lds& L, uint32_t d, uint32_t x) {
+    const uint32_t b = bloom_bit(x);
+    if (!((L.bloom[b >> 5] >> (b & 31)) & 1u)) return -1;
+    return find_slot(L.P, d, x);
+}
+
+// Up to kRC entries of a short CSR row kept in registers for repeated adjacency tests.
+constexpr uint32_t kRC = 4;
+struct RowCache {
+    uint32_t e[kRC];
+    uint32_t n;        // number cached (0..kRC); n > kRC means "row too long, search it"
+    uint32_t lo, hi;   // row bounds for the long case
+};
+__device__ __forceinline__ void row_cache_load(RowCache& rc, const uint32_t* off, const uint32_t* adj, uint32_t v,
+                                               bool active) {
+    rc.n = 0;
+    rc.lo = rc.hi = 0;
+    if (!active) return;
+    const uint32_t lo = off[v], hi = off[v + 1];
+    if (hi - lo <= kRC) {
+        rc.n = hi - lo;
+#pragma unroll
+        for (uint32_t k = 0; k < kRC; k++) rc.e[k] = (lo + k < hi) ? adj[lo + k] : 0xFFFFFFFFu;
+    } else {
+        rc.n = kRC + 1;
+        rc.lo = lo;
+        rc.hi = hi;
+    }
+}
+// arc bits of the pair (u, owner) seen from u, where owner is the vertex whose row is cached
+__device__ __forceinline__ uint32_t row_cache_bits_from(const RowCache& rc, const uint32_t* adj, uint32_t u) {
+    uint32_t e = 0xFFFFFFFFu;
+    if (rc.n <= kRC) {
+#pragma unroll
+        for (uint32_t k = 0; k < kRC; k++)
+            if ((rc.e[k] >> 2) == u) e = rc.e[k];
+    } else {
+        const uint32_t p = lower_bound_rank(adj, rc.lo, rc.hi, u);
+        if (p < rc.hi && (adj[p] >> 2) == u) e = adj[p];
+    }
+    return e == 0xFFFFFFFFu ? 0u : swap_arc_bits(e & 3u);   // entry is seen from the row owner
+}
+
+__global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
+    __shared__ Lds L;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
     const uint32_t wid = tid >> 6;
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
     uint32_t* W = A.scratch + (size_t)blockIdx.x * A.wg_words;
     uint32_t* M = W;
     uint32_t* spar = W + A.o_spar;     // [9][PMAX]  (2,1,0) parent-role counters
     uint32_t* s111 = W + A.o_s111;     // [9][PMAX]  (1,1,1) depth-1 counters
     uint32_t* s3x = W + A.o_s3x;       // [3][PMAX]  k=3 (1,2) depth-1 counters
-    uint32_t* grp = W + A.o_groups;    // 4 words per group: c, p, alist offset, row start
+    uint32_t* grp = W + A.o_groups;    // 4 words per group: c, p, alist offset, unused
     uint32_t* alist = W + A.o_alist;   // A(c) lists: slot << 2 | arc bits seen from the slot
     uint32_t* wlist = W + A.o_wlist + (size_t)wid * A.wl_cap;
     uint32_t* c120 = W + A.o_c120 + (size_t)wid * 3 * A.wl_cap;
     uint8_t* eflag = reinterpret_cast<uint8_t*>(W + A.o_eflag);
-    unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
+    uint16_t* llist = reinterpret_cast<uint16_t*>(W + A.o_llist);   // local neighbours per slot
+    // per-thread counters of the current root (sets per shape, sets on the direct path),
+    // reduced into L.stat once per root
+    uint32_t shape[kShapes] = {0, 0, 0, 0, 0, 0};
+    uint32_t slow[kShapes] = {0, 0, 0, 0, 0, 0};
+    unsigned long long tprev = wall_clock64();
+#define HUB_PHASE(k)                                      \
+    do {                                                  \
+        if (tid == 0) {                                   \
+            const unsigned long long tn = wall_clock64(); \
+            L.stat[8 + (k)] += tn - tprev;                \
+            tprev = tn;                                   \
+        }                                                 \
+    } while (0)
 
-    for (uint32_t i = tid; i < 4096; i += HT) sT4[i] = A.t4[i];
-    for (uint32_t i = tid; i < 64; i += HT) sT3[i] = A.t3[i];
+    for (uint32_t i = tid; i < 4096; i += HT) L.t4[i] = A.t4[i];
+    for (uint32_t i = tid; i < 64; i += HT) L.t3[i] = A.t3[i];
     for (uint32_t i = tid; i < 9 * PMAX; i += HT) { spar[i] = 0; s111[i] = 0; }
     for (uint32_t i = tid; i < 3 * PMAX; i += HT) s3x[i] = 0;
+    for (uint32_t i = tid; i < NW * (PMAX / 32); i += HT) (&L.inA[0][0])[i] = 0;
+    for (uint32_t i = tid; i < NW * (27 + 27 + kClasses3); i += HT) (&L.cw[0][0])[i] = 0;
+    for (uint32_t i = tid; i < kStatSlots; i += HT) L.stat[i] = 0;
 
     for (;;) {
         __syncthreads();
-        if (tid == 0) sRootIdx = atomicAdd(A.queue, 1u);
+        if (tid == 0) L.rootidx = atomicAdd(A.queue, 1u);
         __syncthreads();
-        const uint32_t ri = sRootIdx;
+        const uint32_t ri = L.rootidx;
         if (ri >= A.nhub) break;
         const uint32_t r = A.hubs[ri];
         const uint32_t s0 = A.split[r];
@@ -189,50 +258,65 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         const uint32_t nch = (d + 63) >> 6;
 
         // ---------------------------------------------------------------- stage
+        for (uint32_t i = tid; i < kBloomWords; i += HT) L.bloom[i] = 0;
+        __syncthreads();
         for (uint32_t i = tid; i < d; i += HT) {
             const uint32_t e = A.adj[s0 + i];
-            sP[i] = e;
+            L.P[i] = e;
             const uint32_t a = e >> 2;
+            const uint32_t b = bloom_bit(a);
+            atomicOr(&L.bloom[b >> 5], 1u << (b & 31));
             const uint32_t lo = lower_bound_rank(A.adj, A.off[a], A.off[a + 1], r + 1);
-            sLo[i] = lo;
-            sPre[i + 1] = A.off[a + 1] - lo;
+            L.lo[i] = lo;
+            L.pre[i + 1] = A.off[a + 1] - lo;
         }
-        for (uint32_t i = tid; i < kClasses4; i += HT) sRoot4[i] = 0;
-        for (uint32_t i = tid; i < kClasses3; i += HT) sRoot3[i] = 0;
-        for (uint32_t i = tid; i < 9 * d; i += HT) sCnt[i] = 0;
+        for (uint32_t i = tid; i < kClasses4; i += HT) L.root4[i] = 0;
+        for (uint32_t i = tid; i < kClasses3; i += HT) L.root3[i] = 0;
+        for (uint32_t i = tid; i < 9 * d; i += HT) L.cnt[i] = 0;
         const size_t mwords = (size_t)d * nch * 4;
         for (size_t i = tid; i < mwords; i += HT) M[i] = 0;
-        if (tid == 0) { sGroups = 0; sAlloc = 0; sTask = 0; }
+        if (tid == 0) { L.groups = 0; L.alloc = 0; L.task = 0; }
         __syncthreads();
-        block_prefix(sPre, d, sScan);
-        const uint32_t scan2 = sPre[d];
+        block_prefix(L.pre, d, L.scan);
+        const uint32_t scan2 = L.pre[d];
         __threadfence();
         __syncthreads();
+        HUB_PHASE(0);
 
-        // ---------------------------------------------------------------- local matrix + depth-2 flags
-        for (uint32_t q = tid; q < scan2; q += HT) {
-            const uint32_t i = slot_of(sPre, d, q);
-            const uint32_t e = A.adj[sLo[i] + (q - sPre[i])];
-            const int j = find_slot(sP, d, e >> 2);
-            if (j >= 0) {
-                atomicOr(&M[mword(d, i, (uint32_t)j)], (e & 3u) << mshift((uint32_t)j));
-                eflag[q] = 0;
-            } else {
-                eflag[q] = 1;
+        // ---------------------------------------------------------------- local matrix, local lists, depth-2 flags
+        // one wave per slot: the slot's row above r is split into neighbours inside N+(r)
+        // (kept in slot order in llist and in M) and depth-2 entries (eflag)
+        for (int t = wave_next(&L.task); t < (int)d; t = wave_next(&L.task)) {
+            const uint32_t i = (uint32_t)t;
+            const uint32_t q0 = L.pre[i], q1 = L.pre[i + 1], rlo = L.lo[i];
+            uint32_t nl = 0;
+            for (uint32_t qb = q0; qb < q1; qb += 64) {
+                const uint32_t q = qb + lane;
+                const bool v = q < q1;
+                const uint32_t e = v ? A.adj[rlo + (q - q0)] : 0u;
+                const int j = v ? find_slot_f(L, d, e >> 2) : -1;
+                if (j >= 0) atomicOr(&M[mword(d, i, (uint32_t)j)], (e & 3u) << mshift((uint32_t)j));
+                if (v) eflag[q] = j < 0 ? 1 : 0;
+                const unsigned long long mk = __ballot(j >= 0);
+                if (j >= 0) llist[q0 + nl + __popcll(mk & lt_mask)] = (uint16_t)(((uint32_t)j << 2) | (e & 3u));
+                nl += __popcll(mk);
             }
+            if (lane == 0) L.lcnt[i] = (uint16_t)nl;
         }
         __threadfence();
         __syncthreads();
+        if (tid == 0) L.task = 0;
+        __syncthreads();
+        HUB_PHASE(1);
 
         // ---------------------------------------------------------------- k=3 (1,1): pairs of slots
         if (A.k3) {
-            // tasks (ch, j): lanes are slots i = 64 ch + lane < j
             uint32_t total = 0;
             for (uint32_t ch = 0; ch < nch; ch++) total += (d > 64 * ch + 1) ? d - 1 - 64 * ch : 0;
-            for (int t = wave_next(&sTask); t < (int)total; t = wave_next(&sTask)) {
+            for (int t = wave_next(&L.task); t < (int)total; t = wave_next(&L.task)) {
                 uint32_t ch = 0, rem = (uint32_t)t;
                 while (true) {
-                    uint32_t c = d - 1 - 64 * ch;
+                    const uint32_t c = d - 1 - 64 * ch;
                     if (rem < c) break;
                     rem -= c;
                     ch++;
@@ -240,51 +324,55 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 const uint32_t j = 64 * ch + 1 + rem;
                 const uint32_t i = 64 * ch + lane;
                 const bool va = i < j;
-                const uint32_t ra = va ? (sP[i] & 3u) : 0u, rb = sP[j] & 3u;
-                const uint32_t ab = va ? swap_arc_bits(mget(M, d, j, i)) : 0u;
+                const uint32_t ra = va ? (L.P[i] & 3u) : 0u, rb = L.P[j] & 3u;
+                const uint32_t ab = (va && L.lcnt[i] && L.lcnt[j]) ? swap_arc_bits(mget(M, d, j, i)) : 0u;
                 const bool pure = va && ab == 0;
-                if (pure) atomicAdd(&sCnt[(rb - 1) * d + i], 1u);
+                if (pure) atomicAdd(&L.cnt[(rb - 1) * d + i], 1u);
                 if (va && !pure) {
-                    const uint32_t cls = sT3[motif_index3(ra, rb, ab)];
-                    atomicAdd(&sRoot3[cls], 1ull);
-                    add_out(A.out3, A.perm, kClasses3, sP[i] >> 2, cls, 1);
-                    add_out(A.out3, A.perm, kClasses3, sP[j] >> 2, cls, 1);
+                    slow[0]++;
+                    const uint32_t cls = L.t3[motif_index3(ra, rb, ab)];
+                    atomicAdd(&L.root3[cls], 1ull);
+                    add_out(A.out3, A.perm, kClasses3, L.P[i] >> 2, cls, 1);
+                    add_out(A.out3, A.perm, kClasses3, L.P[j] >> 2, cls, 1);
                 }
                 if (va) shape[0]++;
-                for (uint32_t k = 1; k <= 3; k++) {
-                    const uint32_t nk = __popcll(__ballot(pure && ra == k));
-                    if (lane == k - 1 && nk) {
-                        atomicAdd(&sCnt[(k - 1) * d + j], nk);
-                        atomicAdd(&sRoot3[sT3[motif_index3(k, rb, 0u)]], (unsigned long long)nk);
+                const uint32_t n1 = __popcll(__ballot(pure && ra == 1u));
+                const uint32_t n2 = __popcll(__ballot(pure && ra == 2u));
+                const uint32_t n3 = __popcll(__ballot(pure && ra == 3u));
+                if (lane < 3) {
+                    const uint32_t nk = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
+                    if (nk) {
+                        atomicAdd(&L.cnt[lane * d + j], nk);
+                        atomicAdd(&L.root3[L.t3[motif_index3(lane + 1, rb, 0u)]], (unsigned long long)nk);
                     }
                 }
             }
             __syncthreads();
             for (uint32_t q = tid; q < 3 * d; q += HT) {
-                const uint32_t cnt = sCnt[q];
+                const uint32_t cnt = L.cnt[q];
                 if (!cnt) continue;
                 const uint32_t s = q % d, g = q / d;
-                add_out(A.out3, A.perm, kClasses3, sP[s] >> 2, sT3[motif_index3(sP[s] & 3u, g + 1, 0u)], cnt);
-                sCnt[q] = 0;
+                add_out(A.out3, A.perm, kClasses3, L.P[s] >> 2, L.t3[motif_index3(L.P[s] & 3u, g + 1, 0u)], cnt);
+                L.cnt[q] = 0;
             }
-            if (tid == 0) sTask = 0;
+            if (tid == 0) L.task = 0;
             __syncthreads();
         }
+        HUB_PHASE(2);
 
         // ---------------------------------------------------------------- depth-2 groups
-        // Each depth-2 entry (a, c) scans row(c) above r; it leads the group of c iff a
-        // is the first neighbour of c in N+(r).  The leader records A(c).
-        for (int t = wave_next(&sTask); t < (int)scan2; t = wave_next(&sTask)) {
+        // Each depth-2 entry (a, c) scans row(c); it leads the group of c iff a is the first
+        // (lowest-rank) neighbour of c in N+(r).  The leader records A(c).
+        for (int t = wave_next(&L.task); t < (int)scan2; t = wave_next(&L.task)) {
             if (!eflag[t]) continue;
-            const uint32_t i = slot_of(sPre, d, (uint32_t)t);
-            const uint32_t c = A.adj[sLo[i] + ((uint32_t)t - sPre[i])] >> 2;
-            const uint32_t clo = lower_bound_rank(A.adj, A.off[c], A.off[c + 1], r + 1);
-            const uint32_t chi = A.off[c + 1];
+            const uint32_t i = slot_of(L.pre, d, (uint32_t)t);
+            const uint32_t c = A.adj[L.lo[i] + ((uint32_t)t - L.pre[i])] >> 2;
+            const uint32_t clo = A.off[c], chi = A.off[c + 1];
             int first = -1;
             uint32_t p = 0;
             for (uint32_t base = clo; base < chi; base += 64) {
                 const uint32_t tt = base + lane;
-                const int sl = tt < chi ? find_slot(sP, d, A.adj[tt] >> 2) : -1;
+                const int sl = tt < chi ? find_slot_f(L, d, A.adj[tt] >> 2) : -1;
                 const unsigned long long mk = __ballot(sl >= 0);
                 if (first < 0 && mk) {
                     first = __shfl(sl, (int)__ffsll((long long)mk) - 1);
@@ -295,8 +383,8 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             if (first != (int)i) continue;
             unsigned aoff = 0, g = 0;
             if (lane == 0) {
-                aoff = atomicAdd(&sAlloc, p);
-                g = atomicAdd(&sGroups, 1u);
+                aoff = atomicAdd(&L.alloc, p);
+                g = atomicAdd(&L.groups, 1u);
             }
             aoff = __shfl(aoff, 0);
             g = __shfl(g, 0);
@@ -307,33 +395,35 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 int sl = -1;
                 if (tt < chi) {
                     e = A.adj[tt];
-                    sl = find_slot(sP, d, e >> 2);
+                    sl = find_slot_f(L, d, e >> 2);
                 }
                 const unsigned long long mk = __ballot(sl >= 0);
-                const uint32_t before = __popcll(mk & ((1ull << lane) - 1ull));
-                if (sl >= 0) alist[aoff + pos + before] = ((uint32_t)sl << 2) | swap_arc_bits(e & 3u);
+                if (sl >= 0) alist[aoff + pos + __popcll(mk & lt_mask)] = ((uint32_t)sl << 2) | swap_arc_bits(e & 3u);
                 pos += __popcll(mk);
             }
             if (lane == 0) {
                 grp[4 * g + 0] = c;
                 grp[4 * g + 1] = p;
                 grp[4 * g + 2] = aoff;
-                grp[4 * g + 3] = clo;
             }
         }
         __threadfence();
         __syncthreads();
-        if (tid == 0) sTask = 0;
+        if (tid == 0) L.task = 0;
         __syncthreads();
+        HUB_PHASE(3);
 
         // ---------------------------------------------------------------- k=4 (3,0,0): slot triples
+        // task (ch, j): lanes are a = 64 ch + lane < b = j; the step runs over c > b.
+        // a's and b's local lists are walked in slot order, so a step needs no memory load
+        // besides the LDS code of c.
         if (A.k4) {
             uint32_t total = 0;
             for (uint32_t ch = 0; ch < nch; ch++) total += (d > 64 * ch + 1) ? d - 1 - 64 * ch : 0;
-            for (int t = wave_next(&sTask); t < (int)total; t = wave_next(&sTask)) {
+            for (int t = wave_next(&L.task); t < (int)total; t = wave_next(&L.task)) {
                 uint32_t ch = 0, rem = (uint32_t)t;
                 while (true) {
-                    uint32_t cc = d - 1 - 64 * ch;
+                    const uint32_t cc = d - 1 - 64 * ch;
                     if (rem < cc) break;
                     rem -= cc;
                     ch++;
@@ -341,40 +431,104 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 const uint32_t j = 64 * ch + 1 + rem;    // b
                 const uint32_t i = 64 * ch + lane;       // a (lane)
                 const bool va = i < j;
-                const uint32_t ra = va ? (sP[i] & 3u) : 0u, rb = sP[j] & 3u;
-                const uint32_t ab = va ? swap_arc_bits(mget(M, d, j, i)) : 0u;
-                unsigned long long acc = 0;                  // lane a: fields by rc
-                unsigned long long bacc1 = 0, bacc2 = 0, bacc3 = 0;  // b and r: by ra, fields by rc
+                const uint32_t ra = va ? (L.P[i] & 3u) : 0u, rb = L.P[j] & 3u;
+                // lane walk over a's local neighbours with slot > j
+                uint32_t pa = 0, ea = 0, ab = 0, na = 0xFFFFu;
+                if (va) {
+                    const uint32_t b0 = L.pre[i];
+                    ea = b0 + L.lcnt[i];
+                    uint32_t lo = b0, hi = ea;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if ((uint32_t)(llist[mid] >> 2) <= j) lo = mid + 1; else hi = mid;
+                    }
+                    pa = lo;
+                    if (pa > b0 && (uint32_t)(llist[pa - 1] >> 2) == j) ab = llist[pa - 1] & 3u;
+                    na = pa < ea ? llist[pa] : 0xFFFFu;
+                }
+                // uniform walk over b's local neighbours with slot > j
+                uint32_t pb, eb, nb;
+                {
+                    const uint32_t b0 = L.pre[j];
+                    eb = b0 + L.lcnt[j];
+                    uint32_t lo = b0, hi = eb;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if ((uint32_t)(llist[mid] >> 2) <= j) lo = mid + 1; else hi = mid;
+                    }
+                    pb = lo;
+                    nb = pb < eb ? llist[pb] : 0xFFFFu;
+                }
+                const bool base = va && ab == 0;
+                const bool edge = va && ab != 0;
+                const uint32_t bk1 = __popcll(__ballot(base && ra == 1u));
+                const uint32_t bk2 = __popcll(__ballot(base && ra == 2u));
+                const uint32_t bk3 = __popcll(__ballot(base && ra == 3u));
+                unsigned long long acc = 0;     // lane a: fields by rc (pure sets, or edge sets)
+                unsigned long long bacc1 = 0, bacc2 = 0, bacc3 = 0;   // b and r, pure sets: by ra, fields by rc
                 for (uint32_t l = j + 1; l < d; l++) {
-                    const uint32_t rc = sP[l] & 3u;
-                    const uint32_t bc = mget(M, d, j, l);
-                    const uint32_t ac = va ? swap_arc_bits(mget(M, d, l, i)) : 0u;
-                    const bool pure = va && ((ab | ac | bc) == 0u);
+                    const uint32_t rc = L.P[l] & 3u;
+                    uint32_t ac = 0;
+                    if ((na >> 2) == l) {
+                        ac = na & 3u;
+                        ++pa;
+                        na = pa < ea ? llist[pa] : 0xFFFFu;
+                    }
+                    uint32_t bc = 0;
+                    if ((nb >> 2) == l) {
+                        bc = nb & 3u;
+                        ++pb;
+                        nb = pb < eb ? llist[pb] : 0xFFFFu;
+                    }
                     const uint32_t sh = 21u * (rc - 1u);
-                    if (pure) acc += 1ull << sh;
-                    const uint32_t n1 = __popcll(__ballot(pure && ra == 1u));
-                    const uint32_t n2 = __popcll(__ballot(pure && ra == 2u));
-                    const uint32_t n3 = __popcll(__ballot(pure && ra == 3u));
+                    uint32_t n1 = 0, n2 = 0, n3 = 0;
+                    bool pure = false;
+                    if (bc == 0) {
+                        const unsigned long long hit = __ballot(va && ac != 0);
+                        if (!hit) {
+                            pure = base;
+                            n1 = bk1; n2 = bk2; n3 = bk3;
+                        } else {
+                            pure = base && ac == 0;
+                            n1 = __popcll(__ballot(pure && ra == 1u));
+                            n2 = __popcll(__ballot(pure && ra == 2u));
+                            n3 = __popcll(__ballot(pure && ra == 3u));
+                        }
+                    }
+                    const bool edgeset = edge && ac == 0 && bc == 0;
+                    if (pure || edgeset) acc += 1ull << sh;
                     bacc1 += (unsigned long long)n1 << sh;
                     bacc2 += (unsigned long long)n2 << sh;
                     bacc3 += (unsigned long long)n3 << sh;
                     if (lane < 3) {
                         const uint32_t nk = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
-                        if (nk) atomicAdd(&sCnt[pair_sig(lane + 1u, rb) * d + l], nk);
+                        if (nk) atomicAdd(&L.cnt[pair_sig(lane + 1u, rb) * d + l], nk);
                     }
-                    if (va && !pure) {
-                        const uint32_t cls = sT4[motif_index4(ra, rb, rc, ab, ac, bc)];
-                        atomicAdd(&sRoot4[cls], 1ull);
-                        add_out(A.out4, A.perm, kClasses4, sP[i] >> 2, cls, 1);
-                        add_out(A.out4, A.perm, kClasses4, sP[j] >> 2, cls, 1);
-                        add_out(A.out4, A.perm, kClasses4, sP[l] >> 2, cls, 1);
+                    if (edgeset) {   // only c's credit is per set; a, b and r are summed in acc
+                        slow[2]++;
+                        add_out(A.out4, A.perm, kClasses4, L.P[l] >> 2, L.t4[motif_index4(ra, rb, rc, ab, 0u, 0u)], 1);
+                    } else if (va && !pure) {
+                        slow[2]++;
+                        const uint32_t cls = L.t4[motif_index4(ra, rb, rc, ab, ac, bc)];
+                        atomicAdd(&L.root4[cls], 1ull);
+                        add_out(A.out4, A.perm, kClasses4, L.P[i] >> 2, cls, 1);
+                        add_out(A.out4, A.perm, kClasses4, L.P[j] >> 2, cls, 1);
+                        add_out(A.out4, A.perm, kClasses4, L.P[l] >> 2, cls, 1);
                     }
                     shape[2] += va ? 1 : 0;
                 }
                 if (va) {
                     for (uint32_t rc = 1; rc <= 3; rc++) {
                         const uint32_t cnt = (uint32_t)(acc >> (21u * (rc - 1u))) & F21;
-                        if (cnt) atomicAdd(&sCnt[pair_sig(rb, rc) * d + i], cnt);
+                        if (!cnt) continue;
+                        if (ab == 0) {
+                            atomicAdd(&L.cnt[pair_sig(rb, rc) * d + i], cnt);
+                        } else {
+                            const uint32_t cls = L.t4[motif_index4(ra, rb, rc, ab, 0u, 0u)];
+                            add_out(A.out4, A.perm, kClasses4, L.P[i] >> 2, cls, cnt);
+                            add_out(A.out4, A.perm, kClasses4, L.P[j] >> 2, cls, cnt);
+                            atomicAdd(&L.root4[cls], (unsigned long long)cnt);
+                        }
                     }
                 }
                 if (lane < 9) {
@@ -382,89 +536,87 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     const unsigned long long bw = ka == 1 ? bacc1 : (ka == 2 ? bacc2 : bacc3);
                     const uint32_t cnt = (uint32_t)(bw >> (21u * (rc - 1u))) & F21;
                     if (cnt) {
-                        atomicAdd(&sCnt[pair_sig(ka, rc) * d + j], cnt);
-                        atomicAdd(&sRoot4[sT4[motif_index4(ka, rb, rc, 0u, 0u, 0u)]], (unsigned long long)cnt);
+                        atomicAdd(&L.cnt[pair_sig(ka, rc) * d + j], cnt);
+                        atomicAdd(&L.root4[L.t4[motif_index4(ka, rb, rc, 0u, 0u, 0u)]], (unsigned long long)cnt);
                     }
                 }
             }
             __syncthreads();
             for (uint32_t q = tid; q < 6 * d; q += HT) {
-                const uint32_t cnt = sCnt[q];
+                const uint32_t cnt = L.cnt[q];
                 if (!cnt) continue;
                 const uint32_t s = q % d, g = q / d;
                 uint32_t x, y;
                 sig_pair(g, x, y);
-                add_out(A.out4, A.perm, kClasses4, sP[s] >> 2, sT4[motif_index4(sP[s] & 3u, x, y, 0u, 0u, 0u)], cnt);
-                sCnt[q] = 0;
+                add_out(A.out4, A.perm, kClasses4, L.P[s] >> 2, L.t4[motif_index4(L.P[s] & 3u, x, y, 0u, 0u, 0u)], cnt);
+                L.cnt[q] = 0;
             }
-            if (tid == 0) sTask = 0;
+            if (tid == 0) L.task = 0;
             __syncthreads();
         }
+        HUB_PHASE(4);
 
         // ---------------------------------------------------------------- groups: (2,1,0), (1,1,1), k=3 (1,2)
-        const uint32_t ngroups = sGroups;
-        uint32_t* cw = sCw[wid];
-        for (uint32_t q = lane; q < 27 + 27 + kClasses3; q += 64) cw[q] = 0;
-        for (int t = wave_next(&sTask); t < (int)ngroups; t = wave_next(&sTask)) {
+        const uint32_t ngroups = L.groups;
+        uint32_t* cw = L.cw[wid];
+        uint32_t* inA = L.inA[wid];
+        uint32_t* xacc = L.xacc[wid];
+        for (int t = wave_next(&L.task); t < (int)ngroups; t = wave_next(&L.task)) {
             const uint32_t c = grp[4 * t + 0];
             const uint32_t p = grp[4 * t + 1];
             const uint32_t* Ac = alist + grp[4 * t + 2];
-            const uint32_t clo = grp[4 * t + 3];
             const uint32_t chi = A.off[c + 1];
+            for (uint32_t u = lane; u < p; u += 64) {
+                const uint32_t x = Ac[u] >> 2;
+                atomicOr(&inA[x >> 5], 1u << (x & 31));
+            }
             if (A.k3) {
                 for (uint32_t u = lane; u < p; u += 64) {
-                    const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = sP[x] & 3u;
-                    const uint32_t cls = sT3[motif_index3(rx, 0u, xc)];
-                    atomicAdd(&sRoot3[cls], 1ull);
+                    const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
+                    const uint32_t cls = L.t3[motif_index3(rx, 0u, xc)];
+                    atomicAdd(&L.root3[cls], 1ull);
                     atomicAdd(&s3x[(xc - 1) * PMAX + x], 1u);
                     atomicAdd(&cw[54 + cls], 1u);
                     shape[1]++;
                 }
             }
             if (A.k4) {
-                // (2,1,0) with y outside A(c): lanes are y, the parent x runs over A(c)
-                for (uint32_t ch = 0; ch < nch; ch++) {
-                    const uint32_t y = 64 * ch + lane;
-                    const bool yv = y < d;
-                    const uint32_t ry = yv ? (sP[y] & 3u) : 0u;
-                    bool inA = false;
-                    if (yv) {
-                        uint32_t lo = 0, hi = p;
-                        while (lo < hi) {
-                            uint32_t mid = (lo + hi) >> 1;
-                            if ((Ac[mid] >> 2) < y) lo = mid + 1; else hi = mid;
-                        }
-                        inA = lo < p && (Ac[lo] >> 2) == y;
-                    }
-                    const bool lv = yv && !inA;
-                    unsigned long long acc1 = 0, acc2 = 0, acc3 = 0;   // by rx, fields by xc
-                    for (uint32_t u = 0; u < p; u++) {
-                        const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = sP[x] & 3u;
-                        const uint32_t xy = lv ? mget(M, d, x, y) : 0u;
-                        const bool pure = lv && xy == 0u;
-                        const unsigned long long inc = pure ? (1ull << (21u * (xc - 1u))) : 0ull;
-                        if (rx == 1) acc1 += inc; else if (rx == 2) acc2 += inc; else acc3 += inc;
-                        for (uint32_t k = 1; k <= 3; k++) {
-                            const uint32_t nk = __popcll(__ballot(pure && ry == k));
-                            if (lane == k - 1 && nk) {
-                                atomicAdd(&spar[((xc - 1) * 3 + (k - 1)) * PMAX + x], nk);
-                                cw[(rx - 1) * 9 + (xc - 1) * 3 + (k - 1)] += nk;
+                // (2,1,0), y outside A(c): the parent x runs outside, the chunks of y inside
+                for (uint32_t ub = 0; ub < p; ub += 64) {
+                    const uint32_t areg = ub + lane < p ? Ac[ub + lane] : 0u;
+                    const uint32_t ucnt = min(64u, p - ub);
+                    for (uint32_t uu = 0; uu < ucnt; uu++) {
+                        const uint32_t ex = __shfl(areg, (int)uu);
+                        const uint32_t x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
+                        const bool xloc = L.lcnt[x] != 0;
+                        uint32_t xn1 = 0, xn2 = 0, xn3 = 0;
+                        for (uint32_t ch = 0; ch < nch; ch++) {
+                            const uint32_t y = 64 * ch + lane;
+                            const bool yv = y < d;
+                            const uint32_t ry = yv ? (L.P[y] & 3u) : 0u;
+                            const bool lv = yv && !((inA[y >> 5] >> (y & 31)) & 1u);
+                            const uint32_t xy = (xloc && lv) ? mget(M, d, x, y) : 0u;
+                            const bool pure = lv && xy == 0u;
+                            if (pure) atomicAdd(&L.cnt[((rx - 1) * 3 + (xc - 1)) * d + y], 1u);
+                            xn1 += __popcll(__ballot(pure && ry == 1u));
+                            xn2 += __popcll(__ballot(pure && ry == 2u));
+                            xn3 += __popcll(__ballot(pure && ry == 3u));
+                            if (lv && !pure) {
+                                slow[3]++;
+                                const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, 0u)];
+                                atomicAdd(&L.root4[cls], 1ull);
+                                add_out(A.out4, A.perm, kClasses4, L.P[x] >> 2, cls, 1);
+                                add_out(A.out4, A.perm, kClasses4, L.P[y] >> 2, cls, 1);
+                                add_out(A.out4, A.perm, kClasses4, c, cls, 1);
                             }
+                            shape[3] += lv ? 1 : 0;
                         }
-                        if (lv && !pure) {
-                            const uint32_t cls = sT4[motif_index4(rx, ry, 0u, xy, xc, 0u)];
-                            atomicAdd(&sRoot4[cls], 1ull);
-                            add_out(A.out4, A.perm, kClasses4, sP[x] >> 2, cls, 1);
-                            add_out(A.out4, A.perm, kClasses4, sP[y] >> 2, cls, 1);
-                            add_out(A.out4, A.perm, kClasses4, c, cls, 1);
-                        }
-                        shape[3] += lv ? 1 : 0;
-                    }
-                    if (lv) {
-                        for (uint32_t q = 0; q < 9; q++) {
-                            const unsigned long long w = q < 3 ? acc1 : (q < 6 ? acc2 : acc3);
-                            const uint32_t cnt = (uint32_t)(w >> (21u * (q % 3))) & F21;
-                            if (cnt) atomicAdd(&sCnt[q * d + y], cnt);   // q = (rx-1)*3 + (xc-1)
+                        if (lane < 3) {
+                            const uint32_t nk = lane == 0 ? xn1 : (lane == 1 ? xn2 : xn3);
+                            if (nk) {
+                                atomicAdd(&spar[((xc - 1) * 3 + lane) * PMAX + x], nk);
+                                cw[(rx - 1) * 9 + (xc - 1) * 3 + lane] += nk;
+                            }
                         }
                     }
                 }
@@ -473,47 +625,65 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     const uint32_t vpos = v0 + lane;
                     const bool vv = vpos < p;
                     const uint32_t ey = vv ? Ac[vpos] : 0u;
-                    const uint32_t y = ey >> 2, yc = ey & 3u, ry = vv ? (sP[y] & 3u) : 0u;
+                    const uint32_t y = ey >> 2, yc = ey & 3u, ry = vv ? (L.P[y] & 3u) : 0u;
                     const uint32_t umax = min(p, v0 + 64);
                     for (uint32_t u = 0; u + 1 < umax; u++) {
                         const bool valid = vv && u < vpos;
                         if (!__ballot(valid)) continue;
-                        const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = sP[x] & 3u;
+                        const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
                         if (valid) {
+                            slow[3]++;
                             const uint32_t xy = mget(M, d, x, y);
-                            const uint32_t cls = sT4[motif_index4(rx, ry, 0u, xy, xc, yc)];
-                            atomicAdd(&sRoot4[cls], 1ull);
-                            add_out(A.out4, A.perm, kClasses4, sP[x] >> 2, cls, 1);
-                            add_out(A.out4, A.perm, kClasses4, sP[y] >> 2, cls, 1);
+                            const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, yc)];
+                            atomicAdd(&L.root4[cls], 1ull);
+                            add_out(A.out4, A.perm, kClasses4, L.P[x] >> 2, cls, 1);
+                            add_out(A.out4, A.perm, kClasses4, L.P[y] >> 2, cls, 1);
                             add_out(A.out4, A.perm, kClasses4, c, cls, 1);
                             shape[3]++;
                         }
                     }
                 }
                 // (1,1,1): paths r - x - c - e, e above r, not in N(r), not adjacent to x
-                for (uint32_t base = clo; base < chi; base += 64) {
+                const bool small_p = p <= 64;
+                if (small_p)
+                    for (uint32_t q = lane; q < 3 * 64; q += 64) xacc[q] = 0;
+                for (uint32_t base = A.off[c]; base < chi; base += 64) {
                     const uint32_t tt = base + lane;
                     uint32_t ee = 0;
                     bool ev = tt < chi;
                     if (ev) {
                         ee = A.adj[tt];
-                        ev = find_slot(sP, d, ee >> 2) < 0;
+                        ev = (ee >> 2) > r && find_slot_f(L, d, ee >> 2) < 0;
                     }
+                    if (!__ballot(ev)) continue;
                     const uint32_t e = ee >> 2, ce = ee & 3u;
+                    RowCache rcache;
+                    row_cache_load(rcache, A.off, A.adj, e, ev);
                     unsigned long long acc1 = 0, acc2 = 0, acc3 = 0;
-                    for (uint32_t u = 0; u < p; u++) {
-                        const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = sP[x] & 3u;
-                        const bool valid = ev && arc_bits(A.off, A.adj, sP[x] >> 2, e) == 0u;
-                        const unsigned long long inc = valid ? (1ull << (21u * (xc - 1u))) : 0ull;
-                        if (rx == 1) acc1 += inc; else if (rx == 2) acc2 += inc; else acc3 += inc;
-                        for (uint32_t k = 1; k <= 3; k++) {
-                            const uint32_t nk = __popcll(__ballot(valid && ce == k));
-                            if (lane == k - 1 && nk) {
-                                atomicAdd(&s111[((xc - 1) * 3 + (k - 1)) * PMAX + x], nk);
-                                cw[27 + (rx - 1) * 9 + (xc - 1) * 3 + (k - 1)] += nk;
+                    for (uint32_t ub = 0; ub < p; ub += 64) {
+                        const uint32_t areg = ub + lane < p ? Ac[ub + lane] : 0u;
+                        const uint32_t ucnt = min(64u, p - ub);
+                        for (uint32_t uu = 0; uu < ucnt; uu++) {
+                            const uint32_t ex = __shfl(areg, (int)uu);
+                            const uint32_t x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
+                            // x has no depth-2 neighbour besides c: e cannot touch it
+                            const bool xonly = (L.pre[x + 1] - L.pre[x]) - L.lcnt[x] <= 1u;
+                            const bool valid = ev && (xonly || row_cache_bits_from(rcache, A.adj, L.P[x] >> 2) == 0u);
+                            const unsigned long long inc = valid ? (1ull << (21u * (xc - 1u))) : 0ull;
+                            if (rx == 1) acc1 += inc; else if (rx == 2) acc2 += inc; else acc3 += inc;
+                            const uint32_t n1 = __popcll(__ballot(valid && ce == 1u));
+                            const uint32_t n2 = __popcll(__ballot(valid && ce == 2u));
+                            const uint32_t n3 = __popcll(__ballot(valid && ce == 3u));
+                            if (lane < 3) {
+                                const uint32_t nk = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
+                                if (nk) {
+                                    if (small_p) xacc[uu * 3 + lane] += nk;
+                                    else atomicAdd(&s111[((xc - 1) * 3 + lane) * PMAX + x], nk);
+                                    cw[27 + (rx - 1) * 9 + (xc - 1) * 3 + lane] += nk;
+                                }
                             }
+                            shape[5] += valid ? 1 : 0;
                         }
-                        shape[5] += valid ? 1 : 0;
                     }
                     if (ev) {
                         for (uint32_t q = 0; q < 9; q++) {
@@ -521,8 +691,16 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                             const uint32_t cnt = (uint32_t)(w >> (21u * (q % 3))) & F21;
                             if (cnt)
                                 add_out(A.out4, A.perm, kClasses4, e,
-                                        sT4[motif_index4(q / 3 + 1, 0u, 0u, q % 3 + 1, 0u, ce)], cnt);
+                                        L.t4[motif_index4(q / 3 + 1, 0u, 0u, q % 3 + 1, 0u, ce)], cnt);
                         }
+                    }
+                }
+                if (small_p) {
+                    for (uint32_t q = lane; q < 3 * p; q += 64) {
+                        const uint32_t cnt = xacc[q];
+                        if (!cnt) continue;
+                        const uint32_t ex = Ac[q / 3], x = ex >> 2, xc = ex & 3u;
+                        atomicAdd(&s111[((xc - 1) * 3 + q % 3) * PMAX + x], cnt);
                     }
                 }
             }
@@ -535,76 +713,95 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     const uint32_t qq = q % 27, rx = qq / 9 + 1, xc = (qq / 3) % 3 + 1, z = qq % 3 + 1;
                     const uint32_t code = q < 27 ? motif_index4(rx, z, 0u, 0u, xc, 0u)      // (2,1,0): z = ry
                                                  : motif_index4(rx, 0u, 0u, xc, 0u, z);    // (1,1,1): z = ce
-                    const uint32_t cls = sT4[code];
+                    const uint32_t cls = L.t4[code];
                     add_out(A.out4, A.perm, kClasses4, c, cls, cnt);
-                    atomicAdd(&sRoot4[cls], (unsigned long long)cnt);
+                    atomicAdd(&L.root4[cls], (unsigned long long)cnt);
                 } else {
                     add_out(A.out3, A.perm, kClasses3, c, q - 54, cnt);
                 }
+            }
+            for (uint32_t u = lane; u < p; u += 64) {
+                const uint32_t x = Ac[u] >> 2;
+                atomicAnd(&inA[x >> 5], ~(1u << (x & 31)));
             }
         }
         __threadfence();
         __syncthreads();
         if (A.k4) {
             for (uint32_t q = tid; q < 9 * d; q += HT) {
-                const uint32_t cnt = sCnt[q];
+                const uint32_t cnt = L.cnt[q];
                 if (!cnt) continue;
                 const uint32_t s = q % d, g = q / d, rx = g / 3 + 1, xc = g % 3 + 1;
-                add_out(A.out4, A.perm, kClasses4, sP[s] >> 2,
-                        sT4[motif_index4(rx, sP[s] & 3u, 0u, 0u, xc, 0u)], cnt);
+                add_out(A.out4, A.perm, kClasses4, L.P[s] >> 2,
+                        L.t4[motif_index4(rx, L.P[s] & 3u, 0u, 0u, xc, 0u)], cnt);
             }
         }
-        if (tid == 0) sTask = 0;
+        if (tid == 0) L.task = 0;
         __syncthreads();
+        HUB_PHASE(5);
 
         // ---------------------------------------------------------------- k=4 (1,2,0): two depth-2 children of one slot
         if (A.k4) {
-            for (int t = wave_next(&sTask); t < (int)d; t = wave_next(&sTask)) {
+            for (int t = wave_next(&L.task); t < (int)d; t = wave_next(&L.task)) {
                 const uint32_t a = (uint32_t)t;
-                const uint32_t q0 = sPre[a], q1 = sPre[a + 1];
-                if (q1 - q0 < 2) continue;
+                const uint32_t q0 = L.pre[a], q1 = L.pre[a + 1];
+                if (q1 - q0 - L.lcnt[a] < 2) continue;
                 uint32_t m = 0;
                 for (uint32_t qb = q0; qb < q1; qb += 64) {
                     const uint32_t q = qb + lane;
                     const bool f = q < q1 && eflag[q];
                     const unsigned long long mk = __ballot(f);
-                    if (f) wlist[m + __popcll(mk & ((1ull << lane) - 1ull))] = A.adj[sLo[a] + (q - q0)];
+                    if (f) wlist[m + __popcll(mk & lt_mask)] = A.adj[L.lo[a] + (q - q0)];
                     m += __popcll(mk);
                 }
-                if (m < 2) continue;
                 for (uint32_t q = lane; q < 3 * m; q += 64) c120[q] = 0;
                 __threadfence_block();
-                const uint32_t ra = sP[a] & 3u, va = sP[a] >> 2;
+                const uint32_t ra = L.P[a] & 3u, va = L.P[a] >> 2;
                 unsigned long long a6lo = 0, a6mid = 0, a6hi = 0;   // 6 signatures, 32-bit fields
                 for (uint32_t u0 = 1; u0 < m; u0 += 64) {
                     const uint32_t u = u0 + lane;
                     const bool uv = u < m;
                     const uint32_t e2 = uv ? wlist[u] : 0u, c2 = e2 >> 2, ac2 = e2 & 3u;
+                    RowCache rcache;
+                    row_cache_load(rcache, A.off, A.adj, c2, uv);
                     unsigned long long acc = 0;
                     const uint32_t tmax = min(m, u0 + 64) - 1;
-                    for (uint32_t tt = 0; tt < tmax; tt++) {
-                        const uint32_t e1 = wlist[tt], c1 = e1 >> 2, ac = e1 & 3u;
-                        const bool valid = uv && tt < u;
-                        const uint32_t cc = valid ? arc_bits(A.off, A.adj, c1, c2) : 0u;
-                        const bool pure = valid && cc == 0u;
-                        if (pure) acc += 1ull << (21u * (ac - 1u));
-                        for (uint32_t k = 1; k <= 3; k++) {
-                            const uint32_t nk = __popcll(__ballot(pure && ac2 == k));
-                            if (nk) {
-                                if (lane == k - 1) atomicAdd(&c120[tt * 3 + (k - 1)], nk);
-                                const uint32_t sg = pair_sig(ac, k);
-                                const unsigned long long addv = (unsigned long long)nk << (32u * (sg & 1u));
-                                if (sg < 2) a6lo += addv; else if (sg < 4) a6mid += addv; else a6hi += addv;
+                    for (uint32_t tb = 0; tb < tmax; tb += 64) {
+                        const uint32_t wreg = tb + lane < tmax ? wlist[tb + lane] : 0u;
+                        const uint32_t tcnt = min(64u, tmax - tb);
+                        for (uint32_t k2 = 0; k2 < tcnt; k2++) {
+                            const uint32_t tt = tb + k2;
+                            const uint32_t e1 = __shfl(wreg, (int)k2), c1 = e1 >> 2, ac = e1 & 3u;
+                            const bool valid = uv && tt < u;
+                            const uint32_t cc = valid ? row_cache_bits_from(rcache, A.adj, c1) : 0u;   // seen from c1
+                            const bool pure = valid && cc == 0u;
+                            if (pure) acc += 1ull << (21u * (ac - 1u));
+                            const uint32_t n1 = __popcll(__ballot(pure && ac2 == 1u));
+                            const uint32_t n2 = __popcll(__ballot(pure && ac2 == 2u));
+                            const uint32_t n3 = __popcll(__ballot(pure && ac2 == 3u));
+                            if (lane < 3) {
+                                const uint32_t nk = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
+                                if (nk) atomicAdd(&c120[tt * 3 + lane], nk);
                             }
+                            {
+                                const uint32_t s1 = pair_sig(ac, 1u), s2 = pair_sig(ac, 2u), s3 = pair_sig(ac, 3u);
+                                const unsigned long long v1 = (unsigned long long)n1 << (32u * (s1 & 1u));
+                                const unsigned long long v2 = (unsigned long long)n2 << (32u * (s2 & 1u));
+                                const unsigned long long v3 = (unsigned long long)n3 << (32u * (s3 & 1u));
+                                if (s1 < 2) a6lo += v1; else if (s1 < 4) a6mid += v1; else a6hi += v1;
+                                if (s2 < 2) a6lo += v2; else if (s2 < 4) a6mid += v2; else a6hi += v2;
+                                if (s3 < 2) a6lo += v3; else if (s3 < 4) a6mid += v3; else a6hi += v3;
+                            }
+                            if (valid && !pure) {
+                                slow[4]++;
+                                const uint32_t cls = L.t4[motif_index4(ra, 0u, 0u, ac, ac2, cc)];
+                                atomicAdd(&L.root4[cls], 1ull);
+                                add_out(A.out4, A.perm, kClasses4, va, cls, 1);
+                                add_out(A.out4, A.perm, kClasses4, c1, cls, 1);
+                                add_out(A.out4, A.perm, kClasses4, c2, cls, 1);
+                            }
+                            shape[4] += valid ? 1 : 0;
                         }
-                        if (valid && !pure) {
-                            const uint32_t cls = sT4[motif_index4(ra, 0u, 0u, ac, ac2, cc)];
-                            atomicAdd(&sRoot4[cls], 1ull);
-                            add_out(A.out4, A.perm, kClasses4, va, cls, 1);
-                            add_out(A.out4, A.perm, kClasses4, c1, cls, 1);
-                            add_out(A.out4, A.perm, kClasses4, c2, cls, 1);
-                        }
-                        shape[4] += valid ? 1 : 0;
                     }
                     if (uv) {
                         for (uint32_t g = 0; g < 3; g++) {
@@ -620,7 +817,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     const uint32_t u = q / 3, g = q % 3;
                     const uint32_t eu = wlist[u];
                     add_out(A.out4, A.perm, kClasses4, eu >> 2,
-                            sT4[motif_index4(ra, 0u, 0u, eu & 3u, g + 1, 0u)], cnt);
+                            L.t4[motif_index4(ra, 0u, 0u, eu & 3u, g + 1, 0u)], cnt);
                 }
                 if (lane < 6) {
                     const unsigned long long w = lane < 2 ? a6lo : (lane < 4 ? a6mid : a6hi);
@@ -628,49 +825,62 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     if (cnt) {
                         uint32_t x, y;
                         sig_pair(lane, x, y);
-                        const uint32_t cls = sT4[motif_index4(ra, 0u, 0u, x, y, 0u)];
+                        const uint32_t cls = L.t4[motif_index4(ra, 0u, 0u, x, y, 0u)];
                         add_out(A.out4, A.perm, kClasses4, va, cls, cnt);
-                        atomicAdd(&sRoot4[cls], (unsigned long long)cnt);
+                        atomicAdd(&L.root4[cls], (unsigned long long)cnt);
                     }
                 }
             }
         }
         __threadfence();
         __syncthreads();
+        HUB_PHASE(6);
 
         // ---------------------------------------------------------------- per-root flush
         const uint32_t row = (uint32_t)A.perm[r];
         if (A.k4)
             for (uint32_t q = tid; q < kClasses4; q += HT)
-                if (sRoot4[q]) atomicAdd(&A.out4[(size_t)row * kClasses4 + q], sRoot4[q]);
+                if (L.root4[q]) atomicAdd(&A.out4[(size_t)row * kClasses4 + q], L.root4[q]);
         if (A.k3)
             for (uint32_t q = tid; q < kClasses3; q += HT)
-                if (sRoot3[q]) atomicAdd(&A.out3[(size_t)row * kClasses3 + q], sRoot3[q]);
+                if (L.root3[q]) atomicAdd(&A.out3[(size_t)row * kClasses3 + q], L.root3[q]);
         for (uint32_t q = tid; q < 9 * d; q += HT) {
-            const uint32_t s = q % d, g = q / d, rs = sP[s] & 3u, vs = sP[s] >> 2;
+            const uint32_t s = q % d, g = q / d, rs = L.P[s] & 3u, vs = L.P[s] >> 2;
             const uint32_t a = spar[g * PMAX + s], b = s111[g * PMAX + s];
             if (a) {   // (2,1,0) parent: g = (xc-1)*3 + (ry-1)
-                add_out(A.out4, A.perm, kClasses4, vs, sT4[motif_index4(rs, g % 3 + 1, 0u, 0u, g / 3 + 1, 0u)], a);
+                add_out(A.out4, A.perm, kClasses4, vs, L.t4[motif_index4(rs, g % 3 + 1, 0u, 0u, g / 3 + 1, 0u)], a);
                 spar[g * PMAX + s] = 0;
             }
             if (b) {   // (1,1,1) depth-1: g = (xc-1)*3 + (ce-1)
-                add_out(A.out4, A.perm, kClasses4, vs, sT4[motif_index4(rs, 0u, 0u, g / 3 + 1, 0u, g % 3 + 1)], b);
+                add_out(A.out4, A.perm, kClasses4, vs, L.t4[motif_index4(rs, 0u, 0u, g / 3 + 1, 0u, g % 3 + 1)], b);
                 s111[g * PMAX + s] = 0;
             }
             if (g < 3) {
                 const uint32_t x3 = s3x[g * PMAX + s];
                 if (x3) {
-                    add_out(A.out3, A.perm, kClasses3, vs, sT3[motif_index3(rs, 0u, g + 1)], x3);
+                    add_out(A.out3, A.perm, kClasses3, vs, L.t3[motif_index3(rs, 0u, g + 1)], x3);
                     s3x[g * PMAX + s] = 0;
                 }
             }
         }
+        for (int k = 0; k < kShapes; k++) {
+            unsigned long long v = shape[k], w = slow[k];
+            for (int o = 32; o > 0; o >>= 1) {
+                v += __shfl_down(v, o);
+                w += __shfl_down(w, o);
+            }
+            if (lane == 0 && v) atomicAdd(&L.stat[k], v);
+            if (lane == 0 && w) atomicAdd(&L.stat[16 + k], w);
+            shape[k] = 0;
+            slow[k] = 0;
+        }
+        __syncthreads();
+        HUB_PHASE(7);
     }
-    for (int s = 0; s < kShapes; s++) {
-        unsigned long long v = shape[s];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-        if (lane == 0 && v) atomicAdd(&A.stats[s], v);
-    }
+#undef HUB_PHASE
+    __syncthreads();
+    for (uint32_t k = tid; k < kStatSlots; k += HT)
+        if (L.stat[k]) atomicAdd(&A.stats[k], L.stat[k]);
 }
 
 // ----------------------------------------------------------------------------- binning
@@ -829,6 +1039,7 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         const size_t o_wlist = o; o += NW * wl;
         const size_t o_c120 = o; o += 3 * NW * wl;
         const size_t o_eflag = o; o += (s2 + 3) / 4;
+        const size_t o_llist = o; o += (s2 + 1) / 2;
         o = (o + 63) & ~(size_t)63;
         g->hub_scratch_bytes = o * sizeof(uint32_t) * (size_t)wgs;
         VDMC_HIP(hipMalloc(&g->hub_scratch, g->hub_scratch_bytes));
@@ -842,6 +1053,7 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         g->hub_layout[7] = o_c120;
         g->hub_layout[8] = o_eflag;
         g->hub_layout[9] = wl;
+        g->hub_layout[10] = o_llist;
     }
     g->bins_hub_min = hub_min;
 }
@@ -875,6 +1087,7 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.o_c120 = g->hub_layout[7];
     a.o_eflag = g->hub_layout[8];
     a.wl_cap = (uint32_t)g->hub_layout[9];
+    a.o_llist = g->hub_layout[10];
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 4);
     const int wgs = hub_workgroups();
     hipLaunchKernelGGL(k_hub, dim3(wgs), dim3(HT), 0, st, a);

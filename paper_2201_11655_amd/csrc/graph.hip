@@ -208,8 +208,8 @@ static void build_graph(int64_t n, int64_t m, const int32_t* src, const int32_t*
     VDMC_HIP(hipMalloc(&g->off, (n + 1) * sizeof(uint32_t)));
     VDMC_HIP(hipMalloc(&g->split, (n > 0 ? n : 1) * sizeof(uint32_t)));
     VDMC_HIP(hipMalloc(&g->perm, (n > 0 ? n : 1) * sizeof(int32_t)));
-    VDMC_HIP(hipMalloc(&g->stats, kShapes * sizeof(unsigned long long)));
-    VDMC_HIP(hipMemsetAsync(g->stats, 0, kShapes * sizeof(unsigned long long), st));
+    VDMC_HIP(hipMalloc(&g->stats, kStatSlots * sizeof(unsigned long long)));
+    VDMC_HIP(hipMemsetAsync(g->stats, 0, kStatSlots * sizeof(unsigned long long), st));
 
     int* d_bad = t.alloc<int>(1);
     unsigned long long* d_arcs = t.alloc<unsigned long long>(1);
@@ -409,6 +409,7 @@ vdmc_status vdmc_free_graph(vdmc_graph g) {
         int cur = 0;
         VDMC_HIP(hipGetDevice(&cur));
         VDMC_HIP(hipSetDevice(g->device));
+        vdmc::invalidate_batch_plans(g);
         vdmc::free_graph_arrays(g);
         delete g;
         VDMC_HIP(hipSetDevice(cur));

@@ -68,6 +68,7 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 constexpr int kClasses3 = 13;
 constexpr int kClasses4 = 199;
 constexpr int kShapes = 6;   // (1,1) (1,2) | (3,0,0) (2,1,0) (1,2,0) (1,1,1)
+constexpr int kStatSlots = 32;   // shapes, then profile counters (cycles per phase, direct-path sets)
 
 inline int num_classes(int k) { return k == 3 ? kClasses3 : (k == 4 ? kClasses4 : -1); }
 
@@ -117,10 +118,43 @@ struct vdmc_graph_s {
     void* hub_scratch = nullptr;
     size_t hub_scratch_bytes = 0;
     unsigned* hub_queue = nullptr;
-    size_t hub_layout[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    size_t hub_layout[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace vdmc {
+// one graph as seen by the per-set kernels
+struct GraphView {
+    const uint32_t* off;
+    const uint32_t* adj;
+    const uint32_t* split;
+    const int32_t* perm;
+    unsigned long long* out3;
+    unsigned long long* out4;
+    unsigned long long* stats;
+};
+// batched launch over many graphs (count.hip / batch.hip)
+struct BatchArgs {
+    const GraphView* graphs;        // device array, one per graph
+    const uint64_t* nvert;          // device array: n of every graph
+    const uint2* table;             // device array of (graph, root) pairs
+    unsigned long long nentries;
+    unsigned long long* cursor;     // device work cursor, zeroed inside the launch
+    unsigned long long tile;        // roots taken per cursor step
+    const uint8_t* t3;
+    const uint8_t* t4;
+};
+constexpr int kBatchVariants = 3;   // 64, 128, 256 threads per root
+struct TuneChoice {
+    int variant = 0;      // threads per root: 64, 128, 256
+    int wgs_per_cu = 8;   // persistent workgroups per compute unit
+    unsigned tile = 4;    // roots per cursor step
+};
+// batched count of many graphs (one k), optionally replayed from a captured HIP graph
+void count_batch_impl(const vdmc_graph_s* const* gs, int32_t num, int32_t k, uint64_t* const* outs,
+                      hipStream_t stream, bool use_graph, const TuneChoice* force);
+void launch_batch(const BatchArgs& b, int variant, int k3, int k4, int num_graphs, int wgs_per_cu,
+                  hipStream_t stream);
+void invalidate_batch_plans(vdmc_graph_s* g);
 // launches (count.hip)
 void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
                   hipStream_t stream);

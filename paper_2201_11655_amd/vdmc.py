@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvdmc.so")
 SYMBOLS = [
     "vdmc_last_error", "vdmc_num_classes", "vdmc_class_codes", "vdmc_class_table",
     "vdmc_build_graph", "vdmc_graph_info", "vdmc_graph_export", "vdmc_free_graph",
-    "vdmc_count", "vdmc_count34", "vdmc_shape_counts", "vdmc_count_batch", "vdmc_tune",
+    "vdmc_count", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters", "vdmc_count_batch", "vdmc_tune",
     "vdmc_serve_create", "vdmc_serve_submit", "vdmc_serve_poll", "vdmc_serve_wait",
     "vdmc_serve_stats", "vdmc_serve_destroy",
 ]
@@ -62,6 +62,7 @@ def load():
         "vdmc_count": ([p, i32, p, p], i32),
         "vdmc_count34": ([p, p, p, p], i32),
         "vdmc_shape_counts": ([p, p], i32),
+        "vdmc_profile_counters": ([p, p, i32], i32),
         "vdmc_count_batch": ([p, i32, i32, p, p], i32),
         "vdmc_tune": ([p, i32, i32, ctypes.c_char_p], i32),
         "vdmc_serve_create": ([p, p], i32),
@@ -213,9 +214,18 @@ def shape_counts(g: Graph) -> dict:
     return {s: int(v) for s, v in zip(SHAPES, out)}
 
 
+def profile_counters(g: Graph) -> np.ndarray:
+    """Diagnostic counters of the last count (see vdmc_profile_counters in vdmc.h)."""
+    out = np.zeros(32, np.uint64)
+    _check(load().vdmc_profile_counters(g.handle, _np_ptr(out), 32))
+    return out
+
+
 def count_batch(graphs, k: int, outs=None, stream=None):
     """One batched launch over many graphs; returns the list of output tensors."""
     lib = load()
+    if k not in (3, 4):
+        _check(lib.vdmc_count_batch(None, len(graphs), int(k), None, _stream_handle(stream)))
     if outs is None:
         outs = [_out_tensor(g.n, k, None) for g in graphs]
     hs = (ctypes.c_void_p * max(1, len(graphs)))(*[g.handle.value for g in graphs])

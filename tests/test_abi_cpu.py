@@ -50,3 +50,20 @@ def test_build_graph_rejects_bad_sizes_before_touching_the_device():
     assert lib.vdmc_build_graph(1 << 30, 0, None, None, 0, None, ctypes.byref(h)) == 1
     assert lib.vdmc_build_graph(5, 3, None, None, 0, None, ctypes.byref(h)) == 1
     assert lib.vdmc_build_graph(5, 0, None, None, 0, None, None) == 1
+
+
+def test_serve_config_validation_without_device():
+    """Bad server configurations are rejected before any device call."""
+    from paper_2201_11655_amd import vdmc
+    lib = vdmc.load()
+    h = ctypes.c_void_p()
+    assert lib.vdmc_serve_create(None, ctypes.byref(h)) == 1
+    cfg = vdmc.ServeConfig(0, 4)
+    assert lib.vdmc_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
+    cfg = vdmc.ServeConfig(1 << 20, 0)
+    assert lib.vdmc_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
+    assert lib.vdmc_serve_destroy(None) == 0
+    assert lib.vdmc_serve_poll(None, 1, None) == 1
+    assert lib.vdmc_count_batch(None, 1, 4, None, None) == 1   # NULL arrays
+    assert lib.vdmc_count_batch(None, 0, 6, None, None) == 1   # bad k
+    assert lib.vdmc_count_batch(None, 0, 5, None, None) == 4   # k = 5 unsupported

@@ -1,0 +1,178 @@
+"""GPU tests of the batched launch (many graphs, one persistent captured launch, tuner)
+and of the serving loop (continuous batching, memory admission).  Every count is
+compared bit-exactly with the oracle or with the single-graph path."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def v():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_11655_amd as v
+    v.load()
+    return v
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    # same recipe as the 4096-graph batch workload, fewer graphs
+    return gg.er_batch(48, 20, 500, 2.0, 8.0, seed=3)
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_batch_equals_oracle(v, small_batch, k):
+    import torch
+    _say(f"batch k={k} graphs={len(small_batch)}")
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in small_batch]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        outs = v.count_batch(Gs, k, stream=stream)
+        stream.synchronize()
+        for rep in range(3):   # replays of the captured launch, with eager work in between
+            for o in outs:
+                o.fill_(-1)
+            torch.cuda.synchronize()
+            v.count_batch(Gs, k, outs=outs, stream=stream)
+            stream.synchronize()
+            for g, o in zip(small_batch, outs):
+                want, _ = oracle.count(g.n, g.src, g.dst, k)
+                assert (_np(o) == want).all(), f"replay {rep} graph n={g.n}"
+
+
+def test_batch_with_hub_graph_and_single_path(v, small_batch):
+    import torch
+    graphs = small_batch[:8] + [gg.config_graph("chunglu_2000")] + small_batch[8:12]
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        outs = v.count_batch(Gs, 4, stream=stream)
+        stream.synchronize()
+    for G, o in zip(Gs, outs):
+        single = _np(v.count(G, 4))
+        assert (_np(o) == single).all()
+
+
+def test_tune_and_cache(v, small_batch):
+    import torch
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in small_batch[:16]]
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        v.tune(Gs, 4, path)
+        text = open(path).read()
+        assert "threads_per_root" in text and "tile" in text
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        outs = v.count_batch(Gs, 4, stream=stream)
+        stream.synchronize()
+    for g, o in zip(small_batch[:16], outs):
+        want, _ = oracle.count(g.n, g.src, g.dst, 4)
+        assert (_np(o) == want).all()
+
+
+def test_batch_errors(v, small_batch):
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in small_batch[:2]]
+    with pytest.raises(v.VdmcError) as e:
+        v.count_batch(Gs, 5)
+    assert e.value.name in ("UNSUPPORTED", "INVALID_ARG")
+    assert v.count_batch([], 4) == []
+
+
+# --------------------------------------------------------------------------- serving
+
+def _pool():
+    pool = [gg.er_directed(int(n), mu / (n - 1), (51, i)) for i, (n, mu) in
+            enumerate([(120, 3), (400, 5), (60, 8), (900, 4), (250, 2.5), (30, 6)])]
+    pool.append(gg.config_graph("chunglu_2000"))
+    pool.append(gg.config_graph("er1000"))
+    return pool
+
+
+def test_serve_alone_equals_mix(v):
+    import torch
+    pool = _pool()
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in pool]
+    rng = np.random.default_rng(7)
+    reqs = [(int(rng.integers(len(pool))), int(rng.choice([3, 4]))) for _ in range(40)]
+    # alone: each request by itself through vdmc_count
+    alone = {}
+    for gi, k in set(reqs):
+        alone[(gi, k)] = _np(v.count(Gs[gi], k)).copy()
+    srv = v.Server(mem_budget_bytes=8 << 30, max_inflight=6)
+    outs, ids = [], []
+    for gi, k in reqs:
+        o = torch.empty((pool[gi].n, v.num_classes(k)), dtype=torch.int64, device="cuda")
+        outs.append(o)
+        ids.append(srv.submit(Gs[gi], k, o))
+    for rid in ids:
+        srv.wait(rid)
+        assert srv.poll(rid)
+    torch.cuda.synchronize()
+    for (gi, k), o in zip(reqs, outs):
+        assert (_np(o) == alone[(gi, k)]).all(), f"graph {gi} k={k} differs in the mix"
+    st = srv.stats()
+    assert st["p50_us"] > 0 and st["p99_us"] >= st["p50_us"] and st["req_per_s"] > 0
+    expect_sets = sum(int(alone[(gi, k)].sum()) // k for gi, k in reqs)
+    assert st["sets"] == expect_sets
+    srv.close()
+
+
+def test_serve_admission_and_errors(v):
+    import torch
+    g = gg.config_graph("er1000")
+    G = v.Graph(g.n, g.src, g.dst)
+    out = torch.empty((g.n, 199), dtype=torch.int64, device="cuda")
+    tiny = v.Server(mem_budget_bytes=1 << 16, max_inflight=2)   # smaller than one output
+    with pytest.raises(v.VdmcError) as e:
+        tiny.submit(G, 4, out)
+    assert e.value.name == "REJECTED"
+    with pytest.raises(v.VdmcError) as e:
+        tiny.poll(12345)
+    assert e.value.name == "NOT_FOUND"
+    with pytest.raises(v.VdmcError) as e:
+        tiny.submit(G, 5, out)
+    assert e.value.name == "UNSUPPORTED"
+    tiny.close()
+    # a budget that holds exactly one request at a time still completes every request
+    one = 1000 * 199 * 8 + 1000 * 13 * 8
+    srv = v.Server(mem_budget_bytes=one, max_inflight=4)
+    want4, _ = oracle.count(g.n, g.src, g.dst, 4)
+    outs = [torch.empty((g.n, 199), dtype=torch.int64, device="cuda") for _ in range(5)]
+    ids = [srv.submit(G, 4, o) for o in outs]
+    for rid in ids:
+        srv.wait(rid)
+    for o in outs:
+        assert (_np(o) == want4).all()
+    srv.close()
+
+
+def test_serve_destroy_with_work_in_flight(v):
+    import torch
+    pool = _pool()
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in pool]
+    srv = v.Server(mem_budget_bytes=8 << 30, max_inflight=2)
+    outs = [torch.empty((g.n, 199), dtype=torch.int64, device="cuda") for g in pool]
+    for G, o in zip(Gs, outs):
+        srv.submit(G, 4, o)
+    srv.close()          # waits for running requests, cancels queued ones
+    torch.cuda.synchronize()
