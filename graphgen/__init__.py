@@ -125,14 +125,16 @@ def keyed_cap(n: int, src: np.ndarray, dst: np.ndarray, cap: int, seed) -> tuple
     key = rng.random(npairs)
     plo = pair_key // n
     phi = pair_key % n
+    # every pair is incident to two vertices; rank all incidences of a vertex together
+    end = np.concatenate([plo, phi])
+    pidx = np.concatenate([np.arange(npairs), np.arange(npairs)])
+    order = np.lexsort((np.concatenate([key, key]), end))
+    e_sorted = end[order]
+    starts = np.flatnonzero(np.r_[True, e_sorted[1:] != e_sorted[:-1]])
+    group_start = np.repeat(starts, np.diff(np.r_[starts, e_sorted.shape[0]]))
+    rank_in_group = np.arange(e_sorted.shape[0]) - group_start
     ok = np.ones(npairs, bool)
-    for end in (plo, phi):
-        order = np.lexsort((key, end))
-        e_sorted = end[order]
-        starts = np.flatnonzero(np.r_[True, e_sorted[1:] != e_sorted[:-1]])
-        group_start = np.repeat(starts, np.diff(np.r_[starts, e_sorted.shape[0]]))
-        rank_in_group = np.arange(e_sorted.shape[0]) - group_start
-        ok[order[rank_in_group >= cap]] = False
+    ok[pidx[order[rank_in_group >= cap]]] = False
     keep_arc = ok[pair_of_arc]
     return src[keep_arc].astype(np.int32), dst[keep_arc].astype(np.int32)
 

@@ -59,6 +59,11 @@ enum {
     VDMC_INPUT_ON_DEVICE = 2u   /* src/dst are device pointers (else host pointers) */
 };
 
+/* vdmc_count_range flags */
+enum {
+    VDMC_ACCUMULATE = 1u        /* add to out (and to the shape counters) instead of overwriting */
+};
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* vdmc_last_error(void);
 
@@ -119,6 +124,16 @@ vdmc_status vdmc_free_graph(vdmc_graph g);
  */
 vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream);
 
+/* The part of vdmc_count contributed by roots whose rank lies in [rank_begin, rank_end):
+ * the k-sets whose lowest-rank vertex is in the range (Lemma 1 makes such root ranges
+ * independent; they are the unit the paper proposes for spreading the work over devices,
+ * Sec. 11).  Without VDMC_ACCUMULATE, out is zeroed first; with it, the range's counts
+ * are added to out, so consecutive ranges covering [0, n) give exactly vdmc_count's
+ * result.  Ranks are those of the graph's degree order (vdmc_graph_export's perm maps
+ * them to ids).  Asynchronous on `stream`. */
+vdmc_status vdmc_count_range(vdmc_graph g, int32_t k, uint64_t* out, int64_t rank_begin, int64_t rank_end,
+                             uint32_t flags, void* stream);
+
 /* Both k = 3 (out3: n x 13) and k = 4 (out4: n x 199) in one call; one staging of
  * each root's neighbourhood feeds both. */
 vdmc_status vdmc_count34(vdmc_graph g, uint64_t* out3, uint64_t* out4, void* stream);
@@ -131,8 +146,10 @@ vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
 /* Diagnostic counters of the last count on this graph (host, synchronous): entries 0-5
  * are the shape counts above; entries 8-15 the device cycles the hub workgroups spent
  * per phase (stage, local matrix, k=3 pairs, depth-2 groups, (3,0,0), group shapes,
- * (1,2,0), flush), summed over workgroups; entries 16-23 the numbers of sets that took
- * the direct (unaggregated) crediting path per shape.  Copies min(n, 32) entries. */
+ * (1,2,0), flush), summed over workgroups; entries 16-21 the numbers of sets that took
+ * the direct (unaggregated) crediting path per shape; entries 24-27 the wave time spent
+ * inside the depth-2 groups on (2,1,0) sets, (2,1,0) sets with both parents, (1,1,1)
+ * paths and the rest (100 MHz ticks summed over waves).  Copies min(n, 32) entries. */
 vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n);
 
 /*

@@ -11,6 +11,7 @@ from .vdmc import (  # noqa: F401
     class_table,
     count,
     count34,
+    count_range,
     count_batch,
     load,
     num_classes,

@@ -40,6 +40,7 @@ struct Args {
     unsigned long long* out3;   // n x 13, original ids
     unsigned long long* out4;   // n x 199
     unsigned long long* stats;  // kShapes
+    uint32_t rank_lo, rank_hi;  // only roots with rank in [rank_lo, rank_hi)
 };
 
 // rank x a member of the sorted list P[0..d) ?
@@ -216,8 +217,11 @@ __global__ __launch_bounds__(kThreads) void k_count_roots(Args a) {
     __shared__ RootLds<kStage> S;
     unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
     GraphView gv{a.off, a.adj, a.split, a.perm, a.out3, a.out4, a.stats};
-    for (int64_t ri = blockIdx.x; ri < a.nroots; ri += gridDim.x)
-        process_root<kThreads, kStage, K3, K4>(gv, a.t3, a.t4, a.roots[ri], S, shape);
+    for (int64_t ri = blockIdx.x; ri < a.nroots; ri += gridDim.x) {
+        const uint32_t r = a.roots[ri];
+        if (r < a.rank_lo || r >= a.rank_hi) continue;   // uniform across the workgroup
+        process_root<kThreads, kStage, K3, K4>(gv, a.t3, a.t4, r, S, shape);
+    }
     for (int s = 0; s < kShapes; s++)
         if (shape[s]) atomicAdd(&a.stats[s], shape[s]);
 }
@@ -308,12 +312,18 @@ void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t st) {
     VDMC_HIP(hipGetLastError());
 }
 
-void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st) {
+void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st,
+                  int64_t rank_lo, int64_t rank_hi, bool zero) {
     const ClassTables& t = class_tables();
     ensure_bins(g, hub_min_default(), st);
-    if (k3) launch_fill_u64(out3, (size_t)g->n * kClasses3, 0, st);
-    if (k4) launch_fill_u64(out4, (size_t)g->n * kClasses4, 0, st);
-    launch_fill_u64((uint64_t*)g->stats, kStatSlots, 0, st);
+    if (zero) {
+        if (k3) launch_fill_u64(out3, (size_t)g->n * kClasses3, 0, st);
+        if (k4) launch_fill_u64(out4, (size_t)g->n * kClasses4, 0, st);
+        launch_fill_u64((uint64_t*)g->stats, kStatSlots, 0, st);
+    }
+    const uint32_t lo = (uint32_t)std::max<int64_t>(0, rank_lo);
+    const uint32_t hi = (uint32_t)std::min<int64_t>(g->n, rank_hi);
+    if (lo >= hi) return;
     if (g->nlight > 0) {
         Args a;
         a.off = g->off;
@@ -327,6 +337,8 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
         a.out3 = (unsigned long long*)out3;
         a.out4 = (unsigned long long*)out4;
         a.stats = g->stats;
+        a.rank_lo = lo;
+        a.rank_hi = hi;
         int64_t blocks = g->nlight < 65536 ? g->nlight : 65536;
         if (k3 && k4)
             hipLaunchKernelGGL((k_count_roots<true, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
@@ -336,7 +348,7 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
             hipLaunchKernelGGL((k_count_roots<false, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
         VDMC_HIP(hipGetLastError());
     }
-    launch_hub(g, k3, k4, out3, out4, st);
+    launch_hub(g, k3, k4, out3, out4, st, lo, hi);
 }
 
 }  // namespace vdmc
@@ -372,6 +384,21 @@ vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n) {
         VDMC_HIP(hipDeviceSynchronize());
         const int k = n < vdmc::kStatSlots ? n : vdmc::kStatSlots;
         VDMC_HIP(hipMemcpy(counters, g->stats, k * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    });
+}
+
+vdmc_status vdmc_count_range(vdmc_graph g, int32_t k, uint64_t* out, int64_t rank_begin, int64_t rank_end,
+                             uint32_t flags, void* stream) {
+    return vdmc::guarded([&] {
+        VDMC_REQUIRE(g != nullptr, VDMC_ERR_INVALID_ARG, "graph is NULL");
+        VDMC_REQUIRE(k == 3 || k == 4, k == 5 ? VDMC_ERR_UNSUPPORTED : VDMC_ERR_INVALID_ARG,
+                     "k must be 3 or 4");
+        VDMC_REQUIRE(out != nullptr || g->n == 0, VDMC_ERR_INVALID_ARG, "out is NULL");
+        VDMC_REQUIRE(rank_begin >= 0 && rank_begin <= rank_end, VDMC_ERR_INVALID_ARG, "bad rank range");
+        VDMC_REQUIRE((flags & ~(uint32_t)VDMC_ACCUMULATE) == 0, VDMC_ERR_INVALID_ARG, "unknown flags");
+        VDMC_HIP(hipSetDevice(g->device));
+        vdmc::launch_count(g, k == 3, k == 4, k == 3 ? out : nullptr, k == 4 ? out : nullptr,
+                           vdmc::as_stream(stream), rank_begin, rank_end, !(flags & VDMC_ACCUMULATE));
     });
 }
 

@@ -49,10 +49,12 @@ struct HubArgs {
     unsigned long long* out4;
     unsigned long long* stats;
     int k3, k4;
+    uint32_t rank_lo, rank_hi;   // only roots with rank in [rank_lo, rank_hi)
     // per-workgroup scratch
     uint32_t* scratch;
     size_t wg_words;        // u32 words per workgroup slice
-    size_t o_spar, o_s111, o_s3x, o_groups, o_alist, o_wlist, o_c120, o_eflag, o_llist;
+    size_t o_spar, o_s111, o_s3x, o_groups, o_alist, o_wlist, o_c120, o_eflag, o_llist, o_hash;
+    uint32_t hash_bits;     // per-wave hash table of 2^hash_bits (key, value) pairs
     uint32_t wl_cap;        // per-wave list capacity (>= max degree)
 };
 
@@ -155,6 +157,7 @@ struct Lds {
     uint32_t cw[NW][27 + 27 + kClasses3];      // per-wave group accumulators (c and r credits)
     uint32_t inA[NW][PMAX / 32];               // per-wave membership bitmap of A(c)
     uint32_t xacc[NW][64 * 3];                 // per-wave (1,1,1) depth-1 credits by A(c) position
+    uint32_t rowbuf[NW][PMAX / 16];            // per-wave 2-bit row of one slot's local neighbours
     unsigned long long root4[kClasses4];
     unsigned long long root3[kClasses3];
     unsigned long long stat[kStatSlots];       // shape counts, phase ticks, direct-path counts
@@ -224,6 +227,9 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     uint32_t* c120 = W + A.o_c120 + (size_t)wid * 3 * A.wl_cap;
     uint8_t* eflag = reinterpret_cast<uint8_t*>(W + A.o_eflag);
     uint16_t* llist = reinterpret_cast<uint16_t*>(W + A.o_llist);   // local neighbours per slot
+    const uint32_t hsize = 1u << A.hash_bits;
+    uint32_t* hkey = W + A.o_hash + (size_t)wid * 2 * hsize;        // per-wave: rank + 1, 0 = empty
+    uint32_t* hval = hkey + hsize;                                  // position in the list
     // per-thread counters of the current root (sets per shape, sets on the direct path),
     // reduced into L.stat once per root
     uint32_t shape[kShapes] = {0, 0, 0, 0, 0, 0};
@@ -243,6 +249,8 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     for (uint32_t i = tid; i < 9 * PMAX; i += HT) { spar[i] = 0; s111[i] = 0; }
     for (uint32_t i = tid; i < 3 * PMAX; i += HT) s3x[i] = 0;
     for (uint32_t i = tid; i < NW * (PMAX / 32); i += HT) (&L.inA[0][0])[i] = 0;
+    for (uint32_t i = tid; i < NW * (PMAX / 16); i += HT) (&L.rowbuf[0][0])[i] = 0;
+    for (size_t i = tid; i < (size_t)NW * 2 * hsize; i += HT) W[A.o_hash + i] = 0;
     for (uint32_t i = tid; i < NW * (27 + 27 + kClasses3); i += HT) (&L.cw[0][0])[i] = 0;
     for (uint32_t i = tid; i < kStatSlots; i += HT) L.stat[i] = 0;
 
@@ -253,6 +261,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         const uint32_t ri = L.rootidx;
         if (ri >= A.nhub) break;
         const uint32_t r = A.hubs[ri];
+        if (r < A.rank_lo || r >= A.rank_hi) continue;   // uniform across the workgroup
         const uint32_t s0 = A.split[r];
         const uint32_t d = A.off[r + 1] - s0;
         const uint32_t nch = (d + 63) >> 6;
@@ -561,6 +570,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         uint32_t* cw = L.cw[wid];
         uint32_t* inA = L.inA[wid];
         uint32_t* xacc = L.xacc[wid];
+        uint32_t* rowbuf = L.rowbuf[wid];
         for (int t = wave_next(&L.task); t < (int)ngroups; t = wave_next(&L.task)) {
             const uint32_t c = grp[4 * t + 0];
             const uint32_t p = grp[4 * t + 1];
@@ -580,6 +590,8 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     shape[1]++;
                 }
             }
+            const unsigned long long tg0 = wall_clock64();
+            unsigned long long tg1 = tg0, tg2 = tg0, tg3 = tg0;
             if (A.k4) {
                 // (2,1,0), y outside A(c): the parent x runs outside, the chunks of y inside
                 for (uint32_t ub = 0; ub < p; ub += 64) {
@@ -588,14 +600,20 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     for (uint32_t uu = 0; uu < ucnt; uu++) {
                         const uint32_t ex = __shfl(areg, (int)uu);
                         const uint32_t x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
-                        const bool xloc = L.lcnt[x] != 0;
+                        const uint32_t xl = L.lcnt[x], xq = L.pre[x];
+                        const bool xloc = xl != 0;
+                        // x's local codes, spread into this wave's 2-bit row buffer
+                        for (uint32_t q = lane; q < xl; q += 64) {
+                            const uint32_t vq = llist[xq + q], sl = vq >> 2;
+                            atomicOr(&rowbuf[sl >> 4], (vq & 3u) << ((sl & 15u) << 1));
+                        }
                         uint32_t xn1 = 0, xn2 = 0, xn3 = 0;
                         for (uint32_t ch = 0; ch < nch; ch++) {
                             const uint32_t y = 64 * ch + lane;
                             const bool yv = y < d;
                             const uint32_t ry = yv ? (L.P[y] & 3u) : 0u;
                             const bool lv = yv && !((inA[y >> 5] >> (y & 31)) & 1u);
-                            const uint32_t xy = (xloc && lv) ? mget(M, d, x, y) : 0u;
+                            const uint32_t xy = (xloc && lv) ? ((rowbuf[y >> 4] >> ((y & 15u) << 1)) & 3u) : 0u;
                             const bool pure = lv && xy == 0u;
                             if (pure) atomicAdd(&L.cnt[((rx - 1) * 3 + (xc - 1)) * d + y], 1u);
                             xn1 += __popcll(__ballot(pure && ry == 1u));
@@ -618,8 +636,10 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                                 cw[(rx - 1) * 9 + (xc - 1) * 3 + lane] += nk;
                             }
                         }
+                        for (uint32_t q = lane; q < xl; q += 64) rowbuf[(llist[xq + q] >> 2) >> 4] = 0;
                     }
                 }
+                tg1 = wall_clock64();
                 // (2,1,0) with both depth-1 vertices in A(c): pairs u < v of A(c)
                 for (uint32_t v0 = 0; v0 < p; v0 += 64) {
                     const uint32_t vpos = v0 + lane;
@@ -643,6 +663,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                         }
                     }
                 }
+                tg2 = wall_clock64();
                 // (1,1,1): paths r - x - c - e, e above r, not in N(r), not adjacent to x
                 const bool small_p = p <= 64;
                 if (small_p)
@@ -704,6 +725,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     }
                 }
             }
+            tg3 = A.k4 ? wall_clock64() : tg0;
             // flush the group's depth-2 vertex (and the root, which is in every one of its sets)
             for (uint32_t q = lane; q < 27 + 27 + kClasses3; q += 64) {
                 const uint32_t cnt = cw[q];
@@ -723,6 +745,13 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             for (uint32_t u = lane; u < p; u += 64) {
                 const uint32_t x = Ac[u] >> 2;
                 atomicAnd(&inA[x >> 5], ~(1u << (x & 31)));
+            }
+            if (lane == 0) {   // per-wave time split of the group shapes (diagnostic)
+                const unsigned long long tg4 = wall_clock64();
+                atomicAdd(&L.stat[24], tg1 - tg0);
+                atomicAdd(&L.stat[25], tg2 - tg1);
+                atomicAdd(&L.stat[26], tg3 - tg2);
+                atomicAdd(&L.stat[27], tg4 - tg3);
             }
         }
         __threadfence();
@@ -755,6 +784,17 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     m += __popcll(mk);
                 }
                 for (uint32_t q = lane; q < 3 * m; q += 64) c120[q] = 0;
+                // positions of L_a by rank, in this wave's hash table
+                for (uint32_t q = lane; q < m; q += 64) {
+                    const uint32_t key = (wlist[q] >> 2) + 1u;
+                    uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
+                    while (true) {
+                        const uint32_t old = atomicCAS(&hkey[h], 0u, key);
+                        if (old == 0u || old == key) break;
+                        h = (h + 1u) & (hsize - 1u);
+                    }
+                    hval[h] = q;
+                }
                 __threadfence_block();
                 const uint32_t ra = L.P[a] & 3u, va = L.P[a] >> 2;
                 unsigned long long a6lo = 0, a6mid = 0, a6hi = 0;   // 6 signatures, 32-bit fields
@@ -762,8 +802,32 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     const uint32_t u = u0 + lane;
                     const bool uv = u < m;
                     const uint32_t e2 = uv ? wlist[u] : 0u, c2 = e2 >> 2, ac2 = e2 & 3u;
-                    RowCache rcache;
-                    row_cache_load(rcache, A.off, A.adj, c2, uv);
+                    // neighbours of c2 inside L_a that come before it: up to 4 kept in registers
+                    // as (position << 2 | arc bits seen from that neighbour); more -> search per step
+                    uint32_t nb0 = 0xFFFFFFFFu, nb1 = 0xFFFFFFFFu, nb2 = 0xFFFFFFFFu, nb3 = 0xFFFFFFFFu;
+                    uint32_t nfound = 0;
+                    const uint32_t lo2 = uv ? A.off[c2] : 0u, hi2 = uv ? A.off[c2 + 1] : 0u;
+                    if (hi2 - lo2 > 64) nfound = 5;   // long row: search per step instead
+                    else if (uv) {
+                        for (uint32_t t2 = lo2; t2 < hi2; t2++) {
+                            const uint32_t ew = A.adj[t2];
+                            const uint32_t key = (ew >> 2) + 1u;
+                            uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
+                            uint32_t pos = 0xFFFFFFFFu;
+                            while (true) {
+                                const uint32_t kk = hkey[h];
+                                if (kk == 0u) break;
+                                if (kk == key) { pos = hval[h]; break; }
+                                h = (h + 1u) & (hsize - 1u);
+                            }
+                            if (pos >= u) continue;   // not in L_a, or not before c2
+                            const uint32_t rec = (pos << 2) | swap_arc_bits(ew & 3u);
+                            if (nfound == 0) nb0 = rec; else if (nfound == 1) nb1 = rec;
+                            else if (nfound == 2) nb2 = rec; else if (nfound == 3) nb3 = rec;
+                            nfound++;
+                        }
+                    }
+                    const bool many = nfound > 4;
                     unsigned long long acc = 0;
                     const uint32_t tmax = min(m, u0 + 64) - 1;
                     for (uint32_t tb = 0; tb < tmax; tb += 64) {
@@ -773,7 +837,15 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                             const uint32_t tt = tb + k2;
                             const uint32_t e1 = __shfl(wreg, (int)k2), c1 = e1 >> 2, ac = e1 & 3u;
                             const bool valid = uv && tt < u;
-                            const uint32_t cc = valid ? row_cache_bits_from(rcache, A.adj, c1) : 0u;   // seen from c1
+                            uint32_t cc = 0;
+                            if (valid) {
+                                if (many) {
+                                    cc = arc_bits(A.off, A.adj, c1, c2);
+                                } else if ((nb0 >> 2) == tt) {
+                                    cc = nb0 & 3u;
+                                    nb0 = nb1; nb1 = nb2; nb2 = nb3; nb3 = 0xFFFFFFFFu;
+                                }
+                            }
                             const bool pure = valid && cc == 0u;
                             if (pure) acc += 1ull << (21u * (ac - 1u));
                             const uint32_t n1 = __popcll(__ballot(pure && ac2 == 1u));
@@ -809,6 +881,13 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                             if (cnt) atomicAdd(&c120[u * 3 + g], cnt);
                         }
                     }
+                }
+                // clear this wave's hash table entries
+                for (uint32_t q = lane; q < m; q += 64) {
+                    const uint32_t key = (wlist[q] >> 2) + 1u;
+                    uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
+                    while (hkey[h] != key) h = (h + 1u) & (hsize - 1u);
+                    hkey[h] = 0u;
                 }
                 __threadfence_block();
                 for (uint32_t q = lane; q < 3 * m; q += 64) {
@@ -1040,6 +1119,9 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         const size_t o_c120 = o; o += 3 * NW * wl;
         const size_t o_eflag = o; o += (s2 + 3) / 4;
         const size_t o_llist = o; o += (s2 + 1) / 2;
+        uint32_t hb = 12;
+        while ((1u << hb) < 2 * wl) hb++;
+        const size_t o_hash = o; o += (size_t)NW * 2 * ((size_t)1 << hb);
         o = (o + 63) & ~(size_t)63;
         g->hub_scratch_bytes = o * sizeof(uint32_t) * (size_t)wgs;
         VDMC_HIP(hipMalloc(&g->hub_scratch, g->hub_scratch_bytes));
@@ -1054,11 +1136,14 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         g->hub_layout[8] = o_eflag;
         g->hub_layout[9] = wl;
         g->hub_layout[10] = o_llist;
+        g->hub_layout[11] = o_hash;
+        g->hub_layout[12] = hb;
     }
     g->bins_hub_min = hub_min;
 }
 
-void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st) {
+void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st,
+                uint32_t rank_lo, uint32_t rank_hi) {
     if (g->nhub == 0) return;
     const ClassTables& t = class_tables();
     HubArgs a;
@@ -1076,6 +1161,8 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.stats = g->stats;
     a.k3 = k3;
     a.k4 = k4;
+    a.rank_lo = rank_lo;
+    a.rank_hi = rank_hi;
     a.scratch = (uint32_t*)g->hub_scratch;
     a.wg_words = g->hub_layout[0];
     a.o_spar = g->hub_layout[1];
@@ -1088,6 +1175,8 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.o_eflag = g->hub_layout[8];
     a.wl_cap = (uint32_t)g->hub_layout[9];
     a.o_llist = g->hub_layout[10];
+    a.o_hash = g->hub_layout[11];
+    a.hash_bits = (uint32_t)g->hub_layout[12];
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 4);
     const int wgs = hub_workgroups();
     hipLaunchKernelGGL(k_hub, dim3(wgs), dim3(HT), 0, st, a);

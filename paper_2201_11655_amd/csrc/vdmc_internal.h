@@ -118,7 +118,7 @@ struct vdmc_graph_s {
     void* hub_scratch = nullptr;
     size_t hub_scratch_bytes = 0;
     unsigned* hub_queue = nullptr;
-    size_t hub_layout[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    size_t hub_layout[16] = {0};
 };
 
 namespace vdmc {
@@ -157,11 +157,12 @@ void launch_batch(const BatchArgs& b, int variant, int k3, int k4, int num_graph
 void invalidate_batch_plans(vdmc_graph_s* g);
 // launches (count.hip)
 void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
-                  hipStream_t stream);
+                  hipStream_t stream, int64_t rank_lo = 0, int64_t rank_hi = INT64_MAX, bool zero = true);
 void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t stream);
 // hub path (count_hub.hip)
 void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t stream);
-void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t stream);
+void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t stream,
+                uint32_t rank_lo = 0, uint32_t rank_hi = 0xFFFFFFFFu);
 int hub_min_default();
 void free_hub(vdmc_graph_s* g);
 }  // namespace vdmc

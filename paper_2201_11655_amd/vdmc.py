@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvdmc.so")
 SYMBOLS = [
     "vdmc_last_error", "vdmc_num_classes", "vdmc_class_codes", "vdmc_class_table",
     "vdmc_build_graph", "vdmc_graph_info", "vdmc_graph_export", "vdmc_free_graph",
-    "vdmc_count", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters", "vdmc_count_batch", "vdmc_tune",
+    "vdmc_count", "vdmc_count_range", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters", "vdmc_count_batch", "vdmc_tune",
     "vdmc_serve_create", "vdmc_serve_submit", "vdmc_serve_poll", "vdmc_serve_wait",
     "vdmc_serve_stats", "vdmc_serve_destroy",
 ]
@@ -61,6 +61,7 @@ def load():
         "vdmc_free_graph": ([p], i32),
         "vdmc_count": ([p, i32, p, p], i32),
         "vdmc_count34": ([p, p, p, p], i32),
+        "vdmc_count_range": ([p, i32, p, i64, i64, u32, p], i32),
         "vdmc_shape_counts": ([p, p], i32),
         "vdmc_profile_counters": ([p, p, i32], i32),
         "vdmc_count_batch": ([p, i32, i32, p, p], i32),
@@ -197,6 +198,14 @@ def count(g: Graph, k: int, out=None, stream=None):
         _check(load().vdmc_count(g.handle, int(k), None, _stream_handle(stream)))
     out = _out_tensor(g.n, k, out)
     _check(load().vdmc_count(g.handle, int(k), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def count_range(g: Graph, k: int, out, rank_begin: int, rank_end: int, accumulate: bool, stream=None):
+    """Counts contributed by roots with rank in [rank_begin, rank_end) (see vdmc.h)."""
+    out = _out_tensor(g.n, k, out)
+    _check(load().vdmc_count_range(g.handle, int(k), ctypes.c_void_p(out.data_ptr()), int(rank_begin),
+                                   int(rank_end), 1 if accumulate else 0, _stream_handle(stream)))
     return out
 
 

@@ -199,3 +199,20 @@ def test_relabelling_and_repeat_invariance(v):
         b = _np(v.count(B, k))
         assert (a1 == a2).all()
         assert (b[perm] == a1).all()
+
+
+def test_count_range_slices_sum_to_count(v):
+    """Root-rank ranges are independent (Lemma 1): consecutive ranges accumulate to the
+    full count, for both the light-root and the hub path."""
+    import torch
+    g = gg.config_graph("chunglu_2000")
+    G = v.Graph(g.n, g.src, g.dst)
+    for k in (3, 4):
+        full = _np(v.count(G, k)).copy()
+        out = torch.empty((g.n, v.num_classes(k)), dtype=torch.int64, device="cuda")
+        bounds = [0, 1, 7, 64, 300, 1999, g.n]
+        for i in range(len(bounds) - 1):
+            v.count_range(G, k, out, bounds[i], bounds[i + 1], accumulate=i > 0)
+        assert (_np(out) == full).all()
+        with pytest.raises(v.VdmcError):
+            v.count_range(G, k, out, 5, 2, accumulate=False)
