@@ -6,6 +6,7 @@
 // Sec. 2; last step of Sec. 4.2).  The table maps every raw index to a class id
 // (ascending minimal index among connected classes) so that the merge happens in
 // the same instruction that credits a motif, with no post-processing pass.
+#include <algorithm>
 #include <map>
 
 #include "vdmc_internal.h"
@@ -159,11 +160,40 @@ const ClassTables& class_tables() {
     if (it != g_tables.end()) return *it->second;
     auto* t = new ClassTables();
     uint8_t* d = nullptr;
-    VDMC_HIP(hipMalloc(&d, 64 + 4096));
+    VDMC_HIP(hipMalloc(&d, 64 + 4096 + 256 + 64));
     build_one<3>(d, t->host3, t->codes3);
     build_one<4>(d + 64, t->host4, t->codes4);
     t->t3 = d;
     t->t4 = d + 64;
+    // compact slots: classes of 4-sets whose G_U is a tree; with the set ordered
+    // (v0, v1, v2, v3) and arc bits p_ij, a path v0-v1-v2-v3 has p01, p12, p23 != 0 and a
+    // star centred at v1 has p01, p12, p13 != 0 (every other pair empty)
+    std::vector<uint8_t> slot(256, 0xFF), slotcls;
+    auto idx4 = [](unsigned p01, unsigned p02, unsigned p03, unsigned p12, unsigned p13, unsigned p23) {
+        return ((p01 & 1u) << 11) | ((p01 >> 1) << 8) | ((p02 & 1u) << 10) | ((p02 >> 1) << 5) |
+               ((p03 & 1u) << 9) | ((p03 >> 1) << 2) | ((p12 & 1u) << 7) | ((p12 >> 1) << 4) |
+               ((p13 & 1u) << 6) | ((p13 >> 1) << 1) | ((p23 & 1u) << 3) | (p23 >> 1);
+    };
+    std::vector<int> tree_classes;
+    for (unsigned a = 1; a <= 3; a++)
+        for (unsigned b = 1; b <= 3; b++)
+            for (unsigned c = 1; c <= 3; c++) {
+                tree_classes.push_back(t->host4[idx4(a, 0, 0, b, 0, c)]);   // path
+                tree_classes.push_back(t->host4[idx4(a, 0, 0, b, c, 0)]);   // star centred at v1
+            }
+    std::sort(tree_classes.begin(), tree_classes.end());
+    tree_classes.erase(std::unique(tree_classes.begin(), tree_classes.end()), tree_classes.end());
+    VDMC_REQUIRE((int)tree_classes.size() == kCompact4, VDMC_ERR_DEVICE,
+                 "expected 25 tree classes, found " + std::to_string(tree_classes.size()));
+    for (size_t i = 0; i < tree_classes.size(); i++) {
+        slot[tree_classes[i]] = (uint8_t)i;
+        slotcls.push_back((uint8_t)tree_classes[i]);
+    }
+    slotcls.resize(64, 0);
+    VDMC_HIP(hipMemcpy(d + 64 + 4096, slot.data(), 256, hipMemcpyHostToDevice));
+    VDMC_HIP(hipMemcpy(d + 64 + 4096 + 256, slotcls.data(), 64, hipMemcpyHostToDevice));
+    t->slot4 = d + 64 + 4096;
+    t->slotcls = d + 64 + 4096 + 256;
     g_tables[dev] = t;   // kept for the life of the process
     return *t;
 }

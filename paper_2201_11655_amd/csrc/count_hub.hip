@@ -47,6 +47,8 @@ struct HubArgs {
     const uint8_t* t4;
     unsigned long long* out3;
     unsigned long long* out4;
+    unsigned long long* comp;    // n x kCompact4 rank-indexed accumulator (see add4)
+    const uint8_t* slot4;        // class -> compact slot
     unsigned long long* stats;
     int k3, k4;
     uint32_t rank_lo, rank_hi;   // only roots with rank in [rank_lo, rank_hi)
@@ -143,6 +145,8 @@ __device__ __forceinline__ int wave_next(unsigned* sTask) {
 
 // ----------------------------------------------------------------------------- kernel
 
+constexpr uint32_t kRowStage = 224;   // per-wave LDS entries for the rows of A(c)'s members
+
 // P membership filter: one bit per hash bucket of a rank; a clear bit proves absence.
 constexpr uint32_t kBloomWords = 1024;   // 32768 bits
 __device__ __forceinline__ uint32_t bloom_bit(uint32_t x) { return (x * 2654435761u) >> 17; }
@@ -156,7 +160,9 @@ struct Lds {
     uint32_t scan[HT];
     uint32_t cw[NW][27 + 27 + kClasses3];      // per-wave group accumulators (c and r credits)
     uint32_t inA[NW][PMAX / 32];               // per-wave membership bitmap of A(c)
-    uint32_t xacc[NW][64 * 3];                 // per-wave (1,1,1) depth-1 credits by A(c) position
+    uint16_t xacc[NW][64 * 3];                 // per-wave (1,1,1) depth-1 credits by A(c) position
+    uint32_t rowstage[NW][kRowStage];          // per-wave rows of A(c)'s members (sorted entries)
+    uint16_t rowseg[NW][66];                   // per-wave segment bounds in rowstage
     uint32_t rowbuf[NW][PMAX / 16];            // per-wave 2-bit row of one slot's local neighbours
     unsigned long long root4[kClasses4];
     unsigned long long root3[kClasses3];
@@ -164,8 +170,21 @@ struct Lds {
     uint16_t lcnt[PMAX];                       // local (in-N+(r)) degree of every slot
     uint8_t t4[4096];
     uint8_t t3[64];
+    uint8_t slot4[kClasses4 + 1];              // class -> compact slot (0xFF: none)
     unsigned task, groups, alloc, rootidx;
 };
+
+// Credit cnt sets of class cls to the vertex of rank v.  Classes of sets whose
+// undetermined pairs are all non-adjacent (the 15 directed 4-path and 10 3-star
+// classes) go to a compact rank-indexed accumulator that stays cache-resident and is
+// folded into the output once per launch; every other class goes straight to the output.
+__device__ __forceinline__ void add4(const HubArgs& A, const Lds& L, uint32_t v, uint32_t cls,
+                                     unsigned long long cnt) {
+    if (!cnt || cls >= kClasses4) return;
+    const uint32_t sl = L.slot4[cls];
+    if (sl != 0xFFu) atomicAdd(&A.comp[(size_t)v * kCompact4 + sl], cnt);
+    else atomicAdd(&A.out4[(size_t)A.perm[v] * kClasses4 + cls], cnt);
+}
 
 __device__ __forceinline__ int find_slot_f(const Lds& L, uint32_t d, uint32_t x) {
     const uint32_t b = bloom_bit(x);
@@ -234,6 +253,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     // reduced into L.stat once per root
     uint32_t shape[kShapes] = {0, 0, 0, 0, 0, 0};
     uint32_t slow[kShapes] = {0, 0, 0, 0, 0, 0};
+    uint32_t work[4] = {0, 0, 0, 0};   // groups, (1,1,1) chunks, (1,1,1) steps, (2,1,0) chunk steps
     unsigned long long tprev = wall_clock64();
 #define HUB_PHASE(k)                                      \
     do {                                                  \
@@ -246,6 +266,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
 
     for (uint32_t i = tid; i < 4096; i += HT) L.t4[i] = A.t4[i];
     for (uint32_t i = tid; i < 64; i += HT) L.t3[i] = A.t3[i];
+    for (uint32_t i = tid; i < kClasses4; i += HT) L.slot4[i] = A.slot4[i];
     for (uint32_t i = tid; i < 9 * PMAX; i += HT) { spar[i] = 0; s111[i] = 0; }
     for (uint32_t i = tid; i < 3 * PMAX; i += HT) s3x[i] = 0;
     for (uint32_t i = tid; i < NW * (PMAX / 32); i += HT) (&L.inA[0][0])[i] = 0;
@@ -515,14 +536,14 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     }
                     if (edgeset) {   // only c's credit is per set; a, b and r are summed in acc
                         slow[2]++;
-                        add_out(A.out4, A.perm, kClasses4, L.P[l] >> 2, L.t4[motif_index4(ra, rb, rc, ab, 0u, 0u)], 1);
+                        add4(A, L, L.P[l] >> 2, L.t4[motif_index4(ra, rb, rc, ab, 0u, 0u)], 1);
                     } else if (va && !pure) {
                         slow[2]++;
                         const uint32_t cls = L.t4[motif_index4(ra, rb, rc, ab, ac, bc)];
                         atomicAdd(&L.root4[cls], 1ull);
-                        add_out(A.out4, A.perm, kClasses4, L.P[i] >> 2, cls, 1);
-                        add_out(A.out4, A.perm, kClasses4, L.P[j] >> 2, cls, 1);
-                        add_out(A.out4, A.perm, kClasses4, L.P[l] >> 2, cls, 1);
+                        add4(A, L, L.P[i] >> 2, cls, 1);
+                        add4(A, L, L.P[j] >> 2, cls, 1);
+                        add4(A, L, L.P[l] >> 2, cls, 1);
                     }
                     shape[2] += va ? 1 : 0;
                 }
@@ -534,8 +555,8 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                             atomicAdd(&L.cnt[pair_sig(rb, rc) * d + i], cnt);
                         } else {
                             const uint32_t cls = L.t4[motif_index4(ra, rb, rc, ab, 0u, 0u)];
-                            add_out(A.out4, A.perm, kClasses4, L.P[i] >> 2, cls, cnt);
-                            add_out(A.out4, A.perm, kClasses4, L.P[j] >> 2, cls, cnt);
+                            add4(A, L, L.P[i] >> 2, cls, cnt);
+                            add4(A, L, L.P[j] >> 2, cls, cnt);
                             atomicAdd(&L.root4[cls], (unsigned long long)cnt);
                         }
                     }
@@ -557,7 +578,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 const uint32_t s = q % d, g = q / d;
                 uint32_t x, y;
                 sig_pair(g, x, y);
-                add_out(A.out4, A.perm, kClasses4, L.P[s] >> 2, L.t4[motif_index4(L.P[s] & 3u, x, y, 0u, 0u, 0u)], cnt);
+                add4(A, L, L.P[s] >> 2, L.t4[motif_index4(L.P[s] & 3u, x, y, 0u, 0u, 0u)], cnt);
                 L.cnt[q] = 0;
             }
             if (tid == 0) L.task = 0;
@@ -569,11 +590,14 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         const uint32_t ngroups = L.groups;
         uint32_t* cw = L.cw[wid];
         uint32_t* inA = L.inA[wid];
-        uint32_t* xacc = L.xacc[wid];
+        uint16_t* xacc = L.xacc[wid];
+        uint32_t* rowstage = L.rowstage[wid];
+        uint16_t* rowseg = L.rowseg[wid];
         uint32_t* rowbuf = L.rowbuf[wid];
         for (int t = wave_next(&L.task); t < (int)ngroups; t = wave_next(&L.task)) {
             const uint32_t c = grp[4 * t + 0];
             const uint32_t p = grp[4 * t + 1];
+            if (lane == 0) work[0]++;
             const uint32_t* Ac = alist + grp[4 * t + 2];
             const uint32_t chi = A.off[c + 1];
             for (uint32_t u = lane; u < p; u += 64) {
@@ -615,6 +639,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                             const bool lv = yv && !((inA[y >> 5] >> (y & 31)) & 1u);
                             const uint32_t xy = (xloc && lv) ? ((rowbuf[y >> 4] >> ((y & 15u) << 1)) & 3u) : 0u;
                             const bool pure = lv && xy == 0u;
+                            if (lane == 0) work[3]++;
                             if (pure) atomicAdd(&L.cnt[((rx - 1) * 3 + (xc - 1)) * d + y], 1u);
                             xn1 += __popcll(__ballot(pure && ry == 1u));
                             xn2 += __popcll(__ballot(pure && ry == 2u));
@@ -623,9 +648,9 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                                 slow[3]++;
                                 const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, 0u)];
                                 atomicAdd(&L.root4[cls], 1ull);
-                                add_out(A.out4, A.perm, kClasses4, L.P[x] >> 2, cls, 1);
-                                add_out(A.out4, A.perm, kClasses4, L.P[y] >> 2, cls, 1);
-                                add_out(A.out4, A.perm, kClasses4, c, cls, 1);
+                                add4(A, L, L.P[x] >> 2, cls, 1);
+                                add4(A, L, L.P[y] >> 2, cls, 1);
+                                add4(A, L, c, cls, 1);
                             }
                             shape[3] += lv ? 1 : 0;
                         }
@@ -656,9 +681,9 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                             const uint32_t xy = mget(M, d, x, y);
                             const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, yc)];
                             atomicAdd(&L.root4[cls], 1ull);
-                            add_out(A.out4, A.perm, kClasses4, L.P[x] >> 2, cls, 1);
-                            add_out(A.out4, A.perm, kClasses4, L.P[y] >> 2, cls, 1);
-                            add_out(A.out4, A.perm, kClasses4, c, cls, 1);
+                            add4(A, L, L.P[x] >> 2, cls, 1);
+                            add4(A, L, L.P[y] >> 2, cls, 1);
+                            add4(A, L, c, cls, 1);
                             shape[3]++;
                         }
                     }
@@ -668,6 +693,38 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 const bool small_p = p <= 64;
                 if (small_p)
                     for (uint32_t q = lane; q < 3 * 64; q += 64) xacc[q] = 0;
+                // rows above r of the members of A(c), copied into this wave's LDS buffer
+                // (segment u = row of A(c)[u]) when they fit; e is adjacent to x iff it is in
+                // x's row, and the rows are sorted, so a step needs a short LDS search
+                bool staged = false;
+                if (small_p) {
+                    const uint32_t xs = lane < p ? (Ac[lane] >> 2) : 0u;
+                    const uint32_t len = lane < p ? L.pre[xs + 1] - L.pre[xs] : 0u;
+                    uint32_t incl = len;   // inclusive prefix over lanes
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const uint32_t v = __shfl_up(incl, o);
+                        if ((int)lane >= o) incl += v;
+                    }
+                    const uint32_t total = __shfl(incl, 63);
+                    if (total <= kRowStage) {
+                        staged = true;
+                        if (lane < p) rowseg[lane] = incl - len;
+                        if (lane == 0) rowseg[p] = total;
+                        // copy the segments cooperatively: entry j belongs to the segment u with
+                        // rowseg[u] <= j < rowseg[u + 1]; the row start of A(c)[u] comes from lane u
+                        const uint32_t mysrc = lane < p ? L.lo[xs] : 0u;
+                        for (uint32_t jb = 0; jb < total; jb += 64) {   // all lanes take part in the shuffle
+                            const uint32_t j = jb + lane;
+                            uint32_t lo3 = 0, hi3 = p;   // last u with rowseg[u] <= j
+                            while (hi3 - lo3 > 1) {
+                                const uint32_t mid = (lo3 + hi3) >> 1;
+                                if (rowseg[mid] <= j) lo3 = mid; else hi3 = mid;
+                            }
+                            const uint32_t src = __shfl(mysrc, (int)lo3);
+                            if (j < total) rowstage[j] = A.adj[src + (j - rowseg[lo3])];
+                        }
+                    }
+                }
                 for (uint32_t base = A.off[c]; base < chi; base += 64) {
                     const uint32_t tt = base + lane;
                     uint32_t ee = 0;
@@ -677,9 +734,8 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                         ev = (ee >> 2) > r && find_slot_f(L, d, ee >> 2) < 0;
                     }
                     if (!__ballot(ev)) continue;
+                    if (lane == 0) { work[1]++; work[2] += p; }
                     const uint32_t e = ee >> 2, ce = ee & 3u;
-                    RowCache rcache;
-                    row_cache_load(rcache, A.off, A.adj, e, ev);
                     unsigned long long acc1 = 0, acc2 = 0, acc3 = 0;
                     for (uint32_t ub = 0; ub < p; ub += 64) {
                         const uint32_t areg = ub + lane < p ? Ac[ub + lane] : 0u;
@@ -687,9 +743,21 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                         for (uint32_t uu = 0; uu < ucnt; uu++) {
                             const uint32_t ex = __shfl(areg, (int)uu);
                             const uint32_t x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
-                            // x has no depth-2 neighbour besides c: e cannot touch it
-                            const bool xonly = (L.pre[x + 1] - L.pre[x]) - L.lcnt[x] <= 1u;
-                            const bool valid = ev && (xonly || row_cache_bits_from(rcache, A.adj, L.P[x] >> 2) == 0u);
+                            bool valid = ev;
+                            if (valid && (L.pre[x + 1] - L.pre[x]) - L.lcnt[x] > 1u) {
+                                // x has depth-2 neighbours besides c: is e one of them?
+                                if (staged) {
+                                    uint32_t lo2 = rowseg[ub + uu], hi2 = rowseg[ub + uu + 1];
+                                    const uint32_t key = e << 2;
+                                    while (lo2 < hi2) {
+                                        const uint32_t mid = (lo2 + hi2) >> 1;
+                                        if (rowstage[mid] < key) lo2 = mid + 1; else hi2 = mid;
+                                    }
+                                    valid = !(lo2 < rowseg[ub + uu + 1] && (rowstage[lo2] >> 2) == e);
+                                } else {
+                                    valid = arc_bits(A.off, A.adj, L.P[x] >> 2, e) == 0u;
+                                }
+                            }
                             const unsigned long long inc = valid ? (1ull << (21u * (xc - 1u))) : 0ull;
                             if (rx == 1) acc1 += inc; else if (rx == 2) acc2 += inc; else acc3 += inc;
                             const uint32_t n1 = __popcll(__ballot(valid && ce == 1u));
@@ -711,7 +779,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                             const unsigned long long w = q < 3 ? acc1 : (q < 6 ? acc2 : acc3);
                             const uint32_t cnt = (uint32_t)(w >> (21u * (q % 3))) & F21;
                             if (cnt)
-                                add_out(A.out4, A.perm, kClasses4, e,
+                                add4(A, L, e,
                                         L.t4[motif_index4(q / 3 + 1, 0u, 0u, q % 3 + 1, 0u, ce)], cnt);
                         }
                     }
@@ -736,7 +804,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     const uint32_t code = q < 27 ? motif_index4(rx, z, 0u, 0u, xc, 0u)      // (2,1,0): z = ry
                                                  : motif_index4(rx, 0u, 0u, xc, 0u, z);    // (1,1,1): z = ce
                     const uint32_t cls = L.t4[code];
-                    add_out(A.out4, A.perm, kClasses4, c, cls, cnt);
+                    add4(A, L, c, cls, cnt);
                     atomicAdd(&L.root4[cls], (unsigned long long)cnt);
                 } else {
                     add_out(A.out3, A.perm, kClasses3, c, q - 54, cnt);
@@ -761,7 +829,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 const uint32_t cnt = L.cnt[q];
                 if (!cnt) continue;
                 const uint32_t s = q % d, g = q / d, rx = g / 3 + 1, xc = g % 3 + 1;
-                add_out(A.out4, A.perm, kClasses4, L.P[s] >> 2,
+                add4(A, L, L.P[s] >> 2,
                         L.t4[motif_index4(rx, L.P[s] & 3u, 0u, 0u, xc, 0u)], cnt);
             }
         }
@@ -868,9 +936,9 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                                 slow[4]++;
                                 const uint32_t cls = L.t4[motif_index4(ra, 0u, 0u, ac, ac2, cc)];
                                 atomicAdd(&L.root4[cls], 1ull);
-                                add_out(A.out4, A.perm, kClasses4, va, cls, 1);
-                                add_out(A.out4, A.perm, kClasses4, c1, cls, 1);
-                                add_out(A.out4, A.perm, kClasses4, c2, cls, 1);
+                                add4(A, L, va, cls, 1);
+                                add4(A, L, c1, cls, 1);
+                                add4(A, L, c2, cls, 1);
                             }
                             shape[4] += valid ? 1 : 0;
                         }
@@ -895,7 +963,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     if (!cnt) continue;
                     const uint32_t u = q / 3, g = q % 3;
                     const uint32_t eu = wlist[u];
-                    add_out(A.out4, A.perm, kClasses4, eu >> 2,
+                    add4(A, L, eu >> 2,
                             L.t4[motif_index4(ra, 0u, 0u, eu & 3u, g + 1, 0u)], cnt);
                 }
                 if (lane < 6) {
@@ -905,7 +973,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                         uint32_t x, y;
                         sig_pair(lane, x, y);
                         const uint32_t cls = L.t4[motif_index4(ra, 0u, 0u, x, y, 0u)];
-                        add_out(A.out4, A.perm, kClasses4, va, cls, cnt);
+                        add4(A, L, va, cls, cnt);
                         atomicAdd(&L.root4[cls], (unsigned long long)cnt);
                     }
                 }
@@ -927,11 +995,11 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             const uint32_t s = q % d, g = q / d, rs = L.P[s] & 3u, vs = L.P[s] >> 2;
             const uint32_t a = spar[g * PMAX + s], b = s111[g * PMAX + s];
             if (a) {   // (2,1,0) parent: g = (xc-1)*3 + (ry-1)
-                add_out(A.out4, A.perm, kClasses4, vs, L.t4[motif_index4(rs, g % 3 + 1, 0u, 0u, g / 3 + 1, 0u)], a);
+                add4(A, L, vs, L.t4[motif_index4(rs, g % 3 + 1, 0u, 0u, g / 3 + 1, 0u)], a);
                 spar[g * PMAX + s] = 0;
             }
             if (b) {   // (1,1,1) depth-1: g = (xc-1)*3 + (ce-1)
-                add_out(A.out4, A.perm, kClasses4, vs, L.t4[motif_index4(rs, 0u, 0u, g / 3 + 1, 0u, g % 3 + 1)], b);
+                add4(A, L, vs, L.t4[motif_index4(rs, 0u, 0u, g / 3 + 1, 0u, g % 3 + 1)], b);
                 s111[g * PMAX + s] = 0;
             }
             if (g < 3) {
@@ -953,6 +1021,11 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             shape[k] = 0;
             slow[k] = 0;
         }
+        if (lane == 0)
+            for (int k = 0; k < 4; k++) {
+                if (work[k]) atomicAdd(&L.stat[28 + k], (unsigned long long)work[k]);
+                work[k] = 0;
+            }
         __syncthreads();
         HUB_PHASE(7);
     }
@@ -998,6 +1071,20 @@ __global__ void k_split_bins(const uint32_t* __restrict__ roots, const uint32_t*
         if (!is_hub[i]) light[i - pos[i]] = roots[i];
 }
 
+// out4[perm[v]][class of slot s] += comp[v][s], and comp is cleared for the next launch
+__global__ void k_fold_compact(unsigned long long* __restrict__ comp, const uint8_t* __restrict__ slotcls,
+                               const int32_t* __restrict__ perm, int64_t n, unsigned long long* __restrict__ out4) {
+    const int64_t total = n * kCompact4;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long c = comp[i];
+        if (!c) continue;
+        const int64_t v = i / kCompact4;
+        const int s = (int)(i - v * kCompact4);
+        out4[(size_t)perm[v] * kClasses4 + slotcls[s]] += c;
+        comp[i] = 0;
+    }
+}
+
 __global__ void k_zero_u32(unsigned* p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
@@ -1029,6 +1116,8 @@ void free_hub(vdmc_graph_s* g) {
     (void)hipFree(g->hubs);
     (void)hipFree(g->hub_scratch);
     (void)hipFree(g->hub_queue);
+    (void)hipFree(g->hub_comp);
+    g->hub_comp = nullptr;
     g->light = g->hubs = nullptr;
     g->hub_scratch = nullptr;
     g->hub_queue = nullptr;
@@ -1125,6 +1214,11 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         o = (o + 63) & ~(size_t)63;
         g->hub_scratch_bytes = o * sizeof(uint32_t) * (size_t)wgs;
         VDMC_HIP(hipMalloc(&g->hub_scratch, g->hub_scratch_bytes));
+        const size_t comp_bytes = (size_t)std::max<int64_t>(g->n, 1) * kCompact4 * sizeof(unsigned long long);
+        VDMC_HIP(hipMalloc(&g->hub_comp, comp_bytes));
+        VDMC_HIP(hipMemsetAsync(g->hub_comp, 0, comp_bytes, st));   // cleared again by every fold
+        VDMC_HIP(hipStreamSynchronize(st));
+        g->hub_scratch_bytes += comp_bytes;
         g->hub_layout[0] = o;
         g->hub_layout[1] = o_spar;
         g->hub_layout[2] = o_s111;
@@ -1177,10 +1271,19 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.o_llist = g->hub_layout[10];
     a.o_hash = g->hub_layout[11];
     a.hash_bits = (uint32_t)g->hub_layout[12];
+    a.comp = (unsigned long long*)g->hub_comp;
+    a.slot4 = t.slot4;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 4);
     const int wgs = hub_workgroups();
     hipLaunchKernelGGL(k_hub, dim3(wgs), dim3(HT), 0, st, a);
     VDMC_HIP(hipGetLastError());
+    if (k4) {
+        const int64_t cells = g->n * kCompact4;
+        const unsigned blocks = (unsigned)std::min<int64_t>((cells + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_fold_compact, dim3(blocks), dim3(256), 0, st, (unsigned long long*)g->hub_comp,
+                           t.slotcls, g->perm, g->n, (unsigned long long*)out4);
+        VDMC_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace vdmc

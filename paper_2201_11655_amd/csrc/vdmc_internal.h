@@ -74,9 +74,16 @@ inline int num_classes(int k) { return k == 3 ? kClasses3 : (k == 4 ? kClasses4 
 
 // Device-resident class tables of the current device: code -> class id (0xFF =
 // disconnected).  Built on first use by a kernel; cached per device.
+// Classes of 4-sets whose induced subgraph is a tree (the 15 directed 4-path and the
+// 10 directed 3-star classes): the only classes the aggregated credits of the hub
+// kernel produce; they get compact slots.
+constexpr int kCompact4 = 25;
+
 struct ClassTables {
     const uint8_t* t3;   // 64 entries
     const uint8_t* t4;   // 4096 entries
+    const uint8_t* slot4;     // 199 entries: class -> compact slot or 0xFF
+    const uint8_t* slotcls;   // kCompact4 entries: compact slot -> class
     std::vector<uint8_t> host3, host4;
     std::vector<uint16_t> codes3, codes4;
 };
@@ -118,6 +125,7 @@ struct vdmc_graph_s {
     void* hub_scratch = nullptr;
     size_t hub_scratch_bytes = 0;
     unsigned* hub_queue = nullptr;
+    void* hub_comp = nullptr;    // n x kCompact4 uint64 rank-indexed accumulator
     size_t hub_layout[16] = {0};
 };
 
