@@ -7,8 +7,11 @@
 // cursor and runs the same per-root enumeration as the single-graph path, so the
 // counts are bit-identical.  The zeroing kernel and the counting kernel are captured
 // into a HIP graph the first time a batch signature (graphs, outputs, k, launch
-// parameters) is seen and replayed afterwards.  Roots above the hub threshold (if
-// any) are counted by the hub kernel of their graph after the batched launch.
+// parameters) is seen and replayed afterwards.  Graphs of at most kSmallGraphN
+// vertices are instead taken whole by one workgroup each, which keeps the graph's
+// per-vertex counters in LDS and adds them to the output once.  Roots above the hub
+// threshold of the other graphs are counted by the hub kernel of their graph after
+// the batched launch.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -30,6 +33,9 @@ struct Plan {
     uint2* d_table = nullptr;
     unsigned long long* d_cursor = nullptr;
     unsigned long long nentries = 0;
+    uint32_t* d_small = nullptr;       // graphs counted one workgroup per graph
+    std::vector<char> is_small;
+    uint32_t nsmall = 0, nmax_small = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t captured_for = nullptr;
@@ -40,6 +46,7 @@ struct Plan {
         (void)hipFree(d_nvert);
         (void)hipFree(d_table);
         (void)hipFree(d_cursor);
+        (void)hipFree(d_small);
     }
 };
 
@@ -68,6 +75,12 @@ BatchArgs args_of(const Plan& p) {
     b.tile = p.cfg.tile;
     b.t3 = t.t3;
     b.t4 = t.t4;
+    b.small = p.d_small;
+    b.nsmall = p.nsmall;
+    b.nmax_small = p.nmax_small;
+    b.gcursor = reinterpret_cast<unsigned*>(p.d_cursor + 1);
+    b.slot4 = t.slot4;
+    b.slotcls = t.slotcls;
     return b;
 }
 
@@ -81,21 +94,34 @@ Plan* build_plan(const vdmc_graph* gs, int num, int k, uint64_t* const* outs, co
         std::vector<uint64_t> nvert(num);
         std::vector<const uint32_t*> lists(num);
         std::vector<unsigned long long> counts(num), offsets(num);
+        std::vector<uint32_t> small;
         unsigned long long total = 0;
+        p->is_small.assign(num, 0);
         for (int i = 0; i < num; i++) {
             vdmc_graph_s* g = gs[i];
             p->graphs.push_back(g);
             p->outs.push_back(outs[i]);
+            if (g->n > 0 && g->n <= kSmallGraphN) {   // every root of g, hubs included, in one workgroup
+                p->is_small[i] = 1;
+                small.push_back((uint32_t)i);
+                p->nmax_small = std::max(p->nmax_small, (uint32_t)g->n);
+            }
             views[i] = GraphView{g->off, g->adj, g->split, g->perm,
                                  k == 3 ? (unsigned long long*)outs[i] : nullptr,
                                  k == 4 ? (unsigned long long*)outs[i] : nullptr, g->stats};
             nvert[i] = (uint64_t)g->n;
             lists[i] = g->light;
-            counts[i] = (unsigned long long)g->nlight;
+            counts[i] = p->is_small[i] ? 0ull : (unsigned long long)g->nlight;
             offsets[i] = total;
-            total += (unsigned long long)g->nlight;
+            total += counts[i];
         }
         p->nentries = total;
+        p->nsmall = (uint32_t)small.size();
+        if (!small.empty()) {
+            VDMC_HIP(hipMalloc(&p->d_small, sizeof(uint32_t) * small.size()));
+            VDMC_HIP(hipMemcpyAsync(p->d_small, small.data(), sizeof(uint32_t) * small.size(),
+                                    hipMemcpyHostToDevice, st));
+        }
         VDMC_HIP(hipMalloc(&p->d_graphs, sizeof(GraphView) * std::max(num, 1)));
         VDMC_HIP(hipMalloc(&p->d_nvert, sizeof(uint64_t) * std::max(num, 1)));
         VDMC_HIP(hipMalloc(&p->d_table, sizeof(uint2) * std::max<unsigned long long>(total, 1)));
@@ -164,7 +190,8 @@ void run_plan(Plan& p, hipStream_t st, bool use_graph) {
     // hub roots of large graphs, if any, after the batched light roots
     for (int i = 0; i < num; i++) {
         vdmc_graph_s* g = p.graphs[i];
-        if (g->nhub > 0) launch_hub(g, k3, k4, k3 ? p.outs[i] : nullptr, k4 ? p.outs[i] : nullptr, st);
+        if (g->nhub > 0 && !p.is_small[i])
+            launch_hub(g, k3, k4, k3 ? p.outs[i] : nullptr, k4 ? p.outs[i] : nullptr, st);
     }
 }
 

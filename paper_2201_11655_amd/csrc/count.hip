@@ -58,6 +58,50 @@ __device__ __forceinline__ void credit(unsigned long long* out, const int32_t* p
     if (cls < (uint32_t)C) atomicAdd(&out[(size_t)perm[v] * C + cls], 1ull);   // 0xFF never credited
 }
 
+// Where the per-set increments go.  GlobalSink: one 64-bit atomic per credited vertex
+// into the caller's output.  LdsSink (small graphs, one workgroup per graph): counters
+// of the whole graph in LDS (all 13 classes for k = 3; the 25 tree classes for k = 4,
+// other classes straight to the output), added to the output once per graph.  32-bit
+// counters cannot overflow there: a vertex of a graph with n <= 1024 lies in at most
+// C(1023, 3) < 2^28 four-vertex sets.
+struct GlobalSink {
+    __device__ __forceinline__ void c3(const GraphView& gv, uint32_t v, uint32_t cls) const {
+        credit(gv.out3, gv.perm, kClasses3, v, cls);
+    }
+    __device__ __forceinline__ void c4(const GraphView& gv, uint32_t v, uint32_t cls) const {
+        credit(gv.out4, gv.perm, kClasses4, v, cls);
+    }
+    __device__ __forceinline__ void root3(const GraphView& gv, uint32_t r, uint32_t cls, unsigned long long c) const {
+        atomicAdd(&gv.out3[(size_t)gv.perm[r] * kClasses3 + cls], c);
+    }
+    __device__ __forceinline__ void root4(const GraphView& gv, uint32_t r, uint32_t cls, unsigned long long c) const {
+        atomicAdd(&gv.out4[(size_t)gv.perm[r] * kClasses4 + cls], c);
+    }
+};
+
+struct LdsSink {
+    uint32_t* cnt3;        // n x 13, by rank
+    uint32_t* cnt4;        // n x kCompact4, by rank
+    const uint8_t* slot4;  // class -> compact slot
+    __device__ __forceinline__ void c3(const GraphView&, uint32_t v, uint32_t cls) const {
+        if (cls < (uint32_t)kClasses3) atomicAdd(&cnt3[v * kClasses3 + cls], 1u);
+    }
+    __device__ __forceinline__ void c4(const GraphView& gv, uint32_t v, uint32_t cls) const {
+        if (cls >= (uint32_t)kClasses4) return;
+        const uint32_t sl = slot4[cls];
+        if (sl != 0xFFu) atomicAdd(&cnt4[v * kCompact4 + sl], 1u);
+        else credit(gv.out4, gv.perm, kClasses4, v, cls);
+    }
+    __device__ __forceinline__ void root3(const GraphView&, uint32_t r, uint32_t cls, unsigned long long c) const {
+        atomicAdd(&cnt3[r * kClasses3 + cls], (uint32_t)c);
+    }
+    __device__ __forceinline__ void root4(const GraphView& gv, uint32_t r, uint32_t cls, unsigned long long c) const {
+        const uint32_t sl = slot4[cls];
+        if (sl != 0xFFu) atomicAdd(&cnt4[r * kCompact4 + sl], (uint32_t)c);
+        else atomicAdd(&gv.out4[(size_t)gv.perm[r] * kClasses4 + cls], c);
+    }
+};
+
 template <uint32_t STAGE>
 struct RootLds {
     uint32_t P[STAGE];
@@ -69,9 +113,9 @@ struct RootLds {
 
 // All k-sets whose lowest-rank vertex is r, by one workgroup of BS threads, every set
 // credited to its non-root members with one atomic each (the root is summed in LDS).
-template <int BS, uint32_t STAGE, bool K3, bool K4>
+template <int BS, uint32_t STAGE, bool K3, bool K4, class Sink>
 __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8_t* t4, uint32_t r,
-                             RootLds<STAGE>& S, unsigned long long* shape) {
+                             RootLds<STAGE>& S, unsigned long long* shape, const Sink& sink) {
     const uint32_t tid = threadIdx.x;
     const uint32_t s = gv.split[r];
     const uint32_t d = gv.off[r + 1] - s;
@@ -99,8 +143,8 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
         if (K3) {
             const uint32_t cls = t3[motif_index3(ra, rb, ab)];
             if (cls < kClasses3) atomicAdd(&S.root3[cls], 1ull);
-            credit(gv.out3, gv.perm, kClasses3, va, cls);
-            credit(gv.out3, gv.perm, kClasses3, vb, cls);
+            sink.c3(gv, va, cls);
+            sink.c3(gv, vb, cls);
             shape[0]++;
         }
         if (K4) {
@@ -111,9 +155,9 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                 const uint32_t bc = arc_bits(gv.off, gv.adj, vb, vc);
                 const uint32_t cls = t4[motif_index4(ra, rb, rc, ab, ac, bc)];
                 if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
-                credit(gv.out4, gv.perm, kClasses4, va, cls);
-                credit(gv.out4, gv.perm, kClasses4, vb, cls);
-                credit(gv.out4, gv.perm, kClasses4, vc, cls);
+                sink.c4(gv, va, cls);
+                sink.c4(gv, vb, cls);
+                sink.c4(gv, vc, cls);
                 shape[2]++;
             }
         }
@@ -151,8 +195,8 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
             if (K3) {
                 const uint32_t cls = t3[motif_index3(ra, 0u, ac)];
                 if (cls < kClasses3) atomicAdd(&S.root3[cls], 1ull);
-                credit(gv.out3, gv.perm, kClasses3, va, cls);
-                credit(gv.out3, gv.perm, kClasses3, vc, cls);
+                sink.c3(gv, va, cls);
+                sink.c3(gv, vc, cls);
                 shape[1]++;
             }
             if (K4) {
@@ -166,9 +210,9 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                     const uint32_t ab = arc_bits(gv.off, gv.adj, va, vb);
                     const uint32_t cls = t4[motif_index4(ra, rb, 0u, ab, ac, bc)];
                     if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
-                    credit(gv.out4, gv.perm, kClasses4, va, cls);
-                    credit(gv.out4, gv.perm, kClasses4, vb, cls);
-                    credit(gv.out4, gv.perm, kClasses4, vc, cls);
+                    sink.c4(gv, va, cls);
+                    sink.c4(gv, vb, cls);
+                    sink.c4(gv, vc, cls);
                     shape[3]++;
                 }
                 // (1,2,0): a second depth-2 child c' > c of a
@@ -180,9 +224,9 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                     const uint32_t cc2 = arc_bits(gv.off, gv.adj, vc, vc2);
                     const uint32_t cls = t4[motif_index4(ra, 0u, 0u, ac, e2 & 3u, cc2)];
                     if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
-                    credit(gv.out4, gv.perm, kClasses4, va, cls);
-                    credit(gv.out4, gv.perm, kClasses4, vc, cls);
-                    credit(gv.out4, gv.perm, kClasses4, vc2, cls);
+                    sink.c4(gv, va, cls);
+                    sink.c4(gv, vc, cls);
+                    sink.c4(gv, vc2, cls);
                     shape[4]++;
                 }
                 // (1,1,1): path r - a - c - e, e not adjacent to r nor to a
@@ -194,22 +238,21 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                     if (arc_bits(gv.off, gv.adj, va, ve)) continue; // e adjacent to a: depth 2
                     const uint32_t cls = t4[motif_index4(ra, 0u, 0u, ac, 0u, e3 & 3u)];
                     if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
-                    credit(gv.out4, gv.perm, kClasses4, va, cls);
-                    credit(gv.out4, gv.perm, kClasses4, vc, cls);
-                    credit(gv.out4, gv.perm, kClasses4, ve, cls);
+                    sink.c4(gv, va, cls);
+                    sink.c4(gv, vc, cls);
+                    sink.c4(gv, ve, cls);
                     shape[5]++;
                 }
             }
         }
     }
     __syncthreads();
-    const size_t row = (size_t)gv.perm[r];
     if (K3)
         for (uint32_t i = tid; i < kClasses3; i += BS)
-            if (S.root3[i]) atomicAdd(&gv.out3[row * kClasses3 + i], S.root3[i]);
+            if (S.root3[i]) sink.root3(gv, r, i, S.root3[i]);
     if (K4)
         for (uint32_t i = tid; i < kClasses4; i += BS)
-            if (S.root4[i]) atomicAdd(&gv.out4[row * kClasses4 + i], S.root4[i]);
+            if (S.root4[i]) sink.root4(gv, r, i, S.root4[i]);
 }
 
 template <bool K3, bool K4>
@@ -220,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_count_roots(Args a) {
     for (int64_t ri = blockIdx.x; ri < a.nroots; ri += gridDim.x) {
         const uint32_t r = a.roots[ri];
         if (r < a.rank_lo || r >= a.rank_hi) continue;   // uniform across the workgroup
-        process_root<kThreads, kStage, K3, K4>(gv, a.t3, a.t4, r, S, shape);
+        process_root<kThreads, kStage, K3, K4>(gv, a.t3, a.t4, r, S, shape, GlobalSink());
     }
     for (int s = 0; s < kShapes; s++)
         if (shape[s]) atomicAdd(&a.stats[s], shape[s]);
@@ -249,12 +292,54 @@ __global__ __launch_bounds__(BS) void k_count_batch(BatchArgs b) {
                         if (shape[s]) { atomicAdd(&b.graphs[cur_graph].stats[s], shape[s]); shape[s] = 0; }
                 cur_graph = (int)ent.x;
             }
-            process_root<BS, STAGE, K3, K4>(b.graphs[ent.x], b.t3, b.t4, ent.y, S, shape);
+            process_root<BS, STAGE, K3, K4>(b.graphs[ent.x], b.t3, b.t4, ent.y, S, shape, GlobalSink());
         }
     }
     if (cur_graph >= 0)
         for (int s = 0; s < kShapes; s++)
             if (shape[s]) atomicAdd(&b.graphs[cur_graph].stats[s], shape[s]);
+}
+
+// Small graphs: one workgroup per graph (taken from a device cursor), the whole
+// graph's counters in LDS, every root of the graph enumerated by the workgroup.
+template <int BS, bool K3, bool K4>
+__global__ __launch_bounds__(BS) void k_batch_graph(BatchArgs b) {
+    extern __shared__ uint32_t dyn[];   // K3: nmax x 13 counters, then K4: nmax x 25
+    __shared__ RootLds<256> S;
+    __shared__ uint8_t slot4[kClasses4 + 1];
+    __shared__ unsigned gidx;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < kClasses4; i += BS) slot4[i] = b.slot4[i];
+    uint32_t* cnt3 = dyn;
+    uint32_t* cnt4 = dyn + (K3 ? b.nmax_small * kClasses3 : 0);
+    const LdsSink sink{cnt3, cnt4, slot4};
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) gidx = atomicAdd(b.gcursor, 1u);
+        __syncthreads();
+        if (gidx >= b.nsmall) break;
+        const uint32_t gi = b.small[gidx];
+        const GraphView gv = b.graphs[gi];
+        const uint32_t n = (uint32_t)b.nvert[gi];
+        if (K3)
+            for (uint32_t i = tid; i < n * kClasses3; i += BS) cnt3[i] = 0;
+        if (K4)
+            for (uint32_t i = tid; i < n * kCompact4; i += BS) cnt4[i] = 0;
+        unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
+        for (uint32_t r = 0; r < n; r++)
+            if (gv.split[r] < gv.off[r + 1]) process_root<BS, 256, K3, K4>(gv, b.t3, b.t4, r, S, shape, sink);
+        __syncthreads();
+        if (K3)
+            for (uint32_t i = tid; i < n * kClasses3; i += BS)
+                if (cnt3[i]) atomicAdd(&gv.out3[(size_t)gv.perm[i / kClasses3] * kClasses3 + i % kClasses3],
+                                       (unsigned long long)cnt3[i]);
+        if (K4)
+            for (uint32_t i = tid; i < n * kCompact4; i += BS)
+                if (cnt4[i]) atomicAdd(&gv.out4[(size_t)gv.perm[i / kCompact4] * kClasses4 + b.slotcls[i % kCompact4]],
+                                       (unsigned long long)cnt4[i]);
+        for (int s = 0; s < kShapes; s++)
+            if (shape[s]) atomicAdd(&gv.stats[s], shape[s]);
+    }
 }
 
 // zero every graph's output(s) and shape counters; one workgroup per graph
@@ -266,7 +351,10 @@ __global__ void k_batch_zero(BatchArgs b, int k3, int k4) {
     if (k4)
         for (size_t i = threadIdx.x; i < n * kClasses4; i += blockDim.x) g.out4[i] = 0;
     for (int i = threadIdx.x; i < kStatSlots; i += blockDim.x) g.stats[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *b.cursor = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *b.cursor = 0;
+        *b.gcursor = 0;
+    }
 }
 
 __global__ void k_fill(unsigned long long* p, size_t n, unsigned long long v) {
@@ -288,6 +376,17 @@ void launch_batch(const BatchArgs& b, int variant, int k3, int k4, int num_graph
     hipLaunchKernelGGL(k_batch_zero, dim3(num_graphs), dim3(256), 0, st, b, k3, k4);
     VDMC_HIP(hipGetLastError());
     const unsigned grid = (unsigned)(ncu * wgs_per_cu);
+    if (b.nsmall > 0) {
+        VDMC_REQUIRE(k3 != k4, VDMC_ERR_INVALID_ARG, "a batch counts one k");
+        VDMC_REQUIRE(b.nmax_small <= (uint32_t)kSmallGraphN, VDMC_ERR_INVALID_ARG, "small graph too large");
+        const size_t dyn = (size_t)b.nmax_small * (k3 ? kClasses3 : kCompact4) * sizeof(uint32_t);
+        const unsigned ggrid = (unsigned)std::min<uint64_t>(b.nsmall, (uint64_t)ncu * 4);
+        auto kern = k3 ? (void (*)(BatchArgs))k_batch_graph<256, true, false> : (void (*)(BatchArgs))k_batch_graph<256, false, true>;
+        VDMC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        hipLaunchKernelGGL(kern, dim3(ggrid), dim3(256), dyn, st, b);
+        VDMC_HIP(hipGetLastError());
+    }
+    if (b.nentries == 0) return;
 #define VDMC_BATCH_LAUNCH(BS, STG)                                                                           \
     do {                                                                                                    \
         if (k3 && k4) hipLaunchKernelGGL((k_count_batch<BS, STG, true, true>), dim3(grid), dim3(BS), 0, st, b); \

@@ -150,8 +150,16 @@ struct BatchArgs {
     unsigned long long tile;        // roots taken per cursor step
     const uint8_t* t3;
     const uint8_t* t4;
+    // small graphs counted one workgroup per graph
+    const uint32_t* small;          // device array of graph indices
+    uint32_t nsmall;
+    uint32_t nmax_small;            // largest n among them (LDS sizing)
+    unsigned* gcursor;              // device graph cursor, zeroed inside the launch
+    const uint8_t* slot4;
+    const uint8_t* slotcls;
 };
 constexpr int kBatchVariants = 3;   // 64, 128, 256 threads per root
+constexpr int64_t kSmallGraphN = 1024;   // graphs up to this size: one workgroup per graph
 struct TuneChoice {
     int variant = 0;      // threads per root: 64, 128, 256
     int wgs_per_cu = 8;   // persistent workgroups per compute unit

@@ -60,6 +60,26 @@ def test_batch_equals_oracle(v, small_batch, k):
                 assert (_np(o) == want).all(), f"replay {rep} graph n={g.n}"
 
 
+@pytest.mark.parametrize("k", [3, 4])
+def test_batch_small_graph_edge_cases(v, k):
+    # graphs taken whole by one workgroup: no arcs, one vertex, the largest size taken
+    # that way (1024), a dense graph whose roots exceed the hub threshold, and one just
+    # above the size limit (counted root by root)
+    import torch
+    graphs = [gg.er_directed(1, 0.0, (61, 0)), gg.er_directed(7, 0.0, (61, 1)),
+              gg.er_directed(1024, 6.0 / 1023, (61, 2)), gg.er_directed(200, 0.15, (61, 3)),
+              gg.er_directed(1025, 5.0 / 1024, (61, 4)), gg.er_directed(3, 0.9, (61, 5))]
+    _say(f"batch edge cases k={k} n={[g.n for g in graphs]}")
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        outs = v.count_batch(Gs, k, stream=stream)
+        stream.synchronize()
+    for g, o in zip(graphs, outs):
+        want, _ = oracle.count(g.n, g.src, g.dst, k)
+        assert (_np(o) == want).all(), f"graph n={g.n} arcs={g.m}"
+
+
 def test_batch_with_hub_graph_and_single_path(v, small_batch):
     import torch
     graphs = small_batch[:8] + [gg.config_graph("chunglu_2000")] + small_batch[8:12]
