@@ -117,8 +117,11 @@ def main():
     if only4:
         out3 = torch.zeros((1, 13), dtype=torch.int64, device="cuda")
 
+    hub_ms_steps = []
+
     def step(timing=None):
         G = v.Graph(g.n, dsrc, ddst, stream=stream)
+        hub_ms = 0.0
         if timing is not None:
             timing[0].record(stream)
         if only4:
@@ -129,11 +132,13 @@ def main():
                 v.count_range(G, 4, out4, bounds[i], bounds[i + 1], accumulate=i > 0, stream=stream)
                 if timing is not None:
                     stream.synchronize()
+                    hub_ms += max(0.0, v.kernel_times(G)[1])
                     log(f"[bench] ranks [{bounds[i]}, {bounds[i + 1]}) done")
         else:
             v.count34(G, out3, out4, stream=stream)
         if timing is not None:
             timing[1].record(stream)
+            hub_ms_steps.append(hub_ms)
         return G
 
     for w in range(args.warmup):
@@ -153,8 +158,14 @@ def main():
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     log(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step, count call {kernel_ms:.2f} ms")
 
+    if not only4:   # the hub kernel's own events, recorded by the library in every timed step
+        hub_ms_steps = [v.kernel_times(Gk)[1] for Gk in graphs]
     G = graphs[-1]
     sc = v.shape_counts(G)
+    pc = v.profile_counters(G)
+    hub_ms = float(np.mean(hub_ms_steps))
+    T3_hub = int(pc[32]) + int(pc[33])
+    T4_hub = int(pc[34] + pc[35] + pc[36] + pc[37])
     c3 = out3.sum(dim=0).cpu().numpy()
     c4 = out4.sum(dim=0).cpu().numpy()
     T3 = int(c3.sum()) // 3
@@ -163,11 +174,13 @@ def main():
     assert only4 or sc["(1,1)"] + sc["(1,2)"] == T3, "k=3 shape counts disagree with the column sums"
     assert sc["(3,0,0)"] + sc["(2,1,0)"] + sc["(1,2,0)"] + sc["(1,1,1)"] == T4, "k=4 shapes disagree"
 
-    # Roofline of the count kernel: every k-set costs at least its index assembly
-    # (one placement per vertex pair), one class lookup and one increment per member:
-    # k=4: 6 + 1 + 4 = 11 integer ops; k=3: 3 + 1 + 3 = 7.
-    alg_ops = 11.0 * T4 + 7.0 * T3
-    achieved_tops = alg_ops / (kernel_ms * 1e-3) / 1e12
+    # Roofline of the dominant kernel (the hub kernel): every k-set costs at least its
+    # index assembly (one placement per vertex pair), one class lookup and one increment
+    # per member: k=4: 6 + 1 + 4 = 11 integer ops; k=3: 3 + 1 + 3 = 7.  Achieved = those
+    # ops over the sets the hub kernel enumerated, per hub-kernel second (HIP events
+    # recorded by the library on the count's stream around the launch, every timed step).
+    alg_ops = 11.0 * T4_hub + 7.0 * T3_hub
+    achieved_tops = alg_ops / (hub_ms * 1e-3) / 1e12 if hub_ms > 0 else 0.0
     # compulsory HBM bytes: CSR read once + both outputs written once
     csr_bytes = 4.0 * (g.n + 1) + 4.0 * 2 * G.pairs
     out_bytes = 8.0 * g.n * (13 + 199)
@@ -190,7 +203,8 @@ def main():
         "count_call_ms": kernel_ms,
         "sets3_per_s": T3 / (ms_step * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": hub_traffic(args.workload),
+                     "kernel": "k_hub", "kernel_ms": hub_ms, "sets4": T4_hub, "sets3": T3_hub,
                      "ops_per_set": {"k4": 11, "k3": 7},
                      "hbm_compulsory_frac": (csr_bytes + out_bytes) / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
@@ -202,14 +216,46 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+# HBM bytes per hub-kernel launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
+# this bench (KiB per dispatch), scaled by the readings of a 1 GiB copy (FETCH_SIZE
+# reads half of the copied bytes: factor 2.0; WRITE_SIZE factor 1.0).  Valid only for
+# the kernel sources they were taken with: any change to them reports null.
+HUB_COUNTER_SOURCES = ["paper_2201_11655_amd/csrc/count_hub.hip", "paper_2201_11655_amd/csrc/vdmc_internal.h",
+                       "paper_2201_11655_amd/csrc/motif_device.h"]
+HUB_COUNTERS = {     # workload -> counters of one hub-kernel dispatch (profiles/k_hub_chunglu_1M_hbm_counters.md)
+    "chunglu": {"sources_sha256": "7cb00c4835b25113ef97804c65643de587a7b0cfe044e32b1a4b6127169e37a6",
+                "fetch_kib": 5962706251.0, "write_kib": 1272024246.3},
+}
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+
+
+def hub_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in HUB_COUNTER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def hub_traffic(workload):
+    rec = HUB_COUNTERS.get(workload)
+    if rec is None or rec["sources_sha256"] != hub_sources_sha256():
+        return None
+    return 1024.0 * (FETCH_FACTOR * rec["fetch_kib"] + WRITE_FACTOR * rec["write_kib"])
+
+
 def calibrate_copy(torch):
-    """A plain 1 GiB device-to-device copy: reference reading for the HBM byte counters."""
+    """Reference readings for the HBM byte counters: a plain 1 GiB device-to-device copy,
+    then an elementwise kernel that reads 1 GiB and writes 1 GiB (b = 2 a)."""
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     b.copy_(a)
     torch.cuda.synchronize()
-    log("[bench] calibration copy of 1 GiB done")
+    torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    log("[bench] calibration copy and scale of 1 GiB done")
 
 
 def _alu_roofline(T4, T3, ms):

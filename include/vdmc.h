@@ -150,8 +150,15 @@ vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
  * the direct (unaggregated) crediting path per shape; entries 24-27 the wave time spent
  * inside the depth-2 groups on (2,1,0) sets, (2,1,0) sets with both parents, (1,1,1)
  * paths and the rest (100 MHz ticks summed over waves); entries 28-31 work counts: depth-2
- * groups, (1,1,1) chunks, (1,1,1) steps, (2,1,0) chunk steps.  Copies min(n, 32) entries. */
+ * groups, (1,1,1) chunks, (1,1,1) steps, (2,1,0) chunk steps; entries 32-37 the part of
+ * the shape counts enumerated by the hub kernel.  Copies min(n, 40) entries. */
 vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n);
+
+/* Device time of the kernels of the last count call on this graph, from events recorded
+ * on the count's stream around each launch (host; waits for those events):
+ * ms_out[0] the per-set kernel over the light roots, ms_out[1] the hub kernel; -1 for a
+ * kernel that the call did not launch.  ms_out: 2 floats, caller-owned. */
+vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out);
 
 /*
  * Batched counts: num graphs, one k for all, outs[i] a DEVICE buffer of

@@ -13,8 +13,10 @@ from .vdmc import (  # noqa: F401
     count34,
     count_range,
     count_batch,
+    kernel_times,
     load,
     num_classes,
+    profile_counters,
     shape_counts,
     tune,
 )

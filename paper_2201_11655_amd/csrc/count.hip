@@ -422,8 +422,12 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
     }
     const uint32_t lo = (uint32_t)std::max<int64_t>(0, rank_lo);
     const uint32_t hi = (uint32_t)std::min<int64_t>(g->n, rank_hi);
+    g->timed_light = g->timed_hub = false;
     if (lo >= hi) return;
+    if (!g->ev[0])
+        for (auto& e : g->ev) VDMC_HIP(hipEventCreate(&e));
     if (g->nlight > 0) {
+        VDMC_HIP(hipEventRecord(g->ev[0], st));
         Args a;
         a.off = g->off;
         a.adj = g->adj;
@@ -446,8 +450,11 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
         else
             hipLaunchKernelGGL((k_count_roots<false, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
         VDMC_HIP(hipGetLastError());
+        VDMC_HIP(hipEventRecord(g->ev[1], st));
+        g->timed_light = true;
     }
-    launch_hub(g, k3, k4, out3, out4, st, lo, hi);
+    launch_hub(g, k3, k4, out3, out4, st, lo, hi, g->ev + 2);
+    g->timed_hub = g->nhub > 0;
 }
 
 }  // namespace vdmc
@@ -483,6 +490,22 @@ vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n) {
         VDMC_HIP(hipDeviceSynchronize());
         const int k = n < vdmc::kStatSlots ? n : vdmc::kStatSlots;
         VDMC_HIP(hipMemcpy(counters, g->stats, k * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    });
+}
+
+vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out) {
+    return vdmc::guarded([&] {
+        VDMC_REQUIRE(g != nullptr && ms_out != nullptr, VDMC_ERR_INVALID_ARG, "bad argument");
+        VDMC_HIP(hipSetDevice(g->device));
+        ms_out[0] = ms_out[1] = -1.0f;
+        if (g->timed_light) {
+            VDMC_HIP(hipEventSynchronize(g->ev[1]));
+            VDMC_HIP(hipEventElapsedTime(&ms_out[0], g->ev[0], g->ev[1]));
+        }
+        if (g->timed_hub) {
+            VDMC_HIP(hipEventSynchronize(g->ev[3]));
+            VDMC_HIP(hipEventElapsedTime(&ms_out[1], g->ev[2], g->ev[3]));
+        }
     });
 }
 

@@ -166,7 +166,7 @@ struct Lds {
     uint32_t rowbuf[NW][PMAX / 16];            // per-wave 2-bit row of one slot's local neighbours
     unsigned long long root4[kClasses4];
     unsigned long long root3[kClasses3];
-    unsigned long long stat[kStatSlots];       // shape counts, phase ticks, direct-path counts
+    unsigned long long stat[kLdsStatSlots];    // shape counts, phase ticks, direct-path counts
     uint16_t lcnt[PMAX];                       // local (in-N+(r)) degree of every slot
     uint8_t t4[4096];
     uint8_t t3[64];
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     for (uint32_t i = tid; i < NW * (PMAX / 16); i += HT) (&L.rowbuf[0][0])[i] = 0;
     for (size_t i = tid; i < (size_t)NW * 2 * hsize; i += HT) W[A.o_hash + i] = 0;
     for (uint32_t i = tid; i < NW * (27 + 27 + kClasses3); i += HT) (&L.cw[0][0])[i] = 0;
-    for (uint32_t i = tid; i < kStatSlots; i += HT) L.stat[i] = 0;
+    for (uint32_t i = tid; i < kLdsStatSlots; i += HT) L.stat[i] = 0;
 
     for (;;) {
         __syncthreads();
@@ -1031,8 +1031,11 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     }
 #undef HUB_PHASE
     __syncthreads();
-    for (uint32_t k = tid; k < kStatSlots; k += HT)
-        if (L.stat[k]) atomicAdd(&A.stats[k], L.stat[k]);
+    for (uint32_t k = tid; k < kLdsStatSlots; k += HT)
+        if (L.stat[k]) {
+            atomicAdd(&A.stats[k], L.stat[k]);
+            if (k < kShapes) atomicAdd(&A.stats[32 + k], L.stat[k]);
+        }
 }
 
 // ----------------------------------------------------------------------------- binning
@@ -1237,7 +1240,7 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
 }
 
 void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st,
-                uint32_t rank_lo, uint32_t rank_hi) {
+                uint32_t rank_lo, uint32_t rank_hi, const hipEvent_t* around) {
     if (g->nhub == 0) return;
     const ClassTables& t = class_tables();
     HubArgs a;
@@ -1275,8 +1278,10 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.slot4 = t.slot4;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 4);
     const int wgs = hub_workgroups();
+    if (around) VDMC_HIP(hipEventRecord(around[0], st));
     hipLaunchKernelGGL(k_hub, dim3(wgs), dim3(HT), 0, st, a);
     VDMC_HIP(hipGetLastError());
+    if (around) VDMC_HIP(hipEventRecord(around[1], st));
     if (k4) {
         const int64_t cells = g->n * kCompact4;
         const unsigned blocks = (unsigned)std::min<int64_t>((cells + 255) / 256, 65536);

@@ -351,6 +351,11 @@ static void free_graph_arrays(vdmc_graph_s* g) {
     (void)hipFree(g->perm);
     (void)hipFree(g->roots);
     (void)hipFree(g->stats);
+    for (auto& e : g->ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
     g->off = g->adj = g->split = g->roots = nullptr;
     g->perm = nullptr;
     g->stats = nullptr;

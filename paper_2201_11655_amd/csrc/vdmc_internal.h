@@ -68,7 +68,9 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 constexpr int kClasses3 = 13;
 constexpr int kClasses4 = 199;
 constexpr int kShapes = 6;   // (1,1) (1,2) | (3,0,0) (2,1,0) (1,2,0) (1,1,1)
-constexpr int kStatSlots = 32;   // shapes, then profile counters (cycles per phase, direct-path sets)
+constexpr int kStatSlots = 40;      // shapes, profile counters (cycles per phase, direct-path sets,
+                                    // work counts), then 32-37: sets enumerated by the hub kernel
+constexpr int kLdsStatSlots = 32;   // the part the hub kernel gathers in LDS
 
 inline int num_classes(int k) { return k == 3 ? kClasses3 : (k == 4 ? kClasses4 : -1); }
 
@@ -127,6 +129,10 @@ struct vdmc_graph_s {
     unsigned* hub_queue = nullptr;
     void* hub_comp = nullptr;    // n x kCompact4 uint64 rank-indexed accumulator
     size_t hub_layout[16] = {0};
+    // timing of the last count call: [0,1] around the per-set kernel, [2,3] around the
+    // hub kernel (created at the first count)
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool timed_light = false, timed_hub = false;
 };
 
 namespace vdmc {
@@ -178,7 +184,7 @@ void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t stream);
 // hub path (count_hub.hip)
 void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t stream);
 void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t stream,
-                uint32_t rank_lo = 0, uint32_t rank_hi = 0xFFFFFFFFu);
+                uint32_t rank_lo = 0, uint32_t rank_hi = 0xFFFFFFFFu, const hipEvent_t* around = nullptr);
 int hub_min_default();
 void free_hub(vdmc_graph_s* g);
 }  // namespace vdmc

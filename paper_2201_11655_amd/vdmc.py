@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libvdmc.so")
 SYMBOLS = [
     "vdmc_last_error", "vdmc_num_classes", "vdmc_class_codes", "vdmc_class_table",
     "vdmc_build_graph", "vdmc_graph_info", "vdmc_graph_export", "vdmc_free_graph",
-    "vdmc_count", "vdmc_count_range", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters", "vdmc_count_batch", "vdmc_tune",
+    "vdmc_count", "vdmc_count_range", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters",
+    "vdmc_kernel_times", "vdmc_count_batch", "vdmc_tune",
     "vdmc_serve_create", "vdmc_serve_submit", "vdmc_serve_poll", "vdmc_serve_wait",
     "vdmc_serve_stats", "vdmc_serve_destroy",
 ]
@@ -64,6 +65,7 @@ def load():
         "vdmc_count_range": ([p, i32, p, i64, i64, u32, p], i32),
         "vdmc_shape_counts": ([p, p], i32),
         "vdmc_profile_counters": ([p, p, i32], i32),
+        "vdmc_kernel_times": ([p, p], i32),
         "vdmc_count_batch": ([p, i32, i32, p, p], i32),
         "vdmc_tune": ([p, i32, i32, ctypes.c_char_p], i32),
         "vdmc_serve_create": ([p, p], i32),
@@ -225,9 +227,16 @@ def shape_counts(g: Graph) -> dict:
 
 def profile_counters(g: Graph) -> np.ndarray:
     """Diagnostic counters of the last count (see vdmc_profile_counters in vdmc.h)."""
-    out = np.zeros(32, np.uint64)
-    _check(load().vdmc_profile_counters(g.handle, _np_ptr(out), 32))
+    out = np.zeros(40, np.uint64)
+    _check(load().vdmc_profile_counters(g.handle, _np_ptr(out), 40))
     return out
+
+
+def kernel_times(g: Graph) -> tuple:
+    """(per-set kernel ms, hub kernel ms) of the last count call on g; -1 if not launched."""
+    out = np.zeros(2, np.float32)
+    _check(load().vdmc_kernel_times(g.handle, _np_ptr(out)))
+    return float(out[0]), float(out[1])
 
 
 def count_batch(graphs, k: int, outs=None, stream=None):

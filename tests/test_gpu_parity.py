@@ -216,3 +216,22 @@ def test_count_range_slices_sum_to_count(v):
         assert (_np(out) == full).all()
         with pytest.raises(v.VdmcError):
             v.count_range(G, k, out, 5, 2, accumulate=False)
+
+
+# --------------------------------------------------------------------------- diagnostics
+
+def test_kernel_times_and_hub_share(v):
+    # the per-kernel event times and the hub kernel's share of the shape counts
+    g = gg.config_graph("chunglu_2000")
+    _say(f"kernel times n={g.n}")
+    G = v.Graph(g.n, g.src, g.dst)
+    v.count34(G)
+    light_ms, hub_ms = v.kernel_times(G)
+    pc = v.profile_counters(G)
+    assert light_ms >= 0.0 and hub_ms >= 0.0
+    assert all(pc[32 + s] <= pc[s] for s in range(6))
+    assert pc[32:38].sum() > 0   # chunglu_2000 has hub roots
+    G2 = v.Graph(5, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
+    v.count(G2, 3)
+    lt, ht = v.kernel_times(G2)
+    assert ht == -1.0 and lt >= 0.0   # no hub root: the hub kernel is not launched
