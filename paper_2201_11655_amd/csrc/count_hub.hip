@@ -145,7 +145,6 @@ __device__ __forceinline__ int wave_next(unsigned* sTask) {
 
 // ----------------------------------------------------------------------------- kernel
 
-constexpr uint32_t kRowStage = 224;   // per-wave LDS entries for the rows of A(c)'s members
 
 // P membership filter: one bit per hash bucket of a rank; a clear bit proves absence.
 constexpr uint32_t kBloomWords = 1024;   // 32768 bits
@@ -160,9 +159,6 @@ struct Lds {
     uint32_t scan[HT];
     uint32_t cw[NW][27 + 27 + kClasses3];      // per-wave group accumulators (c and r credits)
     uint32_t inA[NW][PMAX / 32];               // per-wave membership bitmap of A(c)
-    uint16_t xacc[NW][64 * 3];                 // per-wave (1,1,1) depth-1 credits by A(c) position
-    uint32_t rowstage[NW][kRowStage];          // per-wave rows of A(c)'s members (sorted entries)
-    uint16_t rowseg[NW][66];                   // per-wave segment bounds in rowstage
     uint32_t rowbuf[NW][PMAX / 16];            // per-wave 2-bit row of one slot's local neighbours
     unsigned long long root4[kClasses4];
     unsigned long long root3[kClasses3];
@@ -590,9 +586,6 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         const uint32_t ngroups = L.groups;
         uint32_t* cw = L.cw[wid];
         uint32_t* inA = L.inA[wid];
-        uint16_t* xacc = L.xacc[wid];
-        uint32_t* rowstage = L.rowstage[wid];
-        uint16_t* rowseg = L.rowseg[wid];
         uint32_t* rowbuf = L.rowbuf[wid];
         for (int t = wave_next(&L.task); t < (int)ngroups; t = wave_next(&L.task)) {
             const uint32_t c = grp[4 * t + 0];
@@ -689,42 +682,26 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     }
                 }
                 tg2 = wall_clock64();
-                // (1,1,1): paths r - x - c - e, e above r, not in N(r), not adjacent to x
-                const bool small_p = p <= 64;
-                if (small_p)
-                    for (uint32_t q = lane; q < 3 * 64; q += 64) xacc[q] = 0;
-                // rows above r of the members of A(c), copied into this wave's LDS buffer
-                // (segment u = row of A(c)[u]) when they fit; e is adjacent to x iff it is in
-                // x's row, and the rows are sorted, so a step needs a short LDS search
-                bool staged = false;
-                if (small_p) {
-                    const uint32_t xs = lane < p ? (Ac[lane] >> 2) : 0u;
-                    const uint32_t len = lane < p ? L.pre[xs + 1] - L.pre[xs] : 0u;
-                    uint32_t incl = len;   // inclusive prefix over lanes
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const uint32_t v = __shfl_up(incl, o);
-                        if ((int)lane >= o) incl += v;
-                    }
-                    const uint32_t total = __shfl(incl, 63);
-                    if (total <= kRowStage) {
-                        staged = true;
-                        if (lane < p) rowseg[lane] = incl - len;
-                        if (lane == 0) rowseg[p] = total;
-                        // copy the segments cooperatively: entry j belongs to the segment u with
-                        // rowseg[u] <= j < rowseg[u + 1]; the row start of A(c)[u] comes from lane u
-                        const uint32_t mysrc = lane < p ? L.lo[xs] : 0u;
-                        for (uint32_t jb = 0; jb < total; jb += 64) {   // all lanes take part in the shuffle
-                            const uint32_t j = jb + lane;
-                            uint32_t lo3 = 0, hi3 = p;   // last u with rowseg[u] <= j
-                            while (hi3 - lo3 > 1) {
-                                const uint32_t mid = (lo3 + hi3) >> 1;
-                                if (rowseg[mid] <= j) lo3 = mid; else hi3 = mid;
-                            }
-                            const uint32_t src = __shfl(mysrc, (int)lo3);
-                            if (j < total) rowstage[j] = A.adj[src + (j - rowseg[lo3])];
-                        }
+                // (1,1,1): paths r - x - c - e, e above r, not in N(r), not adjacent to x.
+                // Counted by complement: here every x in A(c) is paired with every valid e
+                // of c's row, adjacent to x or not.  A pair with e adjacent to x is a (1,2,0)
+                // set of x whose two depth-2 vertices c, e are adjacent; the (1,2,0) phase
+                // enumerates those and takes both orders (c, e) and (e, c) back out.  So a
+                // chunk of c's row needs no test against the parents' rows.
+                // hist*: per rx, the number of parents with each xc (21-bit fields)
+                unsigned long long hist1 = 0, hist2 = 0, hist3 = 0;
+                for (uint32_t ub = 0; ub < p; ub += 64) {
+                    const uint32_t u = ub + lane;
+                    const uint32_t ex = u < p ? Ac[u] : 0u;
+                    const uint32_t code = u < p ? ((L.P[ex >> 2] & 3u) - 1u) * 3u + ((ex & 3u) - 1u) : 9u;
+#pragma unroll
+                    for (uint32_t q = 0; q < 9; q++) {
+                        const unsigned long long nq = (unsigned long long)__popcll(__ballot(code == q));
+                        const unsigned long long inc = nq << (21u * (q % 3u));
+                        if (q < 3) hist1 += inc; else if (q < 6) hist2 += inc; else hist3 += inc;
                     }
                 }
+                uint32_t T1 = 0, T2 = 0, T3 = 0;   // valid e of c's row by ce (wave-uniform)
                 for (uint32_t base = A.off[c]; base < chi; base += 64) {
                     const uint32_t tt = base + lane;
                     uint32_t ee = 0;
@@ -736,47 +713,13 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     if (!__ballot(ev)) continue;
                     if (lane == 0) { work[1]++; work[2] += p; }
                     const uint32_t e = ee >> 2, ce = ee & 3u;
-                    unsigned long long acc1 = 0, acc2 = 0, acc3 = 0;
-                    for (uint32_t ub = 0; ub < p; ub += 64) {
-                        const uint32_t areg = ub + lane < p ? Ac[ub + lane] : 0u;
-                        const uint32_t ucnt = min(64u, p - ub);
-                        for (uint32_t uu = 0; uu < ucnt; uu++) {
-                            const uint32_t ex = __shfl(areg, (int)uu);
-                            const uint32_t x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
-                            bool valid = ev;
-                            if (valid && (L.pre[x + 1] - L.pre[x]) - L.lcnt[x] > 1u) {
-                                // x has depth-2 neighbours besides c: is e one of them?
-                                if (staged) {
-                                    uint32_t lo2 = rowseg[ub + uu], hi2 = rowseg[ub + uu + 1];
-                                    const uint32_t key = e << 2;
-                                    while (lo2 < hi2) {
-                                        const uint32_t mid = (lo2 + hi2) >> 1;
-                                        if (rowstage[mid] < key) lo2 = mid + 1; else hi2 = mid;
-                                    }
-                                    valid = !(lo2 < rowseg[ub + uu + 1] && (rowstage[lo2] >> 2) == e);
-                                } else {
-                                    valid = arc_bits(A.off, A.adj, L.P[x] >> 2, e) == 0u;
-                                }
-                            }
-                            const unsigned long long inc = valid ? (1ull << (21u * (xc - 1u))) : 0ull;
-                            if (rx == 1) acc1 += inc; else if (rx == 2) acc2 += inc; else acc3 += inc;
-                            const uint32_t n1 = __popcll(__ballot(valid && ce == 1u));
-                            const uint32_t n2 = __popcll(__ballot(valid && ce == 2u));
-                            const uint32_t n3 = __popcll(__ballot(valid && ce == 3u));
-                            if (lane < 3) {
-                                const uint32_t nk = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
-                                if (nk) {
-                                    if (small_p) xacc[uu * 3 + lane] += nk;
-                                    else atomicAdd(&s111[((xc - 1) * 3 + lane) * PMAX + x], nk);
-                                    cw[27 + (rx - 1) * 9 + (xc - 1) * 3 + lane] += nk;
-                                }
-                            }
-                            shape[5] += valid ? 1 : 0;
-                        }
-                    }
+                    T1 += __popcll(__ballot(ev && ce == 1u));
+                    T2 += __popcll(__ballot(ev && ce == 2u));
+                    T3 += __popcll(__ballot(ev && ce == 3u));
                     if (ev) {
+                        shape[5] += p;
                         for (uint32_t q = 0; q < 9; q++) {
-                            const unsigned long long w = q < 3 ? acc1 : (q < 6 ? acc2 : acc3);
+                            const unsigned long long w = q < 3 ? hist1 : (q < 6 ? hist2 : hist3);
                             const uint32_t cnt = (uint32_t)(w >> (21u * (q % 3))) & F21;
                             if (cnt)
                                 add4(A, L, e,
@@ -784,14 +727,20 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                         }
                     }
                 }
-                if (small_p) {
-                    for (uint32_t q = lane; q < 3 * p; q += 64) {
-                        const uint32_t cnt = xacc[q];
-                        if (!cnt) continue;
-                        const uint32_t ex = Ac[q / 3], x = ex >> 2, xc = ex & 3u;
-                        atomicAdd(&s111[((xc - 1) * 3 + q % 3) * PMAX + x], cnt);
+                // every parent x is on T_k of these paths with ce = k (x's and c's credits)
+                if (T1 | T2 | T3)
+                    for (uint32_t u = lane; u < p; u += 64) {
+                        const uint32_t ex = Ac[u], x = ex >> 2, xc = (ex & 3u) - 1u;
+                        const uint32_t code = ((L.P[x] & 3u) - 1u) * 3u + xc;
+                        auto put = [&](uint32_t k, uint32_t h) {
+                            if (!h) return;
+                            atomicAdd(&s111[(xc * 3 + k) * PMAX + x], h);
+                            atomicAdd(&cw[27 + code * 3 + k], h);
+                        };
+                        put(0, T1);
+                        put(1, T2);
+                        put(2, T3);
                     }
-                }
             }
             tg3 = A.k4 ? wall_clock64() : tg0;
             // flush the group's depth-2 vertex (and the root, which is in every one of its sets)
@@ -939,6 +888,22 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                                 add4(A, L, va, cls, 1);
                                 add4(A, L, c1, cls, 1);
                                 add4(A, L, c2, cls, 1);
+                                // c1 and c2 are adjacent: the groups of c1 and c2 counted the
+                                // paths r-a-c1-c2 and r-a-c2-c1 as (1,1,1) sets; take them out
+                                // (every counter here is modular and ends non-negative)
+                                const uint32_t cr = swap_arc_bits(cc);
+                                const uint32_t p1 = L.t4[motif_index4(ra, 0u, 0u, ac, 0u, cc)];
+                                const uint32_t p2 = L.t4[motif_index4(ra, 0u, 0u, ac2, 0u, cr)];
+                                const unsigned long long m1 = ~0ull;
+                                atomicAdd(&L.root4[p1], m1);
+                                atomicAdd(&L.root4[p2], m1);
+                                atomicAdd(&s111[((ac - 1u) * 3u + (cc - 1u)) * PMAX + a], 0xFFFFFFFFu);
+                                atomicAdd(&s111[((ac2 - 1u) * 3u + (cr - 1u)) * PMAX + a], 0xFFFFFFFFu);
+                                add4(A, L, c1, p1, m1);
+                                add4(A, L, c2, p1, m1);
+                                add4(A, L, c1, p2, m1);
+                                add4(A, L, c2, p2, m1);
+                                shape[5] -= 2;
                             }
                             shape[4] += valid ? 1 : 0;
                         }
@@ -1011,7 +976,10 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             }
         }
         for (int k = 0; k < kShapes; k++) {
-            unsigned long long v = shape[k], w = slow[k];
+            // per-lane counts are 32-bit and can be negative for (1,1,1) (its complement
+            // corrections land on other lanes): sign-extend before the wave sum
+            unsigned long long v = k == 5 ? (unsigned long long)(long long)(int32_t)shape[k] : shape[k];
+            unsigned long long w = slow[k];
             for (int o = 32; o > 0; o >>= 1) {
                 v += __shfl_down(v, o);
                 w += __shfl_down(w, o);
