@@ -150,7 +150,7 @@ vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
  * the direct (unaggregated) crediting path per shape; entries 24-27 the wave time spent
  * inside the depth-2 groups on (2,1,0) sets, (2,1,0) sets with both parents, (1,1,1)
  * paths and the rest (100 MHz ticks summed over waves); entries 28-31 work counts: depth-2
- * groups, (1,1,1) chunks, (1,1,1) steps, (2,1,0) chunk steps; entries 32-37 the part of
+ * groups, (1,1,1) chunks, (1,1,1) parent-chunk pairs, (2,1,0) local-list steps; entries 32-37 the part of
  * the shape counts enumerated by the hub kernel.  Copies min(n, 40) entries. */
 vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n);
 

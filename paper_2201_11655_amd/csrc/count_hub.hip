@@ -159,7 +159,7 @@ struct Lds {
     uint32_t scan[HT];
     uint32_t cw[NW][27 + 27 + kClasses3];      // per-wave group accumulators (c and r credits)
     uint32_t inA[NW][PMAX / 32];               // per-wave membership bitmap of A(c)
-    uint32_t rowbuf[NW][PMAX / 16];            // per-wave 2-bit row of one slot's local neighbours
+    uint32_t gall[9];                          // (2,1,0) sets per parent code, credited to every slot
     unsigned long long root4[kClasses4];
     unsigned long long root3[kClasses3];
     unsigned long long stat[kLdsStatSlots];    // shape counts, phase ticks, direct-path counts
@@ -266,7 +266,6 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     for (uint32_t i = tid; i < 9 * PMAX; i += HT) { spar[i] = 0; s111[i] = 0; }
     for (uint32_t i = tid; i < 3 * PMAX; i += HT) s3x[i] = 0;
     for (uint32_t i = tid; i < NW * (PMAX / 32); i += HT) (&L.inA[0][0])[i] = 0;
-    for (uint32_t i = tid; i < NW * (PMAX / 16); i += HT) (&L.rowbuf[0][0])[i] = 0;
     for (size_t i = tid; i < (size_t)NW * 2 * hsize; i += HT) W[A.o_hash + i] = 0;
     for (uint32_t i = tid; i < NW * (27 + 27 + kClasses3); i += HT) (&L.cw[0][0])[i] = 0;
     for (uint32_t i = tid; i < kLdsStatSlots; i += HT) L.stat[i] = 0;
@@ -299,6 +298,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         for (uint32_t i = tid; i < kClasses4; i += HT) L.root4[i] = 0;
         for (uint32_t i = tid; i < kClasses3; i += HT) L.root3[i] = 0;
         for (uint32_t i = tid; i < 9 * d; i += HT) L.cnt[i] = 0;
+        if (tid < 9) L.gall[tid] = 0;
         const size_t mwords = (size_t)d * nch * 4;
         for (size_t i = tid; i < mwords; i += HT) M[i] = 0;
         if (tid == 0) { L.groups = 0; L.alloc = 0; L.task = 0; }
@@ -584,9 +584,15 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
 
         // ---------------------------------------------------------------- groups: (2,1,0), (1,1,1), k=3 (1,2)
         const uint32_t ngroups = L.groups;
+        uint32_t nr1 = 0, nr2 = 0, nr3 = 0;   // slots by their arc code with r (wave-uniform)
+        for (uint32_t yb = 0; yb < d; yb += 64) {
+            const uint32_t ry = yb + lane < d ? (L.P[yb + lane] & 3u) : 0u;
+            nr1 += __popcll(__ballot(ry == 1u));
+            nr2 += __popcll(__ballot(ry == 2u));
+            nr3 += __popcll(__ballot(ry == 3u));
+        }
         uint32_t* cw = L.cw[wid];
         uint32_t* inA = L.inA[wid];
-        uint32_t* rowbuf = L.rowbuf[wid];
         for (int t = wave_next(&L.task); t < (int)ngroups; t = wave_next(&L.task)) {
             const uint32_t c = grp[4 * t + 0];
             const uint32_t p = grp[4 * t + 1];
@@ -610,34 +616,59 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             const unsigned long long tg0 = wall_clock64();
             unsigned long long tg1 = tg0, tg2 = tg0, tg3 = tg0;
             if (A.k4) {
-                // (2,1,0), y outside A(c): the parent x runs outside, the chunks of y inside
+                // per code g = (rx - 1) * 3 + (xc - 1) of the parents: hist[rx] packs, per xc,
+                // the number of parents in A(c) (21-bit fields); ha* = parents per rx
+                unsigned long long hist1 = 0, hist2 = 0, hist3 = 0;
+                for (uint32_t ub = 0; ub < p; ub += 64) {
+                    const uint32_t u = ub + lane;
+                    const uint32_t ex = u < p ? Ac[u] : 0u;
+                    const uint32_t code = u < p ? ((L.P[ex >> 2] & 3u) - 1u) * 3u + ((ex & 3u) - 1u) : 9u;
+#pragma unroll
+                    for (uint32_t q = 0; q < 9; q++) {
+                        const unsigned long long nq = (unsigned long long)__popcll(__ballot(code == q));
+                        const unsigned long long inc = nq << (21u * (q % 3u));
+                        if (q < 3) hist1 += inc; else if (q < 6) hist2 += inc; else hist3 += inc;
+                    }
+                }
+                auto field = [&](uint32_t q) -> uint32_t {
+                    const unsigned long long w = q < 3 ? hist1 : (q < 6 ? hist2 : hist3);
+                    return (uint32_t)(w >> (21u * (q % 3u))) & F21;
+                };
+                const uint32_t ha1 = field(0) + field(1) + field(2);
+                const uint32_t ha2 = field(3) + field(4) + field(5);
+                const uint32_t ha3 = field(6) + field(7) + field(8);
+                // (2,1,0), y outside A(c): for a parent x every slot y not in A(c) makes a set
+                // {r, x, y, c}.  Those with y not adjacent to x (class fixed by rx, xc, ry) are
+                // counted by complement: gall[g] stands for every slot; the slots of A(c) and
+                // x's local neighbours outside A(c) are subtracted from their own counters
+                // (modular; they end non-negative).  x's local neighbours outside A(c) are the
+                // sets with an x-y arc and take the direct path.
                 for (uint32_t ub = 0; ub < p; ub += 64) {
                     const uint32_t areg = ub + lane < p ? Ac[ub + lane] : 0u;
                     const uint32_t ucnt = min(64u, p - ub);
                     for (uint32_t uu = 0; uu < ucnt; uu++) {
                         const uint32_t ex = __shfl(areg, (int)uu);
                         const uint32_t x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
+                        const uint32_t g = (rx - 1u) * 3u + (xc - 1u);
                         const uint32_t xl = L.lcnt[x], xq = L.pre[x];
-                        const bool xloc = xl != 0;
-                        // x's local codes, spread into this wave's 2-bit row buffer
-                        for (uint32_t q = lane; q < xl; q += 64) {
-                            const uint32_t vq = llist[xq + q], sl = vq >> 2;
-                            atomicOr(&rowbuf[sl >> 4], (vq & 3u) << ((sl & 15u) << 1));
-                        }
-                        uint32_t xn1 = 0, xn2 = 0, xn3 = 0;
-                        for (uint32_t ch = 0; ch < nch; ch++) {
-                            const uint32_t y = 64 * ch + lane;
-                            const bool yv = y < d;
-                            const uint32_t ry = yv ? (L.P[y] & 3u) : 0u;
-                            const bool lv = yv && !((inA[y >> 5] >> (y & 31)) & 1u);
-                            const uint32_t xy = (xloc && lv) ? ((rowbuf[y >> 4] >> ((y & 15u) << 1)) & 3u) : 0u;
-                            const bool pure = lv && xy == 0u;
+                        uint32_t n1 = 0, n2 = 0, n3 = 0;   // x's local neighbours outside A(c), by ry
+                        for (uint32_t qb = 0; qb < xl; qb += 64) {
+                            const uint32_t q = qb + lane;
+                            bool out = false;
+                            uint32_t y = 0, xy = 0, ry = 0;
+                            if (q < xl) {
+                                const uint32_t vq = llist[xq + q];
+                                y = vq >> 2;
+                                xy = vq & 3u;
+                                out = !((inA[y >> 5] >> (y & 31)) & 1u);
+                                ry = L.P[y] & 3u;
+                            }
                             if (lane == 0) work[3]++;
-                            if (pure) atomicAdd(&L.cnt[((rx - 1) * 3 + (xc - 1)) * d + y], 1u);
-                            xn1 += __popcll(__ballot(pure && ry == 1u));
-                            xn2 += __popcll(__ballot(pure && ry == 2u));
-                            xn3 += __popcll(__ballot(pure && ry == 3u));
-                            if (lv && !pure) {
+                            n1 += __popcll(__ballot(out && ry == 1u));
+                            n2 += __popcll(__ballot(out && ry == 2u));
+                            n3 += __popcll(__ballot(out && ry == 3u));
+                            if (out) {
+                                atomicAdd(&L.cnt[g * d + y], 0xFFFFFFFFu);
                                 slow[3]++;
                                 const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, 0u)];
                                 atomicAdd(&L.root4[cls], 1ull);
@@ -645,16 +676,26 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                                 add4(A, L, L.P[y] >> 2, cls, 1);
                                 add4(A, L, c, cls, 1);
                             }
-                            shape[3] += lv ? 1 : 0;
                         }
-                        if (lane < 3) {
-                            const uint32_t nk = lane == 0 ? xn1 : (lane == 1 ? xn2 : xn3);
+                        if (lane == 0) {
+                            atomicAdd(&L.gall[g], 1u);
+                            shape[3] += d - p;
+                        }
+                        if (lane < 3) {   // x's sets with a non-adjacent y, by ry
+                            const uint32_t nk = lane == 0 ? nr1 - ha1 - n1 : (lane == 1 ? nr2 - ha2 - n2 : nr3 - ha3 - n3);
                             if (nk) {
                                 atomicAdd(&spar[((xc - 1) * 3 + lane) * PMAX + x], nk);
-                                cw[(rx - 1) * 9 + (xc - 1) * 3 + lane] += nk;
+                                cw[g * 3 + lane] += nk;
                             }
                         }
-                        for (uint32_t q = lane; q < xl; q += 64) rowbuf[(llist[xq + q] >> 2) >> 4] = 0;
+                    }
+                }
+                // A(c)'s own slots are not outside A(c): one set fewer per parent
+                for (uint32_t u = lane; u < p; u += 64) {
+                    const uint32_t y = Ac[u] >> 2;
+                    for (uint32_t q = 0; q < 9; q++) {
+                        const uint32_t h = field(q);
+                        if (h) atomicAdd(&L.cnt[q * d + y], 0u - h);
                     }
                 }
                 tg1 = wall_clock64();
@@ -688,19 +729,6 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 // set of x whose two depth-2 vertices c, e are adjacent; the (1,2,0) phase
                 // enumerates those and takes both orders (c, e) and (e, c) back out.  So a
                 // chunk of c's row needs no test against the parents' rows.
-                // hist*: per rx, the number of parents with each xc (21-bit fields)
-                unsigned long long hist1 = 0, hist2 = 0, hist3 = 0;
-                for (uint32_t ub = 0; ub < p; ub += 64) {
-                    const uint32_t u = ub + lane;
-                    const uint32_t ex = u < p ? Ac[u] : 0u;
-                    const uint32_t code = u < p ? ((L.P[ex >> 2] & 3u) - 1u) * 3u + ((ex & 3u) - 1u) : 9u;
-#pragma unroll
-                    for (uint32_t q = 0; q < 9; q++) {
-                        const unsigned long long nq = (unsigned long long)__popcll(__ballot(code == q));
-                        const unsigned long long inc = nq << (21u * (q % 3u));
-                        if (q < 3) hist1 += inc; else if (q < 6) hist2 += inc; else hist3 += inc;
-                    }
-                }
                 uint32_t T1 = 0, T2 = 0, T3 = 0;   // valid e of c's row by ce (wave-uniform)
                 for (uint32_t base = A.off[c]; base < chi; base += 64) {
                     const uint32_t tt = base + lane;
@@ -775,9 +803,10 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         __syncthreads();
         if (A.k4) {
             for (uint32_t q = tid; q < 9 * d; q += HT) {
-                const uint32_t cnt = L.cnt[q];
+                const uint32_t g = q / d;
+                const uint32_t cnt = L.cnt[q] + L.gall[g];   // (2,1,0) sets with this slot as y
                 if (!cnt) continue;
-                const uint32_t s = q % d, g = q / d, rx = g / 3 + 1, xc = g % 3 + 1;
+                const uint32_t s = q % d, rx = g / 3 + 1, xc = g % 3 + 1;
                 add4(A, L, L.P[s] >> 2,
                         L.t4[motif_index4(rx, L.P[s] & 3u, 0u, 0u, xc, 0u)], cnt);
             }
