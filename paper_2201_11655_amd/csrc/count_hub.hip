@@ -58,6 +58,8 @@ struct HubArgs {
     size_t o_spar, o_s111, o_s3x, o_groups, o_alist, o_wlist, o_c120, o_eflag, o_llist, o_hash;
     uint32_t hash_bits;     // per-wave hash table of 2^hash_bits (key, value) pairs
     uint32_t wl_cap;        // per-wave list capacity (>= max degree)
+    const unsigned long long* ehash;   // the graph's edge hash (edge_code)
+    uint32_t ehash_bits;
 };
 
 // ----------------------------------------------------------------------------- helpers
@@ -147,6 +149,7 @@ __device__ __forceinline__ int wave_next(unsigned* sTask) {
 
 
 // P membership filter: one bit per hash bucket of a rank; a clear bit proves absence.
+constexpr uint32_t kShortRow = 64;     // (1,2,0): rows up to this length are walked
 constexpr uint32_t kBloomWords = 1024;   // 32768 bits
 __device__ __forceinline__ uint32_t bloom_bit(uint32_t x) { return (x * 2654435761u) >> 17; }
 
@@ -816,161 +819,150 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         HUB_PHASE(5);
 
         // ---------------------------------------------------------------- k=4 (1,2,0): two depth-2 children of one slot
+        // The pairs {c1, c2} of a slot's depth-2 children L_a (m of them, m_k with arc code k
+        // from a) are its (1,2,0) sets.  A pair of non-adjacent children has a class fixed by
+        // (ra, ac1, ac2): those are counted from m_1..m_3 by complement.  Only the adjacent
+        // pairs are found and credited one by one (and taken off the complement totals, and
+        // off the (1,1,1) counts of the two groups that also counted them): a child whose row
+        // has at most kShortRow entries walks it and looks each neighbour up in a hash of
+        // L_a's positions; a pair of two longer-row children is looked up in the edge hash.
+        // The list holds the long-row children first, positions [0, kl).
         if (A.k4) {
+            uint32_t* sig6 = cw;   // per-wave adjacent-pair counts by code signature (cw is clear here)
             for (int t = wave_next(&L.task); t < (int)d; t = wave_next(&L.task)) {
                 const uint32_t a = (uint32_t)t;
                 const uint32_t q0 = L.pre[a], q1 = L.pre[a + 1];
-                if (q1 - q0 - L.lcnt[a] < 2) continue;
-                uint32_t m = 0;
+                const uint32_t m = q1 - q0 - L.lcnt[a];
+                if (m < 2) continue;
+                uint32_t kl = 0, ns = 0;
                 for (uint32_t qb = q0; qb < q1; qb += 64) {
                     const uint32_t q = qb + lane;
                     const bool f = q < q1 && eflag[q];
-                    const unsigned long long mk = __ballot(f);
-                    if (f) wlist[m + __popcll(mk & lt_mask)] = A.adj[L.lo[a] + (q - q0)];
-                    m += __popcll(mk);
+                    uint32_t ent = 0;
+                    bool lg = false;
+                    if (f) {
+                        ent = A.adj[L.lo[a] + (q - q0)];
+                        lg = A.off[(ent >> 2) + 1] - A.off[ent >> 2] > kShortRow;
+                    }
+                    const unsigned long long ml = __ballot(f && lg), ms = __ballot(f && !lg);
+                    if (f && lg) wlist[kl + __popcll(ml & lt_mask)] = ent;
+                    if (f && !lg) wlist[m - 1u - (ns + __popcll(ms & lt_mask))] = ent;
+                    kl += __popcll(ml);
+                    ns += __popcll(ms);
+                }
+                uint32_t m1 = 0, m2 = 0, m3 = 0;
+                for (uint32_t ub = 0; ub < m; ub += 64) {
+                    const uint32_t ac = ub + lane < m ? (wlist[ub + lane] & 3u) : 0u;
+                    m1 += __popcll(__ballot(ac == 1u));
+                    m2 += __popcll(__ballot(ac == 2u));
+                    m3 += __popcll(__ballot(ac == 3u));
                 }
                 for (uint32_t q = lane; q < 3 * m; q += 64) c120[q] = 0;
-                // positions of L_a by rank, in this wave's hash table
-                for (uint32_t q = lane; q < m; q += 64) {
-                    const uint32_t key = (wlist[q] >> 2) + 1u;
-                    uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
-                    while (true) {
-                        const uint32_t old = atomicCAS(&hkey[h], 0u, key);
-                        if (old == 0u || old == key) break;
-                        h = (h + 1u) & (hsize - 1u);
+                if (ns > 0)   // positions of L_a by rank, in this wave's hash table
+                    for (uint32_t q = lane; q < m; q += 64) {
+                        const uint32_t key = (wlist[q] >> 2) + 1u;
+                        uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
+                        while (true) {
+                            const uint32_t old = atomicCAS(&hkey[h], 0u, key);
+                            if (old == 0u || old == key) break;
+                            h = (h + 1u) & (hsize - 1u);
+                        }
+                        hval[h] = q;
                     }
-                    hval[h] = q;
-                }
                 __threadfence_block();
                 const uint32_t ra = L.P[a] & 3u, va = L.P[a] >> 2;
-                unsigned long long a6lo = 0, a6mid = 0, a6hi = 0;   // 6 signatures, 32-bit fields
-                for (uint32_t u0 = 1; u0 < m; u0 += 64) {
-                    const uint32_t u = u0 + lane;
-                    const bool uv = u < m;
-                    const uint32_t e2 = uv ? wlist[u] : 0u, c2 = e2 >> 2, ac2 = e2 & 3u;
-                    // neighbours of c2 inside L_a that come before it: up to 4 kept in registers
-                    // as (position << 2 | arc bits seen from that neighbour); more -> search per step
-                    uint32_t nb0 = 0xFFFFFFFFu, nb1 = 0xFFFFFFFFu, nb2 = 0xFFFFFFFFu, nb3 = 0xFFFFFFFFu;
-                    uint32_t nfound = 0;
-                    const uint32_t lo2 = uv ? A.off[c2] : 0u, hi2 = uv ? A.off[c2 + 1] : 0u;
-                    if (hi2 - lo2 > 64) nfound = 5;   // long row: search per step instead
-                    else if (uv) {
-                        for (uint32_t t2 = lo2; t2 < hi2; t2++) {
-                            const uint32_t ew = A.adj[t2];
-                            const uint32_t key = (ew >> 2) + 1u;
-                            uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
-                            uint32_t pos = 0xFFFFFFFFu;
-                            while (true) {
-                                const uint32_t kk = hkey[h];
-                                if (kk == 0u) break;
-                                if (kk == key) { pos = hval[h]; break; }
-                                h = (h + 1u) & (hsize - 1u);
-                            }
-                            if (pos >= u) continue;   // not in L_a, or not before c2
-                            const uint32_t rec = (pos << 2) | swap_arc_bits(ew & 3u);
-                            if (nfound == 0) nb0 = rec; else if (nfound == 1) nb1 = rec;
-                            else if (nfound == 2) nb2 = rec; else if (nfound == 3) nb3 = rec;
-                            nfound++;
+                // one adjacent pair: children at positions ux, uy, cc = arc bits seen from x
+                auto adjacent_pair = [&](uint32_t ux, uint32_t uy, uint32_t ex, uint32_t ey, uint32_t cc) {
+                    const uint32_t cx = ex >> 2, acx = ex & 3u, cy = ey >> 2, acy = ey & 3u;
+                    slow[4]++;
+                    const uint32_t cls = L.t4[motif_index4(ra, 0u, 0u, acx, acy, cc)];
+                    atomicAdd(&L.root4[cls], 1ull);
+                    add4(A, L, va, cls, 1);
+                    add4(A, L, cx, cls, 1);
+                    add4(A, L, cy, cls, 1);
+                    atomicAdd(&sig6[pair_sig(acx, acy)], 1u);
+                    atomicAdd(&c120[ux * 3 + (acy - 1u)], 1u);
+                    atomicAdd(&c120[uy * 3 + (acx - 1u)], 1u);
+                    // the groups of cx and cy counted r-a-cx-cy and r-a-cy-cx as (1,1,1)
+                    // paths; take them out (every counter here is modular, ends non-negative)
+                    const uint32_t cr = swap_arc_bits(cc);
+                    const uint32_t p1 = L.t4[motif_index4(ra, 0u, 0u, acx, 0u, cc)];
+                    const uint32_t p2 = L.t4[motif_index4(ra, 0u, 0u, acy, 0u, cr)];
+                    const unsigned long long m1n = ~0ull;
+                    atomicAdd(&L.root4[p1], m1n);
+                    atomicAdd(&L.root4[p2], m1n);
+                    atomicAdd(&s111[((acx - 1u) * 3u + (cc - 1u)) * PMAX + a], 0xFFFFFFFFu);
+                    atomicAdd(&s111[((acy - 1u) * 3u + (cr - 1u)) * PMAX + a], 0xFFFFFFFFu);
+                    add4(A, L, cx, p1, m1n);
+                    add4(A, L, cy, p1, m1n);
+                    add4(A, L, cx, p2, m1n);
+                    add4(A, L, cy, p2, m1n);
+                    shape[5] -= 2;
+                };
+                // short-row children: walk the row; a short partner is taken by the lower position
+                for (uint32_t u = kl + lane; u < m; u += 64) {
+                    const uint32_t ey = wlist[u], cy = ey >> 2;
+                    const uint32_t hi2 = A.off[cy + 1];
+                    for (uint32_t t2 = A.off[cy]; t2 < hi2; t2++) {
+                        const uint32_t ew = A.adj[t2];
+                        if ((ew >> 2) <= r) continue;   // L_a lies above r
+                        const uint32_t key = (ew >> 2) + 1u;
+                        uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
+                        uint32_t pos = 0xFFFFFFFFu;
+                        while (true) {
+                            const uint32_t kk = hkey[h];
+                            if (kk == 0u) break;
+                            if (kk == key) { pos = hval[h]; break; }
+                            h = (h + 1u) & (hsize - 1u);
                         }
-                    }
-                    const bool many = nfound > 4;
-                    unsigned long long acc = 0;
-                    const uint32_t tmax = min(m, u0 + 64) - 1;
-                    for (uint32_t tb = 0; tb < tmax; tb += 64) {
-                        const uint32_t wreg = tb + lane < tmax ? wlist[tb + lane] : 0u;
-                        const uint32_t tcnt = min(64u, tmax - tb);
-                        for (uint32_t k2 = 0; k2 < tcnt; k2++) {
-                            const uint32_t tt = tb + k2;
-                            const uint32_t e1 = __shfl(wreg, (int)k2), c1 = e1 >> 2, ac = e1 & 3u;
-                            const bool valid = uv && tt < u;
-                            uint32_t cc = 0;
-                            if (valid) {
-                                if (many) {
-                                    cc = arc_bits(A.off, A.adj, c1, c2);
-                                } else if ((nb0 >> 2) == tt) {
-                                    cc = nb0 & 3u;
-                                    nb0 = nb1; nb1 = nb2; nb2 = nb3; nb3 = 0xFFFFFFFFu;
-                                }
-                            }
-                            const bool pure = valid && cc == 0u;
-                            if (pure) acc += 1ull << (21u * (ac - 1u));
-                            const uint32_t n1 = __popcll(__ballot(pure && ac2 == 1u));
-                            const uint32_t n2 = __popcll(__ballot(pure && ac2 == 2u));
-                            const uint32_t n3 = __popcll(__ballot(pure && ac2 == 3u));
-                            if (lane < 3) {
-                                const uint32_t nk = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
-                                if (nk) atomicAdd(&c120[tt * 3 + lane], nk);
-                            }
-                            {
-                                const uint32_t s1 = pair_sig(ac, 1u), s2 = pair_sig(ac, 2u), s3 = pair_sig(ac, 3u);
-                                const unsigned long long v1 = (unsigned long long)n1 << (32u * (s1 & 1u));
-                                const unsigned long long v2 = (unsigned long long)n2 << (32u * (s2 & 1u));
-                                const unsigned long long v3 = (unsigned long long)n3 << (32u * (s3 & 1u));
-                                if (s1 < 2) a6lo += v1; else if (s1 < 4) a6mid += v1; else a6hi += v1;
-                                if (s2 < 2) a6lo += v2; else if (s2 < 4) a6mid += v2; else a6hi += v2;
-                                if (s3 < 2) a6lo += v3; else if (s3 < 4) a6mid += v3; else a6hi += v3;
-                            }
-                            if (valid && !pure) {
-                                slow[4]++;
-                                const uint32_t cls = L.t4[motif_index4(ra, 0u, 0u, ac, ac2, cc)];
-                                atomicAdd(&L.root4[cls], 1ull);
-                                add4(A, L, va, cls, 1);
-                                add4(A, L, c1, cls, 1);
-                                add4(A, L, c2, cls, 1);
-                                // c1 and c2 are adjacent: the groups of c1 and c2 counted the
-                                // paths r-a-c1-c2 and r-a-c2-c1 as (1,1,1) sets; take them out
-                                // (every counter here is modular and ends non-negative)
-                                const uint32_t cr = swap_arc_bits(cc);
-                                const uint32_t p1 = L.t4[motif_index4(ra, 0u, 0u, ac, 0u, cc)];
-                                const uint32_t p2 = L.t4[motif_index4(ra, 0u, 0u, ac2, 0u, cr)];
-                                const unsigned long long m1 = ~0ull;
-                                atomicAdd(&L.root4[p1], m1);
-                                atomicAdd(&L.root4[p2], m1);
-                                atomicAdd(&s111[((ac - 1u) * 3u + (cc - 1u)) * PMAX + a], 0xFFFFFFFFu);
-                                atomicAdd(&s111[((ac2 - 1u) * 3u + (cr - 1u)) * PMAX + a], 0xFFFFFFFFu);
-                                add4(A, L, c1, p1, m1);
-                                add4(A, L, c2, p1, m1);
-                                add4(A, L, c1, p2, m1);
-                                add4(A, L, c2, p2, m1);
-                                shape[5] -= 2;
-                            }
-                            shape[4] += valid ? 1 : 0;
-                        }
-                    }
-                    if (uv) {
-                        for (uint32_t g = 0; g < 3; g++) {
-                            const uint32_t cnt = (uint32_t)(acc >> (21u * g)) & F21;
-                            if (cnt) atomicAdd(&c120[u * 3 + g], cnt);
-                        }
+                        if (pos == 0xFFFFFFFFu || (pos >= kl && pos < u)) continue;
+                        adjacent_pair(u, pos, ey, wlist[pos], ew & 3u);
                     }
                 }
-                // clear this wave's hash table entries
-                for (uint32_t q = lane; q < m; q += 64) {
-                    const uint32_t key = (wlist[q] >> 2) + 1u;
-                    uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
-                    while (hkey[h] != key) h = (h + 1u) & (hsize - 1u);
-                    hkey[h] = 0u;
+                // pairs of long-row children: the edge hash
+                const uint32_t nll = kl * (kl - 1u) / 2u;
+                for (uint32_t q = lane; q < nll; q += 64) {
+                    uint32_t j = (uint32_t)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
+                    while (j * (j - 1u) / 2u > q) j--;
+                    while ((j + 1u) * j / 2u <= q) j++;
+                    const uint32_t i = q - j * (j - 1u) / 2u;
+                    const uint32_t ex = wlist[i], ey = wlist[j];
+                    const uint32_t cc = edge_code(A.ehash, A.ehash_bits, ex >> 2, ey >> 2);
+                    if (cc) adjacent_pair(i, j, ex, ey, cc);
                 }
                 __threadfence_block();
-                for (uint32_t q = lane; q < 3 * m; q += 64) {
-                    const uint32_t cnt = atomicAdd(&c120[q], 0u);
-                    if (!cnt) continue;
-                    const uint32_t u = q / 3, g = q % 3;
-                    const uint32_t eu = wlist[u];
-                    add4(A, L, eu >> 2,
-                            L.t4[motif_index4(ra, 0u, 0u, eu & 3u, g + 1, 0u)], cnt);
+                // every child: its non-adjacent partners by their code k = m_k - own - adjacent
+                for (uint32_t u = lane; u < m; u += 64) {
+                    const uint32_t eu = wlist[u], acu = eu & 3u;
+                    shape[4] += m - 1u - u;
+                    for (uint32_t g = 0; g < 3; g++) {
+                        const uint32_t mk = g == 0 ? m1 : (g == 1 ? m2 : m3);
+                        const uint32_t cnt = mk - (acu == g + 1u ? 1u : 0u) - atomicAdd(&c120[u * 3 + g], 0u);
+                        if (cnt) add4(A, L, eu >> 2, L.t4[motif_index4(ra, 0u, 0u, acu, g + 1u, 0u)], cnt);
+                    }
                 }
+                // a and r: non-adjacent pairs by code signature
                 if (lane < 6) {
-                    const unsigned long long w = lane < 2 ? a6lo : (lane < 4 ? a6mid : a6hi);
-                    const uint32_t cnt = (uint32_t)(w >> (32u * (lane & 1u)));
+                    uint32_t x, y;
+                    sig_pair(lane, x, y);
+                    const uint32_t mx = x == 1 ? m1 : (x == 2 ? m2 : m3), my = y == 1 ? m1 : (y == 2 ? m2 : m3);
+                    const uint32_t total = x == y ? mx * (mx - 1u) / 2u : mx * my;
+                    const uint32_t cnt = total - atomicAdd(&sig6[lane], 0u);
+                    sig6[lane] = 0;
                     if (cnt) {
-                        uint32_t x, y;
-                        sig_pair(lane, x, y);
                         const uint32_t cls = L.t4[motif_index4(ra, 0u, 0u, x, y, 0u)];
                         add4(A, L, va, cls, cnt);
                         atomicAdd(&L.root4[cls], (unsigned long long)cnt);
                     }
                 }
+                if (ns > 0)   // clear this wave's hash table entries
+                    for (uint32_t q = lane; q < m; q += 64) {
+                        const uint32_t key = (wlist[q] >> 2) + 1u;
+                        uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
+                        while (hkey[h] != key) h = (h + 1u) & (hsize - 1u);
+                        hkey[h] = 0u;
+                    }
+                __threadfence_block();
             }
         }
         __threadfence();
@@ -1038,6 +1030,20 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
 // ----------------------------------------------------------------------------- binning
 
 constexpr int BT = 256;
+
+// every pair {u < v} into the edge hash, one thread per row (entries from split[u] on)
+__global__ void k_edge_hash(const uint32_t* __restrict__ off, const uint32_t* __restrict__ split,
+                            const uint32_t* __restrict__ adj, int64_t n, unsigned long long* table, uint32_t bits) {
+    const uint32_t mask = (1u << bits) - 1u;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        for (uint32_t t = split[u]; t < off[u + 1]; t++) {
+            const uint32_t e = adj[t];
+            const unsigned long long key = ((unsigned long long)u << 32) | ((unsigned long long)(e >> 2) << 2);
+            for (uint32_t h = edge_slot(key, bits);; h = (h + 1u) & mask)
+                if (atomicCAS(&table[h], 0ull, key | (e & 3u)) == 0ull) break;
+        }
+    }
+}
 
 __global__ void k_root_work(const uint32_t* __restrict__ off, const uint32_t* __restrict__ adj,
                             const uint32_t* __restrict__ split, const uint32_t* __restrict__ roots, int64_t nroots,
@@ -1117,7 +1123,10 @@ void free_hub(vdmc_graph_s* g) {
     (void)hipFree(g->hub_scratch);
     (void)hipFree(g->hub_queue);
     (void)hipFree(g->hub_comp);
+    (void)hipFree(g->ehash);
     g->hub_comp = nullptr;
+    g->ehash = nullptr;
+    g->ehash_bits = 0;
     g->light = g->hubs = nullptr;
     g->hub_scratch = nullptr;
     g->hub_queue = nullptr;
@@ -1219,6 +1228,22 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         VDMC_HIP(hipMemsetAsync(g->hub_comp, 0, comp_bytes, st));   // cleared again by every fold
         VDMC_HIP(hipStreamSynchronize(st));
         g->hub_scratch_bytes += comp_bytes;
+        // edge hash at load <= 1/4
+        uint32_t eb = 10;
+        while (((size_t)1 << eb) < 4 * (size_t)std::max<int64_t>(g->pairs, 1)) eb++;
+        const size_t eh_bytes = ((size_t)1 << eb) * sizeof(unsigned long long);
+        VDMC_HIP(hipMalloc(&g->ehash, eh_bytes));
+        VDMC_HIP(hipMemsetAsync(g->ehash, 0, eh_bytes, st));
+        {
+            const unsigned blocks = (unsigned)std::min<int64_t>((g->n + BT - 1) / BT, 65536);
+            if (blocks > 0)
+                hipLaunchKernelGGL(k_edge_hash, dim3(blocks), dim3(BT), 0, st, g->off, g->split, g->adj, g->n,
+                                   g->ehash, eb);
+            VDMC_HIP(hipGetLastError());
+        }
+        VDMC_HIP(hipStreamSynchronize(st));
+        g->ehash_bits = eb;
+        g->hub_scratch_bytes += eh_bytes;
         g->hub_layout[0] = o;
         g->hub_layout[1] = o_spar;
         g->hub_layout[2] = o_s111;
@@ -1272,6 +1297,8 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.o_hash = g->hub_layout[11];
     a.hash_bits = (uint32_t)g->hub_layout[12];
     a.comp = (unsigned long long*)g->hub_comp;
+    a.ehash = g->ehash;
+    a.ehash_bits = g->ehash_bits;
     a.slot4 = t.slot4;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 4);
     const int wgs = hub_workgroups();

@@ -37,6 +37,24 @@ __device__ __forceinline__ uint32_t arc_bits(const uint32_t* __restrict__ off,
     return from_u ? (e & 3u) : swap_arc_bits(e & 3u);
 }
 
+// Edge hash: one 64-bit slot per vertex pair {lo < hi} of the graph, holding
+// (lo << 32) | (hi << 2) | arc bits seen from lo; 0 = empty; linear probing.
+__device__ __forceinline__ uint32_t edge_slot(unsigned long long key, uint32_t bits) {
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64u - bits));
+}
+// arc bits of (u, v) seen from u (0 if not adjacent), one probe sequence in the edge hash
+__device__ __forceinline__ uint32_t edge_code(const unsigned long long* __restrict__ table, uint32_t bits,
+                                              uint32_t u, uint32_t v) {
+    const uint32_t lo = u < v ? u : v, hi = u < v ? v : u;
+    const unsigned long long key = ((unsigned long long)lo << 32) | ((unsigned long long)hi << 2);
+    const uint32_t mask = (1u << bits) - 1u;
+    for (uint32_t h = edge_slot(key, bits);; h = (h + 1u) & mask) {
+        const unsigned long long s = table[h];
+        if (s == 0ull) return 0u;
+        if ((s & ~3ull) == key) return u == lo ? (uint32_t)(s & 3u) : swap_arc_bits((uint32_t)(s & 3u));
+    }
+}
+
 // Motif index (Sec. 4.1): the adjacency matrix of the ordered vertices v0..v{k-1},
 // row = source, read row by row without the diagonal, first entry most significant.
 // p_ij (i < j) are the arc bits of (v_i, v_j) seen from v_i: bit 0 sets entry (i,j),

@@ -128,6 +128,8 @@ struct vdmc_graph_s {
     size_t hub_scratch_bytes = 0;
     unsigned* hub_queue = nullptr;
     void* hub_comp = nullptr;    // n x kCompact4 uint64 rank-indexed accumulator
+    unsigned long long* ehash = nullptr;   // edge hash: every pair of the graph, 2^ehash_bits slots
+    uint32_t ehash_bits = 0;
     size_t hub_layout[16] = {0};
     // timing of the last count call: [0,1] around the per-set kernel, [2,3] around the
     // hub kernel (created at the first count)
