@@ -443,142 +443,102 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         HUB_PHASE(3);
 
         // ---------------------------------------------------------------- k=4 (3,0,0): slot triples
-        // task (ch, j): lanes are a = 64 ch + lane < b = j; the step runs over c > b.
-        // a's and b's local lists are walked in slot order, so a step needs no memory load
-        // besides the LDS code of c.
+        // A triple of slots with no arc among its three members (pure) has a class fixed by
+        // the three arc codes with r, so the pure triples are counted from the numbers of
+        // slots per code (per slot s: pairs of other slots by code pair; for r: triples by
+        // code multiset).  The triples with an arc among them are found from the local
+        // arcs: local arc (x, y), x < y, with every third slot z; the triple is taken by its
+        // smallest arc (pairs ordered by (lower slot, higher slot)), so exactly once.  Each
+        // such triple is credited directly and taken off the pure counts of its members
+        // (per-slot counters np[g][s], g = code pair of the other two) and of r.
         if (A.k4) {
-            uint32_t total = 0;
-            for (uint32_t ch = 0; ch < nch; ch++) total += (d > 64 * ch + 1) ? d - 1 - 64 * ch : 0;
-            for (int t = wave_next(&L.task); t < (int)total; t = wave_next(&L.task)) {
-                uint32_t ch = 0, rem = (uint32_t)t;
-                while (true) {
-                    const uint32_t cc = d - 1 - 64 * ch;
-                    if (rem < cc) break;
-                    rem -= cc;
-                    ch++;
-                }
-                const uint32_t j = 64 * ch + 1 + rem;    // b
-                const uint32_t i = 64 * ch + lane;       // a (lane)
-                const bool va = i < j;
-                const uint32_t ra = va ? (L.P[i] & 3u) : 0u, rb = L.P[j] & 3u;
-                // lane walk over a's local neighbours with slot > j
-                uint32_t pa = 0, ea = 0, ab = 0, na = 0xFFFFu;
-                if (va) {
-                    const uint32_t b0 = L.pre[i];
-                    ea = b0 + L.lcnt[i];
-                    uint32_t lo = b0, hi = ea;
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if ((uint32_t)(llist[mid] >> 2) <= j) lo = mid + 1; else hi = mid;
-                    }
-                    pa = lo;
-                    if (pa > b0 && (uint32_t)(llist[pa - 1] >> 2) == j) ab = llist[pa - 1] & 3u;
-                    na = pa < ea ? llist[pa] : 0xFFFFu;
-                }
-                // uniform walk over b's local neighbours with slot > j
-                uint32_t pb, eb, nb;
-                {
-                    const uint32_t b0 = L.pre[j];
-                    eb = b0 + L.lcnt[j];
-                    uint32_t lo = b0, hi = eb;
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if ((uint32_t)(llist[mid] >> 2) <= j) lo = mid + 1; else hi = mid;
-                    }
-                    pb = lo;
-                    nb = pb < eb ? llist[pb] : 0xFFFFu;
-                }
-                const bool base = va && ab == 0;
-                const bool edge = va && ab != 0;
-                const uint32_t bk1 = __popcll(__ballot(base && ra == 1u));
-                const uint32_t bk2 = __popcll(__ballot(base && ra == 2u));
-                const uint32_t bk3 = __popcll(__ballot(base && ra == 3u));
-                unsigned long long acc = 0;     // lane a: fields by rc (pure sets, or edge sets)
-                unsigned long long bacc1 = 0, bacc2 = 0, bacc3 = 0;   // b and r, pure sets: by ra, fields by rc
-                for (uint32_t l = j + 1; l < d; l++) {
-                    const uint32_t rc = L.P[l] & 3u;
-                    uint32_t ac = 0;
-                    if ((na >> 2) == l) {
-                        ac = na & 3u;
-                        ++pa;
-                        na = pa < ea ? llist[pa] : 0xFFFFu;
-                    }
-                    uint32_t bc = 0;
-                    if ((nb >> 2) == l) {
-                        bc = nb & 3u;
-                        ++pb;
-                        nb = pb < eb ? llist[pb] : 0xFFFFu;
-                    }
-                    const uint32_t sh = 21u * (rc - 1u);
-                    uint32_t n1 = 0, n2 = 0, n3 = 0;
-                    bool pure = false;
-                    if (bc == 0) {
-                        const unsigned long long hit = __ballot(va && ac != 0);
-                        if (!hit) {
-                            pure = base;
-                            n1 = bk1; n2 = bk2; n3 = bk3;
-                        } else {
-                            pure = base && ac == 0;
-                            n1 = __popcll(__ballot(pure && ra == 1u));
-                            n2 = __popcll(__ballot(pure && ra == 2u));
-                            n3 = __popcll(__ballot(pure && ra == 3u));
+            uint32_t n1 = 0, n2 = 0, n3 = 0;   // slots by arc code with r (wave-uniform)
+            for (uint32_t yb = 0; yb < d; yb += 64) {
+                const uint32_t ry = yb + lane < d ? (L.P[yb + lane] & 3u) : 0u;
+                n1 += __popcll(__ballot(ry == 1u));
+                n2 += __popcll(__ballot(ry == 2u));
+                n3 += __popcll(__ballot(ry == 3u));
+            }
+            uint32_t* np = L.cnt;   // [6][d], clear
+            for (int t = wave_next(&L.task); t < (int)d; t = wave_next(&L.task)) {
+                const uint32_t x = (uint32_t)t, rx = L.P[x] & 3u;
+                const uint32_t b0 = L.pre[x], b1 = b0 + L.lcnt[x];
+                for (uint32_t qy = b0; qy < b1; qy++) {
+                    const uint32_t ey = llist[qy], y = ey >> 2, xy = ey & 3u;
+                    if (y <= x) continue;
+                    const uint32_t ry = L.P[y] & 3u;
+                    uint32_t agg1 = 0, agg2 = 0, agg3 = 0;   // triples with the single arc x-y, by rz
+                    for (uint32_t zb = 0; zb < d; zb += 64) {
+                        const uint32_t z = zb + lane;
+                        bool v = z < d && z != x && z != y;
+                        uint32_t xz = 0, yz = 0, rz = 0;
+                        if (v) {
+                            xz = mget(M, d, x, z);
+                            yz = mget(M, d, y, z);
+                            v = !((xz && z < y) || (yz && z < x));   // a smaller arc takes it
+                            rz = L.P[z] & 3u;
+                        }
+                        const bool single = v && xz == 0u && yz == 0u;
+                        agg1 += __popcll(__ballot(single && rz == 1u));
+                        agg2 += __popcll(__ballot(single && rz == 2u));
+                        agg3 += __popcll(__ballot(single && rz == 3u));
+                        if (v) {
+                            slow[2]++;
+                            const uint32_t cls = L.t4[motif_index4(rx, ry, rz, xy, xz, yz)];
+                            const uint32_t pcls = L.t4[motif_index4(rx, ry, rz, 0u, 0u, 0u)];
+                            atomicAdd(&L.root4[cls], 1ull);
+                            atomicAdd(&L.root4[pcls], ~0ull);
+                            add4(A, L, L.P[z] >> 2, cls, 1);
+                            atomicAdd(&np[pair_sig(rx, ry) * d + z], 1u);
+                            if (!single) {
+                                add4(A, L, L.P[x] >> 2, cls, 1);
+                                add4(A, L, L.P[y] >> 2, cls, 1);
+                                atomicAdd(&np[pair_sig(ry, rz) * d + x], 1u);
+                                atomicAdd(&np[pair_sig(rx, rz) * d + y], 1u);
+                            }
                         }
                     }
-                    const bool edgeset = edge && ac == 0 && bc == 0;
-                    if (pure || edgeset) acc += 1ull << sh;
-                    bacc1 += (unsigned long long)n1 << sh;
-                    bacc2 += (unsigned long long)n2 << sh;
-                    bacc3 += (unsigned long long)n3 << sh;
-                    if (lane < 3) {
-                        const uint32_t nk = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
-                        if (nk) atomicAdd(&L.cnt[pair_sig(lane + 1u, rb) * d + l], nk);
-                    }
-                    if (edgeset) {   // only c's credit is per set; a, b and r are summed in acc
-                        slow[2]++;
-                        add4(A, L, L.P[l] >> 2, L.t4[motif_index4(ra, rb, rc, ab, 0u, 0u)], 1);
-                    } else if (va && !pure) {
-                        slow[2]++;
-                        const uint32_t cls = L.t4[motif_index4(ra, rb, rc, ab, ac, bc)];
-                        atomicAdd(&L.root4[cls], 1ull);
-                        add4(A, L, L.P[i] >> 2, cls, 1);
-                        add4(A, L, L.P[j] >> 2, cls, 1);
-                        add4(A, L, L.P[l] >> 2, cls, 1);
-                    }
-                    shape[2] += va ? 1 : 0;
-                }
-                if (va) {
-                    for (uint32_t rc = 1; rc <= 3; rc++) {
-                        const uint32_t cnt = (uint32_t)(acc >> (21u * (rc - 1u))) & F21;
-                        if (!cnt) continue;
-                        if (ab == 0) {
-                            atomicAdd(&L.cnt[pair_sig(rb, rc) * d + i], cnt);
-                        } else {
-                            const uint32_t cls = L.t4[motif_index4(ra, rb, rc, ab, 0u, 0u)];
-                            add4(A, L, L.P[i] >> 2, cls, cnt);
-                            add4(A, L, L.P[j] >> 2, cls, cnt);
-                            atomicAdd(&L.root4[cls], (unsigned long long)cnt);
+                    if (lane < 3) {   // x and y in the single-arc triples, by rz = lane + 1
+                        const uint32_t k = lane + 1u, cnt = lane == 0 ? agg1 : (lane == 1 ? agg2 : agg3);
+                        if (cnt) {
+                            const uint32_t cls = L.t4[motif_index4(rx, ry, k, xy, 0u, 0u)];
+                            add4(A, L, L.P[x] >> 2, cls, cnt);
+                            add4(A, L, L.P[y] >> 2, cls, cnt);
+                            atomicAdd(&np[pair_sig(ry, k) * d + x], cnt);
+                            atomicAdd(&np[pair_sig(rx, k) * d + y], cnt);
                         }
-                    }
-                }
-                if (lane < 9) {
-                    const uint32_t ka = lane / 3 + 1, rc = lane % 3 + 1;
-                    const unsigned long long bw = ka == 1 ? bacc1 : (ka == 2 ? bacc2 : bacc3);
-                    const uint32_t cnt = (uint32_t)(bw >> (21u * (rc - 1u))) & F21;
-                    if (cnt) {
-                        atomicAdd(&L.cnt[pair_sig(ka, rc) * d + j], cnt);
-                        atomicAdd(&L.root4[L.t4[motif_index4(ka, rb, rc, 0u, 0u, 0u)]], (unsigned long long)cnt);
                     }
                 }
             }
             __syncthreads();
+            // every slot s: pure triples = pairs of other slots by code pair, minus np
             for (uint32_t q = tid; q < 6 * d; q += HT) {
-                const uint32_t cnt = L.cnt[q];
-                if (!cnt) continue;
-                const uint32_t s = q % d, g = q / d;
-                uint32_t x, y;
-                sig_pair(g, x, y);
-                add4(A, L, L.P[s] >> 2, L.t4[motif_index4(L.P[s] & 3u, x, y, 0u, 0u, 0u)], cnt);
-                L.cnt[q] = 0;
+                const uint32_t sl = q % d, g = q / d, rs = L.P[sl] & 3u;
+                uint32_t cx, cy;
+                sig_pair(g, cx, cy);
+                const uint32_t nx = (cx == 1 ? n1 : (cx == 2 ? n2 : n3)) - (rs == cx ? 1u : 0u);
+                const uint32_t ny = (cy == 1 ? n1 : (cy == 2 ? n2 : n3)) - (rs == cy ? 1u : 0u);
+                const uint32_t all = cx == cy ? nx * (nx - 1u) / 2u : nx * ny;
+                const uint32_t cnt = all - np[q];
+                np[q] = 0;
+                if (cnt) add4(A, L, L.P[sl] >> 2, L.t4[motif_index4(rs, cx, cy, 0u, 0u, 0u)], cnt);
+            }
+            // r: pure triples by code multiset k1 <= k2 <= k3 (the arc triples were taken off)
+            if (tid < 10) {
+                const uint8_t tk[10][3] = {{1, 1, 1}, {1, 1, 2}, {1, 1, 3}, {1, 2, 2}, {1, 2, 3},
+                                           {1, 3, 3}, {2, 2, 2}, {2, 2, 3}, {2, 3, 3}, {3, 3, 3}};
+                const uint32_t k1 = tk[tid][0], k2 = tk[tid][1], k3 = tk[tid][2];
+                auto nk = [&](uint32_t k) -> unsigned long long { return k == 1 ? n1 : (k == 2 ? n2 : n3); };
+                unsigned long long all;
+                if (k1 == k3) all = nk(k1) * (nk(k1) - 1) * (nk(k1) - 2) / 6;
+                else if (k1 == k2) all = nk(k1) * (nk(k1) - 1) / 2 * nk(k3);
+                else if (k2 == k3) all = nk(k1) * (nk(k2) * (nk(k2) - 1) / 2);
+                else all = nk(k1) * nk(k2) * nk(k3);
+                if (all) atomicAdd(&L.root4[L.t4[motif_index4(k1, k2, k3, 0u, 0u, 0u)]], all);
+            }
+            if (tid == 0) {
+                const unsigned long long dd = d;
+                shape[2] += (uint32_t)(dd * (dd - 1) * (dd - 2) / 6);
             }
             if (tid == 0) L.task = 0;
             __syncthreads();
