@@ -223,8 +223,8 @@ def main():
 HUB_COUNTER_SOURCES = ["paper_2201_11655_amd/csrc/count_hub.hip", "paper_2201_11655_amd/csrc/vdmc_internal.h",
                        "paper_2201_11655_amd/csrc/motif_device.h"]
 HUB_COUNTERS = {     # workload -> counters of one hub-kernel dispatch (profiles/k_hub_chunglu_1M_hbm_counters.md)
-    "chunglu": {"sources_sha256": "7cb00c4835b25113ef97804c65643de587a7b0cfe044e32b1a4b6127169e37a6",
-                "fetch_kib": 5962706251.0, "write_kib": 1272024246.3},
+    "chunglu": {"sources_sha256": "e7e82b01f989912b026ef402369e6f19e600f51b1e580ffc91a76aee889ce06b",
+                "fetch_kib": 1816686742.9, "write_kib": 1177642468.4},
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
