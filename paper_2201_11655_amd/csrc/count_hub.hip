@@ -55,7 +55,7 @@ struct HubArgs {
     // per-workgroup scratch
     uint32_t* scratch;
     size_t wg_words;        // u32 words per workgroup slice
-    size_t o_spar, o_s111, o_s3x, o_groups, o_alist, o_wlist, o_c120, o_eflag, o_llist, o_hash;
+    size_t o_spar, o_s111, o_s3x, o_groups, o_wlist, o_c120, o_eflag, o_llist, o_hash;
     uint32_t hash_bits;     // per-wave hash table of 2^hash_bits (key, value) pairs
     uint32_t wl_cap;        // per-wave list capacity (>= max degree)
     const unsigned long long* ehash;   // the graph's edge hash (edge_code)
@@ -75,15 +75,6 @@ __device__ __forceinline__ uint32_t mget(const uint32_t* M, uint32_t d, uint32_t
     return (M[mword(d, row, col)] >> mshift(col)) & 3u;
 }
 
-// slot of rank x in the sorted list sP[0..d), or -1
-__device__ __forceinline__ int find_slot(const uint32_t* sP, uint32_t d, uint32_t x) {
-    uint32_t lo = 0, hi = d, key = x << 2;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (sP[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    return (lo < d && (sP[lo] >> 2) == x) ? (int)lo : -1;
-}
 
 // largest i in [0, n) with pre[i] <= q
 __device__ __forceinline__ uint32_t slot_of(const uint32_t* pre, uint32_t n, uint32_t q) {
@@ -151,6 +142,10 @@ __device__ __forceinline__ int wave_next(unsigned* sTask) {
 // P membership filter: one bit per hash bucket of a rank; a clear bit proves absence.
 constexpr uint32_t kShortRow = 64;     // (1,2,0): rows up to this length are walked
 constexpr uint32_t kBloomWords = 1024;   // 32768 bits
+// P slot lookup: open-addressing table of N+(r) in LDS (rank + 1 -> slot), load <= 1/2
+constexpr uint32_t kPHashBits = 12;
+constexpr uint32_t kPHash = 1u << kPHashBits;
+__device__ __forceinline__ uint32_t phash(uint32_t x) { return (x * 2654435761u) >> (32u - kPHashBits); }
 __device__ __forceinline__ uint32_t bloom_bit(uint32_t x) { return (x * 2654435761u) >> 17; }
 
 struct Lds {
@@ -159,6 +154,8 @@ struct Lds {
     uint32_t lo[PMAX];
     uint32_t cnt[9 * PMAX];
     uint32_t bloom[kBloomWords];
+    uint32_t phk[kPHash];                      // rank + 1 of a slot, 0 = empty
+    uint16_t phs[kPHash];                      // its slot
     uint32_t scan[HT];
     uint32_t cw[NW][27 + 27 + kClasses3];      // per-wave group accumulators (c and r credits)
     uint32_t inA[NW][PMAX / 32];               // per-wave membership bitmap of A(c)
@@ -170,7 +167,7 @@ struct Lds {
     uint8_t t4[4096];
     uint8_t t3[64];
     uint8_t slot4[kClasses4 + 1];              // class -> compact slot (0xFF: none)
-    unsigned task, groups, alloc, rootidx;
+    unsigned task, groups, rootidx;
 };
 
 // Credit cnt sets of class cls to the vertex of rank v.  Classes of sets whose
@@ -188,7 +185,11 @@ __device__ __forceinline__ void add4(const HubArgs& A, const Lds& L, uint32_t v,
 __device__ __forceinline__ int find_slot_f(const Lds& L, uint32_t d, uint32_t x) {
     const uint32_t b = bloom_bit(x);
     if (!((L.bloom[b >> 5] >> (b & 31)) & 1u)) return -1;
-    return find_slot(L.P, d, x);
+    for (uint32_t h = phash(x);; h = (h + 1u) & (kPHash - 1u)) {
+        const uint32_t k = L.phk[h];
+        if (k == 0u) return -1;
+        if (k == x + 1u) return (int)L.phs[h];
+    }
 }
 
 // Up to kRC entries of a short CSR row kept in registers for repeated adjacency tests.
@@ -239,8 +240,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     uint32_t* spar = W + A.o_spar;     // [9][PMAX]  (2,1,0) parent-role counters
     uint32_t* s111 = W + A.o_s111;     // [9][PMAX]  (1,1,1) depth-1 counters
     uint32_t* s3x = W + A.o_s3x;       // [3][PMAX]  k=3 (1,2) depth-1 counters
-    uint32_t* grp = W + A.o_groups;    // 4 words per group: c, p, alist offset, unused
-    uint32_t* alist = W + A.o_alist;   // A(c) lists: slot << 2 | arc bits seen from the slot
+    uint32_t* grp = W + A.o_groups;    // the depth-2 vertex c of every group
     uint32_t* wlist = W + A.o_wlist + (size_t)wid * A.wl_cap;
     uint32_t* c120 = W + A.o_c120 + (size_t)wid * 3 * A.wl_cap;
     uint8_t* eflag = reinterpret_cast<uint8_t*>(W + A.o_eflag);
@@ -287,6 +287,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
 
         // ---------------------------------------------------------------- stage
         for (uint32_t i = tid; i < kBloomWords; i += HT) L.bloom[i] = 0;
+        for (uint32_t i = tid; i < kPHash; i += HT) L.phk[i] = 0;
         __syncthreads();
         for (uint32_t i = tid; i < d; i += HT) {
             const uint32_t e = A.adj[s0 + i];
@@ -294,6 +295,11 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             const uint32_t a = e >> 2;
             const uint32_t b = bloom_bit(a);
             atomicOr(&L.bloom[b >> 5], 1u << (b & 31));
+            for (uint32_t h = phash(a);; h = (h + 1u) & (kPHash - 1u))
+                if (atomicCAS(&L.phk[h], 0u, a + 1u) == 0u) {
+                    L.phs[h] = (uint16_t)i;
+                    break;
+                }
             const uint32_t lo = lower_bound_rank(A.adj, A.off[a], A.off[a + 1], r + 1);
             L.lo[i] = lo;
             L.pre[i + 1] = A.off[a + 1] - lo;
@@ -304,7 +310,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         if (tid < 9) L.gall[tid] = 0;
         const size_t mwords = (size_t)d * nch * 4;
         for (size_t i = tid; i < mwords; i += HT) M[i] = 0;
-        if (tid == 0) { L.groups = 0; L.alloc = 0; L.task = 0; }
+        if (tid == 0) { L.groups = 0; L.task = 0; }
         __syncthreads();
         block_prefix(L.pre, d, L.scan);
         const uint32_t scan2 = L.pre[d];
@@ -390,50 +396,38 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         HUB_PHASE(2);
 
         // ---------------------------------------------------------------- depth-2 groups
-        // Each depth-2 entry (a, c) scans row(c); it leads the group of c iff a is the first
-        // (lowest-rank) neighbour of c in N+(r).  The leader records A(c).
-        for (int t = wave_next(&L.task); t < (int)scan2; t = wave_next(&L.task)) {
-            if (!eflag[t]) continue;
-            const uint32_t i = slot_of(L.pre, d, (uint32_t)t);
-            const uint32_t c = A.adj[L.lo[i] + ((uint32_t)t - L.pre[i])] >> 2;
-            const uint32_t clo = A.off[c], chi = A.off[c + 1];
-            int first = -1;
-            uint32_t p = 0;
-            for (uint32_t base = clo; base < chi; base += 64) {
-                const uint32_t tt = base + lane;
-                const int sl = tt < chi ? find_slot_f(L, d, A.adj[tt] >> 2) : -1;
-                const unsigned long long mk = __ballot(sl >= 0);
-                if (first < 0 && mk) {
-                    first = __shfl(sl, (int)__ffsll((long long)mk) - 1);
-                    if (first != (int)i) break;
+        // c's group is led by c's first (lowest-rank) neighbour in N+(r).  One wave per slot
+        // a; each lane takes one depth-2 entry (a, c) and walks row(c) up to its first
+        // neighbour in N+(r) (a itself at the latest): a leads c's group iff that is a.  The
+        // parent list A(c) is collected when the group is processed.
+        for (int t = wave_next(&L.task); t < (int)d; t = wave_next(&L.task)) {
+            const uint32_t a = (uint32_t)t;
+            const uint32_t q0 = L.pre[a], q1 = L.pre[a + 1], rlo = L.lo[a];
+            if (q1 - q0 == L.lcnt[a]) continue;   // no depth-2 entries
+            for (uint32_t qb = q0; qb < q1; qb += 64) {
+                const uint32_t q = qb + lane;
+                bool lead = false;
+                uint32_t c = 0;
+                if (q < q1 && eflag[q]) {
+                    c = A.adj[rlo + (q - q0)] >> 2;
+                    const uint32_t chi = A.off[c + 1];
+                    for (uint32_t tt = A.off[c]; tt < chi; tt++) {
+                        const uint32_t w = A.adj[tt] >> 2;
+                        if (w <= r) continue;
+                        const int sl = find_slot_f(L, d, w);
+                        if (sl >= 0) {
+                            lead = (uint32_t)sl == a;
+                            break;
+                        }
+                    }
                 }
-                p += __popcll(mk);
-            }
-            if (first != (int)i) continue;
-            unsigned aoff = 0, g = 0;
-            if (lane == 0) {
-                aoff = atomicAdd(&L.alloc, p);
-                g = atomicAdd(&L.groups, 1u);
-            }
-            aoff = __shfl(aoff, 0);
-            g = __shfl(g, 0);
-            uint32_t pos = 0;
-            for (uint32_t base = clo; base < chi; base += 64) {
-                const uint32_t tt = base + lane;
-                uint32_t e = 0;
-                int sl = -1;
-                if (tt < chi) {
-                    e = A.adj[tt];
-                    sl = find_slot_f(L, d, e >> 2);
+                const unsigned long long mk = __ballot(lead);
+                if (mk) {
+                    uint32_t g0 = 0;
+                    if (lane == 0) g0 = atomicAdd(&L.groups, (unsigned)__popcll(mk));
+                    g0 = __shfl(g0, 0);
+                    if (lead) grp[g0 + __popcll(mk & lt_mask)] = c;
                 }
-                const unsigned long long mk = __ballot(sl >= 0);
-                if (sl >= 0) alist[aoff + pos + __popcll(mk & lt_mask)] = ((uint32_t)sl << 2) | swap_arc_bits(e & 3u);
-                pos += __popcll(mk);
-            }
-            if (lane == 0) {
-                grp[4 * g + 0] = c;
-                grp[4 * g + 1] = p;
-                grp[4 * g + 2] = aoff;
             }
         }
         __threadfence();
@@ -557,11 +551,25 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         uint32_t* cw = L.cw[wid];
         uint32_t* inA = L.inA[wid];
         for (int t = wave_next(&L.task); t < (int)ngroups; t = wave_next(&L.task)) {
-            const uint32_t c = grp[4 * t + 0];
-            const uint32_t p = grp[4 * t + 1];
+            const uint32_t c = grp[t];
             if (lane == 0) work[0]++;
-            const uint32_t* Ac = alist + grp[4 * t + 2];
+            // A(c): c's neighbours in N+(r), as (slot << 2) | arc bits seen from the slot
+            uint32_t* Ac = wlist;
             const uint32_t chi = A.off[c + 1];
+            uint32_t p = 0;
+            for (uint32_t base = A.off[c]; base < chi; base += 64) {
+                const uint32_t tt = base + lane;
+                uint32_t e = 0;
+                int sl = -1;
+                if (tt < chi) {
+                    e = A.adj[tt];
+                    if ((e >> 2) > r) sl = find_slot_f(L, d, e >> 2);
+                }
+                const unsigned long long mk = __ballot(sl >= 0);
+                if (sl >= 0) Ac[p + __popcll(mk & lt_mask)] = ((uint32_t)sl << 2) | swap_arc_bits(e & 3u);
+                p += __popcll(mk);
+            }
+            __threadfence_block();
             for (uint32_t u = lane; u < p; u += 64) {
                 const uint32_t x = Ac[u] >> 2;
                 atomicOr(&inA[x >> 5], 1u << (x & 31));
@@ -1171,8 +1179,7 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         const size_t o_spar = o; o += 9 * PMAX;
         const size_t o_s111 = o; o += 9 * PMAX;
         const size_t o_s3x = o; o += 3 * PMAX;
-        const size_t o_groups = o; o += 4 * s2;
-        const size_t o_alist = o; o += s2;
+        const size_t o_groups = o; o += s2;
         const size_t o_wlist = o; o += NW * wl;
         const size_t o_c120 = o; o += 3 * NW * wl;
         const size_t o_eflag = o; o += (s2 + 3) / 4;
@@ -1209,7 +1216,6 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         g->hub_layout[2] = o_s111;
         g->hub_layout[3] = o_s3x;
         g->hub_layout[4] = o_groups;
-        g->hub_layout[5] = o_alist;
         g->hub_layout[6] = o_wlist;
         g->hub_layout[7] = o_c120;
         g->hub_layout[8] = o_eflag;
@@ -1248,7 +1254,6 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.o_s111 = g->hub_layout[2];
     a.o_s3x = g->hub_layout[3];
     a.o_groups = g->hub_layout[4];
-    a.o_alist = g->hub_layout[5];
     a.o_wlist = g->hub_layout[6];
     a.o_c120 = g->hub_layout[7];
     a.o_eflag = g->hub_layout[8];
