@@ -32,6 +32,8 @@ WORKLOADS = {
                "gamma 2.1, undirected degree cap 2000, 20% reciprocated, seed 2; k=3 and k=4 in one call",
     "er1000": "directed G(n=1000, p=0.005), seed 1; k=3 and k=4 in one call",
     "rmat22": "R-MAT scale 22, edge factor 8, (0.57,0.19,0.19,0.05), cap 1500, seed 4; k=4",
+    "chunglu_u": "the Chung-Lu graph of the default workload with arc directions ignored; undirected "
+                 "4-vertex motifs (6 classes), one count call",
     "batch4096": "4096 directed G(n,p) graphs, n ~ U{20..500}, mean out-degree ~ U[2,8], graph i seeded (3,i); "
                  "k=4 in one persistent HIP-graph launch vs 4096 per-graph launches",
     "serve": "serving: pool of resident ER and Chung-Lu graphs, n log-uniform in [1e2,1e6], mean out-degree "
@@ -105,7 +107,8 @@ def main():
     if args.workload == "serve":
         return bench_serve(args, torch, gg, v)
     t0 = time.perf_counter()
-    g = gg.config_graph(args.workload)
+    undirected = args.workload == "chunglu_u"
+    g = gg.config_graph("chunglu" if undirected else args.workload)
     log(f"[bench] generated {args.workload}: n={g.n} arcs={g.m} in {time.perf_counter() - t0:.1f}s")
     dsrc = torch.from_numpy(g.src).cuda()
     ddst = torch.from_numpy(g.dst).cuda()
@@ -113,18 +116,22 @@ def main():
     out4 = torch.empty((g.n, 199), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
 
-    only4 = args.workload == "rmat22"
+    only4 = args.workload in ("rmat22", "chunglu_u")
+    if undirected:
+        out4 = torch.empty((g.n, 6), dtype=torch.int64, device="cuda")
     if only4:
         out3 = torch.zeros((1, 13), dtype=torch.int64, device="cuda")
 
     hub_ms_steps = []
 
     def step(timing=None):
-        G = v.Graph(g.n, dsrc, ddst, stream=stream)
+        G = v.Graph(g.n, dsrc, ddst, stream=stream, undirected=undirected)
         hub_ms = 0.0
         if timing is not None:
             timing[0].record(stream)
-        if only4:
+        if undirected:
+            v.count_undirected(G, 4, out4, stream=stream)
+        elif only4:
             # the same count as one vdmc_count call, issued as consecutive root-rank ranges
             # (Lemma 1: ranges are independent) so that a long run reports its progress
             bounds = [0] + [1 << b for b in range(8, 40) if (1 << b) < g.n] + [g.n]
@@ -158,7 +165,7 @@ def main():
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     log(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step, count call {kernel_ms:.2f} ms")
 
-    if not only4:   # the hub kernel's own events, recorded by the library in every timed step
+    if not only4 or undirected:   # the hub kernel's own events, recorded by the library in every timed step
         hub_ms_steps = [v.kernel_times(Gk)[1] for Gk in graphs]
     G = graphs[-1]
     sc = v.shape_counts(G)
@@ -210,7 +217,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline ...")
-        result["cpu_baseline"] = cpu_baseline(g, args.cpu_budget)
+        gb = g
+        if undirected:   # the oracle counts the digraph with every arc reciprocated (that is G_U)
+            gb = gg.Graph(g.n, np.concatenate([g.src, g.dst]), np.concatenate([g.dst, g.src]), "chunglu_u")
+        result["cpu_baseline"] = cpu_baseline(gb, args.cpu_budget)
     if args.calibrate_copy:
         calibrate_copy(torch)
     print(json.dumps(result), flush=True)

@@ -76,6 +76,19 @@ def digest(g: Graph) -> str:
     return h.hexdigest()
 
 
+def er_undirected(n: int, p: float, seed) -> Graph:
+    """Undirected G(n,p): every unordered pair {u < v} is an edge independently with prob. p,
+    emitted as one arc u -> v (directions are to be ignored by the consumer)."""
+    rng = _rng(seed)
+    n = int(n)
+    if n <= 1 or p <= 0.0:
+        z = np.zeros(0, np.int32)
+        return Graph(n, z, z.copy(), f"er_u({n},{p})")
+    mask = np.triu(rng.random((n, n)) < p, 1)
+    s, d = np.nonzero(mask)
+    return Graph(n, s.astype(np.int32), d.astype(np.int32), f"er_u({n},{p})")
+
+
 def er_directed(n: int, p: float, seed) -> Graph:
     """Directed G(n,p): every ordered pair (u, v), u != v, is an arc independently with prob. p."""
     rng = _rng(seed)

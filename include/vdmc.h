@@ -56,7 +56,8 @@ enum {
 
 /* vdmc_build_graph flags */
 enum {
-    VDMC_INPUT_ON_DEVICE = 2u   /* src/dst are device pointers (else host pointers) */
+    VDMC_INPUT_ON_DEVICE = 2u,  /* src/dst are device pointers (else host pointers) */
+    VDMC_UNDIRECTED = 4u        /* ignore arc directions: count motifs of the undirected graph */
 };
 
 /* vdmc_count_range flags */
@@ -86,6 +87,8 @@ vdmc_status vdmc_class_table(int32_t k, uint8_t* table_out);
  *     the library copies them; the caller keeps ownership.
  *   - Self-loops are dropped and repeated arcs merged; u->v and v->u together form
  *     one undirected pair carrying both arc bits.
+ *   - flags & VDMC_UNDIRECTED: every pair gets both arc bits, i.e. the graph counted is
+ *     the underlying undirected graph G_U; use vdmc_count_undirected on it.
  *   - Vertices are ranked by undirected degree, largest first, ties by original id
  *     (the removal order of Sec. 2 and Sec. 6); the CSR is stored in rank space,
  *     each row ascending, every entry (neighbour_rank << 2) | arc_bits with bit 0 =
@@ -107,6 +110,24 @@ vdmc_status vdmc_graph_info(vdmc_graph g, int64_t* n, int64_t* arcs, int64_t* pa
  * adj[2*pairs] entries (nbr_rank << 2 | arc_bits), perm[n] (rank -> original id).
  * Any pointer may be NULL.  Synchronous. */
 vdmc_status vdmc_graph_export(vdmc_graph g, uint32_t* off, uint32_t* adj, int32_t* perm);
+
+/*
+ * Undirected motifs (the paper's undirected runs, Fig. 3 and Table 2): connected
+ * induced subgraphs of G_U, merged by undirected isomorphism: 2 classes for k = 3
+ * (path, triangle), 6 for k = 4 (path, star, cycle, triangle with a tail, diamond,
+ * complete graph).  Undirected class j is the directed class (of vdmc_class_codes)
+ * whose every vertex pair carries both arcs; classes are ordered by that directed id.
+ *   vdmc_num_classes_undirected: 2, 6, or -1 for another k.
+ *   vdmc_undirected_classes: directed_class_out[j] = the directed class of undirected
+ *     class j (host array of vdmc_num_classes_undirected(k) bytes).  Synchronous.
+ *   vdmc_count_undirected: g built with VDMC_UNDIRECTED (else INVALID_ARG); out is a
+ *     DEVICE buffer of n * vdmc_num_classes_undirected(k) uint64 (row = original id),
+ *     written, not accumulated.  Asynchronous on `stream`; the first call on a graph
+ *     allocates an n x 199 uint64 scratch that the graph keeps until it is freed.
+ */
+int32_t vdmc_num_classes_undirected(int32_t k);
+vdmc_status vdmc_undirected_classes(int32_t k, uint8_t* directed_class_out);
+vdmc_status vdmc_count_undirected(vdmc_graph g, int32_t k, uint64_t* out, void* stream);
 
 /* Releases the graph's device memory.  NULL is a no-op.  The caller must make sure no
  * count on the graph is still running. */

@@ -123,6 +123,36 @@ def count_rows(n: int, src, dst, k: int, rows, threads: int | None = None):
     return out
 
 
+def undirected_classes(k: int) -> np.ndarray:
+    """Class ids (of ``class_table``) whose every vertex pair carries both arcs, ascending.
+    With every arc reciprocated, each connected k-set of G_U lands in exactly one of them,
+    so they are the undirected classes (connected graphs on k vertices; the paper's
+    undirected runs, Fig. 3 caption): 2 for k = 3, 6 for k = 4."""
+    from . import exhaustive
+    _, cls, _ = class_table(k)
+    pairs = [(i, j) for i in range(k) for j in range(i + 1, k)]
+    found = set()
+    for mask in range(1 << len(pairs)):
+        A = [[0] * k for _ in range(k)]
+        for b, (i, j) in enumerate(pairs):
+            if (mask >> b) & 1:
+                A[i][j] = A[j][i] = 1
+        c = int(cls[exhaustive.motif_index(A)])
+        if c >= 0:
+            found.add(c)
+    return np.array(sorted(found), np.int64)
+
+
+def count_undirected(n: int, src, dst, k: int, threads: int | None = None):
+    """Per-vertex undirected counts ``uint64[n][U]`` and totals ``uint64[U]``: the directed
+    count of the graph with every arc reciprocated (that graph is G_U), restricted to the
+    ``undirected_classes`` columns (every other column is zero there)."""
+    s, d = _arcs(src, dst)
+    out, tot = count(n, np.concatenate([s, d]), np.concatenate([d, s]), k, threads)
+    cols = undirected_classes(k)
+    return out[:, cols].copy(), tot[cols].copy()
+
+
 def simple_graph(n: int, src, dst):
     """The oracle's normalised graph: (off[n+1], nbr, dir) with dir bit0 = row->nbr,
     bit1 = nbr->row."""

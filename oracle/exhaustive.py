@@ -101,3 +101,55 @@ def count(n: int, src, dst, k: int):
         for v in S:
             out[v, c] += 1
     return out, tot
+
+
+# ------------------------------------------------------------------ undirected motifs
+
+UNDIRECTED_NAMES = {
+    3: ["path", "triangle"],
+    4: ["path", "star", "cycle", "paw", "diamond", "clique"],
+}
+
+
+def undirected_name(k: int, edges) -> str:
+    """Name of a connected undirected graph on k vertices from its edge count and
+    degree sequence (enough to tell all 2 + 6 of them apart)."""
+    deg = [0] * k
+    for i, j in edges:
+        deg[i] += 1
+        deg[j] += 1
+    m, top = len(edges), max(deg)
+    if k == 3:
+        return "triangle" if m == 3 else "path"
+    if m == 3:
+        return "star" if top == 3 else "path"
+    if m == 4:
+        return "paw" if top == 3 else "cycle"
+    return "diamond" if m == 5 else "clique"
+
+
+def count_undirected(n: int, src, dst, k: int):
+    """{name: uint64[n]} per-vertex counts of the connected induced subgraphs of G_U,
+    by brute force over all k-subsets (arc directions ignored)."""
+    und = [set() for _ in range(n)]
+    for u, v in zip(np.asarray(src).tolist(), np.asarray(dst).tolist()):
+        if u != v:
+            und[u].add(v)
+            und[v].add(u)
+    out = {name: np.zeros(n, np.uint64) for name in UNDIRECTED_NAMES[k]}
+    for S in itertools.combinations(range(n), k):
+        edges = [(i, j) for i in range(k) for j in range(i + 1, k) if S[j] in und[S[i]]]
+        seen, stack = {0}, [0]
+        while stack:
+            x = stack.pop()
+            for i, j in edges:
+                y = j if i == x else (i if j == x else None)
+                if y is not None and y not in seen:
+                    seen.add(y)
+                    stack.append(y)
+        if len(seen) != k:
+            continue
+        name = undirected_name(k, edges)
+        for v in S:
+            out[name][v] += 1
+    return out

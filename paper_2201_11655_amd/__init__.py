@@ -13,10 +13,13 @@ from .vdmc import (  # noqa: F401
     count34,
     count_range,
     count_batch,
+    count_undirected,
     kernel_times,
     load,
     num_classes,
+    num_classes_undirected,
     profile_counters,
     shape_counts,
     tune,
+    undirected_classes,
 )

@@ -193,6 +193,7 @@ static void build_graph(int64_t n, int64_t m, const int32_t* src, const int32_t*
     VDMC_REQUIRE(m < (int64_t(1) << 31), VDMC_ERR_INVALID_ARG, "m must be below 2^31");
     VDMC_HIP(hipGetDevice(&g->device));
     g->n = n;
+    g->undirected = (flags & VDMC_UNDIRECTED) != 0;
     Temps t;
     const int32_t* d_src = src;
     const int32_t* d_dst = dst;
@@ -259,6 +260,8 @@ static void build_graph(int64_t n, int64_t m, const int32_t* src, const int32_t*
         hipLaunchKernelGGL(k_merge_pairs, dim3(blocks_for(m)), dim3(kThreads), 0, st, keys_s, bits_s, head,
                            hpos, m, pkey, pcode);
         VDMC_HIP(hipGetLastError());
+        if (flags & VDMC_UNDIRECTED)   // every pair carries both arcs: the graph is G_U itself
+            hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(np)), dim3(kThreads), 0, st, pcode, np, 3u);
     }
     g->pairs = np;
     VDMC_REQUIRE(2 * np < (int64_t(1) << 32), VDMC_ERR_UNSUPPORTED, "more than 2^31 undirected pairs");
@@ -345,6 +348,8 @@ static void build_graph(int64_t n, int64_t m, const int32_t* src, const int32_t*
 
 static void free_graph_arrays(vdmc_graph_s* g) {
     free_hub(g);
+    (void)hipFree(g->utmp);
+    g->utmp = nullptr;
     (void)hipFree(g->off);
     (void)hipFree(g->adj);
     (void)hipFree(g->split);

@@ -106,6 +106,8 @@ struct vdmc_graph_s {
     int64_t arcs = 0;
     int64_t pairs = 0;
     int32_t max_deg = 0;
+    bool undirected = false;     // built with VDMC_UNDIRECTED: every pair has both arc bits
+    uint64_t* utmp = nullptr;    // directed-class scratch of the undirected counts (n x 199)
     uint32_t* off = nullptr;     // n + 1 row offsets (rank space)
     uint32_t* adj = nullptr;     // 2 * pairs entries: (nbr_rank << 2) | arc bits
     uint32_t* split = nullptr;   // n: index of the first entry with nbr_rank > row

@@ -19,7 +19,8 @@ SYMBOLS = [
     "vdmc_last_error", "vdmc_num_classes", "vdmc_class_codes", "vdmc_class_table",
     "vdmc_build_graph", "vdmc_graph_info", "vdmc_graph_export", "vdmc_free_graph",
     "vdmc_count", "vdmc_count_range", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters",
-    "vdmc_kernel_times", "vdmc_count_batch", "vdmc_tune",
+    "vdmc_kernel_times", "vdmc_num_classes_undirected", "vdmc_undirected_classes", "vdmc_count_undirected",
+    "vdmc_count_batch", "vdmc_tune",
     "vdmc_serve_create", "vdmc_serve_submit", "vdmc_serve_poll", "vdmc_serve_wait",
     "vdmc_serve_stats", "vdmc_serve_destroy",
 ]
@@ -29,6 +30,7 @@ STATUS = {
     5: "BUSY", 6: "NOT_FOUND", 7: "REJECTED", 8: "TIMEOUT",
 }
 INPUT_ON_DEVICE = 2
+UNDIRECTED = 4
 SHAPES = ["(1,1)", "(1,2)", "(3,0,0)", "(2,1,0)", "(1,2,0)", "(1,1,1)"]
 
 
@@ -66,6 +68,9 @@ def load():
         "vdmc_shape_counts": ([p, p], i32),
         "vdmc_profile_counters": ([p, p, i32], i32),
         "vdmc_kernel_times": ([p, p], i32),
+        "vdmc_num_classes_undirected": ([i32], i32),
+        "vdmc_undirected_classes": ([i32, p], i32),
+        "vdmc_count_undirected": ([p, i32, p, p], i32),
         "vdmc_count_batch": ([p, i32, i32, p, p], i32),
         "vdmc_tune": ([p, i32, i32, ctypes.c_char_p], i32),
         "vdmc_serve_create": ([p, p], i32),
@@ -128,13 +133,15 @@ def class_table(k: int) -> np.ndarray:
 class Graph:
     """A graph resident on the current device (ranked symmetric CSR with arc bits).
 
-    ``src``/``dst`` are numpy arrays (host) or int32 CUDA tensors (device)."""
+    ``src``/``dst`` are numpy arrays (host) or int32 CUDA tensors (device).
+    ``undirected=True`` ignores arc directions (count with ``count_undirected``)."""
 
-    def __init__(self, n: int, src, dst, stream=None):
+    def __init__(self, n: int, src, dst, stream=None, undirected: bool = False):
         lib = load()
         self._h = ctypes.c_void_p()
         self.n = int(n)
-        flags = 0
+        self.undirected = bool(undirected)
+        flags = UNDIRECTED if undirected else 0
         keep = []
         if hasattr(src, "is_cuda") and src.is_cuda:
             torch = _torch()
@@ -191,6 +198,35 @@ def _out_tensor(n: int, k: int, out):
         out = torch.empty((n, C), dtype=torch.int64, device="cuda")
     if out.dtype != torch.int64 or not out.is_cuda or not out.is_contiguous() or out.numel() != n * C:
         raise VdmcError(1, f"out must be a contiguous int64 CUDA tensor of {n}x{C}")
+    return out
+
+
+def num_classes_undirected(k: int) -> int:
+    return int(load().vdmc_num_classes_undirected(k))
+
+
+def undirected_classes(k: int) -> np.ndarray:
+    """Directed class id of every undirected class (ascending)."""
+    nc = num_classes_undirected(k)
+    if nc < 0:
+        raise VdmcError(1, f"k={k}")
+    out = np.zeros(nc, np.uint8)
+    _check(load().vdmc_undirected_classes(k, _np_ptr(out)))
+    return out
+
+
+def count_undirected(g: Graph, k: int, out=None, stream=None):
+    """Per-vertex undirected k-motif counts, int64[n, 2 or 6] on the device (row = original id)."""
+    lib = load()
+    U = num_classes_undirected(k)
+    if U < 0:
+        _check(lib.vdmc_count_undirected(g.handle, int(k), None, _stream_handle(stream)))
+    torch = _torch()
+    if out is None:
+        out = torch.empty((g.n, U), dtype=torch.int64, device="cuda")
+    if out.dtype != torch.int64 or not out.is_cuda or not out.is_contiguous() or out.numel() != g.n * U:
+        raise VdmcError(1, f"out must be a contiguous int64 CUDA tensor of {g.n}x{U}")
+    _check(lib.vdmc_count_undirected(g.handle, int(k), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 

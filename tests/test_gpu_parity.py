@@ -240,3 +240,55 @@ def test_kernel_times_and_hub_share(v):
         assert lt == -1.0 and ht >= 0.0
     else:
         assert ht == -1.0 and lt >= 0.0   # no hub root: the hub kernel is not launched
+
+
+# --------------------------------------------------------------------------- undirected motifs
+
+def _undirected_cases():
+    star_clique_s = [0] * 9 + [10 + i for i in range(6) for j in range(6) if i < j]
+    star_clique_d = list(range(1, 10)) + [10 + j for i in range(6) for j in range(6) if i < j]
+    return {
+        "er60_dense": gg.er_directed(60, 0.3, (81, 1)),
+        "er200": gg.er_directed(200, 0.03, (81, 2)),
+        "chunglu_2000": gg.config_graph("chunglu_2000"),
+        "star_and_clique": gg.Graph(16, np.array(star_clique_s, np.int32), np.array(star_clique_d, np.int32), "sc"),
+    }
+
+
+@pytest.mark.parametrize("case", ["er60_dense", "er200", "chunglu_2000", "star_and_clique"])
+def test_undirected_parity(v, case):
+    g = _undirected_cases()[case]
+    _say(f"undirected case {case} n={g.n} m={g.m}")
+    G = v.Graph(g.n, g.src, g.dst, undirected=True)
+    for k in (3, 4):
+        assert (v.undirected_classes(k) == oracle.undirected_classes(k)).all()
+        got = _np(v.count_undirected(G, k))
+        want, _ = oracle.count_undirected(g.n, g.src, g.dst, k)
+        assert got.shape == want.shape
+        bad = np.argwhere(got != want)
+        assert bad.size == 0, f"{case} k={k}: {bad.shape[0]} cells differ, first {bad[:5].tolist()}"
+
+
+def test_undirected_graph_counts_the_symmetric_digraph(v):
+    # a graph built with the undirected flag is the digraph with every arc reciprocated
+    g = gg.er_directed(120, 0.05, (81, 3))
+    G = v.Graph(g.n, g.src, g.dst, undirected=True)
+    s2 = np.concatenate([g.src, g.dst])
+    d2 = np.concatenate([g.dst, g.src])
+    for k in (3, 4):
+        want, _ = oracle.count(g.n, s2, d2, k)
+        assert (_np(v.count(G, k)) == want).all()
+
+
+def test_undirected_errors(v):
+    g = gg.er_directed(30, 0.1, (81, 4))
+    G = v.Graph(g.n, g.src, g.dst)
+    with pytest.raises(v.VdmcError) as e:
+        v.count_undirected(G, 3)
+    assert e.value.name == "INVALID_ARG"
+    Gu = v.Graph(g.n, g.src, g.dst, undirected=True)
+    with pytest.raises(v.VdmcError) as e:
+        v.count_undirected(Gu, 5)
+    assert e.value.name in ("UNSUPPORTED", "INVALID_ARG")
+    G0 = v.Graph(0, np.zeros(0, np.int32), np.zeros(0, np.int32), undirected=True)
+    assert v.count_undirected(G0, 4).shape == (0, 6)

@@ -305,3 +305,83 @@ def test_er_expectation_eq4(k):
     if small.any():
         pooled = S[:, small].sum(axis=1)
         assert abs(pooled.mean() - expect[small].sum()) < 5 * max(pooled.std(ddof=1), 1.0) / math.sqrt(R) + 1.0
+
+
+# --------------------------------------------------------------------------- undirected motifs
+
+def _undirected_column_names(k):
+    """Name of each undirected column of the oracle, read off its class code."""
+    _, _, codes = oracle.class_table(k)
+    names = []
+    for c in oracle.undirected_classes(k):
+        A = ex.matrix_of(k, int(codes[c]))
+        edges = [(i, j) for i in range(k) for j in range(i + 1, k) if A[i][j] or A[j][i]]
+        assert all(A[i][j] and A[j][i] for i, j in edges)   # every pair reciprocal
+        names.append(ex.undirected_name(k, edges))
+    return names
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_undirected_classes_are_the_connected_graphs(k):
+    # Fig. 3 caption: the undirected runs count connected graphs on k vertices: 2 and 6
+    names = _undirected_column_names(k)
+    assert sorted(names) == sorted(ex.UNDIRECTED_NAMES[k])
+
+
+def _undirected_by_name(n, src, dst, k):
+    got, tot = oracle.count_undirected(n, src, dst, k)
+    names = _undirected_column_names(k)
+    return {nm: got[:, j] for j, nm in enumerate(names)}, {nm: int(tot[j]) for j, nm in enumerate(names)}
+
+
+def _edges(pairs):
+    s = np.array([a for a, b in pairs], np.int32)
+    d = np.array([b for a, b in pairs], np.int32)
+    return s, d
+
+
+def test_undirected_closed_forms():
+    comb = math.comb
+    # complete graph K7: every vertex in C(6,2) triangles and C(6,3) cliques, nothing else
+    n = 7
+    s, d = _edges([(i, j) for i in range(n) for j in range(i + 1, n)])
+    c3, _ = _undirected_by_name(n, s, d, 3)
+    c4, _ = _undirected_by_name(n, s, d, 4)
+    assert (c3["triangle"] == comb(6, 2)).all() and (c3["path"] == 0).all()
+    assert (c4["clique"] == comb(6, 3)).all() and sum(int(c4[x].sum()) for x in c4 if x != "clique") == 0
+    # star with centre 0 and 6 leaves (arcs pointing both ways: directions are ignored)
+    s, d = _edges([(0, i) if i % 2 else (i, 0) for i in range(1, 7)])
+    c3, _ = _undirected_by_name(7, s, d, 3)
+    c4, _ = _undirected_by_name(7, s, d, 4)
+    assert c3["path"][0] == comb(6, 2) and (c3["path"][1:] == 5).all()
+    assert c4["star"][0] == comb(6, 3) and (c4["star"][1:] == comb(5, 2)).all()
+    # path 0-1-2-3-4-5: windows of consecutive vertices
+    n = 6
+    s, d = _edges([(i, i + 1) for i in range(n - 1)])
+    c3, _ = _undirected_by_name(n, s, d, 3)
+    c4, _ = _undirected_by_name(n, s, d, 4)
+    win = lambda i, w: sum(1 for a in range(0, n - w + 1) if a <= i < a + w)
+    assert [int(x) for x in c3["path"]] == [win(i, 3) for i in range(n)]
+    assert [int(x) for x in c4["path"]] == [win(i, 4) for i in range(n)]
+    # cycle of 6: every vertex on 3 paths of 3 and 4 paths of 4
+    s, d = _edges([(i, (i + 1) % n) for i in range(n)])
+    c3, _ = _undirected_by_name(n, s, d, 3)
+    c4, _ = _undirected_by_name(n, s, d, 4)
+    assert (c3["path"] == 3).all() and (c4["path"] == 4).all() and (c4["cycle"] == 0).all()
+    # 4-cycle alone, and a diamond (4-cycle plus one chord)
+    s, d = _edges([(0, 1), (1, 2), (2, 3), (3, 0)])
+    c4, t4 = _undirected_by_name(4, s, d, 4)
+    assert t4["cycle"] == 1 and sum(t4.values()) == 1
+    s, d = _edges([(0, 1), (1, 2), (2, 3), (3, 0), (0, 2)])
+    c4, t4 = _undirected_by_name(4, s, d, 4)
+    assert t4["diamond"] == 1 and sum(t4.values()) == 1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_undirected_equals_brute_force(seed):
+    g = gg.er_directed(11, 0.22, (41, seed))
+    for k in (3, 4):
+        got, _ = _undirected_by_name(g.n, g.src, g.dst, k)
+        want = ex.count_undirected(g.n, g.src, g.dst, k)
+        for nm in ex.UNDIRECTED_NAMES[k]:
+            assert (got[nm] == want[nm]).all(), (k, nm)
