@@ -129,6 +129,20 @@ int32_t vdmc_num_classes_undirected(int32_t k);
 vdmc_status vdmc_undirected_classes(int32_t k, uint8_t* directed_class_out);
 vdmc_status vdmc_count_undirected(vdmc_graph g, int32_t k, uint64_t* out, void* stream);
 
+/*
+ * Per-edge counts (Sec. 11, "count per edge"): for every vertex pair {lo < hi} joined in
+ * G_U, the number of connected k-sets of each class that contain both lo and hi.
+ *   vdmc_edge_list: the pairs in output-row order, ascending (lo, hi) original ids, as
+ *     host arrays lo[pairs], hi[pairs] (pairs from vdmc_graph_info).  Synchronous.
+ *   vdmc_count_edges: out is a DEVICE buffer of pairs * vdmc_num_classes(k) uint64,
+ *     written, not accumulated.  Asynchronous on `stream`, except that the first call on
+ *     a graph builds the edge index (an edge hash of 2^ceil(log2(4 pairs)) 8-byte slots
+ *     plus a 4-byte row per slot, kept with the graph) and synchronises `stream`.  Every
+ *     root goes through the per-set kernel, which credits the joined pairs of each set.
+ */
+vdmc_status vdmc_edge_list(vdmc_graph g, int32_t* lo, int32_t* hi);
+vdmc_status vdmc_count_edges(vdmc_graph g, int32_t k, uint64_t* out, void* stream);
+
 /* Releases the graph's device memory.  NULL is a no-op.  The caller must make sure no
  * count on the graph is still running. */
 vdmc_status vdmc_free_graph(vdmc_graph g);

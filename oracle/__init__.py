@@ -58,6 +58,8 @@ def _load():
         lib.oracle_count.restype = i32
         lib.oracle_count_rows.argtypes = [i64, i64, p, p, i32, i32, p, i64, p]
         lib.oracle_count_rows.restype = i32
+        lib.oracle_count_edges.argtypes = [i64, i64, p, p, i32, i32, i64, p, p, p]
+        lib.oracle_count_edges.restype = i32
         lib.oracle_graph_size.argtypes = [i64, i64, p, p, p]
         lib.oracle_graph_size.restype = i32
         lib.oracle_graph_csr.argtypes = [i64, i64, p, p, p, p, p]
@@ -151,6 +153,28 @@ def count_undirected(n: int, src, dst, k: int, threads: int | None = None):
     out, tot = count(n, np.concatenate([s, d]), np.concatenate([d, s]), k, threads)
     cols = undirected_classes(k)
     return out[:, cols].copy(), tot[cols].copy()
+
+
+def count_edges(n: int, src, dst, k: int, threads: int | None = None):
+    """Per-edge counts (Sec. 11): ``(lo[P], hi[P], uint64[P][C])`` for the P vertex pairs
+    {lo < hi} joined in G_U, in ascending (lo, hi) order; row p counts, per class, the
+    connected k-sets containing both lo and hi."""
+    lib = _load()
+    s, d = _arcs(src, dst)
+    e = np.zeros(1, np.int64)
+    rc = lib.oracle_graph_size(int(n), int(s.shape[0]), _ptr(s), _ptr(d), _ptr(e))
+    if rc:
+        raise ValueError(rc)
+    P = int(e[0]) // 2
+    C = NUM_CLASSES[k]
+    out = np.zeros((P, C), np.uint64)
+    lo = np.zeros(max(P, 1), np.int32)
+    hi = np.zeros(max(P, 1), np.int32)
+    rc = lib.oracle_count_edges(int(n), int(s.shape[0]), _ptr(s), _ptr(d), int(k),
+                                int(threads or default_threads()), P, _ptr(out), _ptr(lo), _ptr(hi))
+    if rc != 0:
+        raise ValueError(f"oracle_count_edges failed with {rc}")
+    return lo[:P].copy(), hi[:P].copy(), out
 
 
 def simple_graph(n: int, src, dst):

@@ -153,3 +153,40 @@ def count_undirected(n: int, src, dst, k: int):
         for v in S:
             out[name][v] += 1
     return out
+
+
+# ------------------------------------------------------------------ per-edge counts
+
+def count_edges(n: int, src, dst, k: int):
+    """(pairs, uint64[P][C]): pairs = sorted list of the G_U pairs (lo < hi); row p counts,
+    per class, the connected k-sets containing both endpoints.  Brute force."""
+    arcs = set()
+    for u, v in zip(np.asarray(src).tolist(), np.asarray(dst).tolist()):
+        if u != v:
+            arcs.add((u, v))
+    pairs = sorted({(min(u, v), max(u, v)) for u, v in arcs})
+    pid = {pr: i for i, pr in enumerate(pairs)}
+    und = [set() for _ in range(n)]
+    for u, v in arcs:
+        und[u].add(v)
+        und[v].add(u)
+    mins, conn = classes(k)
+    cid = {c: i for i, c in enumerate(conn)}
+    out = np.zeros((len(pairs), len(conn)), np.uint64)
+    for S in itertools.combinations(range(n), k):
+        seen, stack, members = {S[0]}, [S[0]], set(S)
+        while stack:
+            x = stack.pop()
+            for y in und[x]:
+                if y in members and y not in seen:
+                    seen.add(y)
+                    stack.append(y)
+        if len(seen) != k:
+            continue
+        A = [[1 if (i != j and (S[i], S[j]) in arcs) else 0 for j in range(k)] for i in range(k)]
+        c = cid[mins[motif_index(A)]]
+        for i in range(k):
+            for j in range(i + 1, k):
+                if S[j] in und[S[i]]:
+                    out[pid[(min(S[i], S[j]), max(S[i], S[j]))], c] += 1
+    return pairs, out

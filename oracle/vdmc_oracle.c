@@ -196,7 +196,20 @@ typedef struct {
     uint64_t *totals;      /* private ncls: number of k-sets per class (each set once) */
     int32_t forced;        /* -1: ordinary ESU; else every set contains this vertex */
     int64_t forced_row;    /* forced mode: the only row credited */
+    const int64_t *upre;   /* edge mode (non-NULL): pair id of the entry e > first upper
+                              entry of row u is upre[u] + (e - ufirst[u]) */
+    const int64_t *ufirst;
 } esu_ctx;
+
+/* position of v in u's neighbour list, or -1 */
+static int64_t entry_of(const sgraph *g, int32_t u, int32_t v) {
+    int64_t lo = g->off[u], hi = g->off[u + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (g->nbr[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return (lo < g->off[u + 1] && g->nbr[lo] == v) ? lo : -1;
+}
 
 static void credit(esu_ctx *c, const int32_t *S) {
     int k = c->k;
@@ -212,6 +225,17 @@ static void credit(esu_ctx *c, const int32_t *S) {
     int id = c->cls[encode(k, A)];
     if (id < 0) return;  /* cannot happen for a connected set; kept as a guard */
     c->totals[id]++;
+    if (c->upre) {   /* per-edge counts: every vertex pair of S joined in G_U */
+        for (int i = 0; i < k; i++)
+            for (int j = i + 1; j < k; j++) {
+                if (!A[i][j] && !A[j][i]) continue;
+                int32_t u = S[i] < S[j] ? S[i] : S[j], v = S[i] < S[j] ? S[j] : S[i];
+                int64_t e = entry_of(c->g, u, v);
+                int64_t pid = c->upre[u] + (e - c->ufirst[u]);
+                c->out[(size_t)pid * (size_t)c->ncls + (size_t)id]++;
+            }
+        return;
+    }
     if (c->forced >= 0) {
         c->out[(size_t)c->forced_row * (size_t)c->ncls + (size_t)id]++;
         return;
@@ -315,7 +339,8 @@ static void *run_worker(void *p) {
  * chunks of CHUNK choices so that one high-degree start does not serialise the run. */
 static int run_esu(const sgraph *g, int k, const int32_t *cls, int ncls, int nthreads,
                    const int32_t *starts, const int32_t *rows, int64_t nstarts,
-                   int64_t nrows, uint64_t *out, uint64_t *totals) {
+                   int64_t nrows, uint64_t *out, uint64_t *totals,
+                   const int64_t *upre, const int64_t *ufirst) {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     int64_t ntasks = 0;
@@ -340,6 +365,7 @@ static int run_esu(const sgraph *g, int k, const int32_t *cls, int ncls, int nth
     for (int i = 0; i < nthreads; i++) {
         ws[i].ctx.g = g; ws[i].ctx.k = k; ws[i].ctx.cls = cls; ws[i].ctx.ncls = ncls;
         ws[i].ctx.forced = -1; ws[i].ctx.forced_row = -1;
+        ws[i].ctx.upre = upre; ws[i].ctx.ufirst = ufirst;
         ws[i].ctx.out = (uint64_t *)calloc(cells ? cells : 1, sizeof(uint64_t));
         ws[i].ctx.totals = (uint64_t *)calloc((size_t)ncls, sizeof(uint64_t));
         if (!ws[i].ctx.out || !ws[i].ctx.totals) rc = -1;
@@ -383,8 +409,38 @@ int oracle_count(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, i
     if (table_for(k, &cls, &ncls)) { free_sgraph(&g); return -1; }
     int32_t *starts = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
     for (int64_t v = 0; v < n; v++) starts[v] = (int32_t)v;
-    rc = run_esu(&g, k, cls, ncls, nthreads, starts, NULL, n, n, out, totals);
+    rc = run_esu(&g, k, cls, ncls, nthreads, starts, NULL, n, n, out, totals, NULL, NULL);
     free(starts); free(cls); free_sgraph(&g);
+    return rc;
+}
+
+/* Per-edge counts (Sec. 11, "count per edge"): out[pairs][ncls], row p = the p-th vertex
+ * pair {lo < hi} of G_U in ascending (lo, hi) order, returned in plo/phi; each entry is
+ * the number of connected k-sets of the class that contain both endpoints.  pairs must
+ * be the number oracle_graph_size reports, halved. */
+int oracle_count_edges(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, int k,
+                       int nthreads, int64_t pairs, uint64_t *out, int32_t *plo, int32_t *phi) {
+    if (k != 3 && k != 4) return -3;
+    sgraph g;
+    int rc = build_sgraph(n, m, src, dst, &g);
+    if (rc) return rc;
+    if (g.off[n] != 2 * pairs) { free_sgraph(&g); return -4; }
+    int32_t *cls; int ncls;
+    if (table_for(k, &cls, &ncls)) { free_sgraph(&g); return -1; }
+    int64_t *upre = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t *ufirst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t p = 0;
+    for (int64_t u = 0; u < n; u++) {
+        int64_t e = g.off[u];
+        while (e < g.off[u + 1] && g.nbr[e] < u) e++;
+        ufirst[u] = e;
+        upre[u] = p;
+        for (; e < g.off[u + 1]; e++, p++) { plo[p] = (int32_t)u; phi[p] = g.nbr[e]; }
+    }
+    int32_t *starts = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    for (int64_t v = 0; v < n; v++) starts[v] = (int32_t)v;
+    rc = run_esu(&g, k, cls, ncls, nthreads, starts, NULL, n, pairs, out, NULL, upre, ufirst);
+    free(starts); free(upre); free(ufirst); free(cls); free_sgraph(&g);
     return rc;
 }
 
@@ -403,7 +459,7 @@ int oracle_count_rows(int64_t n, int64_t m, const int32_t *src, const int32_t *d
     if (table_for(k, &cls, &ncls)) { free_sgraph(&g); return -1; }
     int32_t *rowid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nrows + 1));
     for (int64_t i = 0; i < nrows; i++) rowid[i] = (int32_t)i;
-    rc = run_esu(&g, k, cls, ncls, nthreads, rows, rowid, nrows, nrows, out, NULL);
+    rc = run_esu(&g, k, cls, ncls, nthreads, rows, rowid, nrows, nrows, out, NULL, NULL, NULL);
     free(rowid); free(cls); free_sgraph(&g);
     return rc;
 }

@@ -13,7 +13,9 @@ from .vdmc import (  # noqa: F401
     count34,
     count_range,
     count_batch,
+    count_edges,
     count_undirected,
+    edge_list,
     kernel_times,
     load,
     num_classes,

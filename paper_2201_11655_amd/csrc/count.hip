@@ -77,6 +77,9 @@ struct GlobalSink {
     __device__ __forceinline__ void root4(const GraphView& gv, uint32_t r, uint32_t cls, unsigned long long c) const {
         atomicAdd(&gv.out4[(size_t)gv.perm[r] * kClasses4 + cls], c);
     }
+    __device__ __forceinline__ void set3(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t) const {}
+    __device__ __forceinline__ void set4(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
+                                         uint32_t, uint32_t, uint32_t) const {}
 };
 
 struct LdsSink {
@@ -99,6 +102,47 @@ struct LdsSink {
         const uint32_t sl = slot4[cls];
         if (sl != 0xFFu) atomicAdd(&cnt4[r * kCompact4 + sl], (uint32_t)c);
         else atomicAdd(&gv.out4[(size_t)gv.perm[r] * kClasses4 + cls], c);
+    }
+    __device__ __forceinline__ void set3(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t) const {}
+    __device__ __forceinline__ void set4(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
+                                         uint32_t, uint32_t, uint32_t) const {}
+};
+
+// Per-edge counts (Sec. 11: credit the edges of each set instead of its vertices): every
+// vertex pair of a set that is joined in G_U gets one count of the set's class, in the
+// row the edge index gives it.  Vertex credits are dropped.
+struct EdgeSink {
+    const unsigned long long* table;   // the graph's edge hash
+    uint32_t bits;
+    const uint32_t* epid;              // slot -> output row of the pair
+    unsigned long long* out;           // pairs x C
+    uint32_t C;
+    __device__ __forceinline__ void c3(const GraphView&, uint32_t, uint32_t) const {}
+    __device__ __forceinline__ void c4(const GraphView&, uint32_t, uint32_t) const {}
+    __device__ __forceinline__ void root3(const GraphView&, uint32_t, uint32_t, unsigned long long) const {}
+    __device__ __forceinline__ void root4(const GraphView&, uint32_t, uint32_t, unsigned long long) const {}
+    __device__ __forceinline__ void pair(uint32_t u, uint32_t v, uint32_t cls) const {
+        const uint32_t h = edge_find(table, bits, u, v);
+        if (h != 0xFFFFFFFFu) atomicAdd(&out[(size_t)epid[h] * C + cls], 1ull);
+    }
+    // vertices v0..v2 / v0..v3 (v0 = the root) and the arc bits of their pairs
+    __device__ __forceinline__ void set3(uint32_t cls, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t c01,
+                                         uint32_t c02, uint32_t c12) const {
+        if (cls >= C) return;
+        if (c01) pair(v0, v1, cls);
+        if (c02) pair(v0, v2, cls);
+        if (c12) pair(v1, v2, cls);
+    }
+    __device__ __forceinline__ void set4(uint32_t cls, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
+                                         uint32_t c01, uint32_t c02, uint32_t c03, uint32_t c12,
+                                         uint32_t c13c23) const {
+        if (cls >= C) return;
+        if (c01) pair(v0, v1, cls);
+        if (c02) pair(v0, v2, cls);
+        if (c03) pair(v0, v3, cls);
+        if (c12) pair(v1, v2, cls);
+        if (c13c23 & 3u) pair(v1, v3, cls);
+        if (c13c23 >> 2) pair(v2, v3, cls);
     }
 };
 
@@ -142,6 +186,7 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
         const uint32_t ab = arc_bits(gv.off, gv.adj, va, vb);
         if (K3) {
             const uint32_t cls = t3[motif_index3(ra, rb, ab)];
+            sink.set3(cls, r, va, vb, ra, rb, ab);
             if (cls < kClasses3) atomicAdd(&S.root3[cls], 1ull);
             sink.c3(gv, va, cls);
             sink.c3(gv, vb, cls);
@@ -154,6 +199,7 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                 const uint32_t ac = arc_bits(gv.off, gv.adj, va, vc);
                 const uint32_t bc = arc_bits(gv.off, gv.adj, vb, vc);
                 const uint32_t cls = t4[motif_index4(ra, rb, rc, ab, ac, bc)];
+                sink.set4(cls, r, va, vb, vc, ra, rb, rc, ab, ac | (bc << 2));
                 if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
                 sink.c4(gv, va, cls);
                 sink.c4(gv, vb, cls);
@@ -194,6 +240,7 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
             if (in_list(P, d, vc)) continue;   // c adjacent to r: depth 1, not 2
             if (K3) {
                 const uint32_t cls = t3[motif_index3(ra, 0u, ac)];
+                sink.set3(cls, r, va, vc, ra, 0u, ac);
                 if (cls < kClasses3) atomicAdd(&S.root3[cls], 1ull);
                 sink.c3(gv, va, cls);
                 sink.c3(gv, vc, cls);
@@ -209,6 +256,7 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                     if (bc && j < i) continue;   // c hangs under the lower-rank parent b
                     const uint32_t ab = arc_bits(gv.off, gv.adj, va, vb);
                     const uint32_t cls = t4[motif_index4(ra, rb, 0u, ab, ac, bc)];
+                    sink.set4(cls, r, va, vb, vc, ra, rb, 0u, ab, ac | (bc << 2));
                     if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
                     sink.c4(gv, va, cls);
                     sink.c4(gv, vb, cls);
@@ -223,6 +271,7 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                     if (in_list(P, d, vc2)) continue;
                     const uint32_t cc2 = arc_bits(gv.off, gv.adj, vc, vc2);
                     const uint32_t cls = t4[motif_index4(ra, 0u, 0u, ac, e2 & 3u, cc2)];
+                    sink.set4(cls, r, va, vc, vc2, ra, 0u, 0u, ac, (e2 & 3u) | (cc2 << 2));
                     if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
                     sink.c4(gv, va, cls);
                     sink.c4(gv, vc, cls);
@@ -237,6 +286,7 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                     if (in_list(P, d, ve)) continue;                // also excludes a itself
                     if (arc_bits(gv.off, gv.adj, va, ve)) continue; // e adjacent to a: depth 2
                     const uint32_t cls = t4[motif_index4(ra, 0u, 0u, ac, 0u, e3 & 3u)];
+                    sink.set4(cls, r, va, vc, ve, ra, 0u, 0u, ac, (e3 & 3u) << 2);
                     if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
                     sink.c4(gv, va, cls);
                     sink.c4(gv, vc, cls);
@@ -265,6 +315,18 @@ __global__ __launch_bounds__(kThreads) void k_count_roots(Args a) {
         if (r < a.rank_lo || r >= a.rank_hi) continue;   // uniform across the workgroup
         process_root<kThreads, kStage, K3, K4>(gv, a.t3, a.t4, r, S, shape, GlobalSink());
     }
+    for (int s = 0; s < kShapes; s++)
+        if (shape[s]) atomicAdd(&a.stats[s], shape[s]);
+}
+
+// Per-edge counts: every root with a non-empty higher neighbourhood, edges credited
+template <bool K3, bool K4>
+__global__ __launch_bounds__(kThreads) void k_count_edges(Args a, EdgeSink es) {
+    __shared__ RootLds<kStage> S;
+    unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
+    GraphView gv{a.off, a.adj, a.split, a.perm, nullptr, nullptr, a.stats};
+    for (int64_t ri = blockIdx.x; ri < a.nroots; ri += gridDim.x)
+        process_root<kThreads, kStage, K3, K4>(gv, a.t3, a.t4, a.roots[ri], S, shape, es);
     for (int s = 0; s < kShapes; s++)
         if (shape[s]) atomicAdd(&a.stats[s], shape[s]);
 }
@@ -455,6 +517,35 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
     }
     launch_hub(g, k3, k4, out3, out4, st, lo, hi, g->ev + 2);
     g->timed_hub = g->nhub > 0;
+}
+
+void launch_count_edges(vdmc_graph_s* g, int k, uint64_t* out, hipStream_t st) {
+    const ClassTables& t = class_tables();
+    ensure_edge_index(g, st);
+    const int C = num_classes(k);
+    launch_fill_u64((uint64_t*)g->stats, kStatSlots, 0, st);
+    if (g->pairs == 0) return;
+    launch_fill_u64(out, (size_t)g->pairs * C, 0, st);
+    if (g->nroots == 0) return;
+    Args a;
+    a.off = g->off;
+    a.adj = g->adj;
+    a.split = g->split;
+    a.perm = g->perm;
+    a.roots = g->roots;
+    a.nroots = g->nroots;
+    a.t3 = t.t3;
+    a.t4 = t.t4;
+    a.out3 = a.out4 = nullptr;
+    a.stats = g->stats;
+    a.rank_lo = 0;
+    a.rank_hi = 0xFFFFFFFFu;
+    const EdgeSink es{g->ehash, g->ehash_bits, g->epid, (unsigned long long*)out, (uint32_t)C};
+    const unsigned blocks = (unsigned)std::min<int64_t>(g->nroots, 65536);
+    if (k == 3) hipLaunchKernelGGL((k_count_edges<true, false>), dim3(blocks), dim3(kThreads), 0, st, a, es);
+    else hipLaunchKernelGGL((k_count_edges<false, true>), dim3(blocks), dim3(kThreads), 0, st, a, es);
+    VDMC_HIP(hipGetLastError());
+    g->timed_light = g->timed_hub = false;
 }
 
 }  // namespace vdmc

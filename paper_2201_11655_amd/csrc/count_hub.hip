@@ -1091,14 +1091,26 @@ void free_hub(vdmc_graph_s* g) {
     (void)hipFree(g->hub_scratch);
     (void)hipFree(g->hub_queue);
     (void)hipFree(g->hub_comp);
-    (void)hipFree(g->ehash);
     g->hub_comp = nullptr;
-    g->ehash = nullptr;
-    g->ehash_bits = 0;
     g->light = g->hubs = nullptr;
     g->hub_scratch = nullptr;
     g->hub_queue = nullptr;
     g->bins_hub_min = -1;
+}
+
+void ensure_edge_hash(vdmc_graph_s* g, hipStream_t st) {
+    if (g->ehash) return;
+    uint32_t eb = 10;   // load <= 1/4
+    while (((size_t)1 << eb) < 4 * (size_t)std::max<int64_t>(g->pairs, 1)) eb++;
+    const size_t eh_bytes = ((size_t)1 << eb) * sizeof(unsigned long long);
+    VDMC_HIP(hipMalloc(&g->ehash, eh_bytes));
+    VDMC_HIP(hipMemsetAsync(g->ehash, 0, eh_bytes, st));
+    const unsigned blocks = (unsigned)std::min<int64_t>((g->n + BT - 1) / BT, 65536);
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_edge_hash, dim3(blocks), dim3(BT), 0, st, g->off, g->split, g->adj, g->n, g->ehash, eb);
+    VDMC_HIP(hipGetLastError());
+    VDMC_HIP(hipStreamSynchronize(st));
+    g->ehash_bits = eb;
 }
 
 void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
@@ -1195,22 +1207,8 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         VDMC_HIP(hipMemsetAsync(g->hub_comp, 0, comp_bytes, st));   // cleared again by every fold
         VDMC_HIP(hipStreamSynchronize(st));
         g->hub_scratch_bytes += comp_bytes;
-        // edge hash at load <= 1/4
-        uint32_t eb = 10;
-        while (((size_t)1 << eb) < 4 * (size_t)std::max<int64_t>(g->pairs, 1)) eb++;
-        const size_t eh_bytes = ((size_t)1 << eb) * sizeof(unsigned long long);
-        VDMC_HIP(hipMalloc(&g->ehash, eh_bytes));
-        VDMC_HIP(hipMemsetAsync(g->ehash, 0, eh_bytes, st));
-        {
-            const unsigned blocks = (unsigned)std::min<int64_t>((g->n + BT - 1) / BT, 65536);
-            if (blocks > 0)
-                hipLaunchKernelGGL(k_edge_hash, dim3(blocks), dim3(BT), 0, st, g->off, g->split, g->adj, g->n,
-                                   g->ehash, eb);
-            VDMC_HIP(hipGetLastError());
-        }
-        VDMC_HIP(hipStreamSynchronize(st));
-        g->ehash_bits = eb;
-        g->hub_scratch_bytes += eh_bytes;
+        ensure_edge_hash(g, st);
+        g->hub_scratch_bytes += ((size_t)1 << g->ehash_bits) * sizeof(unsigned long long);
         g->hub_layout[0] = o;
         g->hub_layout[1] = o_spar;
         g->hub_layout[2] = o_s111;

@@ -349,7 +349,15 @@ static void build_graph(int64_t n, int64_t m, const int32_t* src, const int32_t*
 static void free_graph_arrays(vdmc_graph_s* g) {
     free_hub(g);
     (void)hipFree(g->utmp);
+    (void)hipFree(g->ehash);
+    (void)hipFree(g->epid);
+    (void)hipFree(g->elo);
+    (void)hipFree(g->ehi);
     g->utmp = nullptr;
+    g->ehash = nullptr;
+    g->ehash_bits = 0;
+    g->epid = nullptr;
+    g->elo = g->ehi = nullptr;
     (void)hipFree(g->off);
     (void)hipFree(g->adj);
     (void)hipFree(g->split);

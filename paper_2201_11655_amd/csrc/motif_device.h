@@ -55,6 +55,20 @@ __device__ __forceinline__ uint32_t edge_code(const unsigned long long* __restri
     }
 }
 
+// slot of the pair (u, v) in the edge hash, or 0xFFFFFFFF if the pair is not in the graph
+// (the probe stops at the first empty slot; the table is never full)
+__device__ __forceinline__ uint32_t edge_find(const unsigned long long* __restrict__ table, uint32_t bits,
+                                              uint32_t u, uint32_t v) {
+    const uint32_t lo = u < v ? u : v, hi = u < v ? v : u;
+    const unsigned long long key = ((unsigned long long)lo << 32) | ((unsigned long long)hi << 2);
+    const uint32_t mask = (1u << bits) - 1u;
+    for (uint32_t h = edge_slot(key, bits);; h = (h + 1u) & mask) {
+        const unsigned long long s = table[h];
+        if (s == 0ull) return 0xFFFFFFFFu;
+        if ((s & ~3ull) == key) return h;
+    }
+}
+
 // Motif index (Sec. 4.1): the adjacency matrix of the ordered vertices v0..v{k-1},
 // row = source, read row by row without the diagonal, first entry most significant.
 // p_ij (i < j) are the arc bits of (v_i, v_j) seen from v_i: bit 0 sets entry (i,j),

@@ -132,6 +132,9 @@ struct vdmc_graph_s {
     void* hub_comp = nullptr;    // n x kCompact4 uint64 rank-indexed accumulator
     unsigned long long* ehash = nullptr;   // edge hash: every pair of the graph, 2^ehash_bits slots
     uint32_t ehash_bits = 0;
+    uint32_t* epid = nullptr;    // per edge-hash slot: output row of the pair (per-edge counts)
+    int32_t* elo = nullptr;      // per output row: the pair's endpoints (original ids, lo < hi)
+    int32_t* ehi = nullptr;
     size_t hub_layout[16] = {0};
     // timing of the last count call: [0,1] around the per-set kernel, [2,3] around the
     // hub kernel (created at the first count)
@@ -187,6 +190,9 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
 void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t stream);
 // hub path (count_hub.hip)
 void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t stream);
+void ensure_edge_hash(vdmc_graph_s* g, hipStream_t stream);    // count_hub.hip
+void ensure_edge_index(vdmc_graph_s* g, hipStream_t stream);   // edges.hip
+void launch_count_edges(vdmc_graph_s* g, int k, uint64_t* out, hipStream_t stream);   // count.hip
 void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t stream,
                 uint32_t rank_lo = 0, uint32_t rank_hi = 0xFFFFFFFFu, const hipEvent_t* around = nullptr);
 int hub_min_default();

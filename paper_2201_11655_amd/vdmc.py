@@ -20,6 +20,7 @@ SYMBOLS = [
     "vdmc_build_graph", "vdmc_graph_info", "vdmc_graph_export", "vdmc_free_graph",
     "vdmc_count", "vdmc_count_range", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters",
     "vdmc_kernel_times", "vdmc_num_classes_undirected", "vdmc_undirected_classes", "vdmc_count_undirected",
+    "vdmc_edge_list", "vdmc_count_edges",
     "vdmc_count_batch", "vdmc_tune",
     "vdmc_serve_create", "vdmc_serve_submit", "vdmc_serve_poll", "vdmc_serve_wait",
     "vdmc_serve_stats", "vdmc_serve_destroy",
@@ -71,6 +72,8 @@ def load():
         "vdmc_num_classes_undirected": ([i32], i32),
         "vdmc_undirected_classes": ([i32, p], i32),
         "vdmc_count_undirected": ([p, i32, p, p], i32),
+        "vdmc_edge_list": ([p, p, p], i32),
+        "vdmc_count_edges": ([p, i32, p, p], i32),
         "vdmc_count_batch": ([p, i32, i32, p, p], i32),
         "vdmc_tune": ([p, i32, i32, ctypes.c_char_p], i32),
         "vdmc_serve_create": ([p, p], i32),
@@ -227,6 +230,29 @@ def count_undirected(g: Graph, k: int, out=None, stream=None):
     if out.dtype != torch.int64 or not out.is_cuda or not out.is_contiguous() or out.numel() != g.n * U:
         raise VdmcError(1, f"out must be a contiguous int64 CUDA tensor of {g.n}x{U}")
     _check(lib.vdmc_count_undirected(g.handle, int(k), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def edge_list(g: Graph):
+    """(lo[P], hi[P]) original-id endpoints of the G_U pairs, in per-edge output order."""
+    lo = np.zeros(max(g.pairs, 1), np.int32)
+    hi = np.zeros(max(g.pairs, 1), np.int32)
+    _check(load().vdmc_edge_list(g.handle, _np_ptr(lo), _np_ptr(hi)))
+    return lo[:g.pairs].copy(), hi[:g.pairs].copy()
+
+
+def count_edges(g: Graph, k: int, out=None, stream=None):
+    """Per-edge k-motif counts, int64[P, C] on the device (row order of ``edge_list``)."""
+    lib = load()
+    C = num_classes(k)
+    if C < 0:
+        _check(lib.vdmc_count_edges(g.handle, int(k), None, _stream_handle(stream)))
+    torch = _torch()
+    if out is None:
+        out = torch.empty((g.pairs, C), dtype=torch.int64, device="cuda")
+    if out.dtype != torch.int64 or not out.is_cuda or not out.is_contiguous() or out.numel() != g.pairs * C:
+        raise VdmcError(1, f"out must be a contiguous int64 CUDA tensor of {g.pairs}x{C}")
+    _check(lib.vdmc_count_edges(g.handle, int(k), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 

@@ -292,3 +292,33 @@ def test_undirected_errors(v):
     assert e.value.name in ("UNSUPPORTED", "INVALID_ARG")
     G0 = v.Graph(0, np.zeros(0, np.int32), np.zeros(0, np.int32), undirected=True)
     assert v.count_undirected(G0, 4).shape == (0, 6)
+
+
+# --------------------------------------------------------------------------- per-edge counts
+
+@pytest.mark.parametrize("case", ["er60_dense", "er200", "chunglu_2000", "star_and_clique"])
+def test_edge_parity(v, case):
+    g = _undirected_cases()[case]
+    _say(f"per-edge case {case} n={g.n} m={g.m}")
+    G = v.Graph(g.n, g.src, g.dst)
+    lo, hi = v.edge_list(G)
+    for k in (3, 4):
+        olo, ohi, want = oracle.count_edges(g.n, g.src, g.dst, k)
+        assert (lo == olo).all() and (hi == ohi).all()
+        got = _np(v.count_edges(G, k))
+        assert got.shape == want.shape
+        bad = np.argwhere(got != want)
+        assert bad.size == 0, f"{case} k={k}: {bad.shape[0]} cells differ, first {bad[:5].tolist()}"
+
+
+def test_edge_counts_edge_cases(v):
+    G0 = v.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert v.count_edges(G0, 4).shape == (0, 199)
+    assert v.edge_list(G0)[0].shape == (0,)
+    G1 = v.Graph(3, np.array([0, 1, 1], np.int32), np.array([1, 0, 2], np.int32))   # one reciprocal pair
+    got = _np(v.count_edges(G1, 3))
+    olo, ohi, want = oracle.count_edges(3, np.array([0, 1, 1]), np.array([1, 0, 2]), 3)
+    assert (got == want).all() and got.sum() == 2
+    with pytest.raises(v.VdmcError) as e:
+        v.count_edges(G1, 5)
+    assert e.value.name in ("UNSUPPORTED", "INVALID_ARG")

@@ -385,3 +385,36 @@ def test_undirected_equals_brute_force(seed):
         want = ex.count_undirected(g.n, g.src, g.dst, k)
         for nm in ex.UNDIRECTED_NAMES[k]:
             assert (got[nm] == want[nm]).all(), (k, nm)
+
+
+# --------------------------------------------------------------------------- per-edge counts
+
+@pytest.mark.parametrize("seed", range(5))
+def test_edge_counts_equal_brute_force(seed):
+    g = gg.er_directed(10, 0.25, (43, seed))
+    for k in (3, 4):
+        lo, hi, got = oracle.count_edges(g.n, g.src, g.dst, k)
+        pairs, want = ex.count_edges(g.n, g.src, g.dst, k)
+        assert list(zip(lo.tolist(), hi.tolist())) == pairs
+        assert (got == want).all()
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_edge_counts_closed_forms_and_invariant(k):
+    comb = math.comb
+    # complete bidirected graph K6: every edge lies in C(4, k-2) sets, all of the last class
+    n = 6
+    s = np.array([i for i in range(n) for j in range(n) if i != j], np.int32)
+    d = np.array([j for i in range(n) for j in range(n) if i != j], np.int32)
+    lo, hi, got = oracle.count_edges(n, s, d, k)
+    assert len(lo) == comb(n, 2)
+    assert (got[:, -1] == comb(n - 2, k - 2)).all() and got[:, :-1].sum() == 0
+    # any graph: summing a class's edge counts gives (edges of the class) x (its sets)
+    g = gg.er_directed(40, 0.1, (44, k))
+    lo, hi, got = oracle.count_edges(g.n, g.src, g.dst, k)
+    _, tot = oracle.count(g.n, g.src, g.dst, k)
+    _, _, codes = oracle.class_table(k)
+    for c in range(len(codes)):
+        A = ex.matrix_of(k, int(codes[c]))
+        ne = sum(1 for i in range(k) for j in range(i + 1, k) if A[i][j] or A[j][i])
+        assert int(got[:, c].sum()) == ne * int(tot[c])
