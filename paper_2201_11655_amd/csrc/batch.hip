@@ -116,6 +116,11 @@ Plan* build_plan(const vdmc_graph* gs, int num, int k, uint64_t* const* outs, co
             total += counts[i];
         }
         p->nentries = total;
+        // largest work first (pairs x largest degree as the estimate), so that the last
+        // workgroups to finish hold small graphs
+        std::stable_sort(small.begin(), small.end(), [&](uint32_t a, uint32_t b) {
+            return (double)gs[a]->pairs * gs[a]->max_deg > (double)gs[b]->pairs * gs[b]->max_deg;
+        });
         p->nsmall = (uint32_t)small.size();
         if (!small.empty()) {
             VDMC_HIP(hipMalloc(&p->d_small, sizeof(uint32_t) * small.size()));
