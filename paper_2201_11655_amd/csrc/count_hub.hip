@@ -60,6 +60,7 @@ struct HubArgs {
     uint32_t wl_cap;        // per-wave list capacity (>= max degree)
     const unsigned long long* ehash;   // the graph's edge hash (edge_code)
     uint32_t ehash_bits;
+    uint32_t* w111;              // n x 9 (rank-indexed): (1,1,1) parent codes per depth-2 vertex
 };
 
 // ----------------------------------------------------------------------------- helpers
@@ -700,31 +701,40 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 // set of x whose two depth-2 vertices c, e are adjacent; the (1,2,0) phase
                 // enumerates those and takes both orders (c, e) and (e, c) back out.  So a
                 // chunk of c's row needs no test against the parents' rows.
+                // The end vertex e of these paths is credited by a pass after the kernel: the
+                // parent codes of this group go into w111[c], and every vertex e later adds
+                // w111 of all its neighbours.  That pass also reaches the entries of c's row
+                // that are not valid here (e below r, or e in N+(r)); those are taken off now.
                 uint32_t T1 = 0, T2 = 0, T3 = 0;   // valid e of c's row by ce (wave-uniform)
                 for (uint32_t base = A.off[c]; base < chi; base += 64) {
                     const uint32_t tt = base + lane;
                     uint32_t ee = 0;
-                    bool ev = tt < chi;
-                    if (ev) {
+                    bool ev = false, inv = false;
+                    if (tt < chi) {
                         ee = A.adj[tt];
-                        ev = (ee >> 2) > r && find_slot_f(L, d, ee >> 2) < 0;
+                        if ((ee >> 2) < r) inv = true;
+                        else if (find_slot_f(L, d, ee >> 2) >= 0) inv = true;
+                        else ev = true;
                     }
-                    if (!__ballot(ev)) continue;
                     if (lane == 0) { work[1]++; work[2] += p; }
                     const uint32_t e = ee >> 2, ce = ee & 3u;
                     T1 += __popcll(__ballot(ev && ce == 1u));
                     T2 += __popcll(__ballot(ev && ce == 2u));
                     T3 += __popcll(__ballot(ev && ce == 3u));
-                    if (ev) {
-                        shape[5] += p;
+                    if (ev) shape[5] += p;
+                    if (inv)
                         for (uint32_t q = 0; q < 9; q++) {
                             const unsigned long long w = q < 3 ? hist1 : (q < 6 ? hist2 : hist3);
                             const uint32_t cnt = (uint32_t)(w >> (21u * (q % 3))) & F21;
                             if (cnt)
-                                add4(A, L, e,
-                                        L.t4[motif_index4(q / 3 + 1, 0u, 0u, q % 3 + 1, 0u, ce)], cnt);
+                                add4(A, L, e, L.t4[motif_index4(q / 3 + 1, 0u, 0u, q % 3 + 1, 0u, ce)],
+                                     0ull - (unsigned long long)cnt);
                         }
-                    }
+                }
+                if (lane < 9) {
+                    const unsigned long long w = lane < 3 ? hist1 : (lane < 6 ? hist2 : hist3);
+                    const uint32_t cnt = (uint32_t)(w >> (21u * (lane % 3))) & F21;
+                    if (cnt) atomicAdd(&A.w111[(size_t)c * 9 + lane], cnt);
                 }
                 // every parent x is on T_k of these paths with ce = k (x's and c's credits)
                 if (T1 | T2 | T3)
@@ -1046,6 +1056,29 @@ __global__ void k_split_bins(const uint32_t* __restrict__ roots, const uint32_t*
 }
 
 // out4[perm[v]][class of slot s] += comp[v][s], and comp is cleared for the next launch
+// (1,1,1) end-vertex credits: vertex e adds, for every neighbour c, the parent codes
+// that c's groups recorded (w111[c][(rx - 1) * 3 + (xc - 1)]), as the path class with the
+// arc code ce of c -> e.  One thread per vertex, so the accumulator needs no atomics (the
+// hub kernel has finished).
+__global__ void k_pull111(const uint32_t* __restrict__ off, const uint32_t* __restrict__ adj,
+                          const uint32_t* __restrict__ w111, const uint8_t* __restrict__ t4,
+                          const uint8_t* __restrict__ slot4, int64_t n, unsigned long long* __restrict__ comp) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long* row = comp + (size_t)e * kCompact4;
+        for (uint32_t t = off[e]; t < off[e + 1]; t++) {
+            const uint32_t ent = adj[t], c = ent >> 2, ce = swap_arc_bits(ent & 3u);
+            const uint32_t* w = w111 + (size_t)c * 9;
+            for (uint32_t q = 0; q < 9; q++) {
+                const uint32_t cnt = w[q];
+                if (!cnt) continue;
+                const uint32_t cls = t4[motif_index4(q / 3 + 1, 0u, 0u, q % 3 + 1, 0u, ce)];
+                const uint32_t sl = cls < kClasses4 ? slot4[cls] : 0xFFu;
+                if (sl < (uint32_t)kCompact4) row[sl] += cnt;   // always a path class
+            }
+        }
+    }
+}
+
 __global__ void k_fold_compact(unsigned long long* __restrict__ comp, const uint8_t* __restrict__ slotcls,
                                const int32_t* __restrict__ perm, int64_t n, unsigned long long* __restrict__ out4) {
     const int64_t total = n * kCompact4;
@@ -1061,6 +1094,11 @@ __global__ void k_fold_compact(unsigned long long* __restrict__ comp, const uint
 
 __global__ void k_zero_u32(unsigned* p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+__global__ void k_fill_zero_u32(uint32_t* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 int g_num_cu = -1;
@@ -1091,7 +1129,9 @@ void free_hub(vdmc_graph_s* g) {
     (void)hipFree(g->hub_scratch);
     (void)hipFree(g->hub_queue);
     (void)hipFree(g->hub_comp);
+    (void)hipFree(g->hub_w111);
     g->hub_comp = nullptr;
+    g->hub_w111 = nullptr;
     g->light = g->hubs = nullptr;
     g->hub_scratch = nullptr;
     g->hub_queue = nullptr;
@@ -1207,6 +1247,9 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         VDMC_HIP(hipMemsetAsync(g->hub_comp, 0, comp_bytes, st));   // cleared again by every fold
         VDMC_HIP(hipStreamSynchronize(st));
         g->hub_scratch_bytes += comp_bytes;
+        const size_t w_bytes = (size_t)std::max<int64_t>(g->n, 1) * 9 * sizeof(uint32_t);
+        VDMC_HIP(hipMalloc(&g->hub_w111, w_bytes));
+        g->hub_scratch_bytes += w_bytes;
         ensure_edge_hash(g, st);
         g->hub_scratch_bytes += ((size_t)1 << g->ehash_bits) * sizeof(unsigned long long);
         g->hub_layout[0] = o;
@@ -1263,13 +1306,21 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.ehash = g->ehash;
     a.ehash_bits = g->ehash_bits;
     a.slot4 = t.slot4;
+    a.w111 = (uint32_t*)g->hub_w111;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 4);
+    const int64_t wcells = g->n * 9;
+    const unsigned vblocks = (unsigned)std::min<int64_t>((g->n + 255) / 256, 65536);
+    if (k4)
+        hipLaunchKernelGGL(k_fill_zero_u32, dim3((unsigned)std::min<int64_t>((wcells + 255) / 256, 65536)), dim3(256),
+                           0, st, a.w111, wcells);
     const int wgs = hub_workgroups();
     if (around) VDMC_HIP(hipEventRecord(around[0], st));
     hipLaunchKernelGGL(k_hub, dim3(wgs), dim3(HT), 0, st, a);
     VDMC_HIP(hipGetLastError());
     if (around) VDMC_HIP(hipEventRecord(around[1], st));
     if (k4) {
+        hipLaunchKernelGGL(k_pull111, dim3(vblocks), dim3(256), 0, st, g->off, g->adj, a.w111, t.t4, t.slot4, g->n,
+                           (unsigned long long*)g->hub_comp);
         const int64_t cells = g->n * kCompact4;
         const unsigned blocks = (unsigned)std::min<int64_t>((cells + 255) / 256, 65536);
         hipLaunchKernelGGL(k_fold_compact, dim3(blocks), dim3(256), 0, st, (unsigned long long*)g->hub_comp,

@@ -130,6 +130,7 @@ struct vdmc_graph_s {
     size_t hub_scratch_bytes = 0;
     unsigned* hub_queue = nullptr;
     void* hub_comp = nullptr;    // n x kCompact4 uint64 rank-indexed accumulator
+    void* hub_w111 = nullptr;    // n x 9 uint32: (1,1,1) parent codes per depth-2 vertex
     unsigned long long* ehash = nullptr;   // edge hash: every pair of the graph, 2^ehash_bits slots
     uint32_t ehash_bits = 0;
     uint32_t* epid = nullptr;    // per edge-hash slot: output row of the pair (per-edge counts)
