@@ -233,8 +233,8 @@ def main():
 HUB_COUNTER_SOURCES = ["paper_2201_11655_amd/csrc/count_hub.hip", "paper_2201_11655_amd/csrc/vdmc_internal.h",
                        "paper_2201_11655_amd/csrc/motif_device.h"]
 HUB_COUNTERS = {     # workload -> counters of one hub-kernel dispatch (profiles/k_hub_chunglu_1M_hbm_counters.md)
-    "chunglu": {"sources_sha256": "e7e82b01f989912b026ef402369e6f19e600f51b1e580ffc91a76aee889ce06b",
-                "fetch_kib": 1816686742.9, "write_kib": 1177642468.4},
+    "chunglu": {"sources_sha256": "4dfd777c7345423dac25a0196dabc79e9d523eddfec8057d0e237acc11ffff29",
+                "fetch_kib": 1790133367.9, "write_kib": 550327453.8},
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
