@@ -108,7 +108,8 @@ Plan* build_plan(const vdmc_graph* gs, int num, int k, uint64_t* const* outs, co
             }
             views[i] = GraphView{g->off, g->adj, g->split, g->perm,
                                  k == 3 ? (unsigned long long*)outs[i] : nullptr,
-                                 k == 4 ? (unsigned long long*)outs[i] : nullptr, g->stats};
+                                 k == 4 ? (unsigned long long*)outs[i] : nullptr, g->stats, g->ehash,
+                                 g->ehash_bits};
             nvert[i] = (uint64_t)g->n;
             lists[i] = g->light;
             counts[i] = p->is_small[i] ? 0ull : (unsigned long long)g->nlight;

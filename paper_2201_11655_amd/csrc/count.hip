@@ -41,7 +41,15 @@ struct Args {
     unsigned long long* out4;   // n x 199
     unsigned long long* stats;  // kShapes
     uint32_t rank_lo, rank_hi;  // only roots with rank in [rank_lo, rank_hi)
+    const unsigned long long* ehash;   // edge hash or nullptr
+    uint32_t ehash_bits;
 };
+
+// arc bits of (u, v) seen from u: one probe sequence in the edge hash when the graph has
+// one, else a binary search of the shorter row
+__device__ __forceinline__ uint32_t gv_arc(const GraphView& gv, uint32_t u, uint32_t v) {
+    return gv.ehash ? edge_code(gv.ehash, gv.ehash_bits, u, v) : arc_bits(gv.off, gv.adj, u, v);
+}
 
 // rank x a member of the sorted list P[0..d) ?
 __device__ __forceinline__ bool in_list(const uint32_t* P, uint32_t d, uint32_t x) {
@@ -183,7 +191,7 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
         const uint32_t i = (uint32_t)(q - (uint64_t)j * (j - 1) / 2);
         const uint32_t ea = P[i], eb = P[j];
         const uint32_t va = ea >> 2, vb = eb >> 2, ra = ea & 3u, rb = eb & 3u;
-        const uint32_t ab = arc_bits(gv.off, gv.adj, va, vb);
+        const uint32_t ab = gv_arc(gv, va, vb);
         if (K3) {
             const uint32_t cls = t3[motif_index3(ra, rb, ab)];
             sink.set3(cls, r, va, vb, ra, rb, ab);
@@ -196,8 +204,8 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
             for (uint32_t l = j + 1; l < d; l++) {
                 const uint32_t ec = P[l];
                 const uint32_t vc = ec >> 2, rc = ec & 3u;
-                const uint32_t ac = arc_bits(gv.off, gv.adj, va, vc);
-                const uint32_t bc = arc_bits(gv.off, gv.adj, vb, vc);
+                const uint32_t ac = gv_arc(gv, va, vc);
+                const uint32_t bc = gv_arc(gv, vb, vc);
                 const uint32_t cls = t4[motif_index4(ra, rb, rc, ab, ac, bc)];
                 sink.set4(cls, r, va, vb, vc, ra, rb, rc, ab, ac | (bc << 2));
                 if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
@@ -252,9 +260,9 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                     if (j == i) continue;
                     const uint32_t eb = P[j];
                     const uint32_t vb = eb >> 2, rb = eb & 3u;
-                    const uint32_t bc = arc_bits(gv.off, gv.adj, vb, vc);
+                    const uint32_t bc = gv_arc(gv, vb, vc);
                     if (bc && j < i) continue;   // c hangs under the lower-rank parent b
-                    const uint32_t ab = arc_bits(gv.off, gv.adj, va, vb);
+                    const uint32_t ab = gv_arc(gv, va, vb);
                     const uint32_t cls = t4[motif_index4(ra, rb, 0u, ab, ac, bc)];
                     sink.set4(cls, r, va, vb, vc, ra, rb, 0u, ab, ac | (bc << 2));
                     if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
@@ -269,7 +277,7 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                     const uint32_t e2 = gv.adj[t2];
                     const uint32_t vc2 = e2 >> 2;
                     if (in_list(P, d, vc2)) continue;
-                    const uint32_t cc2 = arc_bits(gv.off, gv.adj, vc, vc2);
+                    const uint32_t cc2 = gv_arc(gv, vc, vc2);
                     const uint32_t cls = t4[motif_index4(ra, 0u, 0u, ac, e2 & 3u, cc2)];
                     sink.set4(cls, r, va, vc, vc2, ra, 0u, 0u, ac, (e2 & 3u) | (cc2 << 2));
                     if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
@@ -284,7 +292,7 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
                     const uint32_t e3 = gv.adj[t3i];
                     const uint32_t ve = e3 >> 2;
                     if (in_list(P, d, ve)) continue;                // also excludes a itself
-                    if (arc_bits(gv.off, gv.adj, va, ve)) continue; // e adjacent to a: depth 2
+                    if (gv_arc(gv, va, ve)) continue; // e adjacent to a: depth 2
                     const uint32_t cls = t4[motif_index4(ra, 0u, 0u, ac, 0u, e3 & 3u)];
                     sink.set4(cls, r, va, vc, ve, ra, 0u, 0u, ac, (e3 & 3u) << 2);
                     if (cls < kClasses4) atomicAdd(&S.root4[cls], 1ull);
@@ -309,7 +317,7 @@ template <bool K3, bool K4>
 __global__ __launch_bounds__(kThreads) void k_count_roots(Args a) {
     __shared__ RootLds<kStage> S;
     unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
-    GraphView gv{a.off, a.adj, a.split, a.perm, a.out3, a.out4, a.stats};
+    GraphView gv{a.off, a.adj, a.split, a.perm, a.out3, a.out4, a.stats, a.ehash, a.ehash_bits};
     for (int64_t ri = blockIdx.x; ri < a.nroots; ri += gridDim.x) {
         const uint32_t r = a.roots[ri];
         if (r < a.rank_lo || r >= a.rank_hi) continue;   // uniform across the workgroup
@@ -324,7 +332,7 @@ template <bool K3, bool K4>
 __global__ __launch_bounds__(kThreads) void k_count_edges(Args a, EdgeSink es) {
     __shared__ RootLds<kStage> S;
     unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
-    GraphView gv{a.off, a.adj, a.split, a.perm, nullptr, nullptr, a.stats};
+    GraphView gv{a.off, a.adj, a.split, a.perm, nullptr, nullptr, a.stats, a.ehash, a.ehash_bits};
     for (int64_t ri = blockIdx.x; ri < a.nroots; ri += gridDim.x)
         process_root<kThreads, kStage, K3, K4>(gv, a.t3, a.t4, a.roots[ri], S, shape, es);
     for (int s = 0; s < kShapes; s++)
@@ -504,6 +512,8 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
         a.stats = g->stats;
         a.rank_lo = lo;
         a.rank_hi = hi;
+        a.ehash = g->ehash;
+        a.ehash_bits = g->ehash_bits;
         int64_t blocks = g->nlight < 65536 ? g->nlight : 65536;
         if (k3 && k4)
             hipLaunchKernelGGL((k_count_roots<true, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
@@ -540,6 +550,8 @@ void launch_count_edges(vdmc_graph_s* g, int k, uint64_t* out, hipStream_t st) {
     a.stats = g->stats;
     a.rank_lo = 0;
     a.rank_hi = 0xFFFFFFFFu;
+    a.ehash = g->ehash;
+    a.ehash_bits = g->ehash_bits;
     const EdgeSink es{g->ehash, g->ehash_bits, g->epid, (unsigned long long*)out, (uint32_t)C};
     const unsigned blocks = (unsigned)std::min<int64_t>(g->nroots, 65536);
     if (k == 3) hipLaunchKernelGGL((k_count_edges<true, false>), dim3(blocks), dim3(kThreads), 0, st, a, es);

@@ -153,6 +153,8 @@ struct GraphView {
     unsigned long long* out3;
     unsigned long long* out4;
     unsigned long long* stats;
+    const unsigned long long* ehash = nullptr;   // edge hash if the graph has one (adjacency tests)
+    uint32_t ehash_bits = 0;
 };
 // batched launch over many graphs (count.hip / batch.hip)
 struct BatchArgs {
