@@ -551,19 +551,32 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         }
         uint32_t* cw = L.cw[wid];
         uint32_t* inA = L.inA[wid];
-        for (int t = wave_next(&L.task); t < (int)ngroups; t = wave_next(&L.task)) {
-            const uint32_t c = grp[t];
+        // The next group's vertex, row bounds and first row chunk are loaded in stages while
+        // the current group is processed, so that a group does not start with a chain of
+        // dependent loads.
+        int t = wave_next(&L.task);
+        uint32_t cN = 0, loN = 0, hiN = 0, e0N = 0;
+        if (t < (int)ngroups) {
+            cN = grp[t];
+            loN = A.off[cN];
+            hiN = A.off[cN + 1];
+            e0N = loN + lane < hiN ? A.adj[loN + lane] : 0u;
+        }
+        while (t < (int)ngroups) {
+            const uint32_t c = cN, clo = loN, chi = hiN, e0 = e0N;
+            const int tn = wave_next(&L.task);
+            const bool more = tn < (int)ngroups;
+            if (more) cN = grp[tn];
             if (lane == 0) work[0]++;
             // A(c): c's neighbours in N+(r), as (slot << 2) | arc bits seen from the slot
             uint32_t* Ac = wlist;
-            const uint32_t chi = A.off[c + 1];
             uint32_t p = 0;
-            for (uint32_t base = A.off[c]; base < chi; base += 64) {
+            for (uint32_t base = clo; base < chi; base += 64) {
                 const uint32_t tt = base + lane;
                 uint32_t e = 0;
                 int sl = -1;
                 if (tt < chi) {
-                    e = A.adj[tt];
+                    e = base == clo ? e0 : A.adj[tt];
                     if ((e >> 2) > r) sl = find_slot_f(L, d, e >> 2);
                 }
                 const unsigned long long mk = __ballot(sl >= 0);
@@ -574,6 +587,11 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             for (uint32_t u = lane; u < p; u += 64) {
                 const uint32_t x = Ac[u] >> 2;
                 atomicOr(&inA[x >> 5], 1u << (x & 31));
+            }
+            bool e0_done = false;
+            if (more) {   // next group: row bounds
+                loN = A.off[cN];
+                hiN = A.off[cN + 1];
             }
             if (A.k3) {
                 for (uint32_t u = lane; u < p; u += 64) {
@@ -695,6 +713,10 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     }
                 }
                 tg2 = wall_clock64();
+                if (more) {   // next group: first chunk
+                    e0N = loN + lane < hiN ? A.adj[loN + lane] : 0u;
+                    e0_done = true;
+                }
                 // (1,1,1): paths r - x - c - e, e above r, not in N(r), not adjacent to x.
                 // Counted by complement: here every x in A(c) is paired with every valid e
                 // of c's row, adjacent to x or not.  A pair with e adjacent to x is a (1,2,0)
@@ -706,7 +728,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 // w111 of all its neighbours.  That pass also reaches the entries of c's row
                 // that are not valid here (e below r, or e in N+(r)); those are taken off now.
                 uint32_t T1 = 0, T2 = 0, T3 = 0;   // valid e of c's row by ce (wave-uniform)
-                for (uint32_t base = A.off[c]; base < chi; base += 64) {
+                for (uint32_t base = clo; base < chi; base += 64) {
                     const uint32_t tt = base + lane;
                     uint32_t ee = 0;
                     bool ev = false, inv = false;
@@ -752,6 +774,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     }
             }
             tg3 = A.k4 ? wall_clock64() : tg0;
+            if (more && !e0_done) e0N = loN + lane < hiN ? A.adj[loN + lane] : 0u;
             // flush the group's depth-2 vertex (and the root, which is in every one of its sets)
             for (uint32_t q = lane; q < 27 + 27 + kClasses3; q += 64) {
                 const uint32_t cnt = cw[q];
@@ -779,6 +802,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 atomicAdd(&L.stat[26], tg3 - tg2);
                 atomicAdd(&L.stat[27], tg4 - tg3);
             }
+            t = tn;
         }
         __threadfence();
         __syncthreads();
