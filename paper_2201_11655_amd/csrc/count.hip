@@ -313,15 +313,18 @@ __device__ void process_root(const GraphView& gv, const uint8_t* t3, const uint8
             if (S.root4[i]) sink.root4(gv, r, i, S.root4[i]);
 }
 
-template <bool K3, bool K4>
-__global__ __launch_bounds__(kThreads) void k_count_roots(Args a) {
-    __shared__ RootLds<kStage> S;
+// BS threads per root; roots with more than STAGE higher neighbours read them from
+// global memory.  The one-wave variant (BS = STAGE = 64) takes the light roots when the
+// hub threshold is at most 64: no workgroup barrier spans more than one wave.
+template <int BS, uint32_t STAGE, bool K3, bool K4>
+__global__ __launch_bounds__(BS) void k_count_roots(Args a) {
+    __shared__ RootLds<STAGE> S;
     unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
     GraphView gv{a.off, a.adj, a.split, a.perm, a.out3, a.out4, a.stats, a.ehash, a.ehash_bits};
     for (int64_t ri = blockIdx.x; ri < a.nroots; ri += gridDim.x) {
         const uint32_t r = a.roots[ri];
         if (r < a.rank_lo || r >= a.rank_hi) continue;   // uniform across the workgroup
-        process_root<kThreads, kStage, K3, K4>(gv, a.t3, a.t4, r, S, shape, GlobalSink());
+        process_root<BS, STAGE, K3, K4>(gv, a.t3, a.t4, r, S, shape, GlobalSink());
     }
     for (int s = 0; s < kShapes; s++)
         if (shape[s]) atomicAdd(&a.stats[s], shape[s]);
@@ -514,13 +517,17 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
         a.rank_hi = hi;
         a.ehash = g->ehash;
         a.ehash_bits = g->ehash_bits;
-        int64_t blocks = g->nlight < 65536 ? g->nlight : 65536;
-        if (k3 && k4)
-            hipLaunchKernelGGL((k_count_roots<true, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
-        else if (k3)
-            hipLaunchKernelGGL((k_count_roots<true, false>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_count_roots<false, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, a);
+        const int64_t blocks = g->nlight < 65536 ? g->nlight : 65536;
+        const dim3 grid((unsigned)blocks);
+        if (g->bins_hub_min <= 64) {   // every light root has at most 63 higher neighbours
+            if (k3 && k4) hipLaunchKernelGGL((k_count_roots<64, 64, true, true>), grid, dim3(64), 0, st, a);
+            else if (k3) hipLaunchKernelGGL((k_count_roots<64, 64, true, false>), grid, dim3(64), 0, st, a);
+            else hipLaunchKernelGGL((k_count_roots<64, 64, false, true>), grid, dim3(64), 0, st, a);
+        } else {
+            if (k3 && k4) hipLaunchKernelGGL((k_count_roots<kThreads, kStage, true, true>), grid, dim3(kThreads), 0, st, a);
+            else if (k3) hipLaunchKernelGGL((k_count_roots<kThreads, kStage, true, false>), grid, dim3(kThreads), 0, st, a);
+            else hipLaunchKernelGGL((k_count_roots<kThreads, kStage, false, true>), grid, dim3(kThreads), 0, st, a);
+        }
         VDMC_HIP(hipGetLastError());
         VDMC_HIP(hipEventRecord(g->ev[1], st));
         g->timed_light = true;
