@@ -1144,7 +1144,7 @@ int hub_workgroups() {
 int hub_min_default() {
     const char* e = getenv("VDMC_HUB_MIN");
     if (e && *e) return atoi(e);
-    return 48;
+    return 32;
 }
 
 void free_hub(vdmc_graph_s* g) {
