@@ -55,7 +55,7 @@ struct HubArgs {
     // per-workgroup scratch
     uint32_t* scratch;
     size_t wg_words;        // u32 words per workgroup slice
-    size_t o_spar, o_s111, o_s3x, o_groups, o_wlist, o_c120, o_eflag, o_llist, o_hash;
+    size_t o_spar, o_s111, o_s3x, o_groups, o_wlist, o_eflag, o_llist;
     uint32_t hash_bits;     // per-wave hash table of 2^hash_bits (key, value) pairs
     uint32_t wl_cap;        // per-wave list capacity (>= max degree)
     const unsigned long long* ehash;   // the graph's edge hash (edge_code)
@@ -243,12 +243,8 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     uint32_t* s3x = W + A.o_s3x;       // [3][PMAX]  k=3 (1,2) depth-1 counters
     uint32_t* grp = W + A.o_groups;    // the depth-2 vertex c of every group
     uint32_t* wlist = W + A.o_wlist + (size_t)wid * A.wl_cap;
-    uint32_t* c120 = W + A.o_c120 + (size_t)wid * 3 * A.wl_cap;
     uint8_t* eflag = reinterpret_cast<uint8_t*>(W + A.o_eflag);
     uint16_t* llist = reinterpret_cast<uint16_t*>(W + A.o_llist);   // local neighbours per slot
-    const uint32_t hsize = 1u << A.hash_bits;
-    uint32_t* hkey = W + A.o_hash + (size_t)wid * 2 * hsize;        // per-wave: rank + 1, 0 = empty
-    uint32_t* hval = hkey + hsize;                                  // position in the list
     // per-thread counters of the current root (sets per shape, sets on the direct path),
     // reduced into L.stat once per root
     uint32_t shape[kShapes] = {0, 0, 0, 0, 0, 0};
@@ -270,7 +266,6 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     for (uint32_t i = tid; i < 9 * PMAX; i += HT) { spar[i] = 0; s111[i] = 0; }
     for (uint32_t i = tid; i < 3 * PMAX; i += HT) s3x[i] = 0;
     for (uint32_t i = tid; i < NW * (PMAX / 32); i += HT) (&L.inA[0][0])[i] = 0;
-    for (size_t i = tid; i < (size_t)NW * 2 * hsize; i += HT) W[A.o_hash + i] = 0;
     for (uint32_t i = tid; i < NW * (27 + 27 + kClasses3); i += HT) (&L.cw[0][0])[i] = 0;
     for (uint32_t i = tid; i < kLdsStatSlots; i += HT) L.stat[i] = 0;
 
@@ -820,153 +815,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         __syncthreads();
         HUB_PHASE(5);
 
-        // ---------------------------------------------------------------- k=4 (1,2,0): two depth-2 children of one slot
-        // The pairs {c1, c2} of a slot's depth-2 children L_a (m of them, m_k with arc code k
-        // from a) are its (1,2,0) sets.  A pair of non-adjacent children has a class fixed by
-        // (ra, ac1, ac2): those are counted from m_1..m_3 by complement.  Only the adjacent
-        // pairs are found and credited one by one (and taken off the complement totals, and
-        // off the (1,1,1) counts of the two groups that also counted them): a child whose row
-        // has at most kShortRow entries walks it and looks each neighbour up in a hash of
-        // L_a's positions; a pair of two longer-row children is looked up in the edge hash.
-        // The list holds the long-row children first, positions [0, kl).
-        if (A.k4) {
-            uint32_t* sig6 = cw;   // per-wave adjacent-pair counts by code signature (cw is clear here)
-            for (int t = wave_next(&L.task); t < (int)d; t = wave_next(&L.task)) {
-                const uint32_t a = (uint32_t)t;
-                const uint32_t q0 = L.pre[a], q1 = L.pre[a + 1];
-                const uint32_t m = q1 - q0 - L.lcnt[a];
-                if (m < 2) continue;
-                uint32_t kl = 0, ns = 0;
-                for (uint32_t qb = q0; qb < q1; qb += 64) {
-                    const uint32_t q = qb + lane;
-                    const bool f = q < q1 && eflag[q];
-                    uint32_t ent = 0;
-                    bool lg = false;
-                    if (f) {
-                        ent = A.adj[L.lo[a] + (q - q0)];
-                        lg = A.off[(ent >> 2) + 1] - A.off[ent >> 2] > kShortRow;
-                    }
-                    const unsigned long long ml = __ballot(f && lg), ms = __ballot(f && !lg);
-                    if (f && lg) wlist[kl + __popcll(ml & lt_mask)] = ent;
-                    if (f && !lg) wlist[m - 1u - (ns + __popcll(ms & lt_mask))] = ent;
-                    kl += __popcll(ml);
-                    ns += __popcll(ms);
-                }
-                uint32_t m1 = 0, m2 = 0, m3 = 0;
-                for (uint32_t ub = 0; ub < m; ub += 64) {
-                    const uint32_t ac = ub + lane < m ? (wlist[ub + lane] & 3u) : 0u;
-                    m1 += __popcll(__ballot(ac == 1u));
-                    m2 += __popcll(__ballot(ac == 2u));
-                    m3 += __popcll(__ballot(ac == 3u));
-                }
-                for (uint32_t q = lane; q < 3 * m; q += 64) c120[q] = 0;
-                if (ns > 0)   // positions of L_a by rank, in this wave's hash table
-                    for (uint32_t q = lane; q < m; q += 64) {
-                        const uint32_t key = (wlist[q] >> 2) + 1u;
-                        uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
-                        while (true) {
-                            const uint32_t old = atomicCAS(&hkey[h], 0u, key);
-                            if (old == 0u || old == key) break;
-                            h = (h + 1u) & (hsize - 1u);
-                        }
-                        hval[h] = q;
-                    }
-                __threadfence_block();
-                const uint32_t ra = L.P[a] & 3u, va = L.P[a] >> 2;
-                // one adjacent pair: children at positions ux, uy, cc = arc bits seen from x
-                auto adjacent_pair = [&](uint32_t ux, uint32_t uy, uint32_t ex, uint32_t ey, uint32_t cc) {
-                    const uint32_t cx = ex >> 2, acx = ex & 3u, cy = ey >> 2, acy = ey & 3u;
-                    slow[4]++;
-                    const uint32_t cls = L.t4[motif_index4(ra, 0u, 0u, acx, acy, cc)];
-                    atomicAdd(&L.root4[cls], 1ull);
-                    add4(A, L, va, cls, 1);
-                    add4(A, L, cx, cls, 1);
-                    add4(A, L, cy, cls, 1);
-                    atomicAdd(&sig6[pair_sig(acx, acy)], 1u);
-                    atomicAdd(&c120[ux * 3 + (acy - 1u)], 1u);
-                    atomicAdd(&c120[uy * 3 + (acx - 1u)], 1u);
-                    // the groups of cx and cy counted r-a-cx-cy and r-a-cy-cx as (1,1,1)
-                    // paths; take them out (every counter here is modular, ends non-negative)
-                    const uint32_t cr = swap_arc_bits(cc);
-                    const uint32_t p1 = L.t4[motif_index4(ra, 0u, 0u, acx, 0u, cc)];
-                    const uint32_t p2 = L.t4[motif_index4(ra, 0u, 0u, acy, 0u, cr)];
-                    const unsigned long long m1n = ~0ull;
-                    atomicAdd(&L.root4[p1], m1n);
-                    atomicAdd(&L.root4[p2], m1n);
-                    atomicAdd(&s111[((acx - 1u) * 3u + (cc - 1u)) * PMAX + a], 0xFFFFFFFFu);
-                    atomicAdd(&s111[((acy - 1u) * 3u + (cr - 1u)) * PMAX + a], 0xFFFFFFFFu);
-                    add4(A, L, cx, p1, m1n);
-                    add4(A, L, cy, p1, m1n);
-                    add4(A, L, cx, p2, m1n);
-                    add4(A, L, cy, p2, m1n);
-                    shape[5] -= 2;
-                };
-                // short-row children: walk the row; a short partner is taken by the lower position
-                for (uint32_t u = kl + lane; u < m; u += 64) {
-                    const uint32_t ey = wlist[u], cy = ey >> 2;
-                    const uint32_t hi2 = A.off[cy + 1];
-                    for (uint32_t t2 = A.off[cy]; t2 < hi2; t2++) {
-                        const uint32_t ew = A.adj[t2];
-                        if ((ew >> 2) <= r) continue;   // L_a lies above r
-                        const uint32_t key = (ew >> 2) + 1u;
-                        uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
-                        uint32_t pos = 0xFFFFFFFFu;
-                        while (true) {
-                            const uint32_t kk = hkey[h];
-                            if (kk == 0u) break;
-                            if (kk == key) { pos = hval[h]; break; }
-                            h = (h + 1u) & (hsize - 1u);
-                        }
-                        if (pos == 0xFFFFFFFFu || (pos >= kl && pos < u)) continue;
-                        adjacent_pair(u, pos, ey, wlist[pos], ew & 3u);
-                    }
-                }
-                // pairs of long-row children: the edge hash
-                const uint32_t nll = kl * (kl - 1u) / 2u;
-                for (uint32_t q = lane; q < nll; q += 64) {
-                    uint32_t j = (uint32_t)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
-                    while (j * (j - 1u) / 2u > q) j--;
-                    while ((j + 1u) * j / 2u <= q) j++;
-                    const uint32_t i = q - j * (j - 1u) / 2u;
-                    const uint32_t ex = wlist[i], ey = wlist[j];
-                    const uint32_t cc = edge_code(A.ehash, A.ehash_bits, ex >> 2, ey >> 2);
-                    if (cc) adjacent_pair(i, j, ex, ey, cc);
-                }
-                __threadfence_block();
-                // every child: its non-adjacent partners by their code k = m_k - own - adjacent
-                for (uint32_t u = lane; u < m; u += 64) {
-                    const uint32_t eu = wlist[u], acu = eu & 3u;
-                    shape[4] += m - 1u - u;
-                    for (uint32_t g = 0; g < 3; g++) {
-                        const uint32_t mk = g == 0 ? m1 : (g == 1 ? m2 : m3);
-                        const uint32_t cnt = mk - (acu == g + 1u ? 1u : 0u) - atomicAdd(&c120[u * 3 + g], 0u);
-                        if (cnt) add4(A, L, eu >> 2, L.t4[motif_index4(ra, 0u, 0u, acu, g + 1u, 0u)], cnt);
-                    }
-                }
-                // a and r: non-adjacent pairs by code signature
-                if (lane < 6) {
-                    uint32_t x, y;
-                    sig_pair(lane, x, y);
-                    const uint32_t mx = x == 1 ? m1 : (x == 2 ? m2 : m3), my = y == 1 ? m1 : (y == 2 ? m2 : m3);
-                    const uint32_t total = x == y ? mx * (mx - 1u) / 2u : mx * my;
-                    const uint32_t cnt = total - atomicAdd(&sig6[lane], 0u);
-                    sig6[lane] = 0;
-                    if (cnt) {
-                        const uint32_t cls = L.t4[motif_index4(ra, 0u, 0u, x, y, 0u)];
-                        add4(A, L, va, cls, cnt);
-                        atomicAdd(&L.root4[cls], (unsigned long long)cnt);
-                    }
-                }
-                if (ns > 0)   // clear this wave's hash table entries
-                    for (uint32_t q = lane; q < m; q += 64) {
-                        const uint32_t key = (wlist[q] >> 2) + 1u;
-                        uint32_t h = (key * 2654435761u) >> (32u - A.hash_bits);
-                        while (hkey[h] != key) h = (h + 1u) & (hsize - 1u);
-                        hkey[h] = 0u;
-                    }
-                __threadfence_block();
-            }
-        }
+        // (1,2,0) sets: k_slot_pairs, after this kernel (one task per (root, slot))
         __threadfence();
         __syncthreads();
         HUB_PHASE(6);
@@ -1029,6 +878,256 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         }
 }
 
+
+// ----------------------------------------------------------------------------- (1,2,0)
+
+// (1,2,0) sets of the hub roots, one wave per task (root r, slot a of N+(r)).  The pairs
+// {c1, c2} of a's depth-2 children L_a (m of them, m_k with arc code k from a) are the
+// (1,2,0) sets of (r, a).  A pair of non-adjacent children has a class fixed by
+// (ra, ac1, ac2): those are counted from m_1..m_3 by complement.  Only the adjacent pairs
+// are found and credited one by one, and taken off the complement totals and off the
+// (1,1,1) counts of the two groups that also counted them: a child whose row has at most
+// kShortRow entries walks it and looks each neighbour up in a hash of L_a's positions; a
+// pair of two longer-row children is looked up in the edge hash.  The list holds the
+// long-row children first, positions [0, kl).  Separate from k_hub so that it runs with
+// a small register and LDS footprint at full occupancy.
+struct SlotPairArgs {
+    const uint32_t* off;
+    const uint32_t* adj;
+    const uint32_t* split;
+    const int32_t* perm;
+    const uint32_t* hubs;        // hub roots (rank), queue order
+    uint32_t nhub;
+    const uint32_t* hub_pre;     // nhub + 1 prefix sums of |N+(r)| in queue order
+    uint32_t rank_lo, rank_hi;
+    const uint8_t* t4;
+    const uint8_t* slot4;
+    unsigned long long* out4;
+    unsigned long long* comp;
+    unsigned long long* stats;
+    const unsigned long long* ehash;
+    const uint16_t* efp;         // fingerprints of the edge hash
+    uint32_t ehash_bits;
+    unsigned* cursor;            // task cursor, zeroed before the launch
+    uint32_t* scratch;           // per wave: list, partner counts, hash keys, hash values
+    size_t wave_words;
+    uint32_t wl_cap;
+    uint32_t hash_bits;
+};
+constexpr int SP = 256;   // threads per workgroup of k_slot_pairs
+constexpr uint32_t kLHashBits = 9;
+constexpr uint32_t kLHash = 1u << kLHashBits;
+
+__global__ __launch_bounds__(SP) void k_slot_pairs(SlotPairArgs A) {
+    __shared__ uint8_t t4[4096];
+    __shared__ uint8_t slot4[kClasses4 + 1];
+    __shared__ uint32_t sig6w[SP / 64][8];
+    __shared__ uint32_t lkey[SP / 64][kLHash];   // per-wave hash of L_a when m <= kLHash / 2
+    __shared__ uint32_t lval[SP / 64][kLHash];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    for (uint32_t i = tid; i < 4096; i += SP) t4[i] = A.t4[i];
+    for (uint32_t i = tid; i < kClasses4; i += SP) slot4[i] = A.slot4[i];
+    if (lane < 8) sig6w[wid][lane] = 0;
+    __syncthreads();
+    uint32_t* sig6 = sig6w[wid];
+    uint32_t* W = A.scratch + ((size_t)blockIdx.x * (SP / 64) + wid) * A.wave_words;
+    uint32_t* wlist = W;
+    uint32_t* c120 = W + A.wl_cap;
+    const uint32_t hsize = 1u << A.hash_bits;
+    uint32_t* hkey = W + 4 * (size_t)A.wl_cap;
+    uint32_t* hval = hkey + hsize;
+    for (uint32_t i = lane; i < hsize; i += 64) hkey[i] = 0;
+    for (uint32_t i = lane; i < kLHash; i += 64) lkey[wid][i] = 0;
+    __threadfence_block();
+    auto credit = [&](uint32_t v, uint32_t cls, unsigned long long cnt) {
+        if (!cnt || cls >= kClasses4) return;
+        const uint32_t sl = slot4[cls];
+        if (sl != 0xFFu) atomicAdd(&A.comp[(size_t)v * kCompact4 + sl], cnt);
+        else atomicAdd(&A.out4[(size_t)A.perm[v] * kClasses4 + cls], cnt);
+    };
+    unsigned long long n120 = 0, n111 = 0, nslow = 0;   // per lane: (1,2,0) sets, (1,1,1) change, direct sets
+    const uint32_t ntask = A.hub_pre[A.nhub];
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(A.cursor, 1u);
+        t = __shfl(t, 0);
+        if (t >= ntask) break;
+        uint32_t lo = 0, hi = A.nhub;   // root: last index with hub_pre <= t
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (A.hub_pre[mid] <= t) lo = mid; else hi = mid;
+        }
+        const uint32_t r = A.hubs[lo];
+        if (r < A.rank_lo || r >= A.rank_hi) continue;
+        const uint32_t ent_a = A.adj[A.split[r] + (t - A.hub_pre[lo])];
+        const uint32_t va = ent_a >> 2, ra = ent_a & 3u;
+        const uint32_t ahi = A.off[va + 1];
+        const uint32_t alo = lower_bound_rank(A.adj, A.off[va], ahi, r + 1);
+        // depth-2 children of a: entries above r not adjacent to r; long rows first
+        uint32_t kl = 0, ns = 0;
+        uint32_t nbig = 0;   // children, counted first to place the short ones at the end
+        for (uint32_t qb = alo; qb < ahi; qb += 64) {
+            const uint32_t q = qb + lane;
+            bool f = false;
+            if (q < ahi) f = edge_code_fp(A.efp, A.ehash, A.ehash_bits, r, A.adj[q] >> 2) == 0u;
+            nbig += __popcll(__ballot(f));
+        }
+        const uint32_t m = nbig;
+        if (m < 2) continue;
+        for (uint32_t qb = alo; qb < ahi; qb += 64) {
+            const uint32_t q = qb + lane;
+            bool f = false, lg = false;
+            uint32_t ent = 0;
+            if (q < ahi) {
+                ent = A.adj[q];
+                f = edge_code_fp(A.efp, A.ehash, A.ehash_bits, r, ent >> 2) == 0u;
+                if (f) lg = A.off[(ent >> 2) + 1] - A.off[ent >> 2] > kShortRow;
+            }
+            const unsigned long long ml = __ballot(f && lg), ms = __ballot(f && !lg);
+            if (f && lg) wlist[kl + __popcll(ml & lt_mask)] = ent;
+            if (f && !lg) wlist[m - 1u - (ns + __popcll(ms & lt_mask))] = ent;
+            kl += __popcll(ml);
+            ns += __popcll(ms);
+        }
+        uint32_t m1 = 0, m2 = 0, m3 = 0;
+        for (uint32_t q = lane; q < 3 * m; q += 64) c120[q] = 0;
+        __threadfence_block();
+        for (uint32_t ub = 0; ub < m; ub += 64) {
+            const uint32_t ac = ub + lane < m ? (wlist[ub + lane] & 3u) : 0u;
+            m1 += __popcll(__ballot(ac == 1u));
+            m2 += __popcll(__ballot(ac == 2u));
+            m3 += __popcll(__ballot(ac == 3u));
+        }
+        __threadfence_block();
+        const size_t rrow = (size_t)A.perm[r] * kClasses4;
+        // one adjacent pair: children at positions ux, uy, cc = arc bits seen from x
+        auto adjacent_pair = [&](uint32_t ux, uint32_t uy, uint32_t ex, uint32_t ey, uint32_t cc) {
+            const uint32_t cx = ex >> 2, acx = ex & 3u, cy = ey >> 2, acy = ey & 3u;
+            nslow++;
+            const uint32_t cls = t4[motif_index4(ra, 0u, 0u, acx, acy, cc)];
+            atomicAdd(&A.out4[rrow + cls], 1ull);
+            credit(va, cls, 1);
+            credit(cx, cls, 1);
+            credit(cy, cls, 1);
+            atomicAdd(&sig6[pair_sig(acx, acy)], 1u);
+            atomicAdd(&c120[ux * 3 + (acy - 1u)], 1u);
+            atomicAdd(&c120[uy * 3 + (acx - 1u)], 1u);
+            // the groups of cx and cy counted r-a-cx-cy and r-a-cy-cx as (1,1,1) paths;
+            // take them out of all four members (every counter here ends non-negative)
+            const uint32_t cr = swap_arc_bits(cc);
+            const uint32_t p1 = t4[motif_index4(ra, 0u, 0u, acx, 0u, cc)];
+            const uint32_t p2 = t4[motif_index4(ra, 0u, 0u, acy, 0u, cr)];
+            const unsigned long long m1n = ~0ull;
+            atomicAdd(&A.out4[rrow + p1], m1n);
+            atomicAdd(&A.out4[rrow + p2], m1n);
+            credit(va, p1, m1n);
+            credit(va, p2, m1n);
+            credit(cx, p1, m1n);
+            credit(cy, p1, m1n);
+            credit(cx, p2, m1n);
+            credit(cy, p2, m1n);
+            n111 -= 2;
+        };
+        // short-row children: walk the row against a hash of L_a's positions (in LDS when
+        // L_a is small); a short partner is taken by the lower position
+        auto short_walks = [&](uint32_t* hk, uint32_t* hv, uint32_t hbits) {
+            const uint32_t hmask = (1u << hbits) - 1u;
+            for (uint32_t q = lane; q < m; q += 64) {
+                const uint32_t key = (wlist[q] >> 2) + 1u;
+                uint32_t h = (key * 2654435761u) >> (32u - hbits);
+                while (true) {
+                    const uint32_t old = atomicCAS(&hk[h], 0u, key);
+                    if (old == 0u || old == key) break;
+                    h = (h + 1u) & hmask;
+                }
+                hv[h] = q;
+            }
+            __threadfence_block();
+            for (uint32_t u = kl + lane; u < m; u += 64) {
+                const uint32_t ey = wlist[u], cy = ey >> 2;
+                const uint32_t hi2 = A.off[cy + 1];
+                for (uint32_t t2 = A.off[cy]; t2 < hi2; t2++) {
+                    const uint32_t ew = A.adj[t2];
+                    if ((ew >> 2) <= r) continue;   // L_a lies above r
+                    const uint32_t key = (ew >> 2) + 1u;
+                    uint32_t h = (key * 2654435761u) >> (32u - hbits);
+                    uint32_t pos = 0xFFFFFFFFu;
+                    while (true) {
+                        const uint32_t kk = hk[h];
+                        if (kk == 0u) break;
+                        if (kk == key) { pos = hv[h]; break; }
+                        h = (h + 1u) & hmask;
+                    }
+                    if (pos == 0xFFFFFFFFu || (pos >= kl && pos < u)) continue;
+                    adjacent_pair(u, pos, ey, wlist[pos], ew & 3u);
+                }
+            }
+            __threadfence_block();
+            for (uint32_t q = lane; q < m; q += 64) {   // clear the table for the next task
+                const uint32_t key = (wlist[q] >> 2) + 1u;
+                uint32_t h = (key * 2654435761u) >> (32u - hbits);
+                while (hk[h] != key) h = (h + 1u) & hmask;
+                hk[h] = 0u;
+            }
+            __threadfence_block();
+        };
+        if (ns > 0) {
+            if (m <= kLHash / 2) short_walks(lkey[wid], lval[wid], kLHashBits);
+            else short_walks(hkey, hval, A.hash_bits);
+        }
+        // pairs of long-row children: the edge hash
+        const uint32_t nll = kl * (kl - 1u) / 2u;
+        for (uint32_t q = lane; q < nll; q += 64) {
+            uint32_t j = (uint32_t)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
+            while (j * (j - 1u) / 2u > q) j--;
+            while ((j + 1u) * j / 2u <= q) j++;
+            const uint32_t i = q - j * (j - 1u) / 2u;
+            const uint32_t ex = wlist[i], ey = wlist[j];
+            const uint32_t cc = edge_code_fp(A.efp, A.ehash, A.ehash_bits, ex >> 2, ey >> 2);
+            if (cc) adjacent_pair(i, j, ex, ey, cc);
+        }
+        __threadfence_block();
+        // every child: its non-adjacent partners by their code k = m_k - own - adjacent
+        for (uint32_t u = lane; u < m; u += 64) {
+            const uint32_t eu = wlist[u], acu = eu & 3u;
+            n120 += m - 1u - u;
+            for (uint32_t g = 0; g < 3; g++) {
+                const uint32_t mk = g == 0 ? m1 : (g == 1 ? m2 : m3);
+                const uint32_t cnt = mk - (acu == g + 1u ? 1u : 0u) - atomicAdd(&c120[u * 3 + g], 0u);
+                if (cnt) credit(eu >> 2, t4[motif_index4(ra, 0u, 0u, acu, g + 1u, 0u)], cnt);
+            }
+        }
+        // a and r: non-adjacent pairs by code signature
+        if (lane < 6) {
+            uint32_t x, y;
+            sig_pair(lane, x, y);
+            const uint32_t mx = x == 1 ? m1 : (x == 2 ? m2 : m3), my = y == 1 ? m1 : (y == 2 ? m2 : m3);
+            const uint32_t total = x == y ? mx * (mx - 1u) / 2u : mx * my;
+            const uint32_t cnt = total - atomicAdd(&sig6[lane], 0u);
+            sig6[lane] = 0;
+            if (cnt) {
+                const uint32_t cls = t4[motif_index4(ra, 0u, 0u, x, y, 0u)];
+                credit(va, cls, cnt);
+                atomicAdd(&A.out4[rrow + cls], (unsigned long long)cnt);
+            }
+        }
+        __threadfence_block();
+    }
+    // shape counters: (1,2,0) sets, the (1,1,1) correction, direct-path sets; also in the
+    // hub-kernel part (entries 32-37)
+    for (int o = 32; o > 0; o >>= 1) {
+        n120 += __shfl_down(n120, o);
+        n111 += __shfl_down(n111, o);
+        nslow += __shfl_down(nslow, o);
+    }
+    if (lane == 0) {
+        if (n120) { atomicAdd(&A.stats[4], n120); atomicAdd(&A.stats[36], n120); }
+        if (n111) { atomicAdd(&A.stats[5], n111); atomicAdd(&A.stats[37], n111); }
+        if (nslow) atomicAdd(&A.stats[20], nslow);
+    }
+}
+
 // ----------------------------------------------------------------------------- binning
 
 constexpr int BT = 256;
@@ -1044,6 +1143,14 @@ __global__ void k_edge_hash(const uint32_t* __restrict__ off, const uint32_t* __
             for (uint32_t h = edge_slot(key, bits);; h = (h + 1u) & mask)
                 if (atomicCAS(&table[h], 0ull, key | (e & 3u)) == 0ull) break;
         }
+    }
+}
+
+// fingerprints of the filled edge-hash slots (0 for empty ones)
+__global__ void k_edge_fp(const unsigned long long* __restrict__ table, int64_t slots, uint16_t* __restrict__ fp) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < slots; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long s = table[i];
+        fp[i] = s ? edge_fp(s & ~3ull) : (uint16_t)0;
     }
 }
 
@@ -1116,6 +1223,13 @@ __global__ void k_fold_compact(unsigned long long* __restrict__ comp, const uint
     }
 }
 
+// |N+(r)| of every hub root, in queue order; entry nhub is 0 (exclusive scan -> total)
+__global__ void k_hub_dplus(const uint32_t* __restrict__ off, const uint32_t* __restrict__ split,
+                            const uint32_t* __restrict__ hubs, int64_t nhub, uint32_t* __restrict__ dplus) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= nhub; i += (int64_t)gridDim.x * blockDim.x)
+        dplus[i] = i < nhub ? off[hubs[i] + 1] - split[hubs[i]] : 0u;
+}
+
 __global__ void k_zero_u32(unsigned* p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
@@ -1139,6 +1253,8 @@ int hub_workgroups() {
     return g_num_cu;
 }
 
+int slot_pair_workgroups() { return hub_workgroups() * 6; }   // 24 waves per compute unit (occupancy 6)
+
 }  // namespace
 
 int hub_min_default() {
@@ -1154,8 +1270,12 @@ void free_hub(vdmc_graph_s* g) {
     (void)hipFree(g->hub_queue);
     (void)hipFree(g->hub_comp);
     (void)hipFree(g->hub_w111);
+    (void)hipFree(g->hub_pre);
+    (void)hipFree(g->sp_scratch);
     g->hub_comp = nullptr;
     g->hub_w111 = nullptr;
+    g->hub_pre = nullptr;
+    g->sp_scratch = nullptr;
     g->light = g->hubs = nullptr;
     g->hub_scratch = nullptr;
     g->hub_queue = nullptr;
@@ -1172,6 +1292,11 @@ void ensure_edge_hash(vdmc_graph_s* g, hipStream_t st) {
     const unsigned blocks = (unsigned)std::min<int64_t>((g->n + BT - 1) / BT, 65536);
     if (blocks > 0)
         hipLaunchKernelGGL(k_edge_hash, dim3(blocks), dim3(BT), 0, st, g->off, g->split, g->adj, g->n, g->ehash, eb);
+    VDMC_HIP(hipGetLastError());
+    const int64_t slots = (int64_t)1 << eb;
+    VDMC_HIP(hipMalloc(&g->efp, slots * sizeof(uint16_t)));
+    hipLaunchKernelGGL(k_edge_fp, dim3((unsigned)std::min<int64_t>((slots + BT - 1) / BT, 65536)), dim3(BT), 0, st,
+                       g->ehash, slots, g->efp);
     VDMC_HIP(hipGetLastError());
     VDMC_HIP(hipStreamSynchronize(st));
     g->ehash_bits = eb;
@@ -1257,12 +1382,10 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         const size_t o_s3x = o; o += 3 * PMAX;
         const size_t o_groups = o; o += s2;
         const size_t o_wlist = o; o += NW * wl;
-        const size_t o_c120 = o; o += 3 * NW * wl;
         const size_t o_eflag = o; o += (s2 + 3) / 4;
         const size_t o_llist = o; o += (s2 + 1) / 2;
         uint32_t hb = 12;
         while ((1u << hb) < 2 * wl) hb++;
-        const size_t o_hash = o; o += (size_t)NW * 2 * ((size_t)1 << hb);
         o = (o + 63) & ~(size_t)63;
         g->hub_scratch_bytes = o * sizeof(uint32_t) * (size_t)wgs;
         VDMC_HIP(hipMalloc(&g->hub_scratch, g->hub_scratch_bytes));
@@ -1275,19 +1398,36 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         VDMC_HIP(hipMalloc(&g->hub_w111, w_bytes));
         g->hub_scratch_bytes += w_bytes;
         ensure_edge_hash(g, st);
-        g->hub_scratch_bytes += ((size_t)1 << g->ehash_bits) * sizeof(unsigned long long);
+        g->hub_scratch_bytes += ((size_t)1 << g->ehash_bits) * (sizeof(unsigned long long) + sizeof(uint16_t));
         g->hub_layout[0] = o;
         g->hub_layout[1] = o_spar;
         g->hub_layout[2] = o_s111;
         g->hub_layout[3] = o_s3x;
         g->hub_layout[4] = o_groups;
         g->hub_layout[6] = o_wlist;
-        g->hub_layout[7] = o_c120;
         g->hub_layout[8] = o_eflag;
         g->hub_layout[9] = wl;
         g->hub_layout[10] = o_llist;
-        g->hub_layout[11] = o_hash;
         g->hub_layout[12] = hb;
+        // (1,2,0) tasks: prefix sums of |N+(r)| over the hub queue, and per-wave scratch
+        VDMC_HIP(hipMalloc(&g->hub_pre, (nhub + 1) * sizeof(uint32_t)));
+        {
+            uint32_t* dplus = (uint32_t*)alloc((nhub + 1) * sizeof(uint32_t));
+            const unsigned hb2 = (unsigned)std::min<int64_t>((nhub + BT) / BT, 65536);
+            hipLaunchKernelGGL(k_hub_dplus, dim3(hb2), dim3(BT), 0, st, g->off, g->split, g->hubs, nhub, dplus);
+            VDMC_HIP(hipGetLastError());
+            size_t tb = 0;
+            VDMC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, dplus, g->hub_pre, (int)(nhub + 1), st));
+            void* t3 = alloc(tb);
+            VDMC_HIP(hipcub::DeviceScan::ExclusiveSum(t3, tb, dplus, g->hub_pre, (int)(nhub + 1), st));
+        }
+        const size_t sp_words = (((size_t)4 * wl + 2 * ((size_t)1 << hb)) + 63) & ~(size_t)63;
+        const size_t sp_waves = (size_t)slot_pair_workgroups() * (SP / 64);
+        const size_t sp_bytes = sp_words * sp_waves * sizeof(uint32_t);
+        VDMC_HIP(hipMalloc(&g->sp_scratch, sp_bytes));
+        g->hub_scratch_bytes += sp_bytes;
+        g->hub_layout[13] = sp_words;
+        VDMC_HIP(hipStreamSynchronize(st));
     }
     g->bins_hub_min = hub_min;
 }
@@ -1320,11 +1460,9 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.o_s3x = g->hub_layout[3];
     a.o_groups = g->hub_layout[4];
     a.o_wlist = g->hub_layout[6];
-    a.o_c120 = g->hub_layout[7];
     a.o_eflag = g->hub_layout[8];
     a.wl_cap = (uint32_t)g->hub_layout[9];
     a.o_llist = g->hub_layout[10];
-    a.o_hash = g->hub_layout[11];
     a.hash_bits = (uint32_t)g->hub_layout[12];
     a.comp = (unsigned long long*)g->hub_comp;
     a.ehash = g->ehash;
@@ -1338,13 +1476,42 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
         hipLaunchKernelGGL(k_fill_zero_u32, dim3((unsigned)std::min<int64_t>((wcells + 255) / 256, 65536)), dim3(256),
                            0, st, a.w111, wcells);
     const int wgs = hub_workgroups();
+    // the hub path: k_hub, then (k = 4) the (1,2,0) tasks and the (1,1,1) end-vertex pass;
+    // the events bracket all three
     if (around) VDMC_HIP(hipEventRecord(around[0], st));
     hipLaunchKernelGGL(k_hub, dim3(wgs), dim3(HT), 0, st, a);
     VDMC_HIP(hipGetLastError());
-    if (around) VDMC_HIP(hipEventRecord(around[1], st));
     if (k4) {
+        SlotPairArgs sp;
+        sp.off = g->off;
+        sp.adj = g->adj;
+        sp.split = g->split;
+        sp.perm = g->perm;
+        sp.hubs = g->hubs;
+        sp.nhub = (uint32_t)g->nhub;
+        sp.hub_pre = g->hub_pre;
+        sp.rank_lo = rank_lo;
+        sp.rank_hi = rank_hi;
+        sp.t4 = t.t4;
+        sp.slot4 = t.slot4;
+        sp.out4 = (unsigned long long*)out4;
+        sp.comp = (unsigned long long*)g->hub_comp;
+        sp.stats = g->stats;
+        sp.ehash = g->ehash;
+        sp.efp = g->efp;
+        sp.ehash_bits = g->ehash_bits;
+        sp.cursor = g->hub_queue + 1;
+        sp.scratch = (uint32_t*)g->sp_scratch;
+        sp.wave_words = g->hub_layout[13];
+        sp.wl_cap = (uint32_t)g->hub_layout[9];
+        sp.hash_bits = (uint32_t)g->hub_layout[12];
+        hipLaunchKernelGGL(k_slot_pairs, dim3(slot_pair_workgroups()), dim3(SP), 0, st, sp);
+        VDMC_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_pull111, dim3(vblocks), dim3(256), 0, st, g->off, g->adj, a.w111, t.t4, t.slot4, g->n,
                            (unsigned long long*)g->hub_comp);
+    }
+    if (around) VDMC_HIP(hipEventRecord(around[1], st));
+    if (k4) {
         const int64_t cells = g->n * kCompact4;
         const unsigned blocks = (unsigned)std::min<int64_t>((cells + 255) / 256, 65536);
         hipLaunchKernelGGL(k_fold_compact, dim3(blocks), dim3(256), 0, st, (unsigned long long*)g->hub_comp,

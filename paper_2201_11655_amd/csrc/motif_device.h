@@ -55,6 +55,28 @@ __device__ __forceinline__ uint32_t edge_code(const unsigned long long* __restri
     }
 }
 
+// Fingerprint of an edge-hash key (never 0: 0 marks an empty slot).  A 16-bit table of
+// fingerprints at the same slots (4x smaller than the keys, so it stays cache-resident)
+// answers most lookups; the 64-bit key is read only when the fingerprint matches.
+__device__ __forceinline__ uint16_t edge_fp(unsigned long long key) {
+    const uint32_t f = (uint32_t)((key * 0xC2B2AE3D27D4EB4Full) >> 48);
+    return (uint16_t)(f ? f : 1u);
+}
+__device__ __forceinline__ uint32_t edge_code_fp(const uint16_t* __restrict__ fp, const unsigned long long* __restrict__ table,
+                                                 uint32_t bits, uint32_t u, uint32_t v) {
+    const uint32_t lo = u < v ? u : v, hi = u < v ? v : u;
+    const unsigned long long key = ((unsigned long long)lo << 32) | ((unsigned long long)hi << 2);
+    const uint16_t f = edge_fp(key);
+    const uint32_t mask = (1u << bits) - 1u;
+    for (uint32_t h = edge_slot(key, bits);; h = (h + 1u) & mask) {
+        const uint16_t g = fp[h];
+        if (g == 0) return 0u;
+        if (g != f) continue;
+        const unsigned long long s = table[h];
+        if ((s & ~3ull) == key) return u == lo ? (uint32_t)(s & 3u) : swap_arc_bits((uint32_t)(s & 3u));
+    }
+}
+
 // slot of the pair (u, v) in the edge hash, or 0xFFFFFFFF if the pair is not in the graph
 // (the probe stops at the first empty slot; the table is never full)
 __device__ __forceinline__ uint32_t edge_find(const unsigned long long* __restrict__ table, uint32_t bits,

@@ -131,8 +131,11 @@ struct vdmc_graph_s {
     unsigned* hub_queue = nullptr;
     void* hub_comp = nullptr;    // n x kCompact4 uint64 rank-indexed accumulator
     void* hub_w111 = nullptr;    // n x 9 uint32: (1,1,1) parent codes per depth-2 vertex
+    uint32_t* hub_pre = nullptr; // nhub + 1 prefix sums of |N+(r)| over the hub queue
+    void* sp_scratch = nullptr;  // per-wave scratch of the (1,2,0) kernel
     unsigned long long* ehash = nullptr;   // edge hash: every pair of the graph, 2^ehash_bits slots
     uint32_t ehash_bits = 0;
+    uint16_t* efp = nullptr;     // 16-bit fingerprint per edge-hash slot (0 = empty)
     uint32_t* epid = nullptr;    // per edge-hash slot: output row of the pair (per-edge counts)
     int32_t* elo = nullptr;      // per output row: the pair's endpoints (original ids, lo < hi)
     int32_t* ehi = nullptr;
