@@ -908,6 +908,8 @@ struct SlotPairArgs {
     const unsigned long long* ehash;
     const uint16_t* efp;         // fingerprints of the edge hash
     uint32_t ehash_bits;
+    const uint32_t* lbits;       // adjacency bitmap among the long-row vertices (ranks < nlong), or null
+    uint32_t nlong, lwords;      // long-row vertices, 32-bit words per bitmap row
     unsigned* cursor;            // task cursor, zeroed before the launch
     uint32_t* scratch;           // per wave: list, partner counts, hash keys, hash values
     size_t wave_words;
@@ -1084,7 +1086,12 @@ __global__ __launch_bounds__(SP) void k_slot_pairs(SlotPairArgs A) {
             while ((j + 1u) * j / 2u <= q) j++;
             const uint32_t i = q - j * (j - 1u) / 2u;
             const uint32_t ex = wlist[i], ey = wlist[j];
-            const uint32_t cc = edge_code_fp(A.efp, A.ehash, A.ehash_bits, ex >> 2, ey >> 2);
+            uint32_t cc = 0;
+            // long-row vertices are the ranks below nlong (ranks follow degree); their
+            // adjacency bitmap row of ey stays cache-resident across the lanes of a step
+            const bool inbm = A.lbits && (ex >> 2) < A.nlong && (ey >> 2) < A.nlong;
+            if (!inbm || ((A.lbits[(size_t)(ey >> 2) * A.lwords + ((ex >> 2) >> 5)] >> ((ex >> 2) & 31u)) & 1u))
+                cc = edge_code_fp(A.efp, A.ehash, A.ehash_bits, ex >> 2, ey >> 2);
             if (cc) adjacent_pair(i, j, ex, ey, cc);
         }
         __threadfence_block();
@@ -1223,6 +1230,26 @@ __global__ void k_fold_compact(unsigned long long* __restrict__ comp, const uint
     }
 }
 
+// number of ranks whose row is longer than kShortRow (rows shrink with the rank)
+__global__ void k_count_long(const uint32_t* __restrict__ off, int64_t n, uint32_t* __restrict__ nlong) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const bool lg = off[r + 1] - off[r] > kShortRow;
+        const bool next_lg = r + 1 < n && off[r + 2] - off[r + 1] > kShortRow;
+        if (lg && !next_lg) *nlong = (uint32_t)(r + 1);
+    }
+}
+
+// adjacency bitmap among the ranks below nlong: bit (u, v) of row u
+__global__ void k_long_bitmap(const uint32_t* __restrict__ off, const uint32_t* __restrict__ adj, uint32_t nlong,
+                              uint32_t lwords, uint32_t* __restrict__ bits) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < nlong; u += (int64_t)gridDim.x * blockDim.x)
+        for (uint32_t t = off[u]; t < off[u + 1]; t++) {
+            const uint32_t v = adj[t] >> 2;
+            if (v >= nlong) break;   // the row is sorted by rank
+            atomicOr(&bits[(size_t)u * lwords + (v >> 5)], 1u << (v & 31u));
+        }
+}
+
 // |N+(r)| of every hub root, in queue order; entry nhub is 0 (exclusive scan -> total)
 __global__ void k_hub_dplus(const uint32_t* __restrict__ off, const uint32_t* __restrict__ split,
                             const uint32_t* __restrict__ hubs, int64_t nhub, uint32_t* __restrict__ dplus) {
@@ -1272,6 +1299,8 @@ void free_hub(vdmc_graph_s* g) {
     (void)hipFree(g->hub_w111);
     (void)hipFree(g->hub_pre);
     (void)hipFree(g->sp_scratch);
+    (void)hipFree(g->lbits);
+    g->lbits = nullptr;
     g->hub_comp = nullptr;
     g->hub_w111 = nullptr;
     g->hub_pre = nullptr;
@@ -1421,6 +1450,30 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
             void* t3 = alloc(tb);
             VDMC_HIP(hipcub::DeviceScan::ExclusiveSum(t3, tb, dplus, g->hub_pre, (int)(nhub + 1), st));
         }
+        // adjacency bitmap of the long-row vertices (pairs of long children in (1,2,0)),
+        // when it is at most 1 GiB
+        {
+            uint32_t* d_nl = (uint32_t*)alloc(sizeof(uint32_t));
+            VDMC_HIP(hipMemsetAsync(d_nl, 0, sizeof(uint32_t), st));
+            const unsigned nb = (unsigned)std::min<int64_t>((g->n + BT - 1) / BT, 65536);
+            if (nb > 0) hipLaunchKernelGGL(k_count_long, dim3(nb), dim3(BT), 0, st, g->off, g->n, d_nl);
+            VDMC_HIP(hipGetLastError());
+            uint32_t nl = 0;
+            VDMC_HIP(hipMemcpyAsync(&nl, d_nl, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            VDMC_HIP(hipStreamSynchronize(st));
+            const size_t lw = ((size_t)nl + 31) / 32;
+            const size_t lbytes = lw * nl * sizeof(uint32_t);
+            g->nlong = nl;
+            g->lwords = (uint32_t)lw;
+            if (nl > 0 && lbytes <= ((size_t)1 << 30)) {
+                VDMC_HIP(hipMalloc(&g->lbits, lbytes));
+                VDMC_HIP(hipMemsetAsync(g->lbits, 0, lbytes, st));
+                const unsigned lb = (unsigned)std::min<int64_t>((nl + BT - 1) / BT, 65536);
+                hipLaunchKernelGGL(k_long_bitmap, dim3(lb), dim3(BT), 0, st, g->off, g->adj, nl, (uint32_t)lw, g->lbits);
+                VDMC_HIP(hipGetLastError());
+                g->hub_scratch_bytes += lbytes;
+            }
+        }
         const size_t sp_words = (((size_t)4 * wl + 2 * ((size_t)1 << hb)) + 63) & ~(size_t)63;
         const size_t sp_waves = (size_t)slot_pair_workgroups() * (SP / 64);
         const size_t sp_bytes = sp_words * sp_waves * sizeof(uint32_t);
@@ -1500,6 +1553,9 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
         sp.ehash = g->ehash;
         sp.efp = g->efp;
         sp.ehash_bits = g->ehash_bits;
+        sp.lbits = g->lbits;
+        sp.nlong = g->nlong;
+        sp.lwords = g->lwords;
         sp.cursor = g->hub_queue + 1;
         sp.scratch = (uint32_t*)g->sp_scratch;
         sp.wave_words = g->hub_layout[13];

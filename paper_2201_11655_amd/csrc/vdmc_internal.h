@@ -133,6 +133,8 @@ struct vdmc_graph_s {
     void* hub_w111 = nullptr;    // n x 9 uint32: (1,1,1) parent codes per depth-2 vertex
     uint32_t* hub_pre = nullptr; // nhub + 1 prefix sums of |N+(r)| over the hub queue
     void* sp_scratch = nullptr;  // per-wave scratch of the (1,2,0) kernel
+    uint32_t* lbits = nullptr;   // adjacency bitmap among the long-row vertices (ranks < nlong)
+    uint32_t nlong = 0, lwords = 0;
     unsigned long long* ehash = nullptr;   // edge hash: every pair of the graph, 2^ehash_bits slots
     uint32_t ehash_bits = 0;
     uint16_t* efp = nullptr;     // 16-bit fingerprint per edge-hash slot (0 = empty)
