@@ -56,6 +56,7 @@ struct HubArgs {
     uint32_t* scratch;
     size_t wg_words;        // u32 words per workgroup slice
     size_t o_spar, o_s111, o_s3x, o_groups, o_wlist, o_eflag, o_llist;
+    uint32_t s2cap;         // capacity of the group list (the single-parent list follows it)
     uint32_t hash_bits;     // per-wave hash table of 2^hash_bits (key, value) pairs
     uint32_t wl_cap;        // per-wave list capacity (>= max degree)
     const unsigned long long* ehash;   // the graph's edge hash (edge_code)
@@ -168,7 +169,7 @@ struct Lds {
     uint8_t t4[4096];
     uint8_t t3[64];
     uint8_t slot4[kClasses4 + 1];              // class -> compact slot (0xFF: none)
-    unsigned task, groups, rootidx;
+    unsigned task, groups, sgroups, rootidx;
 };
 
 // Credit cnt sets of class cls to the vertex of rank v.  Classes of sets whose
@@ -242,6 +243,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     uint32_t* s111 = W + A.o_s111;     // [9][PMAX]  (1,1,1) depth-1 counters
     uint32_t* s3x = W + A.o_s3x;       // [3][PMAX]  k=3 (1,2) depth-1 counters
     uint32_t* grp = W + A.o_groups;    // the depth-2 vertex c of every group
+    uint32_t* sgrp = grp + A.s2cap;    // single-parent short-row groups: c, then slot << 2 | code
     uint32_t* wlist = W + A.o_wlist + (size_t)wid * A.wl_cap;
     uint8_t* eflag = reinterpret_cast<uint8_t*>(W + A.o_eflag);
     uint16_t* llist = reinterpret_cast<uint16_t*>(W + A.o_llist);   // local neighbours per slot
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         if (tid < 9) L.gall[tid] = 0;
         const size_t mwords = (size_t)d * nch * 4;
         for (size_t i = tid; i < mwords; i += HT) M[i] = 0;
-        if (tid == 0) { L.groups = 0; L.task = 0; }
+        if (tid == 0) { L.groups = 0; L.sgroups = 0; L.task = 0; }
         __syncthreads();
         block_prefix(L.pre, d, L.scan);
         const uint32_t scan2 = L.pre[d];
@@ -402,12 +404,15 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             if (q1 - q0 == L.lcnt[a]) continue;   // no depth-2 entries
             for (uint32_t qb = q0; qb < q1; qb += 64) {
                 const uint32_t q = qb + lane;
-                bool lead = false;
-                uint32_t c = 0;
+                bool lead = false, single = false;
+                uint32_t c = 0, xc = 0;
                 if (q < q1 && eflag[q]) {
-                    c = A.adj[rlo + (q - q0)] >> 2;
-                    const uint32_t chi = A.off[c + 1];
-                    for (uint32_t tt = A.off[c]; tt < chi; tt++) {
+                    const uint32_t ent = A.adj[rlo + (q - q0)];
+                    c = ent >> 2;
+                    xc = ent & 3u;
+                    const uint32_t clo = A.off[c], chi = A.off[c + 1];
+                    uint32_t tt = clo;
+                    for (; tt < chi; tt++) {
                         const uint32_t w = A.adj[tt] >> 2;
                         if (w <= r) continue;
                         const int sl = find_slot_f(L, d, w);
@@ -416,13 +421,32 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                             break;
                         }
                     }
+                    if (lead && chi - clo <= kShortRow) {   // a short row: is a the only parent?
+                        single = true;
+                        for (++tt; tt < chi; tt++)
+                            if (find_slot_f(L, d, A.adj[tt] >> 2) >= 0) {
+                                single = false;
+                                break;
+                            }
+                    }
                 }
-                const unsigned long long mk = __ballot(lead);
+                const bool gen = lead && !single;
+                const unsigned long long mk = __ballot(gen), ms = __ballot(single);
                 if (mk) {
                     uint32_t g0 = 0;
                     if (lane == 0) g0 = atomicAdd(&L.groups, (unsigned)__popcll(mk));
                     g0 = __shfl(g0, 0);
-                    if (lead) grp[g0 + __popcll(mk & lt_mask)] = c;
+                    if (gen) grp[g0 + __popcll(mk & lt_mask)] = c;
+                }
+                if (ms) {   // single-parent short-row groups: (c, slot << 2 | code a -> c)
+                    uint32_t s0 = 0;
+                    if (lane == 0) s0 = atomicAdd(&L.sgroups, (unsigned)__popcll(ms));
+                    s0 = __shfl(s0, 0);
+                    if (single) {
+                        const uint32_t i = s0 + __popcll(ms & lt_mask);
+                        sgrp[2 * i] = c;
+                        sgrp[2 * i + 1] = (a << 2) | xc;
+                    }
                 }
             }
         }
@@ -798,6 +822,83 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 atomicAdd(&L.stat[27], tg4 - tg3);
             }
             t = tn;
+        }
+        // Single-parent groups with a short row (most groups): one lane per group, the same
+        // sets and credits as above with A(c) = {x}.  Task ids past ngroups are chunks of 64.
+        {
+            const uint32_t nsg = L.sgroups;
+            const int nall = (int)(ngroups + (nsg + 63) / 64);
+            for (; t < nall; t = wave_next(&L.task)) {
+                const uint32_t i = (uint32_t)(t - (int)ngroups) * 64u + lane;
+                if (i >= nsg) continue;
+                const uint32_t c = sgrp[2 * i], xw = sgrp[2 * i + 1];
+                const uint32_t x = xw >> 2, xc = xw & 3u;
+                const uint32_t rx = L.P[x] & 3u, vx = L.P[x] >> 2;
+                if (A.k3) {   // k=3 (1,2): {r, x, c}
+                    const uint32_t cls = L.t3[motif_index3(rx, 0u, xc)];
+                    atomicAdd(&L.root3[cls], 1ull);
+                    atomicAdd(&s3x[(xc - 1) * PMAX + x], 1u);
+                    add_out(A.out3, A.perm, kClasses3, c, cls, 1);
+                    shape[1]++;
+                }
+                if (!A.k4) continue;
+                const uint32_t g = (rx - 1u) * 3u + (xc - 1u);
+                // (2,1,0): every slot y other than x; x's local neighbours are the sets with an
+                // x-y arc (direct), the others are pure (complement: gall and per-slot counters)
+                atomicAdd(&L.gall[g], 1u);
+                atomicAdd(&L.cnt[g * d + x], 0xFFFFFFFFu);
+                shape[3] += d - 1u;
+                uint32_t n1 = 0, n2 = 0, n3 = 0;
+                const uint32_t xq = L.pre[x], xl = L.lcnt[x];
+                for (uint32_t q = xq; q < xq + xl; q++) {
+                    const uint32_t vq = llist[q], y = vq >> 2, xy = vq & 3u, ry = L.P[y] & 3u;
+                    n1 += ry == 1u;
+                    n2 += ry == 2u;
+                    n3 += ry == 3u;
+                    atomicAdd(&L.cnt[g * d + y], 0xFFFFFFFFu);
+                    slow[3]++;
+                    const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, 0u)];
+                    atomicAdd(&L.root4[cls], 1ull);
+                    add4(A, L, vx, cls, 1);
+                    add4(A, L, L.P[y] >> 2, cls, 1);
+                    add4(A, L, c, cls, 1);
+                }
+                auto pure210 = [&](uint32_t k, uint32_t nk) {   // x's pure sets with ry = k
+                    if (!nk) return;
+                    atomicAdd(&spar[((xc - 1u) * 3u + (k - 1u)) * PMAX + x], nk);
+                    const uint32_t cls = L.t4[motif_index4(rx, k, 0u, 0u, xc, 0u)];
+                    add4(A, L, c, cls, nk);
+                    atomicAdd(&L.root4[cls], (unsigned long long)nk);
+                };
+                pure210(1, nr1 - (rx == 1u) - n1);
+                pure210(2, nr2 - (rx == 2u) - n2);
+                pure210(3, nr3 - (rx == 3u) - n3);
+                // (1,1,1): c's row; the valid ends by ce, the other entries taken off
+                uint32_t T1 = 0, T2 = 0, T3 = 0;
+                const uint32_t chi = A.off[c + 1];
+                for (uint32_t tt = A.off[c]; tt < chi; tt++) {
+                    const uint32_t ent = A.adj[tt], e = ent >> 2, ce = ent & 3u;
+                    if (e < r || e == vx) {   // below r, or x (c's only neighbour in N+(r))
+                        add4(A, L, e, L.t4[motif_index4(rx, 0u, 0u, xc, 0u, ce)], ~0ull);
+                    } else {
+                        T1 += ce == 1u;
+                        T2 += ce == 2u;
+                        T3 += ce == 3u;
+                    }
+                }
+                shape[5] += T1 + T2 + T3;
+                atomicAdd(&A.w111[(size_t)c * 9 + g], 1u);
+                auto path111 = [&](uint32_t k, uint32_t tk) {
+                    if (!tk) return;
+                    atomicAdd(&s111[((xc - 1u) * 3u + (k - 1u)) * PMAX + x], tk);
+                    const uint32_t cls = L.t4[motif_index4(rx, 0u, 0u, xc, 0u, k)];
+                    add4(A, L, c, cls, tk);
+                    atomicAdd(&L.root4[cls], (unsigned long long)tk);
+                };
+                path111(1, T1);
+                path111(2, T2);
+                path111(3, T3);
+            }
         }
         __threadfence();
         __syncthreads();
@@ -1409,7 +1510,7 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         const size_t o_spar = o; o += 9 * PMAX;
         const size_t o_s111 = o; o += 9 * PMAX;
         const size_t o_s3x = o; o += 3 * PMAX;
-        const size_t o_groups = o; o += s2;
+        const size_t o_groups = o; o += 3 * s2;
         const size_t o_wlist = o; o += NW * wl;
         const size_t o_eflag = o; o += (s2 + 3) / 4;
         const size_t o_llist = o; o += (s2 + 1) / 2;
@@ -1512,6 +1613,7 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.o_s111 = g->hub_layout[2];
     a.o_s3x = g->hub_layout[3];
     a.o_groups = g->hub_layout[4];
+    a.s2cap = (uint32_t)((size_t)g->max_scan2 + 64);
     a.o_wlist = g->hub_layout[6];
     a.o_eflag = g->hub_layout[8];
     a.wl_cap = (uint32_t)g->hub_layout[9];
