@@ -182,11 +182,14 @@ vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
  * are the shape counts above; entries 8-15 the device cycles the hub workgroups spent
  * per phase (stage, local matrix, k=3 pairs, depth-2 groups, (3,0,0), group shapes,
  * (1,2,0), flush), summed over workgroups; entries 16-21 the numbers of sets that took
- * the direct (unaggregated) crediting path per shape; entries 24-27 the wave time spent
- * inside the depth-2 groups on (2,1,0) sets, (2,1,0) sets with both parents, (1,1,1)
- * paths and the rest (100 MHz ticks summed over waves); entries 28-31 work counts: depth-2
- * groups, (1,1,1) chunks, (1,1,1) parent-chunk pairs, (2,1,0) local-list steps; entries 32-37 the part of
- * the shape counts enumerated by the hub kernel.  Copies min(n, 40) entries. */
+ * the direct (unaggregated) crediting path per shape; entries 22-23 the wave time spent
+ * in the wave-per-group loop and in the lane-per-group loop (single-parent groups with a
+ * short row); entries 24-27 the wave time spent inside the wave-per-group loop on
+ * (2,1,0) sets, (2,1,0) sets with both parents, (1,1,1) paths and the rest (all times
+ * 100 MHz ticks summed over waves); entries 28-31 work counts: depth-2 groups of the
+ * wave-per-group loop, (1,1,1) chunks, (1,1,1) parent-chunk pairs, (2,1,0) local-list
+ * steps; entries 32-37 the part of the shape counts enumerated by the hub kernel.
+ * Copies min(n, 40) entries. */
 vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n);
 
 /* Device time of the kernels of the last count call on this graph, from events recorded

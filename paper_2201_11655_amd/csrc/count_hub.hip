@@ -242,6 +242,10 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     uint32_t* spar = W + A.o_spar;     // [9][PMAX]  (2,1,0) parent-role counters
     uint32_t* s111 = W + A.o_s111;     // [9][PMAX]  (1,1,1) depth-1 counters
     uint32_t* s3x = W + A.o_s3x;       // [3][PMAX]  k=3 (1,2) depth-1 counters
+    uint32_t* nsg = s3x + 3 * PMAX;    // [3][PMAX]  single-parent groups per (xc, slot) of a root
+    // [3][PMAX] per slot x and ry: x's local neighbours y with P[y]'s arc code ry, three
+    // 21-bit fields by the x-y arc code xy
+    unsigned long long* prof = reinterpret_cast<unsigned long long*>(s3x + 6 * PMAX);
     uint32_t* grp = W + A.o_groups;    // the depth-2 vertex c of every group
     uint32_t* sgrp = grp + A.s2cap;    // single-parent short-row groups: c, then slot << 2 | code
     uint32_t* wlist = W + A.o_wlist + (size_t)wid * A.wl_cap;
@@ -266,7 +270,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     for (uint32_t i = tid; i < 64; i += HT) L.t3[i] = A.t3[i];
     for (uint32_t i = tid; i < kClasses4; i += HT) L.slot4[i] = A.slot4[i];
     for (uint32_t i = tid; i < 9 * PMAX; i += HT) { spar[i] = 0; s111[i] = 0; }
-    for (uint32_t i = tid; i < 3 * PMAX; i += HT) s3x[i] = 0;
+    for (uint32_t i = tid; i < 3 * PMAX; i += HT) { s3x[i] = 0; nsg[i] = 0; }
     for (uint32_t i = tid; i < NW * (PMAX / 32); i += HT) (&L.inA[0][0])[i] = 0;
     for (uint32_t i = tid; i < NW * (27 + 27 + kClasses3); i += HT) (&L.cw[0][0])[i] = 0;
     for (uint32_t i = tid; i < kLdsStatSlots; i += HT) L.stat[i] = 0;
@@ -323,6 +327,8 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             const uint32_t i = (uint32_t)t;
             const uint32_t q0 = L.pre[i], q1 = L.pre[i + 1], rlo = L.lo[i];
             uint32_t nl = 0;
+            unsigned long long pf1 = 0, pf2 = 0, pf3 = 0;   // the slot's profile (see prof)
+            uint32_t d1 = 0, d2 = 0, d3 = 0;                // depth-2 entries by arc code
             for (uint32_t qb = q0; qb < q1; qb += 64) {
                 const uint32_t q = qb + lane;
                 const bool v = q < q1;
@@ -333,8 +339,37 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 const unsigned long long mk = __ballot(j >= 0);
                 if (j >= 0) llist[q0 + nl + __popcll(mk & lt_mask)] = (uint16_t)(((uint32_t)j << 2) | (e & 3u));
                 nl += __popcll(mk);
+                if (A.k3) {
+                    const bool dep2 = v && j < 0;
+                    d1 += __popcll(__ballot(dep2 && (e & 3u) == 1u));
+                    d2 += __popcll(__ballot(dep2 && (e & 3u) == 2u));
+                    d3 += __popcll(__ballot(dep2 && (e & 3u) == 3u));
+                }
+                if (A.k4 && mk) {
+                    const uint32_t code = j >= 0 ? ((L.P[j] & 3u) - 1u) * 3u + ((e & 3u) - 1u) : 9u;
+#pragma unroll
+                    for (uint32_t c9 = 0; c9 < 9; c9++) {
+                        const unsigned long long inc = (unsigned long long)__popcll(__ballot(code == c9))
+                                                       << (21u * (c9 % 3u));
+                        if (c9 < 3) pf1 += inc; else if (c9 < 6) pf2 += inc; else pf3 += inc;
+                    }
+                }
             }
-            if (lane == 0) L.lcnt[i] = (uint16_t)nl;
+            // k=3 (1,2): every depth-2 entry (i, c) is the set {r, i, c}; i's credit and the
+            // root's are counted here, c's when its group is processed
+            if (A.k3 && lane < 3) {
+                const uint32_t dk = lane == 0 ? d1 : (lane == 1 ? d2 : d3);
+                s3x[lane * PMAX + i] = dk;
+                if (dk) atomicAdd(&L.root3[L.t3[motif_index3(L.P[i] & 3u, 0u, lane + 1u)]], (unsigned long long)dk);
+            }
+            if (lane == 0) {
+                L.lcnt[i] = (uint16_t)nl;
+                if (A.k4) {
+                    prof[i] = pf1;
+                    prof[PMAX + i] = pf2;
+                    prof[2 * PMAX + i] = pf3;
+                }
+            }
         }
         __threadfence();
         __syncthreads();
@@ -402,6 +437,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             const uint32_t a = (uint32_t)t;
             const uint32_t q0 = L.pre[a], q1 = L.pre[a + 1], rlo = L.lo[a];
             if (q1 - q0 == L.lcnt[a]) continue;   // no depth-2 entries
+            uint32_t sg1 = 0, sg2 = 0, sg3 = 0;    // a's single-parent groups by code a -> c
             for (uint32_t qb = q0; qb < q1; qb += 64) {
                 const uint32_t q = qb + lane;
                 bool lead = false, single = false;
@@ -411,27 +447,34 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     c = ent >> 2;
                     xc = ent & 3u;
                     const uint32_t clo = A.off[c], chi = A.off[c + 1];
-                    uint32_t tt = clo;
-                    for (; tt < chi; tt++) {
-                        const uint32_t w = A.adj[tt] >> 2;
-                        if (w <= r) continue;
-                        const int sl = find_slot_f(L, d, w);
-                        if (sl >= 0) {
-                            lead = (uint32_t)sl == a;
-                            break;
-                        }
-                    }
-                    if (lead && chi - clo <= kShortRow) {   // a short row: is a the only parent?
-                        single = true;
-                        for (++tt; tt < chi; tt++)
-                            if (find_slot_f(L, d, A.adj[tt] >> 2) >= 0) {
-                                single = false;
-                                break;
+                    const bool shortrow = chi - clo <= kShortRow;
+                    // row entries in batches of 8 (one memory latency per batch); a short
+                    // row is walked to its end to learn whether a is its only parent
+                    int first = -1;
+                    uint32_t nslot = 0;
+                    for (uint32_t tb = clo; tb < chi; tb += 8) {
+                        uint32_t w[8];
+#pragma unroll
+                        for (int j = 0; j < 8; j++) w[j] = tb + j < chi ? A.adj[tb + j] >> 2 : 0u;
+#pragma unroll
+                        for (int j = 0; j < 8; j++) {
+                            if (w[j] <= r) continue;   // also the padding past the row
+                            const int sl = find_slot_f(L, d, w[j]);
+                            if (sl >= 0) {
+                                if (first < 0) first = sl;
+                                nslot++;
                             }
+                        }
+                        if (first >= 0 && ((uint32_t)first != a || !shortrow || nslot > 1)) break;
                     }
+                    lead = first == (int)a;
+                    single = lead && shortrow && nslot == 1;
                 }
                 const bool gen = lead && !single;
                 const unsigned long long mk = __ballot(gen), ms = __ballot(single);
+                sg1 += __popcll(__ballot(single && xc == 1u));
+                sg2 += __popcll(__ballot(single && xc == 2u));
+                sg3 += __popcll(__ballot(single && xc == 3u));
                 if (mk) {
                     uint32_t g0 = 0;
                     if (lane == 0) g0 = atomicAdd(&L.groups, (unsigned)__popcll(mk));
@@ -449,6 +492,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     }
                 }
             }
+            if (lane < 3) nsg[lane * PMAX + a] = lane == 0 ? sg1 : (lane == 1 ? sg2 : sg3);
         }
         __threadfence();
         __syncthreads();
@@ -573,6 +617,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         // The next group's vertex, row bounds and first row chunk are loaded in stages while
         // the current group is processed, so that a group does not start with a chain of
         // dependent loads.
+        const unsigned long long tw0 = wall_clock64();
         int t = wave_next(&L.task);
         uint32_t cN = 0, loN = 0, hiN = 0, e0N = 0;
         if (t < (int)ngroups) {
@@ -616,8 +661,6 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 for (uint32_t u = lane; u < p; u += 64) {
                     const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
                     const uint32_t cls = L.t3[motif_index3(rx, 0u, xc)];
-                    atomicAdd(&L.root3[cls], 1ull);
-                    atomicAdd(&s3x[(xc - 1) * PMAX + x], 1u);
                     atomicAdd(&cw[54 + cls], 1u);
                     shape[1]++;
                 }
@@ -825,65 +868,68 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         }
         // Single-parent groups with a short row (most groups): one lane per group, the same
         // sets and credits as above with A(c) = {x}.  Task ids past ngroups are chunks of 64.
+        const unsigned long long tw1 = wall_clock64();
         {
-            const uint32_t nsg = L.sgroups;
-            const int nall = (int)(ngroups + (nsg + 63) / 64);
+            const uint32_t nsgl = L.sgroups;
+            const int nall = (int)(ngroups + (nsgl + 63) / 64);
             for (; t < nall; t = wave_next(&L.task)) {
                 const uint32_t i = (uint32_t)(t - (int)ngroups) * 64u + lane;
-                if (i >= nsg) continue;
+                if (i >= nsgl) continue;
                 const uint32_t c = sgrp[2 * i], xw = sgrp[2 * i + 1];
                 const uint32_t x = xw >> 2, xc = xw & 3u;
+                const uint32_t clo = A.off[c], chi = A.off[c + 1];
                 const uint32_t rx = L.P[x] & 3u, vx = L.P[x] >> 2;
                 if (A.k3) {   // k=3 (1,2): {r, x, c}
-                    const uint32_t cls = L.t3[motif_index3(rx, 0u, xc)];
-                    atomicAdd(&L.root3[cls], 1ull);
-                    atomicAdd(&s3x[(xc - 1) * PMAX + x], 1u);
-                    add_out(A.out3, A.perm, kClasses3, c, cls, 1);
+                    add_out(A.out3, A.perm, kClasses3, c, L.t3[motif_index3(rx, 0u, xc)], 1);
                     shape[1]++;
                 }
                 if (!A.k4) continue;
                 const uint32_t g = (rx - 1u) * 3u + (xc - 1u);
-                // (2,1,0): every slot y other than x; x's local neighbours are the sets with an
-                // x-y arc (direct), the others are pure (complement: gall and per-slot counters)
-                atomicAdd(&L.gall[g], 1u);
-                atomicAdd(&L.cnt[g * d + x], 0xFFFFFFFFu);
-                shape[3] += d - 1u;
-                uint32_t n1 = 0, n2 = 0, n3 = 0;
-                const uint32_t xq = L.pre[x], xl = L.lcnt[x];
-                for (uint32_t q = xq; q < xq + xl; q++) {
-                    const uint32_t vq = llist[q], y = vq >> 2, xy = vq & 3u, ry = L.P[y] & 3u;
-                    n1 += ry == 1u;
-                    n2 += ry == 2u;
-                    n3 += ry == 3u;
-                    atomicAdd(&L.cnt[g * d + y], 0xFFFFFFFFu);
-                    slow[3]++;
-                    const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, 0u)];
-                    atomicAdd(&L.root4[cls], 1ull);
-                    add4(A, L, vx, cls, 1);
-                    add4(A, L, L.P[y] >> 2, cls, 1);
-                    add4(A, L, c, cls, 1);
+                // (2,1,0): {r, x, y, c} for every slot y other than x.  The sets' numbers by
+                // class come from x's profile (y a local neighbour of x: x-y arc) and from the
+                // slot counts by ry (the pure rest), so c and the root are credited per class
+                // here; x's and y's credits are made per slot after the groups (nsg).
+                uint32_t nry[3];
+#pragma unroll
+                for (uint32_t k = 0; k < 3; k++) {
+                    const unsigned long long w = prof[k * PMAX + x];
+                    nry[k] = 0;
+#pragma unroll
+                    for (uint32_t xy = 1; xy <= 3; xy++) {
+                        const uint32_t h = (uint32_t)(w >> (21u * (xy - 1u))) & F21;
+                        if (!h) continue;
+                        nry[k] += h;
+                        const uint32_t cls = L.t4[motif_index4(rx, k + 1u, 0u, xy, xc, 0u)];
+                        atomicAdd(&L.root4[cls], (unsigned long long)h);
+                        add4(A, L, c, cls, h);
+                    }
                 }
-                auto pure210 = [&](uint32_t k, uint32_t nk) {   // x's pure sets with ry = k
+                auto pure210 = [&](uint32_t k, uint32_t nk) {   // x's sets with a pure y, ry = k
                     if (!nk) return;
-                    atomicAdd(&spar[((xc - 1u) * 3u + (k - 1u)) * PMAX + x], nk);
                     const uint32_t cls = L.t4[motif_index4(rx, k, 0u, 0u, xc, 0u)];
                     add4(A, L, c, cls, nk);
                     atomicAdd(&L.root4[cls], (unsigned long long)nk);
                 };
-                pure210(1, nr1 - (rx == 1u) - n1);
-                pure210(2, nr2 - (rx == 2u) - n2);
-                pure210(3, nr3 - (rx == 3u) - n3);
+                pure210(1, nr1 - (rx == 1u) - nry[0]);
+                pure210(2, nr2 - (rx == 2u) - nry[1]);
+                pure210(3, nr3 - (rx == 3u) - nry[2]);
                 // (1,1,1): c's row; the valid ends by ce, the other entries taken off
                 uint32_t T1 = 0, T2 = 0, T3 = 0;
-                const uint32_t chi = A.off[c + 1];
-                for (uint32_t tt = A.off[c]; tt < chi; tt++) {
-                    const uint32_t ent = A.adj[tt], e = ent >> 2, ce = ent & 3u;
-                    if (e < r || e == vx) {   // below r, or x (c's only neighbour in N+(r))
-                        add4(A, L, e, L.t4[motif_index4(rx, 0u, 0u, xc, 0u, ce)], ~0ull);
-                    } else {
-                        T1 += ce == 1u;
-                        T2 += ce == 2u;
-                        T3 += ce == 3u;
+                for (uint32_t tb = clo; tb < chi; tb += 8) {   // batches of 8 row entries
+                    uint32_t en[8];
+#pragma unroll
+                    for (int j = 0; j < 8; j++) en[j] = tb + j < chi ? A.adj[tb + j] : 0u;
+#pragma unroll
+                    for (int j = 0; j < 8; j++) {
+                        if (tb + j >= chi) break;
+                        const uint32_t e = en[j] >> 2, ce = en[j] & 3u;
+                        if (e < r || e == vx) {   // below r, or x (c's only neighbour in N+(r))
+                            add4(A, L, e, L.t4[motif_index4(rx, 0u, 0u, xc, 0u, ce)], ~0ull);
+                        } else {
+                            T1 += ce == 1u;
+                            T2 += ce == 2u;
+                            T3 += ce == 3u;
+                        }
                     }
                 }
                 shape[5] += T1 + T2 + T3;
@@ -900,7 +946,68 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 path111(3, T3);
             }
         }
+        if (lane == 0) {   // per-wave time in the two group loops (diagnostic)
+            const unsigned long long tw2 = wall_clock64();
+            atomicAdd(&L.stat[22], tw1 - tw0);
+            atomicAdd(&L.stat[23], tw2 - tw1);
+        }
         __threadfence();
+        __syncthreads();
+        // The single-parent groups' (2,1,0) credits of x and of the slots y, per slot x:
+        // nsg[xc][x] groups, each a set {r, x, y, c} with every slot y other than x.  y a
+        // local neighbour of x (x-y arc): x takes its profile times the group count, y one
+        // credit per parent code.  Pure y: x's credit by ry from the slot counts, y's by
+        // complement (gall stands for every slot; x itself and x's local neighbours are
+        // taken back from their own counters).  One wave per slot x.
+        if (A.k4)
+            for (uint32_t x = wid; x < d; x += NW) {
+                const uint32_t m1 = nsg[x], m2 = nsg[PMAX + x], m3 = nsg[2 * PMAX + x];
+                if (!(m1 | m2 | m3)) continue;
+                const uint32_t rx = L.P[x] & 3u, vx = L.P[x] >> 2;
+                const uint32_t xl = L.lcnt[x];
+                if (lane < 27) {   // lane = (xc-1)*9 + (ry-1)*3 + (xy-1): sets with an x-y arc
+                    const uint32_t xc = lane / 9u + 1u, ry = (lane / 3u) % 3u + 1u, xy = lane % 3u + 1u;
+                    const uint32_t m = xc == 1u ? m1 : (xc == 2u ? m2 : m3);
+                    const uint32_t h = (uint32_t)(prof[(ry - 1u) * PMAX + x] >> (21u * (xy - 1u))) & F21;
+                    if (m && h) {
+                        add4(A, L, vx, L.t4[motif_index4(rx, ry, 0u, xy, xc, 0u)], (unsigned long long)m * h);
+                        slow[3] += m * h;
+                    }
+                } else if (lane >= 32 && lane < 41) {   // lane - 32 = (xc-1)*3 + (ry-1): pure y
+                    const uint32_t xc = (lane - 32u) / 3u + 1u, ry = (lane - 32u) % 3u + 1u;
+                    const uint32_t m = xc == 1u ? m1 : (xc == 2u ? m2 : m3);
+                    const unsigned long long w = prof[(ry - 1u) * PMAX + x];
+                    const uint32_t nl = ((uint32_t)w & F21) + ((uint32_t)(w >> 21) & F21) + ((uint32_t)(w >> 42) & F21);
+                    const uint32_t nr = ry == 1u ? nr1 : (ry == 2u ? nr2 : nr3);
+                    const uint32_t nk = nr - (rx == ry) - nl;
+                    if (m && nk) spar[(lane - 32u) * PMAX + x] += m * nk;   // one lane per counter
+                } else if (lane >= 48 && lane < 51) {   // lane - 48 = xc - 1: complement of y
+                    const uint32_t m = lane == 48 ? m1 : (lane == 49 ? m2 : m3);
+                    if (m) {
+                        const uint32_t g = (rx - 1u) * 3u + (lane - 48u);
+                        atomicAdd(&L.gall[g], m);
+                        atomicAdd(&L.cnt[g * d + x], 0u - m);
+                        shape[3] += m * (d - 1u);
+                    }
+                }
+                const uint32_t xq = L.pre[x];
+                for (uint32_t q = lane; q < xl; q += 64) {
+                    const uint32_t vq = llist[xq + q], y = vq >> 2, xy = vq & 3u;
+                    const uint32_t ry = L.P[y] & 3u, vy = L.P[y] >> 2;
+#pragma unroll
+                    for (uint32_t xc = 1; xc <= 3; xc++) {
+                        const uint32_t m = xc == 1u ? m1 : (xc == 2u ? m2 : m3);
+                        if (!m) continue;
+                        atomicAdd(&L.cnt[((rx - 1u) * 3u + (xc - 1u)) * d + y], 0u - m);
+                        add4(A, L, vy, L.t4[motif_index4(rx, ry, 0u, xy, xc, 0u)], m);
+                    }
+                }
+                if (lane == 0) {
+                    nsg[x] = 0;
+                    nsg[PMAX + x] = 0;
+                    nsg[2 * PMAX + x] = 0;
+                }
+            }
         __syncthreads();
         if (A.k4) {
             for (uint32_t q = tid; q < 9 * d; q += HT) {
@@ -1509,7 +1616,7 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
         size_t o = M_WORDS;
         const size_t o_spar = o; o += 9 * PMAX;
         const size_t o_s111 = o; o += 9 * PMAX;
-        const size_t o_s3x = o; o += 3 * PMAX;
+        const size_t o_s3x = o; o += 12 * PMAX;   // s3x [3][PMAX], nsg [3][PMAX], prof [3][PMAX] u64
         const size_t o_groups = o; o += 3 * s2;
         const size_t o_wlist = o; o += NW * wl;
         const size_t o_eflag = o; o += (s2 + 3) / 4;
