@@ -727,6 +727,26 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                                 add4(A, L, L.P[x] >> 2, cls, 1);
                                 add4(A, L, L.P[y] >> 2, cls, 1);
                                 add4(A, L, c, cls, 1);
+                            } else if (q < xl && x < y) {
+                                // y in A(c) with an x-y arc (rare): the pair {x, y} is counted
+                                // below as if it had none; move it to its class
+                                uint32_t yc = 0;
+                                for (uint32_t w = 0; w < p; w++)
+                                    if ((Ac[w] >> 2) == y) {
+                                        yc = Ac[w] & 3u;
+                                        break;
+                                    }
+                                slow[3]++;
+                                const uint32_t c0 = L.t4[motif_index4(rx, ry, 0u, 0u, xc, yc)];
+                                const uint32_t c1 = L.t4[motif_index4(rx, ry, 0u, xy, xc, yc)];
+                                atomicAdd(&L.root4[c0], ~0ull);
+                                atomicAdd(&L.root4[c1], 1ull);
+                                add4(A, L, L.P[x] >> 2, c0, ~0ull);
+                                add4(A, L, L.P[y] >> 2, c0, ~0ull);
+                                add4(A, L, c, c0, ~0ull);
+                                add4(A, L, L.P[x] >> 2, c1, 1);
+                                add4(A, L, L.P[y] >> 2, c1, 1);
+                                add4(A, L, c, c1, 1);
                             }
                         }
                         if (lane == 0) {
@@ -751,27 +771,34 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                     }
                 }
                 tg1 = wall_clock64();
-                // (2,1,0) with both depth-1 vertices in A(c): pairs u < v of A(c)
-                for (uint32_t v0 = 0; v0 < p; v0 += 64) {
-                    const uint32_t vpos = v0 + lane;
-                    const bool vv = vpos < p;
-                    const uint32_t ey = vv ? Ac[vpos] : 0u;
-                    const uint32_t y = ey >> 2, yc = ey & 3u, ry = vv ? (L.P[y] & 3u) : 0u;
-                    const uint32_t umax = min(p, v0 + 64);
-                    for (uint32_t u = 0; u + 1 < umax; u++) {
-                        const bool valid = vv && u < vpos;
-                        if (!__ballot(valid)) continue;
-                        const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
-                        if (valid) {
-                            slow[3]++;
-                            const uint32_t xy = mget(M, d, x, y);
-                            const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, yc)];
-                            atomicAdd(&L.root4[cls], 1ull);
-                            add4(A, L, L.P[x] >> 2, cls, 1);
-                            add4(A, L, L.P[y] >> 2, cls, 1);
-                            add4(A, L, c, cls, 1);
-                            shape[3]++;
-                        }
+                // (2,1,0) with both depth-1 vertices in A(c): pairs {x, y} of parents.  With no
+                // x-y arc a pair's class is fixed by the two parents' codes, so the pairs are
+                // counted from the code histogram: c and the root per pair of codes, each parent
+                // per partner code.  The pairs with an x-y arc were moved to their classes in
+                // the local-list walk above.
+                if (lane < 45) {   // lane -> codes q1 <= q2
+                    uint32_t q1 = 0, rem = lane;
+                    while (rem >= 9u - q1) {
+                        rem -= 9u - q1;
+                        q1++;
+                    }
+                    const uint32_t q2 = q1 + rem, f1 = field(q1), f2 = field(q2);
+                    const uint32_t n = q1 == q2 ? f1 * (f1 - 1u) / 2u : f1 * f2;
+                    if (n) {
+                        const uint32_t cls = L.t4[motif_index4(q1 / 3u + 1u, q2 / 3u + 1u, 0u, 0u, q1 % 3u + 1u, q2 % 3u + 1u)];
+                        add4(A, L, c, cls, n);
+                        atomicAdd(&L.root4[cls], (unsigned long long)n);
+                        shape[3] += n;
+                    }
+                }
+                for (uint32_t u = lane; u < p; u += 64) {
+                    const uint32_t ex = Ac[u], x = ex >> 2, xc = ex & 3u, px = L.P[x];
+                    const uint32_t qx = ((px & 3u) - 1u) * 3u + (xc - 1u);
+#pragma unroll
+                    for (uint32_t q2 = 0; q2 < 9; q2++) {
+                        const uint32_t n = field(q2) - (q2 == qx ? 1u : 0u);
+                        if (n)
+                            add4(A, L, px >> 2, L.t4[motif_index4(px & 3u, q2 / 3u + 1u, 0u, 0u, xc, q2 % 3u + 1u)], n);
                     }
                 }
                 tg2 = wall_clock64();
