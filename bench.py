@@ -123,10 +123,11 @@ def main():
         out3 = torch.zeros((1, 13), dtype=torch.int64, device="cuda")
 
     hub_ms_steps = []
+    khub_ms_steps = []
 
     def step(timing=None):
         G = v.Graph(g.n, dsrc, ddst, stream=stream, undirected=undirected)
-        hub_ms = 0.0
+        hub_ms = khub = 0.0
         if timing is not None:
             timing[0].record(stream)
         if undirected:
@@ -139,13 +140,16 @@ def main():
                 v.count_range(G, 4, out4, bounds[i], bounds[i + 1], accumulate=i > 0, stream=stream)
                 if timing is not None:
                     stream.synchronize()
-                    hub_ms += max(0.0, v.kernel_times(G)[1])
+                    kt = v.kernel_times(G)
+                    hub_ms += max(0.0, kt[1])
+                    khub += max(0.0, kt[2])
                     log(f"[bench] ranks [{bounds[i]}, {bounds[i + 1]}) done")
         else:
             v.count34(G, out3, out4, stream=stream)
         if timing is not None:
             timing[1].record(stream)
             hub_ms_steps.append(hub_ms)
+            khub_ms_steps.append(khub)
         return G
 
     for w in range(args.warmup):
@@ -165,12 +169,14 @@ def main():
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     log(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step, count call {kernel_ms:.2f} ms")
 
-    if not only4 or undirected:   # the hub kernel's own events, recorded by the library in every timed step
+    if not only4 or undirected:   # the hub path's own events, recorded by the library in every timed step
         hub_ms_steps = [v.kernel_times(Gk)[1] for Gk in graphs]
+        khub_ms_steps = [v.kernel_times(Gk)[2] for Gk in graphs]
     G = graphs[-1]
     sc = v.shape_counts(G)
     pc = v.profile_counters(G)
     hub_ms = float(np.mean(hub_ms_steps))
+    khub_ms = float(np.mean(khub_ms_steps))
     T3_hub = int(pc[32]) + int(pc[33])
     T4_hub = int(pc[34] + pc[35] + pc[36] + pc[37])
     c3 = out3.sum(dim=0).cpu().numpy()
@@ -181,11 +187,12 @@ def main():
     assert only4 or sc["(1,1)"] + sc["(1,2)"] == T3, "k=3 shape counts disagree with the column sums"
     assert sc["(3,0,0)"] + sc["(2,1,0)"] + sc["(1,2,0)"] + sc["(1,1,1)"] == T4, "k=4 shapes disagree"
 
-    # Roofline of the dominant kernel (the hub kernel): every k-set costs at least its
-    # index assembly (one placement per vertex pair), one class lookup and one increment
-    # per member: k=4: 6 + 1 + 4 = 11 integer ops; k=3: 3 + 1 + 3 = 7.  Achieved = those
-    # ops over the sets the hub kernel enumerated, per hub-kernel second (HIP events
-    # recorded by the library on the count's stream around the launch, every timed step).
+    # Roofline of the dominant work, the hub path (k_hub, then the (1,2,0) slot-pair kernel
+    # and the (1,1,1) end-vertex pass, which finish the same roots' sets): every k-set costs
+    # at least its index assembly (one placement per vertex pair), one class lookup and one
+    # increment per member: k=4: 6 + 1 + 4 = 11 integer ops; k=3: 3 + 1 + 3 = 7.  Achieved =
+    # those ops over the sets the hub path enumerated, per second of the path (HIP events
+    # recorded by the library on the count's stream around its launches, every timed step).
     alg_ops = 11.0 * T4_hub + 7.0 * T3_hub
     achieved_tops = alg_ops / (hub_ms * 1e-3) / 1e12 if hub_ms > 0 else 0.0
     # compulsory HBM bytes: CSR read once + both outputs written once
@@ -211,7 +218,8 @@ def main():
         "sets3_per_s": T3 / (ms_step * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": hub_traffic(args.workload),
-                     "kernel": "k_hub", "kernel_ms": hub_ms, "sets4": T4_hub, "sets3": T3_hub,
+                     "kernel": "hub path: k_hub + k_slot_pairs + k_pull111", "kernel_ms": hub_ms,
+                     "k_hub_ms": khub_ms, "sets4": T4_hub, "sets3": T3_hub,
                      "ops_per_set": {"k4": 11, "k3": 7},
                      "hbm_compulsory_frac": (csr_bytes + out_bytes) / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
@@ -226,10 +234,11 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-# HBM bytes per hub-kernel launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
-# this bench (KiB per dispatch), scaled by the readings of a 1 GiB copy (FETCH_SIZE
-# reads half of the copied bytes: factor 2.0; WRITE_SIZE factor 1.0).  Valid only for
-# the kernel sources they were taken with: any change to them reports null.
+# HBM bytes per hub path (k_hub + k_slot_pairs + k_pull111, one dispatch each) from
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this bench (KiB per dispatch, summed
+# over the three), scaled by the readings of a 1 GiB copy (FETCH_SIZE reads half of the
+# copied bytes: factor 2.0; WRITE_SIZE factor 1.0).  Valid only for the kernel sources
+# they were taken with: any change to them reports null.
 HUB_COUNTER_SOURCES = ["paper_2201_11655_amd/csrc/count_hub.hip", "paper_2201_11655_amd/csrc/vdmc_internal.h",
                        "paper_2201_11655_amd/csrc/motif_device.h"]
 HUB_COUNTERS = {     # workload -> counters of one hub-kernel dispatch (profiles/k_hub_chunglu_1M_hbm_counters.md)

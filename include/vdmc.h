@@ -187,16 +187,18 @@ vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
  * short row); entries 24-27 the wave time spent inside the wave-per-group loop on
  * (2,1,0) sets, (2,1,0) sets with both parents, (1,1,1) paths and the rest (all times
  * 100 MHz ticks summed over waves); entries 28-31 work counts: depth-2 groups of the
- * wave-per-group loop, (1,1,1) chunks, (1,1,1) parent-chunk pairs, (2,1,0) local-list
- * steps; entries 32-37 the part of the shape counts enumerated by the hub kernel.
+ * wave-per-group loop, (1,1,1) chunks, (1,1,1) parent-chunk pairs, (2,1,0) parents whose
+ * local list the whole wave walks; entries 32-37 the part of the shape counts enumerated by the hub kernel.
  * Copies min(n, 40) entries. */
 vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n);
 
 /* Device time of the kernels of the last count call on this graph, from events recorded
- * on the count's stream around each launch (host; waits for those events):
- * ms_out[0] the per-set kernel over the light roots, ms_out[1] the hub kernel; -1 for a
- * kernel that the call did not launch.  ms_out: 2 floats, caller-owned. */
-vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out);
+ * on the count's stream around the launches (host; waits for those events):
+ * ms_out[0] the per-set kernel over the light roots, ms_out[1] the hub path (the hub
+ * kernel, then for k = 4 the (1,2,0) slot-pair kernel and the (1,1,1) end-vertex pass),
+ * ms_out[2] the hub kernel alone; -1 for a part that the call did not launch.  ms_out:
+ * n floats, caller-owned; the first min(n, 3) are written. */
+vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out, int32_t n);
 
 /*
  * Batched counts: num graphs, one k for all, outs[i] a DEVICE buffer of

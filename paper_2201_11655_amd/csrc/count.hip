@@ -603,19 +603,21 @@ vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n) {
     });
 }
 
-vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out) {
+vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out, int32_t n) {
     return vdmc::guarded([&] {
-        VDMC_REQUIRE(g != nullptr && ms_out != nullptr, VDMC_ERR_INVALID_ARG, "bad argument");
+        VDMC_REQUIRE(g != nullptr && ms_out != nullptr && n >= 0, VDMC_ERR_INVALID_ARG, "bad argument");
         VDMC_HIP(hipSetDevice(g->device));
-        ms_out[0] = ms_out[1] = -1.0f;
+        float t[3] = {-1.0f, -1.0f, -1.0f};
         if (g->timed_light) {
             VDMC_HIP(hipEventSynchronize(g->ev[1]));
-            VDMC_HIP(hipEventElapsedTime(&ms_out[0], g->ev[0], g->ev[1]));
+            VDMC_HIP(hipEventElapsedTime(&t[0], g->ev[0], g->ev[1]));
         }
         if (g->timed_hub) {
             VDMC_HIP(hipEventSynchronize(g->ev[3]));
-            VDMC_HIP(hipEventElapsedTime(&ms_out[1], g->ev[2], g->ev[3]));
+            VDMC_HIP(hipEventElapsedTime(&t[1], g->ev[2], g->ev[3]));
+            VDMC_HIP(hipEventElapsedTime(&t[2], g->ev[2], g->ev[4]));
         }
+        for (int i = 0; i < n && i < 3; i++) ms_out[i] = t[i];
     });
 }
 

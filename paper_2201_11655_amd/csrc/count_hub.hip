@@ -143,6 +143,7 @@ __device__ __forceinline__ int wave_next(unsigned* sTask) {
 
 // P membership filter: one bit per hash bucket of a rank; a clear bit proves absence.
 constexpr uint32_t kShortRow = 64;     // (1,2,0): rows up to this length are walked
+constexpr uint32_t kLaneList = 16;     // (2,1,0): local lists up to this length walked by one lane
 constexpr uint32_t kBloomWords = 1024;   // 32768 bits
 // P slot lookup: open-addressing table of N+(r) in LDS (rank + 1 -> slot), load <= 1/2
 constexpr uint32_t kPHashBits = 12;
@@ -695,70 +696,93 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 // x's local neighbours outside A(c) are subtracted from their own counters
                 // (modular; they end non-negative).  x's local neighbours outside A(c) are the
                 // sets with an x-y arc and take the direct path.
+                // One entry y of x's local list: a direct set if y is outside A(c); else (rare)
+                // the pair {x, y} of parents with an x-y arc, counted below as if it had none,
+                // is moved to its class.  Returns ry for a set, 0 otherwise.
+                auto local_entry = [&](uint32_t x, uint32_t rx, uint32_t xc, uint32_t g, uint32_t vq) -> uint32_t {
+                    const uint32_t y = vq >> 2, xy = vq & 3u, py = L.P[y], ry = py & 3u;
+                    if (!((inA[y >> 5] >> (y & 31)) & 1u)) {
+                        atomicAdd(&L.cnt[g * d + y], 0xFFFFFFFFu);
+                        slow[3]++;
+                        const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, 0u)];
+                        atomicAdd(&L.root4[cls], 1ull);
+                        add4(A, L, L.P[x] >> 2, cls, 1);
+                        add4(A, L, py >> 2, cls, 1);
+                        add4(A, L, c, cls, 1);
+                        return ry;
+                    }
+                    if (x < y) {
+                        uint32_t yc = 0;
+                        for (uint32_t w = 0; w < p; w++)
+                            if ((Ac[w] >> 2) == y) {
+                                yc = Ac[w] & 3u;
+                                break;
+                            }
+                        slow[3]++;
+                        const uint32_t c0 = L.t4[motif_index4(rx, ry, 0u, 0u, xc, yc)];
+                        const uint32_t c1 = L.t4[motif_index4(rx, ry, 0u, xy, xc, yc)];
+                        atomicAdd(&L.root4[c0], ~0ull);
+                        atomicAdd(&L.root4[c1], 1ull);
+                        add4(A, L, L.P[x] >> 2, c0, ~0ull);
+                        add4(A, L, py >> 2, c0, ~0ull);
+                        add4(A, L, c, c0, ~0ull);
+                        add4(A, L, L.P[x] >> 2, c1, 1);
+                        add4(A, L, py >> 2, c1, 1);
+                        add4(A, L, c, c1, 1);
+                    }
+                    return 0u;
+                };
+                // x's sets with a pure y, by ry = k: the slots minus A(c) minus the direct ones
+                auto pure_parent = [&](uint32_t x, uint32_t xc, uint32_t g, uint32_t k, uint32_t nk) {
+                    if (!nk) return;
+                    atomicAdd(&spar[((xc - 1u) * 3u + (k - 1u)) * PMAX + x], nk);
+                    atomicAdd(&cw[g * 3u + (k - 1u)], nk);
+                };
+                // parents with a short local list: one lane per parent; the others: the wave
                 for (uint32_t ub = 0; ub < p; ub += 64) {
-                    const uint32_t areg = ub + lane < p ? Ac[ub + lane] : 0u;
-                    const uint32_t ucnt = min(64u, p - ub);
-                    for (uint32_t uu = 0; uu < ucnt; uu++) {
-                        const uint32_t ex = __shfl(areg, (int)uu);
-                        const uint32_t x = ex >> 2, xc = ex & 3u, rx = L.P[x] & 3u;
-                        const uint32_t g = (rx - 1u) * 3u + (xc - 1u);
-                        const uint32_t xl = L.lcnt[x], xq = L.pre[x];
-                        uint32_t n1 = 0, n2 = 0, n3 = 0;   // x's local neighbours outside A(c), by ry
-                        for (uint32_t qb = 0; qb < xl; qb += 64) {
+                    const uint32_t u = ub + lane;
+                    const uint32_t ex = u < p ? Ac[u] : 0u;
+                    const uint32_t x = ex >> 2, xc = ex & 3u;
+                    const uint32_t xl = u < p ? L.lcnt[x] : 0u;
+                    const bool small = u < p && xl <= kLaneList;
+                    if (small) {
+                        const uint32_t rx = L.P[x] & 3u, g = (rx - 1u) * 3u + (xc - 1u), xq = L.pre[x];
+                        uint32_t n1 = 0, n2 = 0, n3 = 0;
+                        for (uint32_t q = 0; q < xl; q++) {
+                            const uint32_t ry = local_entry(x, rx, xc, g, llist[xq + q]);
+                            n1 += ry == 1u;
+                            n2 += ry == 2u;
+                            n3 += ry == 3u;
+                        }
+                        atomicAdd(&L.gall[g], 1u);
+                        shape[3] += d - p;
+                        pure_parent(x, xc, g, 1, nr1 - ha1 - n1);
+                        pure_parent(x, xc, g, 2, nr2 - ha2 - n2);
+                        pure_parent(x, xc, g, 3, nr3 - ha3 - n3);
+                    }
+                    unsigned long long big = __ballot(u < p && !small);
+                    while (big) {
+                        const int bl = __ffsll((long long)big) - 1;
+                        big &= big - 1ull;
+                        const uint32_t bx = (uint32_t)__shfl((int)ex, bl);
+                        const uint32_t x2 = bx >> 2, xc2 = bx & 3u, rx2 = L.P[x2] & 3u;
+                        const uint32_t g2 = (rx2 - 1u) * 3u + (xc2 - 1u);
+                        const uint32_t xl2 = L.lcnt[x2], xq2 = L.pre[x2];
+                        if (lane == 0) work[3]++;
+                        uint32_t n1 = 0, n2 = 0, n3 = 0;
+                        for (uint32_t qb = 0; qb < xl2; qb += 64) {
                             const uint32_t q = qb + lane;
-                            bool out = false;
-                            uint32_t y = 0, xy = 0, ry = 0;
-                            if (q < xl) {
-                                const uint32_t vq = llist[xq + q];
-                                y = vq >> 2;
-                                xy = vq & 3u;
-                                out = !((inA[y >> 5] >> (y & 31)) & 1u);
-                                ry = L.P[y] & 3u;
-                            }
-                            if (lane == 0) work[3]++;
-                            n1 += __popcll(__ballot(out && ry == 1u));
-                            n2 += __popcll(__ballot(out && ry == 2u));
-                            n3 += __popcll(__ballot(out && ry == 3u));
-                            if (out) {
-                                atomicAdd(&L.cnt[g * d + y], 0xFFFFFFFFu);
-                                slow[3]++;
-                                const uint32_t cls = L.t4[motif_index4(rx, ry, 0u, xy, xc, 0u)];
-                                atomicAdd(&L.root4[cls], 1ull);
-                                add4(A, L, L.P[x] >> 2, cls, 1);
-                                add4(A, L, L.P[y] >> 2, cls, 1);
-                                add4(A, L, c, cls, 1);
-                            } else if (q < xl && x < y) {
-                                // y in A(c) with an x-y arc (rare): the pair {x, y} is counted
-                                // below as if it had none; move it to its class
-                                uint32_t yc = 0;
-                                for (uint32_t w = 0; w < p; w++)
-                                    if ((Ac[w] >> 2) == y) {
-                                        yc = Ac[w] & 3u;
-                                        break;
-                                    }
-                                slow[3]++;
-                                const uint32_t c0 = L.t4[motif_index4(rx, ry, 0u, 0u, xc, yc)];
-                                const uint32_t c1 = L.t4[motif_index4(rx, ry, 0u, xy, xc, yc)];
-                                atomicAdd(&L.root4[c0], ~0ull);
-                                atomicAdd(&L.root4[c1], 1ull);
-                                add4(A, L, L.P[x] >> 2, c0, ~0ull);
-                                add4(A, L, L.P[y] >> 2, c0, ~0ull);
-                                add4(A, L, c, c0, ~0ull);
-                                add4(A, L, L.P[x] >> 2, c1, 1);
-                                add4(A, L, L.P[y] >> 2, c1, 1);
-                                add4(A, L, c, c1, 1);
-                            }
+                            const uint32_t ry = q < xl2 ? local_entry(x2, rx2, xc2, g2, llist[xq2 + q]) : 0u;
+                            n1 += __popcll(__ballot(ry == 1u));
+                            n2 += __popcll(__ballot(ry == 2u));
+                            n3 += __popcll(__ballot(ry == 3u));
                         }
                         if (lane == 0) {
-                            atomicAdd(&L.gall[g], 1u);
+                            atomicAdd(&L.gall[g2], 1u);
                             shape[3] += d - p;
-                        }
-                        if (lane < 3) {   // x's sets with a non-adjacent y, by ry
-                            const uint32_t nk = lane == 0 ? nr1 - ha1 - n1 : (lane == 1 ? nr2 - ha2 - n2 : nr3 - ha3 - n3);
-                            if (nk) {
-                                atomicAdd(&spar[((xc - 1) * 3 + lane) * PMAX + x], nk);
-                                cw[g * 3 + lane] += nk;
-                            }
+                            pure_parent(x2, xc2, g2, 1, nr1 - ha1 - n1);
+                            pure_parent(x2, xc2, g2, 2, nr2 - ha2 - n2);
+                            pure_parent(x2, xc2, g2, 3, nr3 - ha3 - n3);
                         }
                     }
                 }
@@ -1766,10 +1790,11 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
                            0, st, a.w111, wcells);
     const int wgs = hub_workgroups();
     // the hub path: k_hub, then (k = 4) the (1,2,0) tasks and the (1,1,1) end-vertex pass;
-    // the events bracket all three
+    // around[0] and around[1] bracket all three, around[2] marks the end of k_hub
     if (around) VDMC_HIP(hipEventRecord(around[0], st));
     hipLaunchKernelGGL(k_hub, dim3(wgs), dim3(HT), 0, st, a);
     VDMC_HIP(hipGetLastError());
+    if (around) VDMC_HIP(hipEventRecord(around[2], st));
     if (k4) {
         SlotPairArgs sp;
         sp.off = g->off;

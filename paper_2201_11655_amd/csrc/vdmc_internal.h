@@ -144,7 +144,7 @@ struct vdmc_graph_s {
     size_t hub_layout[16] = {0};
     // timing of the last count call: [0,1] around the per-set kernel, [2,3] around the
     // hub kernel (created at the first count)
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     bool timed_light = false, timed_hub = false;
 };
 

@@ -68,7 +68,7 @@ def load():
         "vdmc_count_range": ([p, i32, p, i64, i64, u32, p], i32),
         "vdmc_shape_counts": ([p, p], i32),
         "vdmc_profile_counters": ([p, p, i32], i32),
-        "vdmc_kernel_times": ([p, p], i32),
+        "vdmc_kernel_times": ([p, p, i32], i32),
         "vdmc_num_classes_undirected": ([i32], i32),
         "vdmc_undirected_classes": ([i32, p], i32),
         "vdmc_count_undirected": ([p, i32, p, p], i32),
@@ -295,10 +295,11 @@ def profile_counters(g: Graph) -> np.ndarray:
 
 
 def kernel_times(g: Graph) -> tuple:
-    """(per-set kernel ms, hub kernel ms) of the last count call on g; -1 if not launched."""
-    out = np.zeros(2, np.float32)
-    _check(load().vdmc_kernel_times(g.handle, _np_ptr(out)))
-    return float(out[0]), float(out[1])
+    """(per-set kernel ms, hub path ms, hub kernel alone ms) of the last count call on g;
+    -1 for a part that was not launched."""
+    out = np.zeros(3, np.float32)
+    _check(load().vdmc_kernel_times(g.handle, _np_ptr(out), 3))
+    return float(out[0]), float(out[1]), float(out[2])
 
 
 def count_batch(graphs, k: int, outs=None, stream=None):

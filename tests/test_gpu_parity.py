@@ -227,19 +227,20 @@ def test_kernel_times_and_hub_share(v):
     _say(f"kernel times n={g.n}")
     G = v.Graph(g.n, g.src, g.dst)
     v.count34(G)
-    light_ms, hub_ms = v.kernel_times(G)
+    light_ms, hub_ms, khub_ms = v.kernel_times(G)
     pc = v.profile_counters(G)
     all_hub = os.environ.get("VDMC_HUB_MIN") == "1"   # every root on the hub path
     assert hub_ms >= 0.0 and (light_ms == -1.0 if all_hub else light_ms >= 0.0)
+    assert 0.0 <= khub_ms <= hub_ms   # the hub kernel is the first part of the hub path
     assert all(pc[32 + s] <= pc[s] for s in range(6))
     assert pc[32:38].sum() > 0   # chunglu_2000 has hub roots
     G2 = v.Graph(5, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
     v.count(G2, 3)
-    lt, ht = v.kernel_times(G2)
+    lt, ht, kt = v.kernel_times(G2)
     if all_hub:
-        assert lt == -1.0 and ht >= 0.0
+        assert lt == -1.0 and ht >= 0.0 and kt >= 0.0
     else:
-        assert ht == -1.0 and lt >= 0.0   # no hub root: the hub kernel is not launched
+        assert ht == -1.0 and kt == -1.0 and lt >= 0.0   # no hub root: no hub path
 
 
 # --------------------------------------------------------------------------- undirected motifs
