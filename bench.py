@@ -241,9 +241,12 @@ def main():
 # they were taken with: any change to them reports null.
 HUB_COUNTER_SOURCES = ["paper_2201_11655_amd/csrc/count_hub.hip", "paper_2201_11655_amd/csrc/vdmc_internal.h",
                        "paper_2201_11655_amd/csrc/motif_device.h"]
-HUB_COUNTERS = {     # workload -> counters of one hub-kernel dispatch (profiles/k_hub_chunglu_1M_hbm_counters.md)
-    "chunglu": {"sources_sha256": "4dfd777c7345423dac25a0196dabc79e9d523eddfec8057d0e237acc11ffff29",
-                "fetch_kib": 1790133367.9, "write_kib": 550327453.8},
+HUB_COUNTERS = {     # workload -> counters of one hub path (profiles/k_hub_chunglu_1M_hbm_counters.md)
+    "chunglu": {"sources_sha256": "6f8681de8a9ee54aa0ecd749086006b1ca98b5fde59fdc099dd3a75eaa3eda0b",
+                # k_hub 144909928.2 + k_slot_pairs 376549150.9 + k_pull111 8615731.2
+                "fetch_kib": 530074810.3,
+                # k_hub 318956788.3 + k_slot_pairs 112841159.3 + k_pull111 2896136.2
+                "write_kib": 434694083.8},
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
