@@ -1337,7 +1337,7 @@ __global__ __launch_bounds__(SP) void k_slot_pairs(SlotPairArgs A) {
             if (m <= kLHash / 2) short_walks(lkey[wid], lval[wid], kLHashBits);
             else short_walks(hkey, hval, A.hash_bits);
         }
-        // pairs of long-row children: the edge hash
+        // pairs of long-row children: the long-vertex bitmap, then the edge hash
         const uint32_t nll = kl * (kl - 1u) / 2u;
         for (uint32_t q = lane; q < nll; q += 64) {
             uint32_t j = (uint32_t)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
@@ -1710,7 +1710,7 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
             VDMC_HIP(hipcub::DeviceScan::ExclusiveSum(t3, tb, dplus, g->hub_pre, (int)(nhub + 1), st));
         }
         // adjacency bitmap of the long-row vertices (pairs of long children in (1,2,0)),
-        // when it is at most 1 GiB
+        // when it is at most 4 GiB
         {
             uint32_t* d_nl = (uint32_t*)alloc(sizeof(uint32_t));
             VDMC_HIP(hipMemsetAsync(d_nl, 0, sizeof(uint32_t), st));
@@ -1724,7 +1724,7 @@ void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
             const size_t lbytes = lw * nl * sizeof(uint32_t);
             g->nlong = nl;
             g->lwords = (uint32_t)lw;
-            if (nl > 0 && lbytes <= ((size_t)1 << 30)) {
+            if (nl > 0 && lbytes <= ((size_t)4 << 30)) {
                 VDMC_HIP(hipMalloc(&g->lbits, lbytes));
                 VDMC_HIP(hipMemsetAsync(g->lbits, 0, lbytes, st));
                 const unsigned lb = (unsigned)std::min<int64_t>((nl + BT - 1) / BT, 65536);

@@ -155,6 +155,22 @@ def test_chunglu_small_full(v):
     _check_graph(v, g.n, g.src, g.dst, label="chunglu_2000")
 
 
+def test_dense_long_children_rows(v):
+    # every vertex has more than 64 neighbours, so every depth-2 child has a long row and
+    # the (1,2,0) pairs of children are all tested in the long-vertex bitmap (dozens of
+    # long children per slot).  The oracle's rows of a few vertices (its full count of
+    # this graph takes minutes), plus the shape totals.
+    g = gg.er_directed(300, 0.25, (71, 1))
+    _say(f"dense long children n={g.n} m={g.m}")
+    G = v.Graph(g.n, g.src, g.dst)
+    got = _np(v.count(G, 4))
+    rows = np.array([0, 150, 299], np.int32)
+    want = oracle.count_rows(g.n, g.src, g.dst, 4, rows)
+    assert (got[rows] == want).all()
+    sc = v.shape_counts(G)
+    assert int(got.sum()) == 4 * (sc["(3,0,0)"] + sc["(2,1,0)"] + sc["(1,2,0)"] + sc["(1,1,1)"])
+
+
 def test_degenerate_graphs(v):
     import torch
     for n, src, dst in [
