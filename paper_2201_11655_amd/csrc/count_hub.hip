@@ -634,8 +634,12 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             if (more) cN = grp[tn];
             if (lane == 0) work[0]++;
             // A(c): c's neighbours in N+(r), as (slot << 2) | arc bits seen from the slot
+            // The same pass counts the valid ends e of the (1,1,1) paths r - x - c - e (e above
+            // r, not in N+(r)) by the arc code ce, and the entries below r (a prefix: rows are
+            // sorted by rank).
             uint32_t* Ac = wlist;
             uint32_t p = 0;
+            uint32_t T1 = 0, T2 = 0, T3 = 0, nlow = 0;
             for (uint32_t base = clo; base < chi; base += 64) {
                 const uint32_t tt = base + lane;
                 uint32_t e = 0;
@@ -647,6 +651,12 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 const unsigned long long mk = __ballot(sl >= 0);
                 if (sl >= 0) Ac[p + __popcll(mk & lt_mask)] = ((uint32_t)sl << 2) | swap_arc_bits(e & 3u);
                 p += __popcll(mk);
+                const bool ev = tt < chi && (e >> 2) > r && sl < 0;
+                T1 += __popcll(__ballot(ev && (e & 3u) == 1u));
+                T2 += __popcll(__ballot(ev && (e & 3u) == 2u));
+                T3 += __popcll(__ballot(ev && (e & 3u) == 3u));
+                nlow += __popcll(__ballot(tt < chi && (e >> 2) < r));
+                if (lane == 0) work[1]++;
             }
             __threadfence_block();
             for (uint32_t u = lane; u < p; u += 64) {
@@ -840,31 +850,27 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 // parent codes of this group go into w111[c], and every vertex e later adds
                 // w111 of all its neighbours.  That pass also reaches the entries of c's row
                 // that are not valid here (e below r, or e in N+(r)); those are taken off now.
-                uint32_t T1 = 0, T2 = 0, T3 = 0;   // valid e of c's row by ce (wave-uniform)
-                for (uint32_t base = clo; base < chi; base += 64) {
-                    const uint32_t tt = base + lane;
-                    uint32_t ee = 0;
-                    bool ev = false, inv = false;
-                    if (tt < chi) {
-                        ee = A.adj[tt];
-                        if ((ee >> 2) < r) inv = true;
-                        else if (find_slot_f(L, d, ee >> 2) >= 0) inv = true;
-                        else ev = true;
+                // the entries of c's row that are not valid ends: the parents themselves (their
+                // arc code from c is the swap of the stored one) and the prefix below r
+                auto take_off = [&](uint32_t e, uint32_t ce) {
+                    for (uint32_t q = 0; q < 9; q++) {
+                        const uint32_t cnt = field(q);
+                        if (cnt)
+                            add4(A, L, e, L.t4[motif_index4(q / 3 + 1, 0u, 0u, q % 3 + 1, 0u, ce)],
+                                 0ull - (unsigned long long)cnt);
                     }
-                    if (lane == 0) { work[1]++; work[2] += p; }
-                    const uint32_t e = ee >> 2, ce = ee & 3u;
-                    T1 += __popcll(__ballot(ev && ce == 1u));
-                    T2 += __popcll(__ballot(ev && ce == 2u));
-                    T3 += __popcll(__ballot(ev && ce == 3u));
-                    if (ev) shape[5] += p;
-                    if (inv)
-                        for (uint32_t q = 0; q < 9; q++) {
-                            const unsigned long long w = q < 3 ? hist1 : (q < 6 ? hist2 : hist3);
-                            const uint32_t cnt = (uint32_t)(w >> (21u * (q % 3))) & F21;
-                            if (cnt)
-                                add4(A, L, e, L.t4[motif_index4(q / 3 + 1, 0u, 0u, q % 3 + 1, 0u, ce)],
-                                     0ull - (unsigned long long)cnt);
-                        }
+                };
+                for (uint32_t u = lane; u < p; u += 64) {
+                    const uint32_t ex = Ac[u];
+                    take_off(L.P[ex >> 2] >> 2, swap_arc_bits(ex & 3u));
+                }
+                for (uint32_t tt = clo + lane; tt < clo + nlow; tt += 64) {
+                    const uint32_t ee = A.adj[tt];
+                    take_off(ee >> 2, ee & 3u);
+                }
+                if (lane == 0) {
+                    shape[5] += p * (T1 + T2 + T3);
+                    work[2] += p;
                 }
                 if (lane < 9) {
                     const unsigned long long w = lane < 3 ? hist1 : (lane < 6 ? hist2 : hist3);
