@@ -242,11 +242,11 @@ def main():
 HUB_COUNTER_SOURCES = ["paper_2201_11655_amd/csrc/count_hub.hip", "paper_2201_11655_amd/csrc/vdmc_internal.h",
                        "paper_2201_11655_amd/csrc/motif_device.h"]
 HUB_COUNTERS = {     # workload -> counters of one hub path (profiles/k_hub_chunglu_1M_hbm_counters.md)
-    "chunglu": {"sources_sha256": "6f8681de8a9ee54aa0ecd749086006b1ca98b5fde59fdc099dd3a75eaa3eda0b",
-                # k_hub 144909928.2 + k_slot_pairs 376549150.9 + k_pull111 8615731.2
-                "fetch_kib": 530074810.3,
-                # k_hub 318956788.3 + k_slot_pairs 112841159.3 + k_pull111 2896136.2
-                "write_kib": 434694083.8},
+    "chunglu": {"sources_sha256": "20056985c95cddf163e7bbced068e4a4a33403ff8eefa1b61e2107e44d3e0e0e",
+                # k_hub 144789320.5 + k_slot_pairs 376542914.4 + k_pull111 8617253.5
+                "fetch_kib": 529949488.4,
+                # k_hub 319016586.9 + k_slot_pairs 112844055.0 + k_pull111 2898616.1
+                "write_kib": 434759258.0},
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
