@@ -187,7 +187,7 @@ vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
  * short row); entries 24-27 the wave time spent inside the wave-per-group loop on
  * (2,1,0) sets, (2,1,0) sets with both parents, (1,1,1) paths and the rest (all times
  * 100 MHz ticks summed over waves); entries 28-31 work counts: depth-2 groups of the
- * wave-per-group loop, (1,1,1) chunks, (1,1,1) parent-chunk pairs, (2,1,0) parents whose
+ * wave-per-group loop, 64-entry chunks of their rows, their parents, (2,1,0) parents whose
  * local list the whole wave walks; entries 32-37 the part of the shape counts enumerated by the hub kernel.
  * Copies min(n, 40) entries. */
 vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n);
