@@ -294,6 +294,10 @@ def bench_batch(args, torch, gg, v):
     log(f"[bench] generated 4096 graphs ({sum(g.n for g in graphs)} vertices) in {time.perf_counter() - t0:.1f}s")
     Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
     outs = [torch.empty((g.n, 199), dtype=torch.int64, device="cuda") for g in graphs]
+    t0 = time.perf_counter()
+    v.tune(Gs, 4)
+    choice = v.tuned_choice(Gs, 4)
+    log(f"[bench] tuned in {time.perf_counter() - t0:.1f}s: {choice}")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         for w in range(max(1, args.warmup)):
@@ -341,7 +345,7 @@ def bench_batch(args, torch, gg, v):
                    "vertices": sum(g.n for g in graphs)},
         "per_graph_ms": ms_single, "per_graph_sync_ms": ms_sync,
         "per_graph_value": T4 / (ms_single * 1e-3), "batched_speedup": ms_single / ms_batch,
-        "batched_device_ms": dev_ms_batch, "batched_equals_per_graph": same,
+        "batched_device_ms": dev_ms_batch, "batched_equals_per_graph": same, "tuned": choice,
         "roofline": _alu_roofline(T4, 0, dev_ms_batch),
     }
     print(json.dumps(result), flush=True)

@@ -169,6 +169,15 @@ vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream);
 vdmc_status vdmc_count_range(vdmc_graph g, int32_t k, uint64_t* out, int64_t rank_begin, int64_t rank_end,
                              uint32_t flags, void* stream);
 
+/* Hub threshold of a graph: roots with at least min_higher higher-rank neighbours
+ * (|N+(r)|, the depth-1 candidates of Lemma 2) are counted by the hub path, the others by
+ * the per-root kernel; both enumerate the same sets (Lemma 1 makes roots independent),
+ * so the counts do not depend on the threshold.  The default is 32.  A change takes
+ * effect at the next count; the root bins and any cached batched launch of the graph
+ * are rebuilt.  min_higher in [1, 2^30] (1: every root with work takes the hub path),
+ * else INVALID_ARG.  Must not be called while a count on the graph is running. */
+vdmc_status vdmc_set_hub_threshold(vdmc_graph g, int32_t min_higher);
+
 /* Both k = 3 (out3: n x 13) and k = 4 (out4: n x 199) in one call; one staging of
  * each root's neighbourhood feeds both. */
 vdmc_status vdmc_count34(vdmc_graph g, uint64_t* out3, uint64_t* out4, void* stream);
@@ -210,10 +219,19 @@ vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out, int32_t n);
 vdmc_status vdmc_count_batch(const vdmc_graph* gs, int32_t num, int32_t k,
                              uint64_t* const* outs, void* stream);
 
-/* Picks the batch launch parameters (tile size, workgroups per CU) by timing the
- * candidates on the given batch; writes the choice to cache_path (NULL: keep in
- * memory only).  Synchronous.  Results are bit-identical for every choice. */
+/* Picks the batch launch parameters (workgroup size of the whole-graph kernel; threads
+ * per root, workgroups per CU and roots per cursor step of the root table) by timing
+ * every candidate on the given batch (median of 3 runs).  The choice is kept for batches
+ * of the same shape (k, number of graphs, total vertices, total pairs) in this process
+ * and appended to cache_path (NULL: memory only); a later process reads such a file when
+ * VDMC_TUNE_CACHE names it.  Synchronous.  Results are bit-identical for every choice. */
 vdmc_status vdmc_tune(const vdmc_graph* gs, int32_t num, int32_t k, const char* cache_path);
+
+/* The launch parameters vdmc_count_batch uses for a batch of this shape: choice_out[0] =
+ * 1 if they come from the tuner (else the defaults), [1] threads per workgroup of the
+ * whole-graph kernel, [2] threads per root, [3] workgroups per CU, [4] roots per cursor
+ * step.  choice_out: 5 host int32.  Synchronous, no device work. */
+vdmc_status vdmc_tuned_choice(const vdmc_graph* gs, int32_t num, int32_t k, int32_t* choice_out);
 
 /*
  * Serving: a request loop over resident graphs.

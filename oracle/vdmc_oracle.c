@@ -264,6 +264,10 @@ static int64_t deg(const sgraph *g, int32_t v) { return g->off[v + 1] - g->off[v
 /* S has ns members; ext[0..next) is the extension set. */
 static void extend(esu_ctx *c, int32_t *S, int ns, const int32_t *ext, int64_t next, int32_t v) {
     if (ns == c->k) { credit(c, S); return; }
+    if (ns + 1 == c->k) {   /* last level: every member of the extension set completes S */
+        for (int64_t i = next - 1; i >= 0; i--) { S[ns] = ext[i]; credit(c, S); }
+        return;
+    }
     int64_t maxdeg = 0;
     for (int64_t i = 0; i < next; i++) if (deg(c->g, ext[i]) > maxdeg) maxdeg = deg(c->g, ext[i]);
     int32_t mine[1024];

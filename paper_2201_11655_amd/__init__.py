@@ -23,5 +23,7 @@ from .vdmc import (  # noqa: F401
     profile_counters,
     shape_counts,
     tune,
+    tuned_choice,
+    set_hub_threshold,
     undirected_classes,
 )

@@ -67,11 +67,8 @@ __device__ __forceinline__ void credit(unsigned long long* out, const int32_t* p
 }
 
 // Where the per-set increments go.  GlobalSink: one 64-bit atomic per credited vertex
-// into the caller's output.  LdsSink (small graphs, one workgroup per graph): counters
-// of the whole graph in LDS (all 13 classes for k = 3; the 25 tree classes for k = 4,
-// other classes straight to the output), added to the output once per graph.  32-bit
-// counters cannot overflow there: a vertex of a graph with n <= 1024 lies in at most
-// C(1023, 3) < 2^28 four-vertex sets.
+// into the caller's output (the root's credits are summed in LDS first).  Small graphs
+// take the whole-graph kernel of small.hip instead, whose counters live in LDS.
 struct GlobalSink {
     __device__ __forceinline__ void c3(const GraphView& gv, uint32_t v, uint32_t cls) const {
         credit(gv.out3, gv.perm, kClasses3, v, cls);
@@ -84,32 +81,6 @@ struct GlobalSink {
     }
     __device__ __forceinline__ void root4(const GraphView& gv, uint32_t r, uint32_t cls, unsigned long long c) const {
         atomicAdd(&gv.out4[(size_t)gv.perm[r] * kClasses4 + cls], c);
-    }
-    __device__ __forceinline__ void set3(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t) const {}
-    __device__ __forceinline__ void set4(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
-                                         uint32_t, uint32_t, uint32_t) const {}
-};
-
-struct LdsSink {
-    uint32_t* cnt3;        // n x 13, by rank
-    uint32_t* cnt4;        // n x kCompact4, by rank
-    const uint8_t* slot4;  // class -> compact slot
-    __device__ __forceinline__ void c3(const GraphView&, uint32_t v, uint32_t cls) const {
-        if (cls < (uint32_t)kClasses3) atomicAdd(&cnt3[v * kClasses3 + cls], 1u);
-    }
-    __device__ __forceinline__ void c4(const GraphView& gv, uint32_t v, uint32_t cls) const {
-        if (cls >= (uint32_t)kClasses4) return;
-        const uint32_t sl = slot4[cls];
-        if (sl != 0xFFu) atomicAdd(&cnt4[v * kCompact4 + sl], 1u);
-        else credit(gv.out4, gv.perm, kClasses4, v, cls);
-    }
-    __device__ __forceinline__ void root3(const GraphView&, uint32_t r, uint32_t cls, unsigned long long c) const {
-        atomicAdd(&cnt3[r * kClasses3 + cls], (uint32_t)c);
-    }
-    __device__ __forceinline__ void root4(const GraphView& gv, uint32_t r, uint32_t cls, unsigned long long c) const {
-        const uint32_t sl = slot4[cls];
-        if (sl != 0xFFu) atomicAdd(&cnt4[r * kCompact4 + sl], (uint32_t)c);
-        else atomicAdd(&gv.out4[(size_t)gv.perm[r] * kClasses4 + cls], c);
     }
     __device__ __forceinline__ void set3(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t) const {}
     __device__ __forceinline__ void set4(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
@@ -373,52 +344,11 @@ __global__ __launch_bounds__(BS) void k_count_batch(BatchArgs b) {
             if (shape[s]) atomicAdd(&b.graphs[cur_graph].stats[s], shape[s]);
 }
 
-// Small graphs: one workgroup per graph (taken from a device cursor), the whole
-// graph's counters in LDS, every root of the graph enumerated by the workgroup.
-template <int BS, bool K3, bool K4>
-__global__ __launch_bounds__(BS) void k_batch_graph(BatchArgs b) {
-    extern __shared__ uint32_t dyn[];   // K3: nmax x 13 counters, then K4: nmax x 25
-    __shared__ RootLds<256> S;
-    __shared__ uint8_t slot4[kClasses4 + 1];
-    __shared__ unsigned gidx;
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < kClasses4; i += BS) slot4[i] = b.slot4[i];
-    uint32_t* cnt3 = dyn;
-    uint32_t* cnt4 = dyn + (K3 ? b.nmax_small * kClasses3 : 0);
-    const LdsSink sink{cnt3, cnt4, slot4};
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) gidx = atomicAdd(b.gcursor, 1u);
-        __syncthreads();
-        if (gidx >= b.nsmall) break;
-        const uint32_t gi = b.small[gidx];
-        const GraphView gv = b.graphs[gi];
-        const uint32_t n = (uint32_t)b.nvert[gi];
-        if (K3)
-            for (uint32_t i = tid; i < n * kClasses3; i += BS) cnt3[i] = 0;
-        if (K4)
-            for (uint32_t i = tid; i < n * kCompact4; i += BS) cnt4[i] = 0;
-        unsigned long long shape[kShapes] = {0, 0, 0, 0, 0, 0};
-        for (uint32_t r = 0; r < n; r++)
-            if (gv.split[r] < gv.off[r + 1]) process_root<BS, 256, K3, K4>(gv, b.t3, b.t4, r, S, shape, sink);
-        __syncthreads();
-        if (K3)
-            for (uint32_t i = tid; i < n * kClasses3; i += BS)
-                if (cnt3[i]) atomicAdd(&gv.out3[(size_t)gv.perm[i / kClasses3] * kClasses3 + i % kClasses3],
-                                       (unsigned long long)cnt3[i]);
-        if (K4)
-            for (uint32_t i = tid; i < n * kCompact4; i += BS)
-                if (cnt4[i]) atomicAdd(&gv.out4[(size_t)gv.perm[i / kCompact4] * kClasses4 + b.slotcls[i % kCompact4]],
-                                       (unsigned long long)cnt4[i]);
-        for (int s = 0; s < kShapes; s++)
-            if (shape[s]) atomicAdd(&gv.stats[s], shape[s]);
-    }
-}
-
-// zero every graph's output(s) and shape counters; one workgroup per graph
+// zero every graph's shape counters and the outputs of the graphs counted by the root
+// table (the whole-graph kernel clears its own graphs' outputs); one workgroup per graph
 __global__ void k_batch_zero(BatchArgs b, int k3, int k4) {
     const GraphView& g = b.graphs[blockIdx.x];
-    const size_t n = b.nvert[blockIdx.x];
+    const size_t n = b.generic[blockIdx.x] ? b.nvert[blockIdx.x] : 0;
     if (k3)
         for (size_t i = threadIdx.x; i < n * kClasses3; i += blockDim.x) g.out3[i] = 0;
     if (k4)
@@ -437,7 +367,8 @@ __global__ void k_fill(unsigned long long* p, size_t n, unsigned long long v) {
 
 }  // namespace
 
-void launch_batch(const BatchArgs& b, int variant, int k3, int k4, int num_graphs, int wgs_per_cu, hipStream_t st) {
+void launch_batch(const BatchArgs& b, const SmallArgs* small, unsigned small_grid, size_t small_lds,
+                  int small_variant, int variant, int k3, int k4, int num_graphs, int wgs_per_cu, hipStream_t st) {
     static int ncu = -1;
     if (ncu < 0) {
         int dev = 0;
@@ -449,15 +380,9 @@ void launch_batch(const BatchArgs& b, int variant, int k3, int k4, int num_graph
     hipLaunchKernelGGL(k_batch_zero, dim3(num_graphs), dim3(256), 0, st, b, k3, k4);
     VDMC_HIP(hipGetLastError());
     const unsigned grid = (unsigned)(ncu * wgs_per_cu);
-    if (b.nsmall > 0) {
+    if (small && small->num > 0) {
         VDMC_REQUIRE(k3 != k4, VDMC_ERR_INVALID_ARG, "a batch counts one k");
-        VDMC_REQUIRE(b.nmax_small <= (uint32_t)kSmallGraphN, VDMC_ERR_INVALID_ARG, "small graph too large");
-        const size_t dyn = (size_t)b.nmax_small * (k3 ? kClasses3 : kCompact4) * sizeof(uint32_t);
-        const unsigned ggrid = (unsigned)std::min<uint64_t>(b.nsmall, (uint64_t)ncu * 4);
-        auto kern = k3 ? (void (*)(BatchArgs))k_batch_graph<256, true, false> : (void (*)(BatchArgs))k_batch_graph<256, false, true>;
-        VDMC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-        hipLaunchKernelGGL(kern, dim3(ggrid), dim3(256), dyn, st, b);
-        VDMC_HIP(hipGetLastError());
+        launch_small(*small, k3 ? 3 : 4, small_variant, small_grid, small_lds, st);
     }
     if (b.nentries == 0) return;
 #define VDMC_BATCH_LAUNCH(BS, STG)                                                                           \
@@ -487,7 +412,10 @@ void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t st) {
 void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st,
                   int64_t rank_lo, int64_t rank_hi, bool zero) {
     const ClassTables& t = class_tables();
-    ensure_bins(g, hub_min_default(), st);
+    {
+        std::lock_guard<std::mutex> lock(g->mu);
+        ensure_bins(g, st);
+    }
     if (zero) {
         if (k3) launch_fill_u64(out3, (size_t)g->n * kClasses3, 0, st);
         if (k4) launch_fill_u64(out4, (size_t)g->n * kClasses4, 0, st);
@@ -580,6 +508,19 @@ vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream) {
         VDMC_HIP(hipSetDevice(g->device));
         vdmc::launch_count(g, k == 3, k == 4, k == 3 ? out : nullptr, k == 4 ? out : nullptr,
                            vdmc::as_stream(stream));
+    });
+}
+
+vdmc_status vdmc_set_hub_threshold(vdmc_graph g, int32_t min_higher) {
+    return vdmc::guarded([&] {
+        VDMC_REQUIRE(g != nullptr, VDMC_ERR_INVALID_ARG, "graph is NULL");
+        VDMC_REQUIRE(min_higher >= 1 && min_higher <= (1 << 30), VDMC_ERR_INVALID_ARG,
+                     "min_higher must be in [1, 2^30]");
+        {
+            std::lock_guard<std::mutex> lock(g->mu);
+            g->hub_min = min_higher;
+        }
+        vdmc::invalidate_batch_plans(g);
     });
 }
 

@@ -1549,11 +1549,6 @@ int slot_pair_workgroups() { return hub_workgroups() * 6; }   // 24 waves per co
 
 }  // namespace
 
-int hub_min_default() {
-    const char* e = getenv("VDMC_HUB_MIN");
-    if (e && *e) return atoi(e);
-    return 32;
-}
 
 void free_hub(vdmc_graph_s* g) {
     (void)hipFree(g->light);
@@ -1596,7 +1591,8 @@ void ensure_edge_hash(vdmc_graph_s* g, hipStream_t st) {
     g->ehash_bits = eb;
 }
 
-void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t st) {
+void ensure_bins(vdmc_graph_s* g, hipStream_t st) {
+    const int hub_min = g->hub_min;
     if (g->bins_hub_min == hub_min) return;
     free_hub(g);
     const int64_t nr = g->nroots;

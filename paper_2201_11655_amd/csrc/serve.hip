@@ -278,11 +278,11 @@ vdmc_status vdmc_serve_submit(vdmc_server s, vdmc_graph g, int32_t k, uint64_t* 
         // bins and hub scratch are built once per graph; their size is part of the request
         {
             std::lock_guard<std::mutex> lock(g->mu);
-            if (g->bins_hub_min != vdmc::hub_min_default()) {
+            if (g->bins_hub_min != g->hub_min) {
                 hipStream_t st = nullptr;
                 VDMC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
                 try {
-                    vdmc::ensure_bins(g, vdmc::hub_min_default(), st);
+                    vdmc::ensure_bins(g, st);
                 } catch (...) {
                     (void)hipStreamDestroy(st);
                     throw;

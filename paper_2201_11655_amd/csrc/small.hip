@@ -1,0 +1,363 @@
+// Small-graph motif kernel: one workgroup counts a whole graph held in LDS.
+//
+// For graphs of a few hundred vertices (the batched workload, small served requests)
+// a per-root launch leaves most of a workgroup idle: a root of such a graph has a
+// handful of higher neighbours.  Here one workgroup takes a whole graph:
+//   * its rank-space CSR, a 1-bit adjacency matrix (so that almost every pair test is
+//     one LDS read; a set bit is resolved to its arc bits by a search of the LDS row)
+//     and per-vertex counters live in LDS;
+//   * the work of all roots is flattened into two item lists, so that threads never
+//     wait at per-root barriers:
+//       - pairs {a < b} of N+(r) for every root r: the k = 3 set (1,1) and the k = 4
+//         sets (3,0,0) that add a third higher neighbour c > b (Lemma 2);
+//       - depth-2 entries (r, a, c): a in N+(r), c in N(a), c > r, c not in N(r): the
+//         k = 3 set (1,2) and, for k = 4, the sets (2,1,0) (second depth-1 vertex b; c
+//         hangs under its lower-rank parent), (1,2,0) (a second child c' > c of a) and
+//         (1,1,1) (an end vertex e of c's row, not adjacent to r or to a: the Lemma-4
+//         rule) (Lemmas 2-4);
+//   * every set is visited once by one lane: its index is assembled from the arc bits
+//     (Sec. 4.1), its class read from the table in LDS, and each of its k vertices
+//     credited (Sec. 4.2).  Credits go to LDS counters (k = 3: all 13 classes; k = 4:
+//     the 25 tree classes, which hold ~96% of the 4-sets of sparse graphs); the other
+//     classes go straight to the graph's output with workgroup-scope atomics (the
+//     output block of a graph belongs to one workgroup for the whole launch).  Credits
+//     shared by the lanes of a wave (the root of a run of items) are summed by ballots
+//     before they reach LDS.
+// The LDS counters are added to the output once per graph.  u32 counters cannot
+// overflow: a vertex of a graph with n <= kSmallMaxN lies in fewer than 2^32 k-sets.
+#include "motif_device.h"
+#include "vdmc_internal.h"
+
+namespace vdmc {
+namespace {
+
+__device__ __forceinline__ uint32_t lane_of() { return threadIdx.x & 63u; }
+
+// wg-scope atomic add on a graph's output (the block is owned by this workgroup)
+__device__ __forceinline__ void out_add(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Adds 1 at base[key] for every lane that reaches this call with active set, one LDS
+// atomic per distinct key among those lanes.
+__device__ __forceinline__ void wave_add(uint32_t* base, uint32_t key, bool active) {
+    unsigned long long m = __ballot(active);
+    while (m) {
+        const uint32_t leader = (uint32_t)(__ffsll((long long)m) - 1);
+        const uint32_t k0 = (uint32_t)__shfl((int)key, (int)leader, 64);
+        const unsigned long long same = __ballot(active && key == k0) & m;
+        if (lane_of() == leader) atomicAdd(&base[k0], (uint32_t)__popcll(same));
+        m &= ~same;
+    }
+}
+
+// exclusive prefix sum of a[0..len) in place (LDS), returns the total; every thread of
+// the workgroup must call it.  part: BS words of LDS scratch.
+template <int BS>
+__device__ uint32_t block_exclusive_scan(uint32_t* a, uint32_t len, uint32_t* part) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (len + BS - 1) / BS;
+    const uint32_t lo = min(len, tid * per), hi = min(len, lo + per);
+    uint32_t s = 0;
+    for (uint32_t i = lo; i < hi; i++) s += a[i];
+    part[tid] = s;
+    __syncthreads();
+    for (uint32_t off = 1; off < BS; off <<= 1) {   // inclusive Hillis-Steele over the parts
+        const uint32_t v = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - s;
+    for (uint32_t i = lo; i < hi; i++) {
+        const uint32_t x = a[i];
+        a[i] = run;
+        run += x;
+    }
+    const uint32_t total = part[BS - 1];
+    __syncthreads();
+    return total;
+}
+
+// largest i in [0, len) with pre[i] <= q (pre ascending, pre[0] = 0 <= q)
+__device__ __forceinline__ uint32_t upper_idx(const uint32_t* pre, uint32_t len, uint32_t q) {
+    uint32_t lo = 0, hi = len;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+struct SmallLds {
+    const uint32_t* off;
+    const uint32_t* adj;
+    const uint32_t* split;
+    const uint32_t* bits;
+    uint32_t W;
+    __device__ __forceinline__ bool adjacent(uint32_t u, uint32_t v) const {
+        return (bits[u * W + (v >> 5)] >> (v & 31u)) & 1u;
+    }
+    // arc bits of (u, v) seen from u, 0 if not adjacent
+    __device__ __forceinline__ uint32_t code(uint32_t u, uint32_t v) const {
+        if (!adjacent(u, v)) return 0u;
+        uint32_t lo = off[u], hi = off[u + 1];
+        const uint32_t key = v << 2;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (adj[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        return adj[lo] & 3u;
+    }
+    __device__ __forceinline__ uint32_t first_above(uint32_t u, uint32_t x) const {
+        uint32_t lo = off[u], hi = off[u + 1];
+        const uint32_t key = (x + 1u) << 2;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (adj[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    }
+};
+
+template <int K>
+struct SmallCredit {
+    static constexpr uint32_t NC = K == 3 ? (uint32_t)kClasses3 : (uint32_t)kCompact4;
+    static constexpr uint32_t C = K == 3 ? (uint32_t)kClasses3 : (uint32_t)kClasses4;
+    uint32_t* cnt;            // n x NC (LDS)
+    const uint8_t* comp;      // k = 4: class -> tree slot or 0xFF (LDS)
+    const int32_t* perm;
+    unsigned long long* out;
+    // slot of cls in the LDS counters, or NC when the class is credited to the output
+    __device__ __forceinline__ uint32_t slot(uint32_t cls) const {
+        if (K == 3) return cls;
+        const uint32_t s = comp[cls];
+        return s == 0xFFu ? NC : s;
+    }
+    // v credited with cls; `shared` = the same v for (most of) the wave's active lanes
+    __device__ __forceinline__ void add(uint32_t v, uint32_t cls, uint32_t s, bool shared) const {
+        const bool lds = s < NC;
+        if (shared) {
+            wave_add(cnt, v * NC + s, lds);
+        } else if (lds) {
+            atomicAdd(&cnt[v * NC + s], 1u);
+        }
+        if (!lds) out_add(&out[(size_t)perm[v] * C + cls], 1ull);
+    }
+};
+
+template <int BS, int K>
+__global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
+    extern __shared__ uint32_t dyn[];
+    __shared__ uint8_t sTable[K == 3 ? 64 : 4096];
+    __shared__ uint8_t sComp[256];
+    __shared__ uint32_t sPart[BS];
+    __shared__ uint32_t sGraph;
+    constexpr uint32_t NC = SmallCredit<K>::NC;
+    constexpr uint32_t C = SmallCredit<K>::C;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < (K == 3 ? 64u : 4096u); i += BS) sTable[i] = A.table[i];
+    if (K == 4)
+        for (uint32_t i = tid; i < 256u; i += BS) sComp[i] = A.comp_of[i];
+
+    for (uint32_t round = 0;; round++) {
+        __syncthreads();
+        if (tid == 0) sGraph = A.graphs ? atomicAdd(A.cursor, 1u) : round;   // single graph: taken once
+        __syncthreads();
+        const uint32_t gidx = sGraph;
+        if (gidx >= A.num) break;
+        const SmallGraph G = A.graphs ? A.graphs[gidx] : A.one;
+        const uint32_t n = G.n, E = G.entries, W = (n + 31u) >> 5;
+        // LDS layout
+        uint32_t* sOff = dyn;                 // n + 1
+        uint32_t* sSplit = sOff + n + 1;      // n
+        uint32_t* sPreD = sSplit + n;         // n + 1: upper entries before row r
+        uint32_t* sPre1 = sPreD + n + 1;      // n + 1: pair items before root r
+        uint32_t* sBits = sPre1 + n + 1;      // n * W
+        uint32_t* sCnt = sBits + n * W;       // n * NC
+        uint32_t* sAdj = sCnt + n * NC;       // E
+        uint32_t* sPre2 = sAdj + E;           // E / 2 + 1: depth-2 candidates before each upper entry
+        // ---- stage the graph, clear bitmap, counters and the output block
+        for (uint32_t i = tid; i <= n; i += BS) sOff[i] = G.off[i];
+        for (uint32_t i = tid; i < E; i += BS) sAdj[i] = G.adj[i];
+        for (uint32_t i = tid; i < n * W; i += BS) sBits[i] = 0u;
+        for (uint32_t i = tid; i < n * NC; i += BS) sCnt[i] = 0u;
+        for (size_t i = tid; i < (size_t)n * C; i += BS) G.out[i] = 0ull;
+        __syncthreads();
+        for (uint32_t r = tid; r < n; r += BS) {
+            const uint32_t lo = sOff[r], hi = sOff[r + 1];
+            uint32_t s = hi;
+            for (uint32_t t = lo; t < hi; t++) {
+                const uint32_t v = sAdj[t] >> 2;
+                atomicOr(&sBits[r * W + (v >> 5)], 1u << (v & 31u));
+                if (v > r && s == hi) s = t;
+            }
+            sSplit[r] = s;
+            const uint32_t d = hi - s;
+            sPreD[r] = d;
+            sPre1[r] = d * (d - 1u) / 2u;
+        }
+        if (tid == 0) {
+            sPreD[n] = 0u;
+            sPre1[n] = 0u;
+        }
+        __syncthreads();
+        const uint32_t U = block_exclusive_scan<BS>(sPreD, n + 1, sPart);
+        const uint32_t N1 = block_exclusive_scan<BS>(sPre1, n + 1, sPart);
+        const SmallLds L{sOff, sAdj, sSplit, sBits, W};
+        // candidates of each upper entry (r, a): entries of a's row above r
+        for (uint32_t r = tid; r < n; r += BS)
+            for (uint32_t t = sSplit[r]; t < sOff[r + 1]; t++) {
+                const uint32_t a = sAdj[t] >> 2;
+                sPre2[sPreD[r] + (t - sSplit[r])] = sOff[a + 1] - L.first_above(a, r);
+            }
+        if (tid == 0) sPre2[U] = 0u;
+        __syncthreads();
+        const uint32_t N2 = block_exclusive_scan<BS>(sPre2, U + 1, sPart);
+
+        const SmallCredit<K> cr{sCnt, sComp, G.perm, G.out};
+        unsigned long long shp[4] = {0, 0, 0, 0};
+        // ---- pairs {a < b} of N+(r): (1,1) / (3,0,0)
+        for (uint32_t q = tid; q < N1; q += BS) {
+            const uint32_t r = upper_idx(sPre1, n + 1, q);
+            const uint32_t idx = q - sPre1[r];
+            uint32_t j = (uint32_t)((1.0f + sqrtf(1.0f + 8.0f * (float)idx)) * 0.5f);
+            while (j * (j - 1u) / 2u > idx) j--;
+            while ((j + 1u) * j / 2u <= idx) j++;
+            const uint32_t i = idx - j * (j - 1u) / 2u;
+            const uint32_t* P = sAdj + sSplit[r];
+            const uint32_t d = sOff[r + 1] - sSplit[r];
+            const uint32_t a = P[i] >> 2, ra = P[i] & 3u, b = P[j] >> 2, rb = P[j] & 3u;
+            const uint32_t ab = L.code(a, b);
+            if (K == 3) {
+                const uint32_t cls = sTable[motif_index3(ra, rb, ab)];
+                const uint32_t s = cr.slot(cls);
+                cr.add(r, cls, s, true);
+                cr.add(a, cls, s, false);
+                cr.add(b, cls, s, true);
+                shp[0]++;
+            } else {
+                for (uint32_t l = j + 1; l < d; l++) {
+                    const uint32_t c = P[l] >> 2, rc = P[l] & 3u;
+                    const uint32_t cls = sTable[motif_index4(ra, rb, rc, ab, L.code(a, c), L.code(b, c))];
+                    const uint32_t s = cr.slot(cls);
+                    cr.add(r, cls, s, true);
+                    cr.add(a, cls, s, false);
+                    cr.add(b, cls, s, false);
+                    cr.add(c, cls, s, false);
+                    shp[0]++;
+                }
+            }
+        }
+        // ---- depth-2 entries (r, a, c)
+        for (uint32_t q = tid; q < N2; q += BS) {
+            const uint32_t u = upper_idx(sPre2, U + 1, q);
+            const uint32_t r = upper_idx(sPreD, n + 1, u);
+            const uint32_t* P = sAdj + sSplit[r];
+            const uint32_t d = sOff[r + 1] - sSplit[r];
+            const uint32_t ia = u - sPreD[r];
+            const uint32_t a = P[ia] >> 2, ra = P[ia] & 3u;
+            const uint32_t t = L.first_above(a, r) + (q - sPre2[u]);
+            const uint32_t c = sAdj[t] >> 2, ac = sAdj[t] & 3u;
+            if (L.adjacent(r, c)) continue;   // c adjacent to r: depth 1, not 2
+            if (K == 3) {
+                const uint32_t cls = sTable[motif_index3(ra, 0u, ac)];
+                const uint32_t s = cr.slot(cls);
+                cr.add(r, cls, s, true);
+                cr.add(a, cls, s, true);
+                cr.add(c, cls, s, false);
+                shp[1]++;
+                continue;
+            }
+            // (2,1,0): a second depth-1 vertex b; c hangs under the lower-rank parent
+            for (uint32_t jb = 0; jb < d; jb++) {
+                if (jb == ia) continue;
+                const uint32_t b = P[jb] >> 2, rb = P[jb] & 3u;
+                const uint32_t bc = L.code(b, c);
+                if (bc && jb < ia) continue;
+                const uint32_t cls = sTable[motif_index4(ra, rb, 0u, L.code(a, b), ac, bc)];
+                const uint32_t s = cr.slot(cls);
+                cr.add(r, cls, s, true);
+                cr.add(a, cls, s, true);
+                cr.add(b, cls, s, false);
+                cr.add(c, cls, s, false);
+                shp[1]++;
+            }
+            // (1,2,0): a second child c2 > c of a, not adjacent to r
+            for (uint32_t t2 = t + 1; t2 < sOff[a + 1]; t2++) {
+                const uint32_t c2 = sAdj[t2] >> 2, ac2 = sAdj[t2] & 3u;
+                if (L.adjacent(r, c2)) continue;
+                const uint32_t cls = sTable[motif_index4(ra, 0u, 0u, ac, ac2, L.code(c, c2))];
+                const uint32_t s = cr.slot(cls);
+                cr.add(r, cls, s, true);
+                cr.add(a, cls, s, true);
+                cr.add(c, cls, s, false);
+                cr.add(c2, cls, s, false);
+                shp[2]++;
+            }
+            // (1,1,1): path r - a - c - e, e not adjacent to r (nor equal to a) nor to a
+            for (uint32_t te = L.first_above(c, r); te < sOff[c + 1]; te++) {
+                const uint32_t e = sAdj[te] >> 2, ce = sAdj[te] & 3u;
+                if (L.adjacent(r, e) || L.adjacent(a, e)) continue;
+                const uint32_t cls = sTable[motif_index4(ra, 0u, 0u, ac, 0u, ce)];
+                const uint32_t s = cr.slot(cls);
+                cr.add(r, cls, s, true);
+                cr.add(a, cls, s, true);
+                cr.add(c, cls, s, false);
+                cr.add(e, cls, s, false);
+                shp[3]++;
+            }
+        }
+        __syncthreads();
+        // ---- counters -> output (workgroup-owned rows)
+        for (uint32_t i = tid; i < n * NC; i += BS) {
+            const uint32_t x = sCnt[i];
+            if (!x) continue;
+            const uint32_t v = i / NC, s = i - v * NC;
+            const uint32_t cls = K == 3 ? s : A.comp_cls[s];
+            out_add(&G.out[(size_t)G.perm[v] * C + cls], (unsigned long long)x);
+        }
+        // visited-set counters per shape: k = 3 -> (1,1), (1,2); k = 4 -> the four shapes
+        for (int s = 0; s < 4; s++) {
+            unsigned long long x = shp[s];
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+            shp[s] = x;
+        }
+        if (lane_of() == 0) {
+            if (K == 3) {
+                if (shp[0]) atomicAdd(&G.stats[0], shp[0]);
+                if (shp[1]) atomicAdd(&G.stats[1], shp[1]);
+            } else {
+                for (int s = 0; s < 4; s++)
+                    if (shp[s]) atomicAdd(&G.stats[2 + s], shp[s]);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+size_t small_lds_bytes(int64_t n, int64_t entries, int k) {
+    const int64_t W = (n + 31) / 32;
+    const int64_t nc = k == 3 ? kClasses3 : kCompact4;
+    const int64_t words = (n + 1) * 3 + n + n * W + n * nc + entries + entries / 2 + 1;
+    return (size_t)words * sizeof(uint32_t);
+}
+
+bool small_eligible(int64_t n, int64_t entries, int k) {
+    return n >= 1 && n <= kSmallMaxN && small_lds_bytes(n, entries, k) <= kSmallLdsBudget;
+}
+
+int small_threads(int variant) { return variant <= 0 ? 256 : (variant == 1 ? 512 : 1024); }
+
+void launch_small(const SmallArgs& a, int k, int variant, unsigned grid, size_t lds, hipStream_t st) {
+    void (*kern)(SmallArgs) = nullptr;
+    const int bs = small_threads(variant);
+    if (k == 3) kern = bs == 256 ? k_small<256, 3> : (bs == 512 ? k_small<512, 3> : k_small<1024, 3>);
+    else kern = bs == 256 ? k_small<256, 4> : (bs == 512 ? k_small<512, 4> : k_small<1024, 4>);
+    VDMC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(bs), lds, st, a);
+    VDMC_HIP(hipGetLastError());
+}
+
+}  // namespace vdmc

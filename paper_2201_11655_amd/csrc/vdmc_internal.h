@@ -117,7 +117,8 @@ struct vdmc_graph_s {
     int64_t nroots = 0;
     unsigned long long* stats = nullptr;  // kShapes shape counters of the last count
     std::mutex mu;
-    // root bins (built at the first count for a given hub threshold)
+    // root bins (built at the first count after a change of the hub threshold)
+    int hub_min = 32;            // roots with at least this many higher neighbours take the hub path
     int bins_hub_min = -1;
     uint32_t* light = nullptr;   // roots handled by the per-set kernel
     int64_t nlight = 0;
@@ -171,17 +172,36 @@ struct BatchArgs {
     unsigned long long tile;        // roots taken per cursor step
     const uint8_t* t3;
     const uint8_t* t4;
-    // small graphs counted one workgroup per graph
-    const uint32_t* small;          // device array of graph indices
-    uint32_t nsmall;
-    uint32_t nmax_small;            // largest n among them (LDS sizing)
-    unsigned* gcursor;              // device graph cursor, zeroed inside the launch
-    const uint8_t* slot4;
-    const uint8_t* slotcls;
+    const uint8_t* generic;         // per graph: 1 = counted through the root table (output zeroed first)
+    unsigned* gcursor;              // graph cursor of the whole-graph kernel, zeroed inside the launch
 };
+// Small graphs (small.hip): one workgroup counts a whole graph held in LDS.
+struct SmallGraph {
+    const uint32_t* off;        // n + 1 (rank space)
+    const uint32_t* adj;        // entries
+    const int32_t* perm;        // rank -> original id
+    unsigned long long* out;    // n x C, rows by original id
+    unsigned long long* stats;  // shape (visited-set) counters of the graph
+    uint32_t n, entries;
+};
+struct SmallArgs {
+    const SmallGraph* graphs;   // device array of num graphs, or nullptr: the single graph `one`
+    SmallGraph one;
+    uint32_t num;
+    unsigned* cursor;           // graph cursor of a batched launch (zeroed before it)
+    const uint8_t* table;       // code -> class id for the launch's k
+    const uint8_t* comp_of;     // class -> tree slot or 0xFF (256 entries)
+    const uint8_t* comp_cls;    // tree slot -> class
+};
+constexpr int64_t kSmallMaxN = 1024;            // u32 LDS counters cannot overflow below this
+constexpr size_t kSmallLdsBudget = 163840 - 9216;   // dynamic LDS of one workgroup (gfx950: 160 KiB per CU)
+size_t small_lds_bytes(int64_t n, int64_t entries, int k);
+bool small_eligible(int64_t n, int64_t entries, int k);
+int small_threads(int variant);
+void launch_small(const SmallArgs& a, int k, int variant, unsigned grid, size_t lds, hipStream_t stream);
 constexpr int kBatchVariants = 3;   // 64, 128, 256 threads per root
-constexpr int64_t kSmallGraphN = 1024;   // graphs up to this size: one workgroup per graph
 struct TuneChoice {
+    int small_variant = 2;   // threads per workgroup of the whole-graph kernel: 256, 512, 1024
     int variant = 0;      // threads per root: 64, 128, 256
     int wgs_per_cu = 8;   // persistent workgroups per compute unit
     unsigned tile = 4;    // roots per cursor step
@@ -189,20 +209,19 @@ struct TuneChoice {
 // batched count of many graphs (one k), optionally replayed from a captured HIP graph
 void count_batch_impl(const vdmc_graph_s* const* gs, int32_t num, int32_t k, uint64_t* const* outs,
                       hipStream_t stream, bool use_graph, const TuneChoice* force);
-void launch_batch(const BatchArgs& b, int variant, int k3, int k4, int num_graphs, int wgs_per_cu,
-                  hipStream_t stream);
+void launch_batch(const BatchArgs& b, const SmallArgs* small, unsigned small_grid, size_t small_lds,
+                  int small_variant, int variant, int k3, int k4, int num_graphs, int wgs_per_cu, hipStream_t stream);
 void invalidate_batch_plans(vdmc_graph_s* g);
 // launches (count.hip)
 void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
                   hipStream_t stream, int64_t rank_lo = 0, int64_t rank_hi = INT64_MAX, bool zero = true);
 void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t stream);
 // hub path (count_hub.hip)
-void ensure_bins(vdmc_graph_s* g, int hub_min, hipStream_t stream);
+void ensure_bins(vdmc_graph_s* g, hipStream_t stream);   // for g->hub_min; caller holds g->mu
 void ensure_edge_hash(vdmc_graph_s* g, hipStream_t stream);    // count_hub.hip
 void ensure_edge_index(vdmc_graph_s* g, hipStream_t stream);   // edges.hip
 void launch_count_edges(vdmc_graph_s* g, int k, uint64_t* out, hipStream_t stream);   // count.hip
 void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t stream,
                 uint32_t rank_lo = 0, uint32_t rank_hi = 0xFFFFFFFFu, const hipEvent_t* around = nullptr);
-int hub_min_default();
 void free_hub(vdmc_graph_s* g);
 }  // namespace vdmc

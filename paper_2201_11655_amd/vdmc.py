@@ -21,7 +21,7 @@ SYMBOLS = [
     "vdmc_count", "vdmc_count_range", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters",
     "vdmc_kernel_times", "vdmc_num_classes_undirected", "vdmc_undirected_classes", "vdmc_count_undirected",
     "vdmc_edge_list", "vdmc_count_edges",
-    "vdmc_count_batch", "vdmc_tune",
+    "vdmc_count_batch", "vdmc_tune", "vdmc_tuned_choice", "vdmc_set_hub_threshold",
     "vdmc_serve_create", "vdmc_serve_submit", "vdmc_serve_poll", "vdmc_serve_wait",
     "vdmc_serve_stats", "vdmc_serve_destroy",
 ]
@@ -76,6 +76,8 @@ def load():
         "vdmc_count_edges": ([p, i32, p, p], i32),
         "vdmc_count_batch": ([p, i32, i32, p, p], i32),
         "vdmc_tune": ([p, i32, i32, ctypes.c_char_p], i32),
+        "vdmc_tuned_choice": ([p, i32, i32, p], i32),
+        "vdmc_set_hub_threshold": ([p, i32], i32),
         "vdmc_serve_create": ([p, p], i32),
         "vdmc_serve_submit": ([p, p, i32, p, p], i32),
         "vdmc_serve_poll": ([p, u64, p], i32),
@@ -320,6 +322,21 @@ def tune(graphs, k: int, cache_path: str | None = None):
     hs = (ctypes.c_void_p * max(1, len(graphs)))(*[g.handle.value for g in graphs])
     _check(load().vdmc_tune(ctypes.cast(hs, ctypes.c_void_p), len(graphs), int(k),
                             cache_path.encode() if cache_path else None))
+
+
+def tuned_choice(graphs, k: int) -> dict:
+    """Launch parameters vdmc_count_batch uses for a batch of this shape."""
+    hs = (ctypes.c_void_p * max(1, len(graphs)))(*[g.handle.value for g in graphs])
+    c = (ctypes.c_int32 * 5)()
+    _check(load().vdmc_tuned_choice(ctypes.cast(hs, ctypes.c_void_p), len(graphs), int(k),
+                                    ctypes.cast(c, ctypes.c_void_p)))
+    return {"tuned": bool(c[0]), "small_threads": c[1], "threads_per_root": c[2],
+            "workgroups_per_cu": c[3], "tile": c[4]}
+
+
+def set_hub_threshold(g: "Graph", min_higher: int):
+    """Roots with at least min_higher higher neighbours take the hub path (counts unchanged)."""
+    _check(load().vdmc_set_hub_threshold(g.handle, int(min_higher)))
 
 
 class ServeConfig(ctypes.Structure):

@@ -98,9 +98,14 @@ def test_tune_and_cache(v, small_batch):
     Gs = [v.Graph(g.n, g.src, g.dst) for g in small_batch[:16]]
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tune.txt")
+        assert not v.tuned_choice(Gs, 4)["tuned"]
         v.tune(Gs, 4, path)
-        text = open(path).read()
-        assert "threads_per_root" in text and "tile" in text
+        fields = open(path).read().split()
+        # k, graphs, vertices, pairs, small-kernel variant, root variant, workgroups/CU, tile, ms
+        assert len(fields) == 9 and fields[:4] == ["4", "16", str(sum(g.n for g in Gs)), str(sum(g.pairs for g in Gs))]
+        c = v.tuned_choice(Gs, 4)
+        assert c["tuned"] and c["small_threads"] in (256, 512, 1024)
+        assert not v.tuned_choice(Gs[:15], 4)["tuned"]   # another batch shape keeps the defaults
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         outs = v.count_batch(Gs, 4, stream=stream)
