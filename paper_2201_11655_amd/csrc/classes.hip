@@ -160,7 +160,7 @@ const ClassTables& class_tables() {
     if (it != g_tables.end()) return *it->second;
     auto* t = new ClassTables();
     uint8_t* d = nullptr;
-    VDMC_HIP(hipMalloc(&d, 64 + 4096 + 256 + 64));
+    VDMC_HIP(hipMalloc(&d, 64 + 4096 + 256 + 64 + 768 + 16 + 16));
     build_one<3>(d, t->host3, t->codes3);
     build_one<4>(d + 64, t->host4, t->codes4);
     t->t3 = d;
@@ -168,19 +168,34 @@ const ClassTables& class_tables() {
     // compact slots: classes of 4-sets whose G_U is a tree; with the set ordered
     // (v0, v1, v2, v3) and arc bits p_ij, a path v0-v1-v2-v3 has p01, p12, p23 != 0 and a
     // star centred at v1 has p01, p12, p13 != 0 (every other pair empty)
-    std::vector<uint8_t> slot(256, 0xFF), slotcls;
+    std::vector<uint8_t> slot(256, 0xFF), slotcls, star_of(256, 0xFF), path_of(256, 0xFF), star_cls, path_cls;
     auto idx4 = [](unsigned p01, unsigned p02, unsigned p03, unsigned p12, unsigned p13, unsigned p23) {
         return ((p01 & 1u) << 11) | ((p01 >> 1) << 8) | ((p02 & 1u) << 10) | ((p02 >> 1) << 5) |
                ((p03 & 1u) << 9) | ((p03 >> 1) << 2) | ((p12 & 1u) << 7) | ((p12 >> 1) << 4) |
                ((p13 & 1u) << 6) | ((p13 >> 1) << 1) | ((p23 & 1u) << 3) | (p23 >> 1);
     };
-    std::vector<int> tree_classes;
+    std::vector<int> tree_classes, stars, paths;
     for (unsigned a = 1; a <= 3; a++)
         for (unsigned b = 1; b <= 3; b++)
             for (unsigned c = 1; c <= 3; c++) {
-                tree_classes.push_back(t->host4[idx4(a, 0, 0, b, 0, c)]);   // path
-                tree_classes.push_back(t->host4[idx4(a, 0, 0, b, c, 0)]);   // star centred at v1
+                paths.push_back(t->host4[idx4(a, 0, 0, b, 0, c)]);   // path v0 - v1 - v2 - v3
+                stars.push_back(t->host4[idx4(a, 0, 0, b, c, 0)]);   // star centred at v1
             }
+    for (auto* v : {&stars, &paths}) {
+        std::sort(v->begin(), v->end());
+        v->erase(std::unique(v->begin(), v->end()), v->end());
+    }
+    VDMC_REQUIRE(stars.size() == 10 && paths.size() == 15, VDMC_ERR_DEVICE, "expected 10 star and 15 path classes");
+    for (size_t i = 0; i < stars.size(); i++) {
+        star_of[stars[i]] = (uint8_t)i;
+        star_cls.push_back((uint8_t)stars[i]);
+    }
+    for (size_t i = 0; i < paths.size(); i++) {
+        path_of[paths[i]] = (uint8_t)i;
+        path_cls.push_back((uint8_t)paths[i]);
+    }
+    tree_classes = stars;
+    tree_classes.insert(tree_classes.end(), paths.begin(), paths.end());
     std::sort(tree_classes.begin(), tree_classes.end());
     tree_classes.erase(std::unique(tree_classes.begin(), tree_classes.end()), tree_classes.end());
     VDMC_REQUIRE((int)tree_classes.size() == kCompact4, VDMC_ERR_DEVICE,
@@ -194,6 +209,19 @@ const ClassTables& class_tables() {
     VDMC_HIP(hipMemcpy(d + 64 + 4096 + 256, slotcls.data(), 64, hipMemcpyHostToDevice));
     t->slot4 = d + 64 + 4096;
     t->slotcls = d + 64 + 4096 + 256;
+    // class -> star slot | path slot | tree slot, then slot -> class for stars and paths
+    std::vector<uint8_t> maps(star_of);
+    maps.insert(maps.end(), path_of.begin(), path_of.end());
+    maps.insert(maps.end(), slot.begin(), slot.end());
+    star_cls.resize(16, 0);
+    path_cls.resize(16, 0);
+    uint8_t* dm = d + 64 + 4096 + 256 + 64;
+    VDMC_HIP(hipMemcpy(dm, maps.data(), 768, hipMemcpyHostToDevice));
+    VDMC_HIP(hipMemcpy(dm + 768, star_cls.data(), 16, hipMemcpyHostToDevice));
+    VDMC_HIP(hipMemcpy(dm + 784, path_cls.data(), 16, hipMemcpyHostToDevice));
+    t->maps4 = dm;
+    t->star_cls = dm + 768;
+    t->path_cls = dm + 784;
     g_tables[dev] = t;   // kept for the life of the process
     return *t;
 }

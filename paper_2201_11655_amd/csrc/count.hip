@@ -61,9 +61,21 @@ __device__ __forceinline__ bool in_list(const uint32_t* P, uint32_t d, uint32_t 
     return lo < d && (P[lo] >> 2) == x;
 }
 
+// One count of class cls to vertex v.  When every lane that gets here credits the same
+// (vertex, class) -- lanes that share a member of their sets, e.g. the centre of a star
+// -- one lane adds them all.
 __device__ __forceinline__ void credit(unsigned long long* out, const int32_t* perm, int C, uint32_t v,
                                        uint32_t cls) {
-    if (cls < (uint32_t)C) atomicAdd(&out[(size_t)perm[v] * C + cls], 1ull);   // 0xFF never credited
+    if (cls >= (uint32_t)C) return;   // 0xFF never credited
+    const uint32_t fv = __builtin_amdgcn_readfirstlane(v), fc = __builtin_amdgcn_readfirstlane(cls);
+    const unsigned long long act = __ballot(1);
+    const unsigned long long same = __ballot(v == fv && cls == fc);
+    if (same == act) {
+        if ((threadIdx.x & 63u) == (uint32_t)(__ffsll((long long)act) - 1))
+            atomicAdd(&out[(size_t)perm[v] * C + cls], (unsigned long long)__popcll(act));
+    } else {
+        atomicAdd(&out[(size_t)perm[v] * C + cls], 1ull);
+    }
 }
 
 // Where the per-set increments go.  GlobalSink: one 64-bit atomic per credited vertex
@@ -447,7 +459,7 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
         a.ehash_bits = g->ehash_bits;
         const int64_t blocks = g->nlight < 65536 ? g->nlight : 65536;
         const dim3 grid((unsigned)blocks);
-        if (g->bins_hub_min <= 64) {   // every light root has at most 63 higher neighbours
+        if (g->light_max_d <= 64) {   // every light root has at most 64 higher neighbours
             if (k3 && k4) hipLaunchKernelGGL((k_count_roots<64, 64, true, true>), grid, dim3(64), 0, st, a);
             else if (k3) hipLaunchKernelGGL((k_count_roots<64, 64, true, false>), grid, dim3(64), 0, st, a);
             else hipLaunchKernelGGL((k_count_roots<64, 64, false, true>), grid, dim3(64), 0, st, a);

@@ -350,13 +350,11 @@ static void free_graph_arrays(vdmc_graph_s* g) {
     free_hub(g);
     (void)hipFree(g->utmp);
     (void)hipFree(g->ehash);
-    (void)hipFree(g->efp);
     (void)hipFree(g->epid);
     (void)hipFree(g->elo);
     (void)hipFree(g->ehi);
     g->utmp = nullptr;
     g->ehash = nullptr;
-    g->efp = nullptr;
     g->ehash_bits = 0;
     g->epid = nullptr;
     g->elo = g->ehi = nullptr;

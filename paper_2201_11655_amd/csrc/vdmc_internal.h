@@ -68,24 +68,28 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 constexpr int kClasses3 = 13;
 constexpr int kClasses4 = 199;
 constexpr int kShapes = 6;   // (1,1) (1,2) | (3,0,0) (2,1,0) (1,2,0) (1,1,1)
-constexpr int kStatSlots = 40;      // shapes, profile counters (cycles per phase, direct-path sets,
-                                    // work counts), then 32-37: sets enumerated by the hub kernel
-constexpr int kLdsStatSlots = 32;   // the part the hub kernel gathers in LDS
+constexpr int kStatSlots = 8;       // per graph: sets visited per shape (kShapes), then spare
 
 inline int num_classes(int k) { return k == 3 ? kClasses3 : (k == 4 ? kClasses4 : -1); }
 
 // Device-resident class tables of the current device: code -> class id (0xFF =
 // disconnected).  Built on first use by a kernel; cached per device.
 // Classes of 4-sets whose induced subgraph is a tree (the 15 directed 4-path and the
-// 10 directed 3-star classes): the only classes the aggregated credits of the hub
-// kernel produce; they get compact slots.
+// 10 directed 3-star classes): the classes of the sets whose pairs outside their BFS
+// tree are non-adjacent, most of the 4-sets of sparse graphs; LDS counters are kept
+// for them.
 constexpr int kCompact4 = 25;
+// the hub path takes graphs whose largest degree is at most this (slot and child lists in LDS)
+constexpr uint32_t kHubMaxDegree = 2048;
 
 struct ClassTables {
     const uint8_t* t3;   // 64 entries
     const uint8_t* t4;   // 4096 entries
     const uint8_t* slot4;     // 199 entries: class -> compact slot or 0xFF
     const uint8_t* slotcls;   // kCompact4 entries: compact slot -> class
+    const uint8_t* maps4;     // 768 entries: class -> star slot (10), path slot (15), tree slot (25); 0xFF none
+    const uint8_t* star_cls;  // 10 entries: star slot -> class
+    const uint8_t* path_cls;  // 15 entries: path slot -> class
     std::vector<uint8_t> host3, host4;
     std::vector<uint16_t> codes3, codes4;
 };
@@ -126,19 +130,16 @@ struct vdmc_graph_s {
     int64_t nhub = 0;
     int64_t max_scan2 = 0;       // largest depth-2 scan over hub roots (scratch sizing)
     int32_t max_hi = 0;          // largest |N+(r)|
-    // hub-kernel scratch (per workgroup slices), sized for this graph
+    int32_t light_max_d = 0;     // largest |N+(r)| among the light roots
+    // hub-path scratch (per workgroup slices), sized for this graph
     void* hub_scratch = nullptr;
     size_t hub_scratch_bytes = 0;
-    unsigned* hub_queue = nullptr;
-    void* hub_comp = nullptr;    // n x kCompact4 uint64 rank-indexed accumulator
-    void* hub_w111 = nullptr;    // n x 9 uint32: (1,1,1) parent codes per depth-2 vertex
-    uint32_t* hub_pre = nullptr; // nhub + 1 prefix sums of |N+(r)| over the hub queue
-    void* sp_scratch = nullptr;  // per-wave scratch of the (1,2,0) kernel
-    uint32_t* lbits = nullptr;   // adjacency bitmap among the long-row vertices (ranks < nlong)
-    uint32_t nlong = 0, lwords = 0;
+    unsigned* hub_queue = nullptr;   // root cursor, long-slot task count and cursor
+    uint32_t* hub_s2 = nullptr;      // per hub root: entries of its slots' rows above it
+    void* hub_tasks = nullptr;       // long-slot tasks (hub index, slot)
+    uint32_t hub_task_cap = 0;
     unsigned long long* ehash = nullptr;   // edge hash: every pair of the graph, 2^ehash_bits slots
     uint32_t ehash_bits = 0;
-    uint16_t* efp = nullptr;     // 16-bit fingerprint per edge-hash slot (0 = empty)
     uint32_t* epid = nullptr;    // per edge-hash slot: output row of the pair (per-edge counts)
     int32_t* elo = nullptr;      // per output row: the pair's endpoints (original ids, lo < hi)
     int32_t* ehi = nullptr;

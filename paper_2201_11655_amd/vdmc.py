@@ -291,8 +291,8 @@ def shape_counts(g: Graph) -> dict:
 
 def profile_counters(g: Graph) -> np.ndarray:
     """Diagnostic counters of the last count (see vdmc_profile_counters in vdmc.h)."""
-    out = np.zeros(40, np.uint64)
-    _check(load().vdmc_profile_counters(g.handle, _np_ptr(out), 40))
+    out = np.zeros(8, np.uint64)
+    _check(load().vdmc_profile_counters(g.handle, _np_ptr(out), 8))
     return out
 
 

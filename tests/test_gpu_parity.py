@@ -35,20 +35,30 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _check_graph(v, n, src, dst, ks=(3, 4), threads=None, label=""):
-    _say(f"case {label} n={n} m={len(src)}")
+PATHS = ["default", "hub"]   # "hub": every root with a higher neighbour takes the hub path
+
+
+def _check_graph(v, n, src, dst, ks=(3, 4), threads=None, label="", path="default"):
+    _say(f"case {label} n={n} m={len(src)} path={path}")
     G = v.Graph(n, src, dst)
+    if path == "hub":
+        v.set_hub_threshold(G, 1)
     for k in ks:
         got = _np(v.count(G, k))
         want, tot = oracle.count(n, src, dst, k, threads=threads)
         assert got.shape == want.shape
         bad = np.argwhere(got != want)
         assert bad.size == 0, f"{label} k={k}: {bad.shape[0]} cells differ, first {bad[:5].tolist()}"
-        sc = v.shape_counts(G)
+        sc = v.shape_counts(G)   # sets visited one by one, per shape
         if k == 3:
             assert sc["(1,1)"] + sc["(1,2)"] == int(tot.sum())
         else:
             assert sc["(3,0,0)"] + sc["(2,1,0)"] + sc["(1,2,0)"] + sc["(1,1,1)"] == int(tot.sum())
+    if tuple(ks) == (3, 4):
+        o3, o4 = v.count34(G)
+        want3, _ = oracle.count(n, src, dst, 3, threads=threads)
+        want4, _ = oracle.count(n, src, dst, 4, threads=threads)
+        assert (_np(o3) == want3).all() and (_np(o4) == want4).all(), f"{label}: count34 differs"
     return G
 
 
@@ -119,56 +129,112 @@ def test_csr_example_sec42(v):
 
 # --------------------------------------------------------------------------- counts
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("seed", range(16))
-def test_tiny_random_graphs(v, seed):
+def test_tiny_random_graphs(v, seed, path):
     rng = np.random.default_rng(100 + seed)
     n = int(rng.integers(1, 14))
     p = float(rng.uniform(0.05, 0.8))
     g = gg.er_directed(n, p, (21, seed))
-    _check_graph(v, n, g.src, g.dst, label=f"tiny{seed}")
+    _check_graph(v, n, g.src, g.dst, label=f"tiny{seed}", path=path)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("kind", ["complete", "tournament", "cycle", "outstar", "instar", "path"])
-def test_special_graphs(v, kind):
+def test_special_graphs(v, kind, path):
     n = 12
     g = gg.special_graph(kind, n)
-    _check_graph(v, n, g.src, g.dst, label=kind)
+    _check_graph(v, n, g.src, g.dst, label=kind, path=path)
 
 
-def test_dense_er60_all_classes(v):
+@pytest.mark.parametrize("path", PATHS)
+def test_dense_er60_all_classes(v, path):
     g = gg.er_directed(60, 0.5, 7)
-    _check_graph(v, g.n, g.src, g.dst, label="er60")
+    _check_graph(v, g.n, g.src, g.dst, label="er60", path=path)
 
 
-def test_er1000_count_and_count34(v):
+@pytest.mark.parametrize("path", PATHS)
+def test_er1000(v, path):
     g = gg.config_graph("er1000")
-    G = _check_graph(v, g.n, g.src, g.dst, label="er1000")
-    o3, o4 = v.count34(G)
-    want3, _ = oracle.count(g.n, g.src, g.dst, 3)
-    want4, _ = oracle.count(g.n, g.src, g.dst, 4)
-    assert (_np(o3) == want3).all() and (_np(o4) == want4).all()
+    _check_graph(v, g.n, g.src, g.dst, label="er1000", path=path)
 
 
-def test_chunglu_small_full(v):
+@pytest.mark.parametrize("path", PATHS)
+def test_chunglu_small_full(v, path):
     """Scaled-down Chung-Lu (same recipe, n = 2,000, 2.5e7 4-sets): hubs, reciprocated arcs."""
     g = gg.config_graph("chunglu_2000")
-    _check_graph(v, g.n, g.src, g.dst, label="chunglu_2000")
+    _check_graph(v, g.n, g.src, g.dst, label="chunglu_2000", path=path)
 
 
-def test_dense_long_children_rows(v):
-    # every vertex has more than 64 neighbours, so every depth-2 child has a long row and
-    # the (1,2,0) pairs of children are all tested in the long-vertex bitmap (dozens of
-    # long children per slot).  The oracle's rows of a few vertices (its full count of
-    # this graph takes minutes), plus the shape totals.
-    g = gg.er_directed(300, 0.25, (71, 1))
-    _say(f"dense long children n={g.n} m={g.m}")
-    G = v.Graph(g.n, g.src, g.dst)
+@pytest.mark.parametrize("path", PATHS)
+def test_dense_long_children(v, path):
+    # every vertex has about 150 neighbours: every slot's row above the root is longer
+    # than 64 entries, so the (1,2,0)/(1,1,1) sets below it take the long-slot kernel;
+    # dense local adjacency among the slots.  Full comparison with the oracle.
+    g = gg.er_directed(160, 0.5, (71, 1))
+    _check_graph(v, g.n, g.src, g.dst, label="dense160", path=path)
+
+
+def _hub_graph(d, outer, seed):
+    """A root of degree d (rank 0) with random arc directions (some reciprocal), sparse arcs
+    among its neighbours, `outer` vertices each joined to a few neighbours (depth-2
+    vertices with one or several parents) and sparsely to each other (depth 3), and a few
+    neighbours with long rows into the outer vertices."""
+    rng = np.random.default_rng(seed)
+    n = 1 + d + outer
+    leaves = np.arange(1, d + 1)
+    outs = np.arange(d + 1, n)
+    src, dst = [], []
+    kind = rng.integers(0, 3, size=d)
+    for x, k in zip(leaves, kind):
+        if k in (0, 2):
+            src.append(0); dst.append(x)
+        if k in (1, 2):
+            src.append(x); dst.append(0)
+    m_local = 2 * d
+    src += list(rng.choice(leaves, m_local)); dst += list(rng.choice(leaves, m_local))
+    for o in outs:
+        for x in rng.choice(leaves, int(rng.integers(1, 5)), replace=False):
+            if rng.random() < 0.5:
+                src.append(o); dst.append(x)
+            else:
+                src.append(x); dst.append(o)
+    src += list(rng.choice(outs, 2 * outer)); dst += list(rng.choice(outs, 2 * outer))
+    for x in rng.choice(leaves, 4, replace=False):   # long rows below the root
+        for o in rng.choice(outs, min(100, outer), replace=False):
+            src.append(x); dst.append(o)
+    return gg.Graph(n, np.array(src, np.int32), np.array(dst, np.int32), f"hub{d}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_hub_root_over_1024(v, path):
+    """One root with 1,100 higher neighbours (a hub root between 1,025 and 2,048), every
+    shape below it, counted in full and compared with the oracle."""
+    g = _hub_graph(1100, 300, 91)
+    G = _check_graph(v, g.n, g.src, g.dst, label="hub1100", path=path)
+    assert G.max_deg >= 1100
+
+
+def test_root_over_2048_takes_per_root_kernel(v):
+    """A root with 2,100 higher neighbours (more than the hub path stages) goes through the
+    per-root kernel: k = 3 in full against the oracle; k = 4 against the closed form of an
+    out-star (centre C(2099+1, 3) sets, each leaf C(2099, 2), one class) and the oracle's
+    rows of a few leaves."""
+    from math import comb
+    n = 2101
+    g = gg.special_graph("outstar", n)
+    G = _check_graph(v, n, g.src, g.dst, ks=(3,), label="outstar2101")
     got = _np(v.count(G, 4))
-    rows = np.array([0, 150, 299], np.int32)
-    want = oracle.count_rows(g.n, g.src, g.dst, 4, rows)
-    assert (got[rows] == want).all()
-    sc = v.shape_counts(G)
-    assert int(got.sum()) == 4 * (sc["(3,0,0)"] + sc["(2,1,0)"] + sc["(1,2,0)"] + sc["(1,1,1)"])
+    cls0 = 0   # the out-star class (canonical index 7) has class id 0
+    assert got[0, cls0] == comb(n - 1, 3) and got[0].sum() == comb(n - 1, 3)
+    assert (got[1:, cls0] == comb(n - 2, 2)).all() and int(got[1:].sum()) == (n - 1) * comb(n - 2, 2)
+    rows = np.array([1, 1050, 2100], np.int32)
+    assert (got[rows] == oracle.count_rows(n, g.src, g.dst, 4, rows)).all()
+    # the same star with sparse arcs among the leaves, k = 3 in full
+    rng = np.random.default_rng(5)
+    s2 = np.concatenate([g.src, rng.integers(1, n, 3000).astype(np.int32)])
+    d2 = np.concatenate([g.dst, rng.integers(1, n, 3000).astype(np.int32)])
+    _check_graph(v, n, s2, d2, ks=(3,), label="outstar2101+leaf arcs")
 
 
 def test_degenerate_graphs(v):
@@ -184,7 +250,8 @@ def test_degenerate_graphs(v):
     ]:
         s = np.array(src, np.int32)
         d = np.array(dst, np.int32)
-        _check_graph(v, n, s, d, label=f"degenerate n={n}")
+        for path in PATHS:
+            _check_graph(v, n, s, d, label=f"degenerate n={n}", path=path)
 
 
 def test_errors(v):
@@ -218,45 +285,52 @@ def test_relabelling_and_repeat_invariance(v):
         assert (b[perm] == a1).all()
 
 
-def test_count_range_slices_sum_to_count(v):
+@pytest.mark.parametrize("path", PATHS)
+def test_count_range_slices_sum_to_count(v, path):
     """Root-rank ranges are independent (Lemma 1): consecutive ranges accumulate to the
     full count, for both the light-root and the hub path."""
     import torch
     g = gg.config_graph("chunglu_2000")
     G = v.Graph(g.n, g.src, g.dst)
+    if path == "hub":
+        v.set_hub_threshold(G, 1)
     for k in (3, 4):
-        full = _np(v.count(G, k)).copy()
+        want, _ = oracle.count(g.n, g.src, g.dst, k)
         out = torch.empty((g.n, v.num_classes(k)), dtype=torch.int64, device="cuda")
         bounds = [0, 1, 7, 64, 300, 1999, g.n]
         for i in range(len(bounds) - 1):
             v.count_range(G, k, out, bounds[i], bounds[i + 1], accumulate=i > 0)
-        assert (_np(out) == full).all()
+        assert (_np(out) == want).all()
         with pytest.raises(v.VdmcError):
             v.count_range(G, k, out, 5, 2, accumulate=False)
 
 
+def test_hub_threshold_changes_nothing(v):
+    g = gg.config_graph("chunglu_2000")
+    G = v.Graph(g.n, g.src, g.dst)
+    want, _ = oracle.count(g.n, g.src, g.dst, 4)
+    for t in (1, 2, 8, 32, 100, 1 << 30):
+        v.set_hub_threshold(G, t)
+        assert (_np(v.count(G, 4)) == want).all(), f"threshold {t}"
+    with pytest.raises(v.VdmcError) as e:
+        v.set_hub_threshold(G, 0)
+    assert e.value.name == "INVALID_ARG"
+
+
 # --------------------------------------------------------------------------- diagnostics
 
-def test_kernel_times_and_hub_share(v):
-    # the per-kernel event times and the hub kernel's share of the shape counts
+def test_kernel_times(v):
     g = gg.config_graph("chunglu_2000")
     _say(f"kernel times n={g.n}")
     G = v.Graph(g.n, g.src, g.dst)
     v.count34(G)
     light_ms, hub_ms, khub_ms = v.kernel_times(G)
-    pc = v.profile_counters(G)
-    all_hub = os.environ.get("VDMC_HUB_MIN") == "1"   # every root on the hub path
-    assert hub_ms >= 0.0 and (light_ms == -1.0 if all_hub else light_ms >= 0.0)
+    assert hub_ms >= 0.0 and light_ms >= 0.0
     assert 0.0 <= khub_ms <= hub_ms   # the hub kernel is the first part of the hub path
-    assert all(pc[32 + s] <= pc[s] for s in range(6))
-    assert pc[32:38].sum() > 0   # chunglu_2000 has hub roots
     G2 = v.Graph(5, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
     v.count(G2, 3)
     lt, ht, kt = v.kernel_times(G2)
-    if all_hub:
-        assert lt == -1.0 and ht >= 0.0 and kt >= 0.0
-    else:
-        assert ht == -1.0 and kt == -1.0 and lt >= 0.0   # no hub root: no hub path
+    assert ht == -1.0 and kt == -1.0 and lt >= 0.0   # no hub root: no hub path
 
 
 # --------------------------------------------------------------------------- undirected motifs
