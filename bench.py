@@ -1,20 +1,32 @@
 """Benchmark: connected 4-vertex subgraphs counted per second on one MI355X.
 
-One step = the whole hot path over one synthetic graph already resident in HBM:
-device graph build (normalise, rank, CSR; Sec. 4.2, 6) + one count call for k = 3
-and k = 4 together (Sec. 4.2).  The metric value counts the connected 4-vertex
-sets enumerated per second of step time.  Every count is checked afterwards against
-invariants (column sums divisible by k, shape counts = set totals); the bit-exact
-parity against the oracle is the test suite's job.
+Default workload (the configuration the metric names first): a batch of 4096 directed
+G(n, p) graphs, n ~ U{20..500}, mean out-degree ~ U[2, 8], counted for k = 4 by one
+batched launch (whole-graph kernel, replayed from a captured HIP graph, launch
+parameters from the autotuner) against 4096 per-graph launches on the same GPU.  One
+step = one batched launch over all 4096 graphs, inputs resident in HBM.  The same JSON
+line carries the serving run (Poisson arrivals, continuous batching, p50/p99) and the
+oracle timed on the host cores.
 
-Prints ONE JSON line (rank 0).  ``--gpus N`` with N > 1 exits with a message: this
-build runs on one GPU.
+Other workloads (``--workload``): ``chunglu`` (n = 1e6 Chung-Lu, k = 3 and 4 in one
+call), ``rmat22`` (R-MAT scale 22, k = 4), ``er1000``, ``chunglu_u`` (undirected
+motifs), ``serve`` (the serving workload alone at its full pool).  There, one step =
+device graph build + one count call.
+
+Every count is checked: column sums are multiples of k and equal k x the number of sets
+the kernels visited one by one (the per-shape visit counters); batched = per-graph,
+served = alone.  Bit-exact parity with the oracle is the test suite's job.
+
+Prints ONE JSON line.  ``--gpus N`` with N > 1 exits with a message: this build runs on
+one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -24,20 +36,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit VALU lane-ops: 256 CU x 64 lanes/clk x 2.4 GHz
+HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E, GB/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12    # 32-bit VALU lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+MODEL_OPS_PER_SET = 40                      # lower end of the per-set integer work of the method
 
 WORKLOADS = {
+    "batch4096": "4096 directed G(n,p) graphs, n ~ U{20..500}, mean out-degree ~ U[2,8], graph i seeded (3,i); "
+                 "k=4 in one batched launch (autotuned, HIP-graph replay) vs 4096 per-graph launches",
     "chunglu": "Chung-Lu directed power-law graph, n=1,000,000, 8.4M base arcs (~10M arcs), "
                "gamma 2.1, undirected degree cap 2000, 20% reciprocated, seed 2; k=3 and k=4 in one call",
     "er1000": "directed G(n=1000, p=0.005), seed 1; k=3 and k=4 in one call",
     "rmat22": "R-MAT scale 22, edge factor 8, (0.57,0.19,0.19,0.05), cap 1500, seed 4; k=4",
-    "chunglu_u": "the Chung-Lu graph of the default workload with arc directions ignored; undirected "
-                 "4-vertex motifs (6 classes), one count call",
-    "batch4096": "4096 directed G(n,p) graphs, n ~ U{20..500}, mean out-degree ~ U[2,8], graph i seeded (3,i); "
-                 "k=4 in one persistent HIP-graph launch vs 4096 per-graph launches",
-    "serve": "serving: pool of resident ER and Chung-Lu graphs, n log-uniform in [1e2,1e6], mean out-degree "
-             "U[2,10], k in {3,4} 50/50, Poisson arrivals at half the measured capacity",
+    "chunglu_u": "the Chung-Lu graph with arc directions ignored; undirected 4-vertex motifs (6 classes)",
+    "serve": "serving: pool of resident ER and Chung-Lu graphs (even/odd), n log-uniform, mean out-degree "
+             "U[2,10], k in {3,4} 50/50, Poisson arrivals at 0.5x and 0.8x the measured capacity",
 }
 
 
@@ -45,49 +57,391 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, budget_s: float):
-    """The oracle (as it is) on a bounded sample: rows of seeded random non-isolated
-    vertices, enumerated by the oracle's per-vertex mode until about budget_s of work."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+# ---------------------------------------------------------------------------------------------
+# counters from committed rocprofv3 runs (profiles/), keyed by a hash of the kernel sources
+
+COUNTER_SOURCES = ["paper_2201_11655_amd/csrc/small.hip", "paper_2201_11655_amd/csrc/count.hip",
+                   "paper_2201_11655_amd/csrc/count_hub.hip", "paper_2201_11655_amd/csrc/motif_device.h",
+                   "paper_2201_11655_amd/csrc/vdmc_internal.h"]
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0   # FETCH_SIZE / WRITE_SIZE of a 1 GiB copy read 0.5x / 1.0x its bytes
+
+
+def sources_sha256():
+    h = hashlib.sha256()
+    for f in COUNTER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def load_counters(workload):
+    """Per-launch counters of the dominant kernel(s) from profiles/counters.json, or None when
+    they were taken with other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("sources_sha256") != sources_sha256():
+        return None
+    return rec
+
+
+def roofline(workload, sets, kernel_ms, kernel_name, compulsory_bytes):
+    """ALU roofline of the dominant kernel: VALU lane-ops per launch from the committed
+    SQ_INSTS_VALU counters (x 64 lanes) over the launch time measured live; the method's
+    per-set model (MODEL_OPS_PER_SET) beside it; HBM bytes from FETCH_SIZE/WRITE_SIZE."""
+    rec = load_counters(workload)
+    out = {"bound": "alu", "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "kernel": kernel_name,
+           "kernel_ms": kernel_ms, "sets_per_launch": sets}
+    secs = kernel_ms * 1e-3
+    if rec is not None and rec.get("valu_insts"):
+        lane_ops = 64.0 * rec["valu_insts"]
+        out["achieved"] = lane_ops / secs / 1e12
+        out["valu_lane_ops_per_set"] = lane_ops / max(sets, 1)
+        out["traffic"] = 1024.0 * (FETCH_FACTOR * rec["fetch_kib"] + WRITE_FACTOR * rec["write_kib"]) \
+            if rec.get("fetch_kib") is not None else None
+        out["counters"] = {k: rec[k] for k in rec if k not in ("sources_sha256",)}
+    else:
+        out["achieved"] = MODEL_OPS_PER_SET * sets / secs / 1e12
+        out["traffic"] = None
+        out["note"] = "no counters for these kernel sources: achieved from the per-set model"
+    out["frac"] = out["achieved"] / VALU_PEAK_TOPS
+    out["model_ops_per_set"] = MODEL_OPS_PER_SET
+    out["model_frac"] = MODEL_OPS_PER_SET * sets / secs / 1e12 / VALU_PEAK_TOPS
+    out["hbm_compulsory_bytes"] = compulsory_bytes
+    out["hbm_compulsory_frac"] = compulsory_bytes / secs / 1e9 / HBM_PEAK_GBS
+    if out.get("traffic"):
+        out["hbm_traffic_frac"] = out["traffic"] / secs / 1e9 / HBM_PEAK_GBS
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+# the oracle on the host cores
+
+def cpu_baseline_batch(graphs, budget_s):
+    """The oracle (as it is) on the batch workload: all 4096 graphs on every host core, and
+    on one core over the first graphs until about budget_s/2 of work; plus the small ER
+    graph er1000 in full."""
+    import graphgen as gg
+    import oracle
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    sets_all = 0
+    for g in graphs:
+        _, tot = oracle.count(g.n, g.src, g.dst, 4, threads=threads)
+        sets_all += int(tot.sum())
+    t_all = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sets_one, done = 0, 0
+    for g in graphs:
+        _, tot = oracle.count(g.n, g.src, g.dst, 4, threads=1)
+        sets_one += int(tot.sum())
+        done += 1
+        if time.perf_counter() - t0 > budget_s / 2:
+            break
+    t_one = time.perf_counter() - t0
+    e = gg.config_graph("er1000")
+    t0 = time.perf_counter()
+    _, tot = oracle.count(e.n, e.src, e.dst, 4, threads=threads)
+    t_er = time.perf_counter() - t0
+    return {
+        "value": sets_all / t_all, "unit": "4-vertex sets/s", "cores": threads, "kind": "oracle",
+        "sample": f"oracle ESU + k!-canonicalisation, full count of all {len(graphs)} graphs ({sets_all} sets) "
+                  f"in {t_all:.1f} s on {threads} threads",
+        "one_core": {"value": sets_one / t_one, "graphs": done, "sets": sets_one, "seconds": t_one},
+        "er1000": {"value": int(tot.sum()) / t_er, "sets": int(tot.sum()), "seconds": t_er, "cores": threads},
+        "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+    }
+
+
+def cpu_baseline_rows(g, budget_s):
+    """Large graphs: the oracle's per-vertex mode on seeded random vertices of the graph
+    until about budget_s of work, as (vertex, set) incidences per second; a full count is
+    out of reach on the host (extrapolation = sets / rate)."""
     import oracle
     rng = np.random.default_rng(12345)
     deg = np.bincount(np.concatenate([g.src, g.dst]), minlength=g.n)
-    cand = np.flatnonzero((deg > 0) & (deg <= 4))
-    if cand.size == 0:
-        cand = np.flatnonzero(deg > 0)
+    cand = np.flatnonzero(deg > 0)
     threads = oracle.default_threads()
-    done_rows = 0
-    sets = 0
-    t_used = 0.0
-    batch = threads
-    while t_used < budget_s and done_rows < cand.shape[0]:
-        rows = rng.choice(cand, size=batch, replace=False).astype(np.int32)
+    rows, sets, used = 0, 0, 0.0
+    while used < budget_s and rows < cand.size:
+        pick = rng.choice(cand, size=threads, replace=False).astype(np.int32)
         t0 = time.perf_counter()
-        out = oracle.count_rows(g.n, g.src, g.dst, 4, rows, threads=threads)
-        t_used += time.perf_counter() - t0
+        out = oracle.count_rows(g.n, g.src, g.dst, 4, pick, threads=threads)
+        used += time.perf_counter() - t0
         sets += int(out.sum())
-        done_rows += batch
-    return {
-        "value": sets / t_used if t_used > 0 else None,
-        "unit": "4-vertex sets/s (per-vertex rows)",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": f"oracle per-vertex mode on {done_rows} seeded random vertices of degree 1-4 of the same "
-                  f"graph: {sets} (vertex, 4-set) incidences in {t_used:.1f} s",
+        rows += threads
+    return {"value": sets / used if used > 0 else None, "unit": "(vertex, 4-set) incidences/s", "cores": threads,
+            "kind": "oracle", "sample": f"oracle per-vertex mode on {rows} seeded random non-isolated vertices: "
+                                        f"{sets} incidences in {used:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+# ---------------------------------------------------------------------------------------------
+
+def visited_sets(v, G, k):
+    sc = v.shape_counts(G)
+    return sc["(1,1)"] + sc["(1,2)"] if k == 3 else sc["(3,0,0)"] + sc["(2,1,0)"] + sc["(1,2,0)"] + sc["(1,1,1)"]
+
+
+def bench_batch(args, torch, gg, v):
+    t0 = time.perf_counter()
+    graphs = gg.er_batch(4096, 20, 500, 2.0, 8.0, seed=3)
+    log(f"[bench] generated 4096 graphs ({sum(g.n for g in graphs)} vertices) in {time.perf_counter() - t0:.1f}s")
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
+    outs = [torch.empty((g.n, 199), dtype=torch.int64, device="cuda") for g in graphs]
+    t0 = time.perf_counter()
+    v.tune(Gs, 4)
+    choice = v.tuned_choice(Gs, 4)
+    log(f"[bench] tuned in {time.perf_counter() - t0:.1f}s: {choice}")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for w in range(args.warmup):
+            v.count_batch(Gs, 4, outs=outs, stream=stream)
+            stream.synchronize()
+            log(f"[bench] warmup {w} done")
+        v.count_batch(Gs, 4, outs=outs, stream=stream)   # at least one capture before timing
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            v.count_batch(Gs, 4, outs=outs, stream=stream)
+        ev1.record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
+        dev_ms = ev0.elapsed_time(ev1) / args.steps
+        log(f"[bench] {args.steps} batched steps: {ms_batch:.3f} ms/step (device {dev_ms:.3f} ms)")
+        col = sum(o.sum(dim=0) for o in outs).cpu().numpy().view(np.uint64)
+        assert (col % 4 == 0).all(), "column sums must be multiples of 4"
+        T4 = int(col.sum()) // 4
+        visited = sum(visited_sets(v, G, 4) for G in Gs)
+        assert visited == T4, f"sets visited one by one ({visited}) != sets counted ({T4})"
+        ref = [o.clone() for o in outs]
+        # per-graph launches, back to back on one stream
+        reps = max(1, args.steps // 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for G, o in zip(Gs, outs):
+                v.count(G, 4, o, stream=stream)
+        stream.synchronize()
+        ms_single = (time.perf_counter() - t0) * 1e3 / reps
+        # per-graph, host-synchronised after every graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for G, o in zip(Gs, outs):
+            v.count(G, 4, o, stream=stream)
+            stream.synchronize()
+        ms_sync = (time.perf_counter() - t0) * 1e3
+        same = all(bool(torch.equal(a, b)) for a, b in zip(ref, outs))
+    assert same, "batched and per-graph outputs differ"
+    log(f"[bench] per-graph {ms_single:.1f} ms, host-synced {ms_sync:.1f} ms")
+    out_bytes = 8.0 * 199 * sum(g.n for g in graphs)
+    csr_bytes = sum(4.0 * (G.n + 1) + 8.0 * G.pairs for G in Gs)
+    result = {
+        "metric": "connected 4-vertex subgraphs counted/s (bit-exact), batched vs per-graph; p99",
+        "value": T4 / (ms_batch * 1e-3), "unit": "4-vertex sets/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["batch4096"], "graphs": 4096, "vertices": sum(g.n for g in graphs),
+                   "arcs": int(sum(G.arcs for G in Gs)), "sets4": T4, "sets_visited": visited},
+        "batched": {"sets_per_s": T4 / (ms_batch * 1e-3), "ms": ms_batch, "device_ms": dev_ms, "tuned": choice},
+        "per_graph": {"sets_per_s": T4 / (ms_single * 1e-3), "ms": ms_single, "host_synced_ms": ms_sync,
+                      "host_synced_sets_per_s": T4 / (ms_sync * 1e-3)},
+        "batched_speedup": ms_single / ms_batch, "batched_equals_per_graph": same,
+        "roofline": roofline("batch4096", T4, dev_ms, "k_small (whole-graph kernel) + k_batch_zero",
+                             csr_bytes + out_bytes),
     }
+    return result, graphs
+
+
+def run_serve(v, torch, gg, pool_graphs, requests, log_hi, rates, seed=5):
+    """Serving: a pool of resident graphs; requests with seeded Poisson arrivals at each rate
+    (a fraction of the measured capacity); every served result equal to the alone result."""
+    rng = np.random.default_rng(seed)
+    t0 = time.perf_counter()
+    pool = gg.serve_pool(pool_graphs, 2.0, log_hi, 2.0, 10.0, seed=seed)
+    log(f"[bench] serve pool: {len(pool)} graphs, n <= {max(g.n for g in pool)}, "
+        f"{sum(g.m for g in pool)} arcs, generated in {time.perf_counter() - t0:.1f}s")
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in pool]
+    picks = rng.integers(0, len(pool), size=requests)
+    ks = rng.choice([3, 4], size=requests)
+    # alone: every (graph, k) once, timed one at a time; capacity = 1 / mean service time
+    alone, service = {}, []
+    need = sorted(set(zip(picks.tolist(), ks.tolist())))
+    t0 = time.perf_counter()
+    for gi, k in need:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        o = v.count(Gs[gi], k)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t)
+        alone[(gi, k)] = o
+    log(f"[bench] alone pass over {len(need)} (graph, k) in {time.perf_counter() - t0:.1f}s")
+    weights = np.array([sum(1 for p, k in zip(picks, ks) if (p, k) == key) for key in need], np.float64)
+    mean_service = float(np.dot(weights, service) / weights.sum())
+    runs = []
+    for frac in rates:
+        lam = frac / mean_service
+        gaps = rng.exponential(1.0 / lam, size=requests)
+        srv = v.Server(mem_budget_bytes=64 << 30, max_inflight=16)
+        outs = [torch.empty((pool[gi].n, v.num_classes(int(k))), dtype=torch.int64, device="cuda")
+                for gi, k in zip(picks, ks)]
+        torch.cuda.synchronize()
+        ids = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for i in range(requests):
+            t_next += gaps[i]
+            while time.perf_counter() < t_next:
+                time.sleep(min(1e-4, max(0.0, t_next - time.perf_counter())))
+            ids.append(srv.submit(Gs[picks[i]], int(ks[i]), outs[i]))
+        for rid in ids:
+            srv.wait(rid)
+        wall = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        bad = sum(int(not torch.equal(outs[i], alone[(int(picks[i]), int(ks[i]))])) for i in range(requests))
+        assert bad == 0, f"{bad} served results differ from the alone results"
+        runs.append({"load": frac, "arrival_rate_per_s": lam, "wall_s": wall, "sets_per_s": st["sets"] / wall,
+                     "req_per_s": st["req_per_s"], "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3,
+                     "sets": st["sets"], "served_equals_alone": True,
+                     "max_queue_depth": st.get("max_queue_depth"), "admitted": st.get("admitted"),
+                     "deferred_by_memory": st.get("deferred_by_memory")})
+        log(f"[bench] serve at {frac}x capacity: p50 {st['p50_us'] / 1e3:.2f} ms, p99 {st['p99_us'] / 1e3:.2f} ms, "
+            f"{st['sets'] / wall:.3e} sets/s over {wall:.1f}s")
+    return {"workload": WORKLOADS["serve"], "pool_graphs": len(pool), "n_log10_range": [2.0, log_hi],
+            "requests": requests, "mean_alone_service_ms": mean_service * 1e3, "runs": runs}
+
+
+def bench_graph(args, torch, gg, v):
+    """One large graph: device build + count per step."""
+    t0 = time.perf_counter()
+    undirected = args.workload == "chunglu_u"
+    g = gg.config_graph("chunglu" if undirected else args.workload)
+    log(f"[bench] generated {args.workload}: n={g.n} arcs={g.m} in {time.perf_counter() - t0:.1f}s")
+    dsrc = torch.from_numpy(g.src).cuda()
+    ddst = torch.from_numpy(g.dst).cuda()
+    only4 = args.workload in ("rmat22", "chunglu_u")
+    out3 = torch.empty((g.n if not only4 else 1, 13), dtype=torch.int64, device="cuda")
+    out4 = torch.empty((g.n, 6 if undirected else 199), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    kt_steps = []
+
+    def step(progress=False):
+        G = v.Graph(g.n, dsrc, ddst, stream=stream, undirected=undirected)
+        if undirected:
+            v.count_undirected(G, 4, out4, stream=stream)
+        elif only4:
+            # one count issued as consecutive root-rank ranges (Lemma 1: independent) so that a
+            # long run reports progress
+            bounds = [0] + [1 << b for b in range(8, 40) if (1 << b) < g.n] + [g.n]
+            for i in range(len(bounds) - 1):
+                v.count_range(G, 4, out4, bounds[i], bounds[i + 1], accumulate=i > 0, stream=stream)
+                if progress:
+                    stream.synchronize()
+                    kt_steps.append(v.kernel_times(G))
+                    log(f"[bench] ranks [{bounds[i]}, {bounds[i + 1]}) done")
+        else:
+            v.count34(G, out3, out4, stream=stream)
+        return G
+
+    for w in range(args.warmup):
+        step(progress=True)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w} done")
+    graphs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graphs.append(step(progress=only4))
+        if not only4:
+            stream.synchronize()
+            kt_steps.append(v.kernel_times(graphs[-1]))
+            log(f"[bench] step done: {kt_steps[-1]}")
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    G = graphs[-1]
+    c4 = out4.sum(dim=0).cpu().numpy().view(np.uint64)
+    assert (c4 % 4 == 0).all()
+    T4 = int(c4.sum()) // 4
+    if not undirected:
+        assert visited_sets(v, G, 4) == T4, "k=4 sets visited one by one != sets counted"
+    T3 = 0
+    if not only4:
+        c3 = out3.sum(dim=0).cpu().numpy().view(np.uint64)
+        assert (c3 % 3 == 0).all()
+        T3 = int(c3.sum()) // 3
+        assert visited_sets(v, G, 3) == T3, "k=3 sets visited one by one != sets counted"
+    # kernel times (HIP events the library records on the stream): one record per timed step,
+    # or one per root range of each step for the ranged count
+    timed = kt_steps[-(len(kt_steps) * args.steps // (args.steps + (args.warmup if only4 else 0))):]
+    light = sum(max(0.0, k[0]) for k in timed) / args.steps
+    hub = sum(max(0.0, k[1]) for k in timed) / args.steps
+    khub = sum(max(0.0, k[2]) for k in timed) / args.steps
+    log(f"[bench] {args.steps} steps: {ms_step:.1f} ms/step, T4={T4} T3={T3}")
+    sc = v.shape_counts(G)
+    csr_bytes = 4.0 * (g.n + 1) + 8.0 * G.pairs
+    result = {
+        "metric": "connected 4-vertex subgraphs counted/s (bit-exact)", "value": T4 / (ms_step * 1e-3),
+        "unit": "4-vertex sets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "n": g.n, "arcs": G.arcs, "pairs": G.pairs,
+                   "max_degree": G.max_deg, "sets3": T3, "sets4": T4, "shapes_visited": sc},
+        "sets3_per_s": T3 / (ms_step * 1e-3), "light_ms": light, "hub_path_ms": hub, "k_hub_ms": khub,
+    }
+    if hub:
+        result["roofline"] = roofline(args.workload, T4 + T3, hub + (light or 0.0),
+                                      "hub path (k_hub + k_long_slots) + per-root kernel",
+                                      csr_bytes + 8.0 * g.n * (13 + 199))
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline ...")
+        gb = g if not undirected else gg.Graph(g.n, np.concatenate([g.src, g.dst]),
+                                               np.concatenate([g.dst, g.src]), "chunglu_u")
+        result["cpu_baseline"] = cpu_baseline_rows(gb, args.cpu_budget)
+    return result
+
+
+def calibrate_copy(torch):
+    """Reference readings for the HBM byte counters: a plain 1 GiB device-to-device copy."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("[bench] calibration copy of 1 GiB done")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chunglu", choices=sorted(WORKLOADS) + ["chunglu_50000", "chunglu_200000"])
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="after the run, copy 1 GiB device to device (reference for HBM byte counters)")
-    ap.add_argument("--serve-graphs", type=int, default=48)
-    ap.add_argument("--serve-requests", type=int, default=300)
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batch4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--serve-graphs", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-log-hi", type=float, default=None,
+                    help="pool n up to 10^this (default: 4.5 in the default run, 6 for --workload serve)")
+    ap.add_argument("--no-serve", action="store_true", help="default run without the serving leg")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -103,308 +457,26 @@ def main():
     torch.cuda.set_device(0)
     v.load()
     if args.workload == "batch4096":
-        return bench_batch(args, torch, gg, v)
-    if args.workload == "serve":
-        return bench_serve(args, torch, gg, v)
-    t0 = time.perf_counter()
-    undirected = args.workload == "chunglu_u"
-    g = gg.config_graph("chunglu" if undirected else args.workload)
-    log(f"[bench] generated {args.workload}: n={g.n} arcs={g.m} in {time.perf_counter() - t0:.1f}s")
-    dsrc = torch.from_numpy(g.src).cuda()
-    ddst = torch.from_numpy(g.dst).cuda()
-    out3 = torch.empty((g.n, 13), dtype=torch.int64, device="cuda")
-    out4 = torch.empty((g.n, 199), dtype=torch.int64, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    only4 = args.workload in ("rmat22", "chunglu_u")
-    if undirected:
-        out4 = torch.empty((g.n, 6), dtype=torch.int64, device="cuda")
-    if only4:
-        out3 = torch.zeros((1, 13), dtype=torch.int64, device="cuda")
-
-    hub_ms_steps = []
-    khub_ms_steps = []
-
-    def step(timing=None):
-        G = v.Graph(g.n, dsrc, ddst, stream=stream, undirected=undirected)
-        hub_ms = khub = 0.0
-        if timing is not None:
-            timing[0].record(stream)
-        if undirected:
-            v.count_undirected(G, 4, out4, stream=stream)
-        elif only4:
-            # the same count as one vdmc_count call, issued as consecutive root-rank ranges
-            # (Lemma 1: ranges are independent) so that a long run reports its progress
-            bounds = [0] + [1 << b for b in range(8, 40) if (1 << b) < g.n] + [g.n]
-            for i in range(len(bounds) - 1):
-                v.count_range(G, 4, out4, bounds[i], bounds[i + 1], accumulate=i > 0, stream=stream)
-                if timing is not None:
-                    stream.synchronize()
-                    kt = v.kernel_times(G)
-                    hub_ms += max(0.0, kt[1])
-                    khub += max(0.0, kt[2])
-                    log(f"[bench] ranks [{bounds[i]}, {bounds[i + 1]}) done")
-        else:
-            v.count34(G, out3, out4, stream=stream)
-        if timing is not None:
-            timing[1].record(stream)
-            hub_ms_steps.append(hub_ms)
-            khub_ms_steps.append(khub)
-        return G
-
-    for w in range(args.warmup):
-        G = step()
-        torch.cuda.synchronize()
-        log(f"[bench] warmup {w} done")
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-    graphs = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        graphs.append(step(events[k]))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
-    log(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step, count call {kernel_ms:.2f} ms")
-
-    if not only4 or undirected:   # the hub path's own events, recorded by the library in every timed step
-        hub_ms_steps = [v.kernel_times(Gk)[1] for Gk in graphs]
-        khub_ms_steps = [v.kernel_times(Gk)[2] for Gk in graphs]
-    G = graphs[-1]
-    sc = v.shape_counts(G)
-    pc = v.profile_counters(G)
-    hub_ms = float(np.mean(hub_ms_steps))
-    khub_ms = float(np.mean(khub_ms_steps))
-    T3_hub = int(pc[32]) + int(pc[33])
-    T4_hub = int(pc[34] + pc[35] + pc[36] + pc[37])
-    c3 = out3.sum(dim=0).cpu().numpy()
-    c4 = out4.sum(dim=0).cpu().numpy()
-    T3 = int(c3.sum()) // 3
-    T4 = int(c4.sum()) // 4
-    assert (c3 % 3 == 0).all() and (c4 % 4 == 0).all(), "column sums must be multiples of k"
-    assert only4 or sc["(1,1)"] + sc["(1,2)"] == T3, "k=3 shape counts disagree with the column sums"
-    assert sc["(3,0,0)"] + sc["(2,1,0)"] + sc["(1,2,0)"] + sc["(1,1,1)"] == T4, "k=4 shapes disagree"
-
-    # Roofline of the dominant work, the hub path (k_hub, then the (1,2,0) slot-pair kernel
-    # and the (1,1,1) end-vertex pass, which finish the same roots' sets): every k-set costs
-    # at least its index assembly (one placement per vertex pair), one class lookup and one
-    # increment per member: k=4: 6 + 1 + 4 = 11 integer ops; k=3: 3 + 1 + 3 = 7.  Achieved =
-    # those ops over the sets the hub path enumerated, per second of the path (HIP events
-    # recorded by the library on the count's stream around its launches, every timed step).
-    alg_ops = 11.0 * T4_hub + 7.0 * T3_hub
-    achieved_tops = alg_ops / (hub_ms * 1e-3) / 1e12 if hub_ms > 0 else 0.0
-    # compulsory HBM bytes: CSR read once + both outputs written once
-    csr_bytes = 4.0 * (g.n + 1) + 4.0 * 2 * G.pairs
-    out_bytes = 8.0 * g.n * (13 + 199)
-    result = {
-        "metric": "connected 4-vertex subgraphs counted/s (bit-exact)",
-        "value": T4 / (ms_step * 1e-3),
-        "unit": "4-vertex sets/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS.get(args.workload, args.workload), "n": g.n, "arcs": G.arcs,
-                   "pairs": G.pairs, "max_degree": G.max_deg, "sets3": T3, "sets4": T4,
-                   "shapes": sc},
-        "count_call_ms": kernel_ms,
-        "sets3_per_s": T3 / (ms_step * 1e-3),
-        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": hub_traffic(args.workload),
-                     "kernel": "hub path: k_hub + k_slot_pairs + k_pull111", "kernel_ms": hub_ms,
-                     "k_hub_ms": khub_ms, "sets4": T4_hub, "sets3": T3_hub,
-                     "ops_per_set": {"k4": 11, "k3": 7},
-                     "hbm_compulsory_frac": (csr_bytes + out_bytes) / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-    }
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline ...")
-        gb = g
-        if undirected:   # the oracle counts the digraph with every arc reciprocated (that is G_U)
-            gb = gg.Graph(g.n, np.concatenate([g.src, g.dst]), np.concatenate([g.dst, g.src]), "chunglu_u")
-        result["cpu_baseline"] = cpu_baseline(gb, args.cpu_budget)
+        result, graphs = bench_batch(args, torch, gg, v)
+        if not args.no_serve:
+            log_hi = 4.5 if args.serve_log_hi is None else args.serve_log_hi
+            result["serve"] = run_serve(v, torch, gg, args.serve_graphs, args.serve_requests, log_hi, (0.5, 0.8))
+        if not args.no_cpu_baseline:
+            log("[bench] cpu baseline ...")
+            result["cpu_baseline"] = cpu_baseline_batch(graphs, args.cpu_budget)
+    elif args.workload == "serve":
+        log_hi = 6.0 if args.serve_log_hi is None else args.serve_log_hi
+        s = run_serve(v, torch, gg, args.serve_graphs, args.serve_requests, log_hi, (0.5, 0.8))
+        r8 = s["runs"][-1]
+        result = {"metric": "served k-vertex sets counted/s (bit-exact); p50/p99 latency",
+                  "value": r8["sets_per_s"], "unit": "sets/s", "n_gpus": 1, "steps": args.serve_requests,
+                  "warmup": 0, "ms_per_step": r8["wall_s"] * 1e3 / args.serve_requests, "higher_is_better": True,
+                  "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+                  "config": {"workload": WORKLOADS["serve"]}, "serve": s}
+    else:
+        result = bench_graph(args, torch, gg, v)
     if args.calibrate_copy:
         calibrate_copy(torch)
-    print(json.dumps(result), flush=True)
-
-
-# HBM bytes per hub path (k_hub + k_slot_pairs + k_pull111, one dispatch each) from
-# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this bench (KiB per dispatch, summed
-# over the three), scaled by the readings of a 1 GiB copy (FETCH_SIZE reads half of the
-# copied bytes: factor 2.0; WRITE_SIZE factor 1.0).  Valid only for the kernel sources
-# they were taken with: any change to them reports null.
-HUB_COUNTER_SOURCES = ["paper_2201_11655_amd/csrc/count_hub.hip", "paper_2201_11655_amd/csrc/vdmc_internal.h",
-                       "paper_2201_11655_amd/csrc/motif_device.h"]
-HUB_COUNTERS = {     # workload -> counters of one hub path (profiles/k_hub_chunglu_1M_hbm_counters.md)
-    "chunglu": {"sources_sha256": "20056985c95cddf163e7bbced068e4a4a33403ff8eefa1b61e2107e44d3e0e0e",
-                # k_hub 144789320.5 + k_slot_pairs 376542914.4 + k_pull111 8617253.5
-                "fetch_kib": 529949488.4,
-                # k_hub 319016586.9 + k_slot_pairs 112844055.0 + k_pull111 2898616.1
-                "write_kib": 434759258.0},
-}
-FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
-
-
-def hub_sources_sha256():
-    import hashlib
-    h = hashlib.sha256()
-    for f in HUB_COUNTER_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
-def hub_traffic(workload):
-    rec = HUB_COUNTERS.get(workload)
-    if rec is None or rec["sources_sha256"] != hub_sources_sha256():
-        return None
-    return 1024.0 * (FETCH_FACTOR * rec["fetch_kib"] + WRITE_FACTOR * rec["write_kib"])
-
-
-def calibrate_copy(torch):
-    """Reference readings for the HBM byte counters: a plain 1 GiB device-to-device copy,
-    then an elementwise kernel that reads 1 GiB and writes 1 GiB (b = 2 a)."""
-    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-    b = torch.empty_like(a)
-    torch.cuda.synchronize()
-    b.copy_(a)
-    torch.cuda.synchronize()
-    torch.mul(a, 2.0, out=b)
-    torch.cuda.synchronize()
-    log("[bench] calibration copy and scale of 1 GiB done")
-
-
-def _alu_roofline(T4, T3, ms):
-    alg_ops = 11.0 * T4 + 7.0 * T3
-    achieved = alg_ops / (ms * 1e-3) / 1e12
-    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "ops_per_set": {"k4": 11, "k3": 7}}
-
-
-def bench_batch(args, torch, gg, v):
-    """4096 small graphs, k=4: one batched launch vs per-graph launches, same outputs."""
-    t0 = time.perf_counter()
-    graphs = gg.er_batch(4096, 20, 500, 2.0, 8.0, seed=3)
-    log(f"[bench] generated 4096 graphs ({sum(g.n for g in graphs)} vertices) in {time.perf_counter() - t0:.1f}s")
-    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
-    outs = [torch.empty((g.n, 199), dtype=torch.int64, device="cuda") for g in graphs]
-    t0 = time.perf_counter()
-    v.tune(Gs, 4)
-    choice = v.tuned_choice(Gs, 4)
-    log(f"[bench] tuned in {time.perf_counter() - t0:.1f}s: {choice}")
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        for w in range(max(1, args.warmup)):
-            v.count_batch(Gs, 4, outs=outs, stream=stream)        # captures the HIP graph
-            for G, o in zip(Gs, outs):                             # warms per-graph bins
-                v.count(G, 4, o, stream=stream)
-        stream.synchronize()
-        # batched
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev[0].record(stream)
-        for _ in range(args.steps):
-            v.count_batch(Gs, 4, outs=outs, stream=stream)
-        ev[1].record(stream)
-        stream.synchronize()
-        ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
-        dev_ms_batch = ev[0].elapsed_time(ev[1]) / args.steps
-        sums = [int(o.sum().item()) for o in outs]
-        T4 = sum(sums) // 4
-        ref = [o.clone() for o in outs]
-        # per-graph launches, back to back on one stream
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            for G, o in zip(Gs, outs):
-                v.count(G, 4, o, stream=stream)
-        stream.synchronize()
-        ms_single = (time.perf_counter() - t0) * 1e3 / args.steps
-        # per-graph, host-synchronised after every graph
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for G, o in zip(Gs, outs):
-            v.count(G, 4, o, stream=stream)
-            stream.synchronize()
-        ms_sync = (time.perf_counter() - t0) * 1e3
-        same = all(bool(torch.equal(a, b)) for a, b in zip(ref, outs))
-    assert same, "batched and per-graph outputs differ"
-    result = {
-        "metric": "connected 4-vertex subgraphs counted/s (bit-exact), batched",
-        "value": T4 / (ms_batch * 1e-3), "unit": "4-vertex sets/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": WORKLOADS["batch4096"], "graphs": 4096, "sets4": T4,
-                   "vertices": sum(g.n for g in graphs)},
-        "per_graph_ms": ms_single, "per_graph_sync_ms": ms_sync,
-        "per_graph_value": T4 / (ms_single * 1e-3), "batched_speedup": ms_single / ms_batch,
-        "batched_device_ms": dev_ms_batch, "batched_equals_per_graph": same, "tuned": choice,
-        "roofline": _alu_roofline(T4, 0, dev_ms_batch),
-    }
-    print(json.dumps(result), flush=True)
-
-
-def bench_serve(args, torch, gg, v):
-    """Continuous-batching server over a pool of resident graphs; Poisson arrivals."""
-    rng = np.random.default_rng(5)
-    t0 = time.perf_counter()
-    pool = gg.serve_pool(args.serve_graphs, 2.0, 6.0, 2.0, 10.0, seed=5)
-    log(f"[bench] generated pool of {len(pool)} graphs (max n {max(g.n for g in pool)}) "
-        f"in {time.perf_counter() - t0:.1f}s")
-    Gs = [v.Graph(g.n, g.src, g.dst) for g in pool]
-    nreq = args.serve_requests
-    picks = rng.integers(0, len(pool), size=nreq)
-    ks = rng.choice([3, 4], size=nreq)
-    # capacity: mean service time of one request alone (warm bins on the way)
-    service = []
-    alone = {}
-    for gi in range(len(pool)):
-        for k in (3, 4):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            o = v.count(Gs[gi], k)
-            torch.cuda.synchronize()
-            service.append(time.perf_counter() - t)
-            alone[(gi, k)] = o
-    mean_service = float(np.mean(service))
-    lam = 0.5 / mean_service                     # arrivals at half the one-at-a-time capacity
-    gaps = rng.exponential(1.0 / lam, size=nreq)
-    srv = v.Server(mem_budget_bytes=64 << 30, max_inflight=8)
-    outs = [torch.empty((pool[gi].n, v.num_classes(int(k))), dtype=torch.int64, device="cuda")
-            for gi, k in zip(picks, ks)]
-    torch.cuda.synchronize()
-    ids = []
-    t_start = time.perf_counter()
-    t_next = t_start
-    for i in range(nreq):
-        t_next += gaps[i]
-        while time.perf_counter() < t_next:
-            time.sleep(min(1e-4, max(0.0, t_next - time.perf_counter())))
-        ids.append(srv.submit(Gs[picks[i]], int(ks[i]), outs[i]))
-    for rid in ids:
-        srv.wait(rid)
-    wall = time.perf_counter() - t_start
-    st = srv.stats()
-    srv.close()
-    mismatch = sum(int(not torch.equal(outs[i], alone[(int(picks[i]), int(ks[i]))])) for i in range(nreq))
-    assert mismatch == 0, f"{mismatch} served results differ from the alone results"
-    result = {
-        "metric": "served k-vertex sets counted/s (bit-exact); p50/p99 latency",
-        "value": st["sets"] / wall, "unit": "sets/s", "n_gpus": 1, "steps": nreq, "warmup": 0,
-        "ms_per_step": wall * 1e3 / nreq, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": WORKLOADS["serve"], "pool_graphs": len(pool), "requests": nreq,
-                   "arrival_rate_per_s": lam, "mean_alone_service_ms": mean_service * 1e3},
-        "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3, "req_per_s": st["req_per_s"],
-        "served_equals_alone": True,
-    }
     print(json.dumps(result), flush=True)
 
 
