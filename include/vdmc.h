@@ -28,6 +28,12 @@
  *     ORIGINAL vertex id and column = class id; the caller owns them.
  *   - Input arcs may contain self-loops (dropped) and repeated arcs (merged):
  *     the paper works on a simple graph (Sec. 4.1).
+ *   - A graph is immutable after build and may be counted from several host threads
+ *     and streams at once: the device work of every call on a graph (count, count34,
+ *     count_range, count_undirected, count_edges, count_batch, served requests) is
+ *     ordered after the previous call's on that graph, whatever its stream, so each
+ *     output is that of the call alone.  Calls on different graphs overlap freely.
+ *     Output buffers of calls in flight must not alias.
  */
 #ifndef VDMC_H
 #define VDMC_H
@@ -150,12 +156,17 @@ vdmc_status vdmc_free_graph(vdmc_graph g);
 /*
  * Per-vertex k-motif counts (Sec. 4.2): out is a caller-owned DEVICE buffer of
  * n * vdmc_num_classes(k) uint64, fully overwritten (zeroed first, inside the call).
- * Every connected k-set is enumerated exactly once from its lowest-rank vertex
- * (Lemma 1) along the BFS shapes of Lemma 2 under the rules of Lemmas 3-4, encoded
- * (Sec. 4.1), mapped to its class and credited to its k vertices.
+ * Every connected k-set is visited exactly once, from its lowest-rank vertex (Lemma 1)
+ * along the BFS shapes of Lemma 2 under the rules of Lemmas 3-4: one lane assembles
+ * its index (Sec. 4.1), looks up its class and credits the class to its k vertices
+ * (vdmc_shape_counts reports the sets visited per shape).
  * k in {3, 4}; k = 5 gives UNSUPPORTED, other k INVALID_ARG.  A graph with n < k
  * gives an all-zero matrix.  Asynchronous on `stream`; `out` must not be in use by
- * another call.  Uses library-owned scratch allocated at the graph's first count.
+ * another call.  The first count on a graph (and the first after a change of its hub
+ * threshold) bins its roots and synchronises `stream`; the hub path's scratch is
+ * allocated then and kept with the graph.  Roots with at most 2048 higher neighbours
+ * in graphs whose largest degree is at most 2048 (and n < 2^26) can take the hub
+ * path; every other root is counted by the per-root kernel.
  */
 vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream);
 
@@ -182,31 +193,22 @@ vdmc_status vdmc_set_hub_threshold(vdmc_graph g, int32_t min_higher);
  * each root's neighbourhood feeds both. */
 vdmc_status vdmc_count34(vdmc_graph g, uint64_t* out3, uint64_t* out4, void* stream);
 
-/* Enumeration statistics of the last count on this graph (host, synchronous):
- * number of k-sets per BFS shape, in the order k=3: (1,1), (1,2); k=4: (3,0,0),
- * (2,1,0), (1,2,0), (1,1,1).  shape_counts: 6 entries. */
+/* Sets visited one by one by the last count on this graph (host; waits for it), per BFS
+ * shape in the order k=3: (1,1), (1,2); k=4: (3,0,0), (2,1,0), (1,2,0), (1,1,1).  Every
+ * visit is one set whose index was assembled, class looked up and vertices credited, so
+ * the k=4 entries add up to the number of 4-sets.  shape_counts: 6 entries. */
 vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
 
-/* Diagnostic counters of the last count on this graph (host, synchronous): entries 0-5
- * are the shape counts above; entries 8-15 the device cycles the hub workgroups spent
- * per phase (stage, local matrix, k=3 pairs, depth-2 groups, (3,0,0), group shapes,
- * (1,2,0), flush), summed over workgroups; entries 16-21 the numbers of sets that took
- * the direct (unaggregated) crediting path per shape; entries 22-23 the wave time spent
- * in the wave-per-group loop and in the lane-per-group loop (single-parent groups with a
- * short row); entries 24-27 the wave time spent inside the wave-per-group loop on
- * (2,1,0) sets, (2,1,0) sets with both parents, (1,1,1) paths and the rest (all times
- * 100 MHz ticks summed over waves); entries 28-31 work counts: depth-2 groups of the
- * wave-per-group loop, 64-entry chunks of their rows, their parents, (2,1,0) parents whose
- * local list the whole wave walks; entries 32-37 the part of the shape counts enumerated by the hub kernel.
- * Copies min(n, 40) entries. */
+/* The graph's counters of the last count (host; waits for it): entries 0-5 are the
+ * shape counts above, 6-7 are zero.  Copies min(n, 8) entries. */
 vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n);
 
 /* Device time of the kernels of the last count call on this graph, from events recorded
  * on the count's stream around the launches (host; waits for those events):
- * ms_out[0] the per-set kernel over the light roots, ms_out[1] the hub path (the hub
- * kernel, then for k = 4 the (1,2,0) slot-pair kernel and the (1,1,1) end-vertex pass),
- * ms_out[2] the hub kernel alone; -1 for a part that the call did not launch.  ms_out:
- * n floats, caller-owned; the first min(n, 3) are written. */
+ * ms_out[0] the per-root kernel over the light roots, ms_out[1] the hub path (the hub
+ * kernel, then for k = 4 the long-slot kernel), ms_out[2] the hub kernel alone; -1 for a
+ * part that the call did not launch.  ms_out: n floats, caller-owned; the first
+ * min(n, 3) are written. */
 vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out, int32_t n);
 
 /*
@@ -235,18 +237,26 @@ vdmc_status vdmc_tuned_choice(const vdmc_graph* gs, int32_t num, int32_t k, int3
 
 /*
  * Serving: a request loop over resident graphs.
- *   vdmc_serve_create: mem_budget_bytes caps the device memory held by in-flight
- *     requests' scratch and outputs that the server allocates; max_inflight caps the
- *     number of requests on the GPU at once.
+ *   vdmc_serve_create: mem_budget_bytes caps the device memory that the server allocates
+ *     for requests in flight (the hub-path scratch of a request's graph; outputs belong to
+ *     the caller and are not counted); max_inflight caps the number of requests on the
+ *     GPU at once.  The server also holds small fixed buffers per stream slot.
  *   vdmc_serve_submit: queue a count of graph g for k into the caller's DEVICE buffer
- *     out (n x C uint64); returns a request id.  REJECTED if the request can never fit
- *     the budget.  Requests are admitted in arrival order as slots and memory free up;
- *     admitted requests run concurrently on the device.
- *   vdmc_serve_poll: non-blocking; *done = 1 when the request's output is complete.
- *   vdmc_serve_wait: blocks up to timeout_us (< 0: no limit); TIMEOUT if not done.
+ *     out (n x C uint64); returns a request id at once (nothing is allocated).  Requests
+ *     are admitted in arrival order as slots and memory free up: a request on a graph
+ *     the whole-graph kernel takes needs no memory and is fused with others of the same
+ *     k; any other needs its graph's hub scratch, allocated at admission inside the
+ *     budget and freed at completion.  A request whose scratch cannot fit now waits; one
+ *     that can never fit fails with REJECTED (at submit when the graph's size is already
+ *     known, else at admission, reported by poll/wait).  Admitted requests run
+ *     concurrently on the device.
+ *   vdmc_serve_poll: non-blocking; *done = 1 when the request's output is complete; the
+ *     request's own error status if it failed.
+ *   vdmc_serve_wait: blocks up to timeout_us (< 0: no limit); TIMEOUT if not done; the
+ *     request's own status (REJECTED, DEVICE, ...) if it failed.
  *   vdmc_serve_stats: latency percentiles (submit -> completion seen), throughput and
  *     number of k-sets counted by completed requests.
- *   vdmc_serve_destroy: waits for in-flight requests, then frees the server.
+ *   vdmc_serve_destroy: waits for running requests, cancels queued ones, frees the server.
  */
 typedef struct {
     uint64_t mem_budget_bytes;
@@ -261,6 +271,13 @@ vdmc_status vdmc_serve_wait(vdmc_server s, uint64_t req_id, int64_t timeout_us);
 vdmc_status vdmc_serve_stats(vdmc_server s, double* p50_us, double* p99_us, double* req_per_s,
                              uint64_t* sets);
 vdmc_status vdmc_serve_destroy(vdmc_server s);
+
+/* Request-loop counters (host, synchronous): counters[0] submitted, [1] admitted,
+ * [2] completed, [3] rejected (could never fit the budget, or cancelled by destroy),
+ * [4] failed on the device, [5] times the head of the queue waited for memory,
+ * [6] queue depth now, [7] largest queue depth, [8] server-allocated bytes in flight now,
+ * [9] largest bytes in flight.  Copies min(n, 10) entries. */
+vdmc_status vdmc_serve_counters(vdmc_server s, uint64_t* counters, int32_t n);
 
 #ifdef __cplusplus
 }

@@ -220,6 +220,7 @@ bool same_signature(const Plan& p, const vdmc_graph* gs, int num, int k, uint64_
 void run_plan(Plan& p, hipStream_t st, bool use_graph) {
     const int k3 = p.k == 3, k4 = p.k == 4;
     const int num = (int)p.graphs.size();
+    GraphUse use(p.graphs, st);   // ordered after earlier work on these graphs
     const SmallArgs sa = small_args_of(p);
     auto launch = [&] {
         launch_batch(args_of(p), &sa, p.small_grid, p.small_lds, p.cfg.small_variant, p.cfg.variant, k3, k4, num,
@@ -320,7 +321,10 @@ void count_batch_impl(const vdmc_graph_s* const* gs_in, int32_t num, int32_t k, 
     if (num == 0) return;
     (void)class_tables();
     for (int i = 0; i < num; i++)
-        if (!small_eligible(gs[i]->n, 2 * gs[i]->pairs, k)) ensure_bins(gs[i], st);
+        if (!small_eligible(gs[i]->n, 2 * gs[i]->pairs, k)) {
+            std::lock_guard<std::mutex> lock(gs[i]->mu);
+            ensure_bins(gs[i], st);
+        }
     std::lock_guard<std::mutex> lock(g_plan_mu);
     load_tune_cache_once();
     TuneChoice cfg;

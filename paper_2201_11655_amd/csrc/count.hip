@@ -424,10 +424,7 @@ void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t st) {
 void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st,
                   int64_t rank_lo, int64_t rank_hi, bool zero) {
     const ClassTables& t = class_tables();
-    {
-        std::lock_guard<std::mutex> lock(g->mu);
-        ensure_bins(g, st);
-    }
+    ensure_bins(g, st);   // the caller holds g->mu (GraphUse)
     if (zero) {
         if (k3) launch_fill_u64(out3, (size_t)g->n * kClasses3, 0, st);
         if (k4) launch_fill_u64(out4, (size_t)g->n * kClasses4, 0, st);
@@ -518,6 +515,7 @@ vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream) {
                      "k must be 3 or 4");
         VDMC_REQUIRE(out != nullptr || g->n == 0, VDMC_ERR_INVALID_ARG, "out is NULL");
         VDMC_HIP(hipSetDevice(g->device));
+        vdmc::GraphUse use(g, vdmc::as_stream(stream));
         vdmc::launch_count(g, k == 3, k == 4, k == 3 ? out : nullptr, k == 4 ? out : nullptr,
                            vdmc::as_stream(stream));
     });
@@ -542,6 +540,7 @@ vdmc_status vdmc_count34(vdmc_graph g, uint64_t* out3, uint64_t* out4, void* str
         VDMC_REQUIRE((out3 && out4) || g->n == 0, VDMC_ERR_INVALID_ARG, "out3/out4 is NULL");
         VDMC_REQUIRE(out3 != out4 || g->n == 0, VDMC_ERR_INVALID_ARG, "out3 and out4 alias");
         VDMC_HIP(hipSetDevice(g->device));
+        vdmc::GraphUse use(g, vdmc::as_stream(stream));
         vdmc::launch_count(g, 1, 1, out3, out4, vdmc::as_stream(stream));
     });
 }
@@ -550,7 +549,8 @@ vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n) {
     return vdmc::guarded([&] {
         VDMC_REQUIRE(g != nullptr && counters != nullptr && n >= 0, VDMC_ERR_INVALID_ARG, "bad argument");
         VDMC_HIP(hipSetDevice(g->device));
-        VDMC_HIP(hipDeviceSynchronize());
+        std::lock_guard<std::mutex> lock(g->mu);
+        vdmc::wait_graph(g);
         const int k = n < vdmc::kStatSlots ? n : vdmc::kStatSlots;
         VDMC_HIP(hipMemcpy(counters, g->stats, k * sizeof(uint64_t), hipMemcpyDeviceToHost));
     });
@@ -560,6 +560,7 @@ vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out, int32_t n) {
     return vdmc::guarded([&] {
         VDMC_REQUIRE(g != nullptr && ms_out != nullptr && n >= 0, VDMC_ERR_INVALID_ARG, "bad argument");
         VDMC_HIP(hipSetDevice(g->device));
+        std::lock_guard<std::mutex> lock(g->mu);
         float t[3] = {-1.0f, -1.0f, -1.0f};
         if (g->timed_light) {
             VDMC_HIP(hipEventSynchronize(g->ev[1]));
@@ -584,6 +585,7 @@ vdmc_status vdmc_count_range(vdmc_graph g, int32_t k, uint64_t* out, int64_t ran
         VDMC_REQUIRE(rank_begin >= 0 && rank_begin <= rank_end, VDMC_ERR_INVALID_ARG, "bad rank range");
         VDMC_REQUIRE((flags & ~(uint32_t)VDMC_ACCUMULATE) == 0, VDMC_ERR_INVALID_ARG, "unknown flags");
         VDMC_HIP(hipSetDevice(g->device));
+        vdmc::GraphUse use(g, vdmc::as_stream(stream));
         vdmc::launch_count(g, k == 3, k == 4, k == 3 ? out : nullptr, k == 4 ? out : nullptr,
                            vdmc::as_stream(stream), rank_begin, rank_end, !(flags & VDMC_ACCUMULATE));
     });
@@ -593,7 +595,8 @@ vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts) {
     return vdmc::guarded([&] {
         VDMC_REQUIRE(g != nullptr && shape_counts != nullptr, VDMC_ERR_INVALID_ARG, "NULL argument");
         VDMC_HIP(hipSetDevice(g->device));
-        VDMC_HIP(hipDeviceSynchronize());
+        std::lock_guard<std::mutex> lock(g->mu);
+        vdmc::wait_graph(g);
         VDMC_HIP(hipMemcpy(shape_counts, g->stats, vdmc::kShapes * sizeof(uint64_t), hipMemcpyDeviceToHost));
     });
 }

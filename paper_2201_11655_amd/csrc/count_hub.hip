@@ -863,21 +863,44 @@ int hub_workgroups() {
 
 }  // namespace
 
-void free_hub(vdmc_graph_s* g) {
-    (void)hipFree(g->light);
-    (void)hipFree(g->hubs);
+void free_hub_scratch(vdmc_graph_s* g) {
+    if (!g->hub_scratch && !g->hub_tasks) return;
+    wait_graph(g);
     (void)hipFree(g->hub_scratch);
-    (void)hipFree(g->hub_queue);
-    (void)hipFree(g->hub_s2);
     (void)hipFree(g->hub_tasks);
-    g->light = g->hubs = nullptr;
     g->hub_scratch = nullptr;
-    g->hub_queue = nullptr;
-    g->hub_s2 = nullptr;
     g->hub_tasks = nullptr;
     g->hub_scratch_bytes = 0;
+}
+
+void free_hub(vdmc_graph_s* g) {
+    wait_graph(g);
+    free_hub_scratch(g);
+    (void)hipFree(g->light);
+    (void)hipFree(g->hubs);
+    (void)hipFree(g->hub_queue);
+    (void)hipFree(g->hub_s2);
+    g->light = g->hubs = nullptr;
+    g->hub_queue = nullptr;
+    g->hub_s2 = nullptr;
+    g->hub_scratch_need = 0;
     g->nhub = g->nlight = 0;
     g->bins_hub_min = -1;
+}
+
+size_t hub_scratch_need(const vdmc_graph_s* g) { return g->nhub > 0 ? g->hub_scratch_need : 0; }
+
+void ensure_hub_scratch(vdmc_graph_s* g) {
+    if (g->nhub == 0 || g->hub_scratch) return;
+    const size_t wg_bytes = g->hub_layout[0] * sizeof(uint32_t) * (size_t)hub_workgroups();
+    VDMC_HIP(hipMalloc(&g->hub_scratch, wg_bytes));
+    const hipError_t e = hipMalloc(&g->hub_tasks, (size_t)g->hub_task_cap * sizeof(uint2));
+    if (e != hipSuccess) {
+        (void)hipFree(g->hub_scratch);
+        g->hub_scratch = nullptr;
+        VDMC_HIP(e);
+    }
+    g->hub_scratch_bytes = wg_bytes + (size_t)g->hub_task_cap * sizeof(uint2);
 }
 
 void ensure_edge_hash(vdmc_graph_s* g, hipStream_t st) {
@@ -898,7 +921,7 @@ void ensure_edge_hash(vdmc_graph_s* g, hipStream_t st) {
 void ensure_bins(vdmc_graph_s* g, hipStream_t st) {
     const int hub_min = g->hub_min;
     if (g->bins_hub_min == hub_min) return;
-    free_hub(g);
+    free_hub(g);   // waits for running work on the old bins
     const int64_t nr = g->nroots;
     std::vector<void*> tmp;
     auto alloc = [&](size_t bytes) {
@@ -987,16 +1010,13 @@ void ensure_bins(vdmc_graph_s* g, hipStream_t st) {
         while (tcap < 2 * s2cap + 64) tcap <<= 1;
         const size_t words = (DMAX + 2) + s2cap + (s2cap & 1) + 2 * s2cap + s2cap + 2 * tcap;
         const size_t wg_words = (words + 63) & ~(size_t)63;
-        g->hub_scratch_bytes = wg_words * sizeof(uint32_t) * (size_t)wgs;
-        VDMC_HIP(hipMalloc(&g->hub_scratch, g->hub_scratch_bytes));
         g->hub_layout[0] = wg_words;
         g->hub_layout[1] = s2cap;
         g->hub_layout[2] = tcap;
         // long-slot tasks: at most one per (hub root, slot)
         const size_t ntask = (size_t)std::max<unsigned long long>(dsum, 1ull);
-        VDMC_HIP(hipMalloc(&g->hub_tasks, ntask * sizeof(uint2)));
         g->hub_task_cap = (uint32_t)std::min<size_t>(ntask, 0xFFFFFFFFu);
-        g->hub_scratch_bytes += ntask * sizeof(uint2);
+        g->hub_scratch_need = wg_words * sizeof(uint32_t) * (size_t)wgs + (size_t)g->hub_task_cap * sizeof(uint2);
     }
     g->bins_hub_min = hub_min;
 }
@@ -1004,6 +1024,7 @@ void ensure_bins(vdmc_graph_s* g, hipStream_t st) {
 void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t st,
                 uint32_t rank_lo, uint32_t rank_hi, const hipEvent_t* around) {
     if (g->nhub == 0) return;
+    ensure_hub_scratch(g);
     const ClassTables& t = class_tables();
     HubArgs a;
     a.off = g->off;

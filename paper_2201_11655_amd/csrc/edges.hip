@@ -129,6 +129,7 @@ vdmc_status vdmc_count_edges(vdmc_graph g, int32_t k, uint64_t* out, void* strea
         VDMC_REQUIRE(k == 3 || k == 4, k == 5 ? VDMC_ERR_UNSUPPORTED : VDMC_ERR_INVALID_ARG, "k must be 3 or 4");
         VDMC_REQUIRE(out != nullptr || g->pairs == 0, VDMC_ERR_INVALID_ARG, "out is NULL");
         VDMC_HIP(hipSetDevice(g->device));
+        vdmc::GraphUse use(g, vdmc::as_stream(stream));
         vdmc::launch_count_edges(g, k, out, vdmc::as_stream(stream));
     });
 }
@@ -138,6 +139,7 @@ vdmc_status vdmc_edge_list(vdmc_graph g, int32_t* lo, int32_t* hi) {
         VDMC_REQUIRE(g != nullptr, VDMC_ERR_INVALID_ARG, "graph is NULL");
         VDMC_REQUIRE((lo && hi) || g->pairs == 0, VDMC_ERR_INVALID_ARG, "lo/hi is NULL");
         VDMC_HIP(hipSetDevice(g->device));
+        std::lock_guard<std::mutex> lock(g->mu);
         vdmc::ensure_edge_index(g, nullptr);
         if (g->pairs == 0) return;
         VDMC_HIP(hipMemcpy(lo, g->elo, g->pairs * sizeof(int32_t), hipMemcpyDeviceToHost));

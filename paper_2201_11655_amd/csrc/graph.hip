@@ -428,7 +428,14 @@ vdmc_status vdmc_free_graph(vdmc_graph g) {
         VDMC_HIP(hipGetDevice(&cur));
         VDMC_HIP(hipSetDevice(g->device));
         vdmc::invalidate_batch_plans(g);
+        {
+            std::lock_guard<std::mutex> lock(g->mu);
+            vdmc::wait_graph(g);
+        }
         vdmc::free_graph_arrays(g);
+        g->last.reset();
+        for (auto e : g->ev)
+            if (e) (void)hipEventDestroy(e);
         delete g;
         VDMC_HIP(hipSetDevice(cur));
     });

@@ -183,6 +183,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
         for (uint32_t i = tid; i < n * W; i += BS) sBits[i] = 0u;
         for (uint32_t i = tid; i < n * NC; i += BS) sCnt[i] = 0u;
         for (size_t i = tid; i < (size_t)n * C; i += BS) G.out[i] = 0ull;
+        if (tid < (uint32_t)kShapes) G.stats[tid] = 0ull;   // this launch's visit counters of the graph
         __syncthreads();
         for (uint32_t r = tid; r < n; r += BS) {
             const uint32_t lo = sOff[r], hi = sOff[r + 1];

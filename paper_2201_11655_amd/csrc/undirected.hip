@@ -75,8 +75,9 @@ vdmc_status vdmc_count_undirected(vdmc_graph g, int32_t k, uint64_t* out, void* 
         VDMC_HIP(hipSetDevice(g->device));
         if (g->n == 0) return;
         const auto cls = vdmc::undirected_list(k);
-        if (!g->utmp) VDMC_HIP(hipMalloc(&g->utmp, (size_t)g->n * vdmc::kClasses4 * sizeof(uint64_t)));
         const hipStream_t st = vdmc::as_stream(stream);
+        vdmc::GraphUse use(g, st);
+        if (!g->utmp) VDMC_HIP(hipMalloc(&g->utmp, (size_t)g->n * vdmc::kClasses4 * sizeof(uint64_t)));
         vdmc::launch_count(g, k == 3, k == 4, k == 3 ? g->utmp : nullptr, k == 4 ? g->utmp : nullptr, st);
         vdmc::Cols c{};
         for (size_t j = 0; j < cls.size(); j++) c.c[j] = cls[j];

@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -101,6 +103,7 @@ struct DeviceScratch {
     void* ptr = nullptr;
     size_t bytes = 0;
 };
+struct DoneEvent;
 
 }  // namespace vdmc
 
@@ -138,6 +141,7 @@ struct vdmc_graph_s {
     uint32_t* hub_s2 = nullptr;      // per hub root: entries of its slots' rows above it
     void* hub_tasks = nullptr;       // long-slot tasks (hub index, slot)
     uint32_t hub_task_cap = 0;
+    size_t hub_scratch_need = 0;     // bytes of hub_scratch + hub_tasks for the current bins
     unsigned long long* ehash = nullptr;   // edge hash: every pair of the graph, 2^ehash_bits slots
     uint32_t ehash_bits = 0;
     uint32_t* epid = nullptr;    // per edge-hash slot: output row of the pair (per-edge counts)
@@ -148,9 +152,63 @@ struct vdmc_graph_s {
     // hub kernel (created at the first count)
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     bool timed_light = false, timed_hub = false;
+    // end of the last call's device work on this graph (every call's work is ordered after
+    // the previous call's, whatever the streams)
+    std::shared_ptr<vdmc::DoneEvent> last;
 };
 
 namespace vdmc {
+// An event that ends the device work of one call (shared by the graphs the call used).
+struct DoneEvent {
+    hipEvent_t e = nullptr;
+    DoneEvent() { VDMC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+    ~DoneEvent() {
+        if (e) (void)hipEventDestroy(e);
+    }
+    DoneEvent(const DoneEvent&) = delete;
+    DoneEvent& operator=(const DoneEvent&) = delete;
+};
+
+// One call's use of one or more graphs.  Holds the graphs' mutexes (in address order)
+// while the call enqueues its work (the host-side state: bins, scratch, timing events),
+// makes the call's stream wait for the end of the previous calls' work on those graphs
+// (whatever their streams), and records one event at the end of this call's work.
+// Concurrent calls on a graph are therefore serialised on the device, and each one's
+// result is that of the call alone.
+struct GraphUse {
+    std::vector<vdmc_graph_s*> gs;
+    hipStream_t st;
+    std::vector<std::unique_lock<std::mutex>> locks;
+    GraphUse(vdmc_graph_s* g, hipStream_t s) : GraphUse(std::vector<vdmc_graph_s*>{g}, s) {}
+    GraphUse(std::vector<vdmc_graph_s*> graphs, hipStream_t s) : gs(std::move(graphs)), st(s) {
+        std::sort(gs.begin(), gs.end());
+        gs.erase(std::unique(gs.begin(), gs.end()), gs.end());
+        locks.reserve(gs.size());
+        for (auto* g : gs) locks.emplace_back(g->mu);
+        std::vector<DoneEvent*> waited;
+        for (auto* g : gs) {
+            DoneEvent* e = g->last.get();
+            if (e && std::find(waited.begin(), waited.end(), e) == waited.end()) {
+                VDMC_HIP(hipStreamWaitEvent(st, e->e, 0));
+                waited.push_back(e);
+            }
+        }
+    }
+    ~GraphUse() {
+        try {
+            auto ev = std::make_shared<DoneEvent>();
+            if (hipEventRecord(ev->e, st) == hipSuccess)
+                for (auto* g : gs) g->last = ev;
+        } catch (...) {
+        }
+    }
+    GraphUse(const GraphUse&) = delete;
+    GraphUse& operator=(const GraphUse&) = delete;
+};
+// waits (host) for the end of the last call's work on g; the caller holds g->mu
+inline void wait_graph(vdmc_graph_s* g) {
+    if (g->last) VDMC_HIP(hipEventSynchronize(g->last->e));
+}
 // one graph as seen by the per-set kernels
 struct GraphView {
     const uint32_t* off;
@@ -219,6 +277,9 @@ void launch_count(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out
 void launch_fill_u64(uint64_t* p, size_t n, uint64_t value, hipStream_t stream);
 // hub path (count_hub.hip)
 void ensure_bins(vdmc_graph_s* g, hipStream_t stream);   // for g->hub_min; caller holds g->mu
+size_t hub_scratch_need(const vdmc_graph_s* g);           // bytes ensure_hub_scratch allocates (after ensure_bins)
+void ensure_hub_scratch(vdmc_graph_s* g);                 // caller holds g->mu
+void free_hub_scratch(vdmc_graph_s* g);                   // caller holds g->mu; waits for the graph's work
 void ensure_edge_hash(vdmc_graph_s* g, hipStream_t stream);    // count_hub.hip
 void ensure_edge_index(vdmc_graph_s* g, hipStream_t stream);   // edges.hip
 void launch_count_edges(vdmc_graph_s* g, int k, uint64_t* out, hipStream_t stream);   // count.hip

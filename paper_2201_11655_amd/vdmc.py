@@ -23,7 +23,7 @@ SYMBOLS = [
     "vdmc_edge_list", "vdmc_count_edges",
     "vdmc_count_batch", "vdmc_tune", "vdmc_tuned_choice", "vdmc_set_hub_threshold",
     "vdmc_serve_create", "vdmc_serve_submit", "vdmc_serve_poll", "vdmc_serve_wait",
-    "vdmc_serve_stats", "vdmc_serve_destroy",
+    "vdmc_serve_stats", "vdmc_serve_destroy", "vdmc_serve_counters",
 ]
 
 STATUS = {
@@ -84,6 +84,7 @@ def load():
         "vdmc_serve_wait": ([p, u64, i64], i32),
         "vdmc_serve_stats": ([p, p, p, p, p], i32),
         "vdmc_serve_destroy": ([p], i32),
+        "vdmc_serve_counters": ([p, p, i32], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -370,7 +371,13 @@ class Server:
         sets = ctypes.c_uint64()
         _check(load().vdmc_serve_stats(self._h, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(rps),
                                        ctypes.byref(sets)))
-        return {"p50_us": p50.value, "p99_us": p99.value, "req_per_s": rps.value, "sets": sets.value}
+        out = {"p50_us": p50.value, "p99_us": p99.value, "req_per_s": rps.value, "sets": sets.value}
+        c = np.zeros(10, np.uint64)
+        _check(load().vdmc_serve_counters(self._h, _np_ptr(c), 10))
+        names = ["submitted", "admitted", "completed", "rejected", "failed", "deferred_by_memory",
+                 "queue_depth", "max_queue_depth", "bytes_in_flight", "max_bytes_in_flight"]
+        out.update({k: int(x) for k, x in zip(names, c)})
+        return out
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -162,13 +162,23 @@ def test_serve_alone_equals_mix(v):
     srv.close()
 
 
+def _hub_graphs(count):
+    # Chung-Lu graphs of the benchmark recipe at n = 2,000: every one has hub roots, so a
+    # request on it needs the hub path's scratch
+    return [gg.chung_lu(2000, 16800, 2.1, 45.0, 0.2, 90, (77, i)) for i in range(count)]
+
+
 def test_serve_admission_and_errors(v):
     import torch
-    g = gg.config_graph("er1000")
-    G = v.Graph(g.n, g.src, g.dst)
-    out = torch.empty((g.n, 199), dtype=torch.int64, device="cuda")
-    tiny = v.Server(mem_budget_bytes=1 << 16, max_inflight=2)   # smaller than one output
+    hubs = _hub_graphs(1)[0]
+    G = v.Graph(hubs.n, hubs.src, hubs.dst)
+    out = torch.empty((hubs.n, 199), dtype=torch.int64, device="cuda")
+    tiny = v.Server(mem_budget_bytes=1 << 16, max_inflight=2)   # smaller than the hub scratch
+    rid = tiny.submit(G, 4, out)             # the graph's bins are built at its first admission
     with pytest.raises(v.VdmcError) as e:
+        tiny.wait(rid)
+    assert e.value.name == "REJECTED"
+    with pytest.raises(v.VdmcError) as e:    # bins known now: refused at submit
         tiny.submit(G, 4, out)
     assert e.value.name == "REJECTED"
     with pytest.raises(v.VdmcError) as e:
@@ -177,18 +187,72 @@ def test_serve_admission_and_errors(v):
     with pytest.raises(v.VdmcError) as e:
         tiny.submit(G, 5, out)
     assert e.value.name == "UNSUPPORTED"
+    c = tiny.stats()
+    assert c["rejected"] == 1 and c["completed"] == 0
     tiny.close()
-    # a budget that holds exactly one request at a time still completes every request
-    one = 1000 * 199 * 8 + 1000 * 13 * 8
-    srv = v.Server(mem_budget_bytes=one, max_inflight=4)
-    want4, _ = oracle.count(g.n, g.src, g.dst, 4)
-    outs = [torch.empty((g.n, 199), dtype=torch.int64, device="cuda") for _ in range(5)]
-    ids = [srv.submit(G, 4, o) for o in outs]
+
+
+def test_serve_budget_holds_requests_back(v):
+    """The memory budget, not max_inflight, limits what runs: the budget fits the hub
+    scratch of one request at a time, so later requests wait for memory; every result
+    equals the alone count and the server never holds more than the budget."""
+    import torch
+    graphs = _hub_graphs(4)
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
+    alone = [_np(v.count(G, 4)).copy() for G in Gs]
+    # the alone counts keep each graph's scratch: served requests start from new graphs;
+    # one probe server per graph measures the scratch a request on it needs
+    needs = []
+    for g in graphs:
+        G = v.Graph(g.n, g.src, g.dst)
+        probe = v.Server(mem_budget_bytes=1 << 40, max_inflight=1)
+        o = torch.empty((g.n, 199), dtype=torch.int64, device="cuda")
+        probe.wait(probe.submit(G, 4, o))
+        needs.append(probe.stats()["max_bytes_in_flight"])
+        probe.close()
+    assert min(needs) > 0 and max(needs) < 2 * min(needs)
+    budget = (max(needs) + 2 * min(needs)) // 2   # fits any one request, never two
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
+    srv = v.Server(mem_budget_bytes=budget, max_inflight=8)
+    outs = [torch.empty((g.n, 199), dtype=torch.int64, device="cuda") for g in graphs]
+    ids = [srv.submit(G, 4, o) for G, o in zip(Gs, outs)]
     for rid in ids:
         srv.wait(rid)
-    for o in outs:
-        assert (_np(o) == want4).all()
+    st = srv.stats()
     srv.close()
+    for o, a in zip(outs, alone):
+        assert (_np(o) == a).all()
+    assert st["completed"] == 4 and st["deferred_by_memory"] > 0
+    assert st["max_bytes_in_flight"] <= budget
+
+
+def test_concurrent_counts_on_one_graph(v):
+    """One graph counted on two streams at once (and inside a batch on a third): every
+    call's work is ordered after the previous call's on the graph, so each output equals
+    the oracle."""
+    import torch
+    g = gg.config_graph("chunglu_2000")
+    want3, _ = oracle.count(g.n, g.src, g.dst, 3)
+    want4, _ = oracle.count(g.n, g.src, g.dst, 4)
+    G = v.Graph(g.n, g.src, g.dst)
+    small = gg.er_directed(300, 0.02, (5, 5))
+    Gs = v.Graph(small.n, small.src, small.dst)
+    want_s, _ = oracle.count(small.n, small.src, small.dst, 4)
+    s1, s2, s3 = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(3):
+        a4 = torch.full((g.n, 199), -1, dtype=torch.int64, device="cuda")
+        b4 = torch.full((g.n, 199), -1, dtype=torch.int64, device="cuda")
+        b3 = torch.full((g.n, 13), -1, dtype=torch.int64, device="cuda")
+        c4 = torch.full((g.n, 199), -1, dtype=torch.int64, device="cuda")
+        cs = torch.full((small.n, 199), -1, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        v.count(G, 4, a4, stream=s1)
+        v.count34(G, b3, b4, stream=s2)
+        v.count_batch([Gs, G], 4, outs=[cs, c4], stream=s3)
+        torch.cuda.synchronize()
+        assert (_np(a4) == want4).all(), f"rep {rep}: stream 1"
+        assert (_np(b4) == want4).all() and (_np(b3) == want3).all(), f"rep {rep}: stream 2"
+        assert (_np(c4) == want4).all() and (_np(cs) == want_s).all(), f"rep {rep}: batch"
 
 
 def test_serve_destroy_with_work_in_flight(v):
