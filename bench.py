@@ -232,6 +232,8 @@ def bench_batch(args, torch, gg, v):
         visited = sum(visited_sets(v, G, 4) for G in Gs)
         assert visited == T4, f"sets visited one by one ({visited}) != sets counted ({T4})"
         ref = [o.clone() for o in outs]
+        if args.no_per_graph:
+            return _batch_result(args, graphs, Gs, T4, visited, ms_batch, dev_ms, choice, None, None, None), graphs
         # per-graph launches, back to back on one stream
         reps = max(1, args.steps // 10)
         torch.cuda.synchronize()
@@ -251,8 +253,16 @@ def bench_batch(args, torch, gg, v):
         same = all(bool(torch.equal(a, b)) for a, b in zip(ref, outs))
     assert same, "batched and per-graph outputs differ"
     log(f"[bench] per-graph {ms_single:.1f} ms, host-synced {ms_sync:.1f} ms")
+    return _batch_result(args, graphs, Gs, T4, visited, ms_batch, dev_ms, choice, ms_single, ms_sync, same), graphs
+
+
+def _batch_result(args, graphs, Gs, T4, visited, ms_batch, dev_ms, choice, ms_single, ms_sync, same):
     out_bytes = 8.0 * 199 * sum(g.n for g in graphs)
     csr_bytes = sum(4.0 * (G.n + 1) + 8.0 * G.pairs for G in Gs)
+    per_graph = None
+    if ms_single is not None:
+        per_graph = {"sets_per_s": T4 / (ms_single * 1e-3), "ms": ms_single, "host_synced_ms": ms_sync,
+                     "host_synced_sets_per_s": T4 / (ms_sync * 1e-3)}
     result = {
         "metric": "connected 4-vertex subgraphs counted/s (bit-exact), batched vs per-graph; p99",
         "value": T4 / (ms_batch * 1e-3), "unit": "4-vertex sets/s", "n_gpus": 1, "steps": args.steps,
@@ -261,13 +271,12 @@ def bench_batch(args, torch, gg, v):
         "config": {"workload": WORKLOADS["batch4096"], "graphs": 4096, "vertices": sum(g.n for g in graphs),
                    "arcs": int(sum(G.arcs for G in Gs)), "sets4": T4, "sets_visited": visited},
         "batched": {"sets_per_s": T4 / (ms_batch * 1e-3), "ms": ms_batch, "device_ms": dev_ms, "tuned": choice},
-        "per_graph": {"sets_per_s": T4 / (ms_single * 1e-3), "ms": ms_single, "host_synced_ms": ms_sync,
-                      "host_synced_sets_per_s": T4 / (ms_sync * 1e-3)},
-        "batched_speedup": ms_single / ms_batch, "batched_equals_per_graph": same,
+        "per_graph": per_graph,
+        "batched_speedup": ms_single / ms_batch if ms_single else None, "batched_equals_per_graph": same,
         "roofline": roofline("batch4096", T4, dev_ms, "k_small (whole-graph kernel) + k_batch_zero",
                              csr_bytes + out_bytes),
     }
-    return result, graphs
+    return result
 
 
 def run_serve(v, torch, gg, pool_graphs, requests, log_hi, rates, seed=5):
@@ -439,6 +448,8 @@ def main():
     ap.add_argument("--serve-log-hi", type=float, default=None,
                     help="pool n up to 10^this (default: 4.5 in the default run, 6 for --workload serve)")
     ap.add_argument("--no-serve", action="store_true", help="default run without the serving leg")
+    ap.add_argument("--no-per-graph", action="store_true",
+                    help="default run without the per-graph comparison (for profiler runs)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")

@@ -73,7 +73,7 @@ struct HubArgs {
     uint32_t* scratch;           // per workgroup: locoff | locnbr | nodes (u64) | groups | keys | heads
     size_t wg_words;
     uint32_t s2cap, tcap;
-    uint2* tasks;                // long-slot tasks: (hub index, slot)
+    uint2* tasks;                // long-slot tasks: (hub index, the slot's entry in r's row)
     uint32_t task_cap;
 };
 
@@ -229,7 +229,31 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         const uint32_t TS = 1u << tbits;
         // ---- phase A: stage the slots, the lengths of their rows above r, clear counters
         uint16_t* H = (uint16_t*)L.U;   // slot hash (phases A-B)
-        for (uint32_t i = tid; i < D; i += HT) L.P[i] = A.adj[s0 + i];
+        // Slots ordered by their arc code to r, by rank within a code.  Any fixed order of
+        // N+(r) enumerates each set once ((3,0,0) takes a < b < c, (2,1,0) hangs c under
+        // its lowest parent); this one gives the lanes of a step over consecutive slots
+        // the same code to r, so that sets without extra pairs share their class.
+        if (wid == 0) {
+            const unsigned long long below = (1ull << lane) - 1ull;
+            uint32_t n1 = 0, n2 = 0;
+            for (uint32_t q0 = 0; q0 < D; q0 += 64) {
+                const uint32_t k = q0 + lane < D ? (A.adj[s0 + q0 + lane] & 3u) : 0u;
+                n1 += (uint32_t)__popcll(__ballot(k == 1u));
+                n2 += (uint32_t)__popcll(__ballot(k == 2u));
+            }
+            uint32_t o[4] = {0u, 0u, n1, n1 + n2};
+            for (uint32_t q0 = 0; q0 < D; q0 += 64) {
+                const bool in = q0 + lane < D;
+                const uint32_t e = in ? A.adj[s0 + q0 + lane] : 0u, k = e & 3u;
+                const unsigned long long m1 = __ballot(in && k == 1u), m2 = __ballot(in && k == 2u),
+                                         m3 = __ballot(in && k == 3u);
+                const unsigned long long mk = k == 1u ? m1 : (k == 2u ? m2 : m3);
+                if (in) L.P[o[k] + (uint32_t)__popcll(mk & below)] = e;
+                o[1] += (uint32_t)__popcll(m1);
+                o[2] += (uint32_t)__popcll(m2);
+                o[3] += (uint32_t)__popcll(m3);
+            }
+        }
         for (uint32_t i = tid; i < SHASH / 2; i += HT) L.U[i] = 0u;
         for (uint32_t i = tid; i < kClasses3; i += HT) L.root3[i] = 0ull;
         for (uint32_t i = tid; i < kClasses4; i += HT) L.root4[i] = 0ull;
@@ -264,7 +288,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             uint32_t nloc = 0;
             if (A.k4 && hi - lo > SHORT && lane == 0) {
                 const uint32_t t = atomicAdd(&A.cursor[1], 1u);
-                if (t < A.task_cap) A.tasks[t] = make_uint2(hi_idx, x);
+                if (t < A.task_cap) A.tasks[t] = make_uint2(hi_idx, L.P[x]);
             }
             for (uint32_t q0 = lo; q0 < hi; q0 += 64) {
                 const uint32_t q = q0 + lane;
@@ -661,7 +685,7 @@ __global__ __launch_bounds__(HT) void k_long_slots(HubArgs A) {
             __syncthreads();
             if (tid == 0) L.root = r;
         }
-        const uint32_t ea = L.P[task.y];
+        const uint32_t ea = task.y;   // the slot's entry in r's row
         const uint32_t va = ea >> 2, ra = ea & 3u;
         const uint32_t hi = A.off[va + 1], lo = first_above(A.adj, A.off[va], hi, r);
         for (uint32_t i = tid; i < BLOOM_WORDS; i += HT) L.bloomC[i] = 0u;

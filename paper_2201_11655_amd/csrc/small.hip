@@ -20,9 +20,10 @@
 //     credited (Sec. 4.2).  Credits go to LDS counters (k = 3: all 13 classes; k = 4:
 //     the 25 tree classes, which hold ~96% of the 4-sets of sparse graphs); the other
 //     classes go straight to the graph's output with workgroup-scope atomics (the
-//     output block of a graph belongs to one workgroup for the whole launch).  Credits
-//     shared by the lanes of a wave (the root of a run of items) are summed by ballots
-//     before they reach LDS.
+//     output block of a graph belongs to one workgroup for the whole launch).  Members
+//     that all lanes of a wave step share (the root, the depth-1 vertex of a run of
+//     depth-2 items, the loop's current vertex) are credited once per class present in
+//     the step, grouped by ballots, instead of once per lane.
 // The LDS counters are added to the output once per graph.  u32 counters cannot
 // overflow: a vertex of a graph with n <= kSmallMaxN lies in fewer than 2^32 k-sets.
 #include "motif_device.h"
@@ -36,19 +37,6 @@ __device__ __forceinline__ uint32_t lane_of() { return threadIdx.x & 63u; }
 // wg-scope atomic add on a graph's output (the block is owned by this workgroup)
 __device__ __forceinline__ void out_add(unsigned long long* p, unsigned long long v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Adds 1 at base[key] for every lane that reaches this call with active set, one LDS
-// atomic per distinct key among those lanes.
-__device__ __forceinline__ void wave_add(uint32_t* base, uint32_t key, bool active) {
-    unsigned long long m = __ballot(active);
-    while (m) {
-        const uint32_t leader = (uint32_t)(__ffsll((long long)m) - 1);
-        const uint32_t k0 = (uint32_t)__shfl((int)key, (int)leader, 64);
-        const unsigned long long same = __ballot(active && key == k0) & m;
-        if (lane_of() == leader) atomicAdd(&base[k0], (uint32_t)__popcll(same));
-        m &= ~same;
-    }
 }
 
 // exclusive prefix sum of a[0..len) in place (LDS), returns the total; every thread of
@@ -134,15 +122,38 @@ struct SmallCredit {
         const uint32_t s = comp[cls];
         return s == 0xFFu ? NC : s;
     }
-    // v credited with cls; `shared` = the same v for (most of) the wave's active lanes
-    __device__ __forceinline__ void add(uint32_t v, uint32_t cls, uint32_t s, bool shared) const {
-        const bool lds = s < NC;
-        if (shared) {
-            wave_add(cnt, v * NC + s, lds);
-        } else if (lds) {
-            atomicAdd(&cnt[v * NC + s], 1u);
+    __device__ __forceinline__ void add_n(uint32_t v, uint32_t cls, uint32_t n) const {
+        const uint32_t s = slot(cls);
+        if (s < NC) atomicAdd(&cnt[v * NC + s], n);
+        else out_add(&out[(size_t)perm[v] * C + cls], (unsigned long long)n);
+    }
+    // One set per active lane, of class cls, credited to the NS members in sv, which the
+    // lanes often share (the root, and the members fixed by the wave's loop position): a
+    // member common to all active lanes gets each class present once, with the lanes'
+    // count; a member that differs between lanes is added lane by lane.
+    template <int NS>
+    __device__ __forceinline__ void shared(uint32_t cls, const uint32_t (&sv)[NS], bool active) const {
+        const unsigned long long act = __ballot(active);
+        if (!act) return;
+        const int first = __ffsll((long long)act) - 1;
+        uint32_t common = 0;   // wave-uniform bit mask of the members all active lanes share
+        for (int i = 0; i < NS; i++)
+            if (__ballot(active && sv[i] != (uint32_t)__shfl((int)sv[i], first, 64)) == 0ull) common |= 1u << i;
+        if (common) {
+            unsigned long long m = act;
+            while (m) {
+                const uint32_t leader = (uint32_t)(__ffsll((long long)m) - 1);
+                const uint32_t k0 = (uint32_t)__shfl((int)cls, (int)leader, 64);
+                const unsigned long long grp = __ballot(active && cls == k0) & m;
+                if (lane_of() == leader)
+                    for (int i = 0; i < NS; i++)
+                        if ((common >> i) & 1u) add_n(sv[i], k0, (uint32_t)__popcll(grp));
+                m &= ~grp;
+            }
         }
-        if (!lds) out_add(&out[(size_t)perm[v] * C + cls], 1ull);
+        if (active)
+            for (int i = 0; i < NS; i++)
+                if (!((common >> i) & 1u)) add_n(sv[i], cls, 1u);
     }
 };
 
@@ -232,20 +243,17 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
             const uint32_t ab = L.code(a, b);
             if (K == 3) {
                 const uint32_t cls = sTable[motif_index3(ra, rb, ab)];
-                const uint32_t s = cr.slot(cls);
-                cr.add(r, cls, s, true);
-                cr.add(a, cls, s, false);
-                cr.add(b, cls, s, true);
+                const uint32_t sv[2] = {r, b};
+                cr.shared(cls, sv, true);
+                cr.add_n(a, cls, 1u);
                 shp[0]++;
             } else {
                 for (uint32_t l = j + 1; l < d; l++) {
                     const uint32_t c = P[l] >> 2, rc = P[l] & 3u;
                     const uint32_t cls = sTable[motif_index4(ra, rb, rc, ab, L.code(a, c), L.code(b, c))];
-                    const uint32_t s = cr.slot(cls);
-                    cr.add(r, cls, s, true);
-                    cr.add(a, cls, s, false);
-                    cr.add(b, cls, s, false);
-                    cr.add(c, cls, s, false);
+                    const uint32_t sv[3] = {r, b, c};   // lanes share j, hence b and c
+                    cr.shared(cls, sv, true);
+                    cr.add_n(a, cls, 1u);
                     shp[0]++;
                 }
             }
@@ -263,10 +271,9 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
             if (L.adjacent(r, c)) continue;   // c adjacent to r: depth 1, not 2
             if (K == 3) {
                 const uint32_t cls = sTable[motif_index3(ra, 0u, ac)];
-                const uint32_t s = cr.slot(cls);
-                cr.add(r, cls, s, true);
-                cr.add(a, cls, s, true);
-                cr.add(c, cls, s, false);
+                const uint32_t sv[2] = {r, a};
+                cr.shared(cls, sv, true);
+                cr.add_n(c, cls, 1u);
                 shp[1]++;
                 continue;
             }
@@ -277,11 +284,9 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t bc = L.code(b, c);
                 if (bc && jb < ia) continue;
                 const uint32_t cls = sTable[motif_index4(ra, rb, 0u, L.code(a, b), ac, bc)];
-                const uint32_t s = cr.slot(cls);
-                cr.add(r, cls, s, true);
-                cr.add(a, cls, s, true);
-                cr.add(b, cls, s, false);
-                cr.add(c, cls, s, false);
+                const uint32_t sv[3] = {r, a, b};   // lanes share (r, a) and the loop position
+                cr.shared(cls, sv, true);
+                cr.add_n(c, cls, 1u);
                 shp[1]++;
             }
             // (1,2,0): a second child c2 > c of a, not adjacent to r
@@ -289,11 +294,10 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t c2 = sAdj[t2] >> 2, ac2 = sAdj[t2] & 3u;
                 if (L.adjacent(r, c2)) continue;
                 const uint32_t cls = sTable[motif_index4(ra, 0u, 0u, ac, ac2, L.code(c, c2))];
-                const uint32_t s = cr.slot(cls);
-                cr.add(r, cls, s, true);
-                cr.add(a, cls, s, true);
-                cr.add(c, cls, s, false);
-                cr.add(c2, cls, s, false);
+                const uint32_t sv[2] = {r, a};
+                cr.shared(cls, sv, true);
+                cr.add_n(c, cls, 1u);
+                cr.add_n(c2, cls, 1u);
                 shp[2]++;
             }
             // (1,1,1): path r - a - c - e, e not adjacent to r (nor equal to a) nor to a
@@ -301,11 +305,10 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t e = sAdj[te] >> 2, ce = sAdj[te] & 3u;
                 if (L.adjacent(r, e) || L.adjacent(a, e)) continue;
                 const uint32_t cls = sTable[motif_index4(ra, 0u, 0u, ac, 0u, ce)];
-                const uint32_t s = cr.slot(cls);
-                cr.add(r, cls, s, true);
-                cr.add(a, cls, s, true);
-                cr.add(c, cls, s, false);
-                cr.add(e, cls, s, false);
+                const uint32_t sv[2] = {r, a};
+                cr.shared(cls, sv, true);
+                cr.add_n(c, cls, 1u);
+                cr.add_n(e, cls, 1u);
                 shp[3]++;
             }
         }
