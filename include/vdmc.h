@@ -221,6 +221,28 @@ vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out, int32_t n);
 vdmc_status vdmc_count_batch(const vdmc_graph* gs, int32_t num, int32_t k,
                              uint64_t* const* outs, void* stream);
 
+/* Per-device set-up: builds the class tables and resolves the device address of the
+ * allocation-free entry point's scratch array on the current device.  Idempotent; may
+ * allocate.  Call it on each device before vdmc_count_batch_noalloc there. */
+vdmc_status vdmc_init(void);
+
+/*
+ * vdmc_count_batch without any allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid it).
+ * Same arguments and results as vdmc_count_batch, for graphs that the whole-graph kernel
+ * takes (n <= 1024 and the graph's CSR, adjacency bitmap and counters fit one
+ * workgroup's LDS; UNSUPPORTED otherwise) and at most 8192 graphs per call
+ * (INVALID_ARG beyond).  Requires vdmc_init on the current device (INVALID_ARG
+ * otherwise).  The graph descriptors and the work cursor live in a fixed device array
+ * of ~384 KiB per device, held until the process ends; the call allocates nothing,
+ * issues no memset and no host-to-device copy (descriptors travel as kernel arguments),
+ * and is asynchronous on `stream`.  Every call on a device shares that array: calls that
+ * overlap on one device race, and the caller orders them, also against other calls on
+ * the same graphs (this entry point skips the per-graph ordering of the others).
+ */
+vdmc_status vdmc_count_batch_noalloc(const vdmc_graph* gs, int32_t num, int32_t k, uint64_t* const* outs,
+                                     void* stream);
+
 /* Picks the batch launch parameters (workgroup size of the whole-graph kernel; threads
  * per root, workgroups per CU and roots per cursor step of the root table) by timing
  * every candidate on the given batch (median of 3 runs).  The choice is kept for batches

@@ -13,6 +13,8 @@ from .vdmc import (  # noqa: F401
     count34,
     count_range,
     count_batch,
+    count_batch_noalloc,
+    init,
     count_edges,
     count_undirected,
     edge_list,

@@ -22,6 +22,7 @@ SYMBOLS = [
     "vdmc_kernel_times", "vdmc_num_classes_undirected", "vdmc_undirected_classes", "vdmc_count_undirected",
     "vdmc_edge_list", "vdmc_count_edges",
     "vdmc_count_batch", "vdmc_tune", "vdmc_tuned_choice", "vdmc_set_hub_threshold",
+    "vdmc_init", "vdmc_count_batch_noalloc",
     "vdmc_serve_create", "vdmc_serve_submit", "vdmc_serve_poll", "vdmc_serve_wait",
     "vdmc_serve_stats", "vdmc_serve_destroy", "vdmc_serve_counters",
 ]
@@ -78,6 +79,8 @@ def load():
         "vdmc_tune": ([p, i32, i32, ctypes.c_char_p], i32),
         "vdmc_tuned_choice": ([p, i32, i32, p], i32),
         "vdmc_set_hub_threshold": ([p, i32], i32),
+        "vdmc_init": ([], i32),
+        "vdmc_count_batch_noalloc": ([p, i32, i32, p, p], i32),
         "vdmc_serve_create": ([p, p], i32),
         "vdmc_serve_submit": ([p, p, i32, p, p], i32),
         "vdmc_serve_poll": ([p, u64, p], i32),
@@ -316,6 +319,21 @@ def count_batch(graphs, k: int, outs=None, stream=None):
     ps = (ctypes.c_void_p * max(1, len(graphs)))(*[o.data_ptr() for o in outs])
     _check(lib.vdmc_count_batch(ctypes.cast(hs, ctypes.c_void_p), len(graphs), int(k),
                                 ctypes.cast(ps, ctypes.c_void_p), _stream_handle(stream)))
+    return outs
+
+
+def init():
+    """Per-device set-up of the library on the current device (see vdmc_init)."""
+    _check(load().vdmc_init())
+
+
+def count_batch_noalloc(graphs, k: int, outs, stream=None):
+    """vdmc_count_batch_noalloc: the batched count into caller-owned outputs, no allocation."""
+    lib = load()
+    hs = (ctypes.c_void_p * max(1, len(graphs)))(*[g.handle.value for g in graphs])
+    ps = (ctypes.c_void_p * max(1, len(graphs)))(*[o.data_ptr() for o in outs])
+    _check(lib.vdmc_count_batch_noalloc(ctypes.cast(hs, ctypes.c_void_p), len(graphs), int(k),
+                                        ctypes.cast(ps, ctypes.c_void_p), _stream_handle(stream)))
     return outs
 
 
