@@ -1,4 +1,4 @@
-"""CPU oracle for per-vertex directed 3-/4-motif counts.
+"""CPU oracle for per-vertex directed 3-, 4- and 5-motif counts.
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
 baseline leg of ``bench.py`` may import this package.  It shares no code with the GPU
@@ -15,9 +15,10 @@ Contents
   tiny graphs, with its own canonicalisation.  It pins the C oracle.
 
 Pins (tests/test_oracle_*.py): Fig. 1 (53 -> 30), the CSR example of Sec. 4.2, the
-class counts 13/199 and the labelled counts 54/3834 (known sequence values), closed
-forms on cliques, transitive tournaments, cycles and stars, brute force on tiny
-graphs, the column-sum invariant and the G(n,p) expectation of Sec. 7, Eq. 4.
+class counts 13/199/9364 and the labelled counts 54/3834/1027080 (known sequence
+values; k = 5 is the extension Sec. 11 names), closed forms on cliques, transitive
+tournaments, cycles and stars, brute force on tiny graphs (k = 5 keyed by minimal
+index), the column-sum invariant and the G(n,p) expectation of Sec. 7, Eq. 4.
 """
 from __future__ import annotations
 
@@ -32,7 +33,7 @@ _SRC = os.path.join(_HERE, "vdmc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-NUM_CLASSES = {3: 13, 4: 199}
+NUM_CLASSES = {3: 13, 4: 199, 5: 9364}
 
 
 def build(force: bool = True) -> str:

@@ -13,6 +13,7 @@ Class ids are the minimal indices of connected motifs in ascending order.
 """
 from __future__ import annotations
 
+import functools
 import itertools
 
 import numpy as np
@@ -66,6 +67,45 @@ def classes(k: int):
     mins = [minimal_index(k, c) for c in range(n_codes)]
     conn = sorted({mins[c] for c in range(n_codes) if weakly_connected(matrix_of(k, c))})
     return mins, conn
+
+
+@functools.lru_cache(maxsize=None)
+def _minimal_index_cached(k: int, code: int) -> int:
+    return minimal_index(k, code)
+
+
+def count_by_code(n: int, src, dst, k: int):
+    """Brute force keyed by the minimal index itself rather than by a class id, so that it
+    needs no table of all 2^(k(k-1)) codes (k = 5 has 2^20): ({min index: uint64[n]}
+    per-vertex counts, {min index: total}), over every connected k-subset."""
+    arcs = set()
+    for u, v in zip(np.asarray(src).tolist(), np.asarray(dst).tolist()):
+        if u != v:
+            arcs.add((u, v))
+    und = [set() for _ in range(n)]
+    for u, v in arcs:
+        und[u].add(v)
+        und[v].add(u)
+    rows, tot = {}, {}
+    for S in itertools.combinations(range(n), k):
+        seen, stack, members = {S[0]}, [S[0]], set(S)
+        while stack:
+            x = stack.pop()
+            for y in und[x]:
+                if y in members and y not in seen:
+                    seen.add(y)
+                    stack.append(y)
+        if len(seen) != k:
+            continue
+        A = [[1 if (i != j and (S[i], S[j]) in arcs) else 0 for j in range(k)] for i in range(k)]
+        m = _minimal_index_cached(k, motif_index(A))
+        if m not in rows:
+            rows[m] = np.zeros(n, np.uint64)
+            tot[m] = 0
+        tot[m] += 1
+        for v in S:
+            rows[m][v] += 1
+    return rows, tot
 
 
 def count(n: int, src, dst, k: int):

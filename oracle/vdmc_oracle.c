@@ -1,5 +1,5 @@
 /*
- * CPU oracle for per-vertex directed 3- and 4-motif counts.
+ * CPU oracle for per-vertex directed 3-, 4- and 5-motif counts.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
  * leg of the benchmark may load this file's library.  It shares no code with the
@@ -35,7 +35,7 @@
 #include <string.h>
 #include <pthread.h>
 
-#define MAXK 4
+#define MAXK 5
 
 /* ---------------------------------------------------------------------------
  * Class table: code -> canonical (minimal) code, connectivity, class id.
@@ -74,19 +74,17 @@ static int next_perm(int *p, int k) {
     return 1;
 }
 
-/* min over all k! relabellings pi of code(B), B[i][j] = A[pi(i)][pi(j)] */
-static uint32_t canon_of(int k, uint32_t code) {
+/* Sets canon[x] = c for every relabelling x of the code c: x = code(B) with
+ * B[i][j] = A[pi(i)][pi(j)] over all k! permutations pi. */
+static void mark_orbit(int k, uint32_t code, uint32_t *canon) {
     int A[MAXK][MAXK], B[MAXK][MAXK], p[MAXK];
     decode(k, code, A);
     for (int i = 0; i < k; i++) p[i] = i;
-    uint32_t best = 0xffffffffu;
     do {
         for (int i = 0; i < k; i++)
             for (int j = 0; j < k; j++) B[i][j] = A[p[i]][p[j]];
-        uint32_t c = encode(k, B);
-        if (c < best) best = c;
+        canon[encode(k, B)] = code;
     } while (next_perm(p, k));
-    return best;
 }
 
 /* connectivity of the underlying undirected graph of the code */
@@ -108,15 +106,26 @@ static int connected_of(int k, uint32_t code) {
 int oracle_class_table(int k, uint32_t *canon, int32_t *cls, uint32_t *class_codes) {
     if (k < 2 || k > MAXK) return -1;
     uint32_t ncode = 1u << (k * (k - 1));
-    for (uint32_t c = 0; c < ncode; c++) canon[c] = canon_of(k, c);
+    /* canon[c] = min over all relabellings of c.  The relabellings of c form its orbit,
+     * and every member of an orbit has the same orbit; scanning codes upwards, the first
+     * member met is the orbit's minimum, and marking the orbit from it settles every
+     * member (k! encodings per orbit rather than per code). */
+    const uint32_t unset = 0xffffffffu;
+    for (uint32_t c = 0; c < ncode; c++) canon[c] = unset;
+    for (uint32_t c = 0; c < ncode; c++)
+        if (canon[c] == unset) mark_orbit(k, c, canon);
     int nc = 0;
     for (uint32_t c = 0; c < ncode; c++)          /* ascending scan = ascending class ids */
         if (canon[c] == c && connected_of(k, c)) class_codes[nc++] = c;
     for (uint32_t c = 0; c < ncode; c++) {
         cls[c] = -1;
         if (!connected_of(k, c)) continue;
-        for (int t = 0; t < nc; t++)
-            if (class_codes[t] == canon[c]) { cls[c] = t; break; }
+        int lo = 0, hi = nc;                       /* class_codes is ascending */
+        while (lo < hi) {
+            int mid = (lo + hi) / 2;
+            if (class_codes[mid] < canon[c]) lo = mid + 1; else hi = mid;
+        }
+        if (lo < nc && class_codes[lo] == canon[c]) cls[c] = lo;
     }
     return nc;
 }
@@ -390,22 +399,40 @@ static int run_esu(const sgraph *g, int k, const int32_t *cls, int ncls, int nth
     return rc;
 }
 
+/* The class table of k (built once per process and kept: 2^20 codes for k = 5); the
+ * caller gets a private copy. */
+static pthread_mutex_t table_mu = PTHREAD_MUTEX_INITIALIZER;
+static int32_t *table_cache[MAXK + 1];
+static int table_ncls[MAXK + 1];
+
 static int table_for(int k, int32_t **cls_out, int *ncls) {
     uint32_t ncode = 1u << (k * (k - 1));
-    uint32_t *canon = (uint32_t *)malloc(sizeof(uint32_t) * ncode);
-    uint32_t *codes = (uint32_t *)malloc(sizeof(uint32_t) * ncode);
-    int32_t *cls = (int32_t *)malloc(sizeof(int32_t) * ncode);
-    *ncls = oracle_class_table(k, canon, cls, codes);
-    free(canon); free(codes);
-    *cls_out = cls;
-    return *ncls > 0 ? 0 : -1;
+    pthread_mutex_lock(&table_mu);
+    if (!table_cache[k]) {
+        uint32_t *canon = (uint32_t *)malloc(sizeof(uint32_t) * ncode);
+        uint32_t *codes = (uint32_t *)malloc(sizeof(uint32_t) * ncode);
+        int32_t *cls = (int32_t *)malloc(sizeof(int32_t) * ncode);
+        int nc = oracle_class_table(k, canon, cls, codes);
+        free(canon); free(codes);
+        if (nc > 0) { table_cache[k] = cls; table_ncls[k] = nc; }
+        else free(cls);
+    }
+    int32_t *copy = NULL;
+    if (table_cache[k]) {
+        copy = (int32_t *)malloc(sizeof(int32_t) * ncode);
+        memcpy(copy, table_cache[k], sizeof(int32_t) * ncode);
+        *ncls = table_ncls[k];
+    }
+    pthread_mutex_unlock(&table_mu);
+    *cls_out = copy;
+    return copy ? 0 : -1;
 }
 
 /* Full per-vertex counts: out[n][ncls] (row = original vertex id) and per-class
  * totals T[ncls] (every k-set once).  Returns 0 on success. */
 int oracle_count(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, int k,
                  int nthreads, uint64_t *out, uint64_t *totals) {
-    if (k != 3 && k != 4) return -3;
+    if (k < 3 || k > MAXK) return -3;
     sgraph g;
     int rc = build_sgraph(n, m, src, dst, &g);
     if (rc) return rc;
@@ -424,7 +451,7 @@ int oracle_count(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, i
  * be the number oracle_graph_size reports, halved. */
 int oracle_count_edges(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, int k,
                        int nthreads, int64_t pairs, uint64_t *out, int32_t *plo, int32_t *phi) {
-    if (k != 3 && k != 4) return -3;
+    if (k < 3 || k > MAXK) return -3;
     sgraph g;
     int rc = build_sgraph(n, m, src, dst, &g);
     if (rc) return rc;
@@ -453,7 +480,7 @@ int oracle_count_edges(int64_t n, int64_t m, const int32_t *src, const int32_t *
  * ESU's vertex order, and only rows[i] is credited. */
 int oracle_count_rows(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, int k,
                       int nthreads, const int32_t *rows, int64_t nrows, uint64_t *out) {
-    if (k != 3 && k != 4) return -3;
+    if (k < 3 || k > MAXK) return -3;
     for (int64_t i = 0; i < nrows; i++)
         if (rows[i] < 0 || rows[i] >= n) return -2;
     sgraph g;

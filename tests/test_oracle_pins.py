@@ -35,7 +35,7 @@ def test_fig1_index_and_minimal_index():
     assert canon[30] == 30 and cls[53] == cls[30] >= 0
 
 
-@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("k", [3, 4, 5])
 def test_class_table_sizes_match_known_enumerations(k):
     """Sizes of the class tables equal the textbook digraph counts (golden file)."""
     ref = {}
@@ -46,10 +46,19 @@ def test_class_table_sizes_match_known_enumerations(k):
     assert len(np.unique(canon)) == ref[k]["all"]
     assert len(codes) == ref[k]["connected"] == oracle.NUM_CLASSES[k]
     assert int((cls >= 0).sum()) == ref[k]["labelled_connected"]
-    # pure-Python table built independently agrees code by code
-    mins, conn = ex.classes(k)
-    assert list(codes) == conn
-    assert list(canon) == mins
+    if k <= 4:
+        # pure-Python table built independently agrees code by code
+        mins, conn = ex.classes(k)
+        assert list(codes) == conn
+        assert list(canon) == mins
+    else:
+        # 2^20 codes are too many for the pure-Python table: a seeded sample of codes, plus
+        # every class representative, checked against it one by one
+        rng = np.random.default_rng(55)
+        sample = set(rng.integers(0, 1 << 20, 600).tolist()) | set(codes[::97].tolist())
+        for c in sorted(sample):
+            assert canon[c] == ex.minimal_index(k, c)
+            assert (cls[c] >= 0) == ex.weakly_connected(ex.matrix_of(k, c))
     # class ids ascend with the canonical code and every code maps to its own class
     assert all(codes[i] < codes[i + 1] for i in range(len(codes) - 1))
     for c in range(1 << (k * (k - 1))):
@@ -125,7 +134,7 @@ def _class_of_matrix(k, A):
     return list(codes).index(ex.minimal_index(k, ex.motif_index(A)))
 
 
-@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("k", [3, 4, 5])
 def test_complete_bidirected(k):
     """K_n with every ordered pair an arc: every k-set is the complete motif, so each
     vertex lies in C(n-1, k-1) of them (cliques: Sec. 7 validation on toy graphs)."""
@@ -139,7 +148,7 @@ def test_complete_bidirected(k):
     assert int(t[cid]) == math.comb(n, k)
 
 
-@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("k", [3, 4, 5])
 def test_transitive_tournament(k):
     """Regular DAG i -> j for i < j: every k-set induces the transitive tournament."""
     n = 10
@@ -150,7 +159,7 @@ def test_transitive_tournament(k):
     assert int(c.sum()) == n * math.comb(n - 1, k - 1)
 
 
-@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("k", [3, 4, 5])
 def test_directed_cycle(k):
     """Directed n-cycle (n > k): the connected k-sets are the n windows of k consecutive
     vertices, each a directed path; every vertex lies in k of them."""
@@ -161,7 +170,7 @@ def test_directed_cycle(k):
     assert (c[:, cid] == k).all() and int(c.sum()) == n * k and int(t.sum()) == n
 
 
-@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("k", [3, 4, 5])
 def test_k_cycle_alone(k):
     """A directed k-cycle on k vertices is one motif; each vertex gets one count."""
     g = gg.special_graph("cycle", k)
@@ -170,7 +179,7 @@ def test_k_cycle_alone(k):
     assert (c[:, cid] == 1).all() and int(c.sum()) == k
 
 
-@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("k", [3, 4, 5])
 @pytest.mark.parametrize("kind", ["outstar", "instar"])
 def test_stars(k, kind):
     """Star with hub 0: the hub lies in C(n-1, k-1) sets, every leaf in C(n-2, k-2)."""
@@ -187,7 +196,7 @@ def test_stars(k, kind):
     assert int(c.sum()) == k * math.comb(n - 1, k - 1)
 
 
-@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("k", [3, 4, 5])
 def test_degenerate_inputs(k):
     """n < k, no arcs, self-loops only, isolated vertices: all-zero rows."""
     c, t = oracle.count(k - 1, np.array([0], np.int32), np.array([1], np.int32), k, threads=1)
@@ -219,6 +228,34 @@ def test_esu_equals_brute_force_small(seed):
         assert (a == b).all() and (ta == tb).all()
 
 
+def _by_code(k, c):
+    """Oracle per-vertex counts keyed by minimal index, as the brute force keys them."""
+    _, _, codes = oracle.class_table(k)
+    cols = np.nonzero(c.sum(axis=0))[0]
+    return {int(codes[j]): c[:, j] for j in cols}
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_esu_equals_brute_force_k5(seed):
+    """k = 5: ESU (C) against the plain definition over all 5-subsets, compared per
+    minimal index (the brute force canonicalises each set it meets by trying all 120
+    relabellings, independently of the oracle's table)."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(5, 11))
+    p = float(rng.uniform(0.15, 0.6))
+    g = gg.er_directed(n, p, (12, seed))
+    src = np.concatenate([g.src, g.src[:2], np.arange(2, dtype=np.int32)])
+    dst = np.concatenate([g.dst, g.dst[:2], np.arange(2, dtype=np.int32)])
+    a, ta = oracle.count(n, src, dst, 5, threads=3)
+    rows, tot = ex.count_by_code(n, src, dst, 5)
+    got = _by_code(5, a)
+    assert sorted(got) == sorted(rows)
+    for m in rows:
+        assert (got[m] == rows[m]).all()
+    _, _, codes = oracle.class_table(5)
+    assert {int(codes[j]): int(ta[j]) for j in np.nonzero(ta)[0]} == tot
+
+
 @pytest.mark.slow
 def test_esu_equals_brute_force_dense_all_classes():
     """G(60, 0.5): 487,635 4-subsets, every one of the 199 classes present."""
@@ -235,13 +272,16 @@ def test_invariants_er1000():
     for k in (3, 4):
         c, t = oracle.count(g.n, g.src, g.dst, k)
         assert (c.sum(axis=0) == k * t).all()
+    g = gg.er_directed(300, 0.012, 8)
+    c, t = oracle.count(g.n, g.src, g.dst, 5)
+    assert (c.sum(axis=0) == 5 * t).all() and t.sum() > 0
 
 
 def test_relabelling_permutes_rows():
     """Renaming the vertices permutes the rows and changes nothing else."""
     g = gg.er_directed(80, 0.06, 5)
     perm = np.random.default_rng(3).permutation(80).astype(np.int32)
-    for k in (3, 4):
+    for k in (3, 4, 5):
         a, _ = oracle.count(80, g.src, g.dst, k)
         b, _ = oracle.count(80, perm[g.src], perm[g.dst], k)
         assert (b[perm] == a).all()
@@ -252,7 +292,7 @@ def test_disjoint_union_concatenates():
     g2 = gg.er_directed(25, 0.2, 2)
     src = np.concatenate([g1.src, g2.src + 30])
     dst = np.concatenate([g1.dst, g2.dst + 30])
-    for k in (3, 4):
+    for k in (3, 4, 5):
         a, _ = oracle.count(30, g1.src, g1.dst, k)
         b, _ = oracle.count(25, g2.src, g2.dst, k)
         u, _ = oracle.count(55, src, dst, k)
@@ -262,7 +302,7 @@ def test_disjoint_union_concatenates():
 def test_rows_mode_equals_full_rows():
     g = gg.er_directed(150, 0.04, 9)
     rows = np.array([0, 3, 77, 149, 3], np.int32)
-    for k in (3, 4):
+    for k in (3, 4, 5):
         full, _ = oracle.count(150, g.src, g.dst, k)
         part = oracle.count_rows(150, g.src, g.dst, k, rows)
         assert (part == full[rows]).all()
@@ -270,7 +310,7 @@ def test_rows_mode_equals_full_rows():
 
 # --------------------------------------------------------------------------- Sec. 7
 
-@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("k", [3, 4, 5])
 def test_er_expectation_eq4(k):
     """Sec. 7, Eq. 4 summed over vertices (each set counted once): for directed G(n,p)
     the expected number of sets in class m is C(n,k) N_Iso(m) p^e (1-p)^(k(k-1)-e),
@@ -280,12 +320,14 @@ def test_er_expectation_eq4(k):
     n, p, R = 40, 0.12, 24
     canon, cls, codes = oracle.class_table(k)
     C = len(codes)
-    n_iso = np.zeros(C)
+    allc = np.arange(1 << (k * (k - 1)), dtype=np.int64)
+    conn = cls >= 0
+    n_iso = np.bincount(cls[conn], minlength=C).astype(np.float64)
+    ones = np.zeros(allc.shape[0], np.int64)
+    for b in range(k * (k - 1)):
+        ones += (allc >> b) & 1
     e = np.zeros(C)
-    for code in range(1 << (k * (k - 1))):
-        if cls[code] >= 0:
-            n_iso[cls[code]] += 1
-            e[cls[code]] = bin(code).count("1")
+    e[cls[conn]] = ones[conn]   # relabelling keeps the arc count, so any member will do
     L = k * (k - 1)
     expect = math.comb(n, k) * n_iso * p ** e * (1 - p) ** (L - e)
     samples = []
@@ -297,7 +339,7 @@ def test_er_expectation_eq4(k):
     mean = S.mean(axis=0)
     sd = S.std(axis=0, ddof=1)
     big = expect >= 10
-    assert big.sum() >= (5 if k == 3 else 20)
+    assert big.sum() >= {3: 5, 4: 20, 5: 40}[k]
     se = np.maximum(sd[big], 1.0) / math.sqrt(R)
     assert (np.abs(mean[big] - expect[big]) < 5 * se).all()
     # pooled small classes
