@@ -1,10 +1,12 @@
 /*
  * vdmc.h -- C ABI of the MI355X (gfx950) per-vertex directed motif counter.
  *
- * The library computes, for every vertex v of a directed graph G and for k = 3
- * or 4, the number of connected k-vertex induced subgraphs ("k-motifs") that
+ * The library computes, for every vertex v of a directed graph G and for k = 3,
+ * 4 or 5, the number of connected k-vertex induced subgraphs ("k-motifs") that
  * contain v, split over the isomorphism classes of k-vertex weakly connected
- * digraphs (13 classes for k = 3, 199 for k = 4).
+ * digraphs (13 classes for k = 3, 199 for k = 4, 9364 for k = 5; 5-vertex motifs
+ * are the extension Sec. 11 names, counted for graphs held whole in one
+ * workgroup's LDS).
  *
  * Definitions (paper: Levinas, Scherz, Louzoun, "BFS based distributed algorithm
  * for parallel local directed sub-graph enumeration"):
@@ -53,7 +55,7 @@ enum {
     VDMC_ERR_INVALID_ARG = 1,   /* bad pointer, size, id or k */
     VDMC_ERR_OUT_OF_MEMORY = 2, /* a device or host allocation failed */
     VDMC_ERR_DEVICE = 3,        /* a HIP runtime call failed */
-    VDMC_ERR_UNSUPPORTED = 4,   /* valid request this library does not implement (e.g. k = 5) */
+    VDMC_ERR_UNSUPPORTED = 4,   /* valid request this library does not implement (e.g. k = 5 on a large graph) */
     VDMC_ERR_BUSY = 5,          /* server has no free slot right now */
     VDMC_ERR_NOT_FOUND = 6,     /* unknown request id */
     VDMC_ERR_REJECTED = 7,      /* request can never fit the server's memory budget */
@@ -74,18 +76,29 @@ enum {
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* vdmc_last_error(void);
 
-/* Number of classes: 13 for k = 3, 199 for k = 4, -1 otherwise. */
+/* Number of classes: 13 for k = 3, 199 for k = 4, 9364 for k = 5, -1 otherwise. */
 int32_t vdmc_num_classes(int32_t k);
 
 /* Minimal motif index (Sec. 4.1, Fig. 1) of every class, ascending by class id.
- * codes_out: host array of vdmc_num_classes(k) entries.  Synchronous. */
+ * codes_out: host array of vdmc_num_classes(k) entries.  k = 3 or 4 (5-vertex
+ * indices have 20 bits: UNSUPPORTED, use vdmc_class_codes_u32).  Synchronous. */
 vdmc_status vdmc_class_codes(int32_t k, uint16_t* codes_out);
 
 /* Class id of every raw motif index: table_out is a host array of 2^(k(k-1))
  * bytes; 0xFF marks a disconnected index.  Built once per device by a kernel that
  * tries all k! relabellings (the "combine isomorphisms once" step, Sec. 2, 4.2).
+ * k = 3 or 4 (k = 5 has 9364 ids: UNSUPPORTED, use vdmc_class_table_u16).
  * Synchronous. */
 vdmc_status vdmc_class_table(int32_t k, uint8_t* table_out);
+
+/* The same two tables for k = 3, 4 or 5 in wider types: codes_out holds
+ * vdmc_num_classes(k) uint32 minimal indices; table_out holds 2^(k(k-1)) uint16 class
+ * ids, 0xFFFF marking a disconnected index (k = 5: 2^20 entries).  The k = 5 table is
+ * built on the device at its first use (three kernels: every code's minimal
+ * relabelling over the 120 permutations, the ascending ids, the table) and kept.
+ * INVALID_ARG for another k.  Synchronous. */
+vdmc_status vdmc_class_codes_u32(int32_t k, uint32_t* codes_out);
+vdmc_status vdmc_class_table_u16(int32_t k, uint16_t* table_out);
 
 /*
  * Build the device graph from arcs src[i] -> dst[i], i < m, vertex ids in [0, n).
@@ -160,7 +173,11 @@ vdmc_status vdmc_free_graph(vdmc_graph g);
  * along the BFS shapes of Lemma 2 under the rules of Lemmas 3-4: one lane assembles
  * its index (Sec. 4.1), looks up its class and credits the class to its k vertices
  * (vdmc_shape_counts reports the sets visited per shape).
- * k in {3, 4}; k = 5 gives UNSUPPORTED, other k INVALID_ARG.  A graph with n < k
+ * k in {3, 4, 5}, other k INVALID_ARG.  k = 5 (n x 9364 output) takes graphs held
+ * whole in one workgroup's LDS -- n <= 512 and 4 (4n + 2 + 2 pairs + n ceil(n/16))
+ * bytes of CSR, id map and 2-bit arc matrix within 161792 -- and gives UNSUPPORTED
+ * for any other (vdmc_count_supported tells which); its sets are visited along the
+ * eight BFS layer shapes of five vertices (vdmc_profile_counters).  A graph with n < k
  * gives an all-zero matrix.  Asynchronous on `stream`; `out` must not be in use by
  * another call.  The first count on a graph (and the first after a change of its hub
  * threshold) bins its roots and synchronises `stream`; the hub path's scratch is
@@ -169,6 +186,11 @@ vdmc_status vdmc_free_graph(vdmc_graph g);
  * path; every other root is counted by the per-root kernel.
  */
 vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream);
+
+/* 1 if vdmc_count(g, k, ...) and vdmc_count_batch with g can run (k = 3, 4: any graph;
+ * k = 5: the LDS bound above), 0 if they give UNSUPPORTED, -1 for a NULL graph or a k
+ * outside 3..5.  Lets a caller skip allocating an n x 9364 output it cannot use. */
+int32_t vdmc_count_supported(vdmc_graph g, int32_t k);
 
 /* The part of vdmc_count contributed by roots whose rank lies in [rank_begin, rank_end):
  * the k-sets whose lowest-rank vertex is in the range (Lemma 1 makes such root ranges
@@ -199,8 +221,11 @@ vdmc_status vdmc_count34(vdmc_graph g, uint64_t* out3, uint64_t* out4, void* str
  * the k=4 entries add up to the number of 4-sets.  shape_counts: 6 entries. */
 vdmc_status vdmc_shape_counts(vdmc_graph g, uint64_t* shape_counts);
 
-/* The graph's counters of the last count (host; waits for it): entries 0-5 are the
- * shape counts above, 6-7 are zero.  Copies min(n, 8) entries. */
+/* The graph's counters of the last count (host; waits for it): after k = 3, 4 entries
+ * 0-5 are the shape counts above, 6-7 are zero; after k = 5 the 8 entries are the sets
+ * visited per BFS layer shape of five vertices, in the order (4) (3,1) (2,2) (2,1,1)
+ * (1,3) (1,2,1) (1,1,2) (1,1,1,1) (layer sizes from the root outwards), adding up to
+ * the number of connected 5-sets.  Copies min(n, 8) entries. */
 vdmc_status vdmc_profile_counters(vdmc_graph g, uint64_t* counters, int32_t n);
 
 /* Device time of the kernels of the last count call on this graph, from events recorded
@@ -217,6 +242,9 @@ vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out, int32_t n);
  * persistent launch whose work tiles come from a device-side cursor; the launch is
  * captured in a HIP graph the first time a batch signature (same graphs, same
  * outputs, same k) is seen and replayed afterwards.  Asynchronous on `stream`.
+ * k = 5: every graph must satisfy vdmc_count_supported (else UNSUPPORTED); with at
+ * least one graph per compute unit each graph is counted whole by one workgroup, else
+ * the graphs' items are split over the grid; the launch is not captured.
  */
 vdmc_status vdmc_count_batch(const vdmc_graph* gs, int32_t num, int32_t k,
                              uint64_t* const* outs, void* stream);

@@ -1,4 +1,4 @@
-"""MI355X-native per-vertex directed 3/4-motif counting (the VDMC method).
+"""MI355X-native per-vertex directed 3-, 4- and 5-motif counting (the VDMC method).
 
 The work runs in the HIP library ``libvdmc.so`` behind the C ABI of ``include/vdmc.h``;
 this package is its Python binding (``vdmc.py``) and build script (``build.py``).
@@ -14,6 +14,7 @@ from .vdmc import (  # noqa: F401
     count_range,
     count_batch,
     count_batch_noalloc,
+    count_supported,
     init,
     count_edges,
     count_undirected,
@@ -24,6 +25,8 @@ from .vdmc import (  # noqa: F401
     num_classes_undirected,
     profile_counters,
     shape_counts,
+    shape_counts5,
+    SHAPES5,
     tune,
     tuned_choice,
     set_hub_threshold,

@@ -262,7 +262,7 @@ void run_plan(Plan& p, hipStream_t st, bool use_graph) {
 }
 
 void validate_batch(const vdmc_graph* gs, int32_t num, int32_t k, uint64_t* const* outs) {
-    VDMC_REQUIRE(k == 3 || k == 4, k == 5 ? VDMC_ERR_UNSUPPORTED : VDMC_ERR_INVALID_ARG, "k must be 3 or 4");
+    VDMC_REQUIRE(k >= 3 && k <= 5, VDMC_ERR_INVALID_ARG, "k must be 3, 4 or 5");
     VDMC_REQUIRE(num >= 0, VDMC_ERR_INVALID_ARG, "num must be non-negative");
     VDMC_REQUIRE(num == 0 || (gs && outs), VDMC_ERR_INVALID_ARG, "gs/outs is NULL");
     int dev = -1;
@@ -279,6 +279,7 @@ void validate_batch(const vdmc_graph* gs, int32_t num, int32_t k, uint64_t* cons
 }  // namespace
 
 void invalidate_batch_plans(vdmc_graph_s* g) {
+    invalidate_five_plans(g);
     std::lock_guard<std::mutex> lock(g_plan_mu);
     for (auto it = g_plans.begin(); it != g_plans.end();) {
         if (std::find((*it)->graphs.begin(), (*it)->graphs.end(), g) != (*it)->graphs.end()) {
@@ -319,6 +320,10 @@ void count_batch_impl(const vdmc_graph_s* const* gs_in, int32_t num, int32_t k, 
     const vdmc_graph* gs = const_cast<const vdmc_graph*>(gs_in);
     validate_batch(gs, num, k, outs);
     if (num == 0) return;
+    if (k == 5) {
+        count5_batch(gs_in, num, outs, st);
+        return;
+    }
     (void)class_tables();
     for (int i = 0; i < num; i++)
         if (!small_eligible(gs[i]->n, 2 * gs[i]->pairs, k)) {

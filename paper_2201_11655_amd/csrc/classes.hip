@@ -1,4 +1,4 @@
-// Isomorphism class table, built once per device by a kernel.
+// Isomorphism class tables (k = 3, 4, 5), built once per device by kernels.
 //
 // Paper: the motif index is the induced adjacency matrix read row by row without
 // the diagonal, first entry most significant (Sec. 4.1, Fig. 1); isomorphs are
@@ -124,8 +124,55 @@ __global__ __launch_bounds__(kTableThreads) void k_class_table(uint8_t* table, u
     }
 }
 
+// k = 5: 2^20 codes, too many for one workgroup's LDS.  Three launches: every code's
+// minimal relabelling and connectivity (one thread per code); the class ids, ascending
+// with the minimal index, by one workgroup scanning 1024 codes per thread; the table.
+constexpr uint32_t kCodes5 = 1u << 20;
+
+__global__ __launch_bounds__(256) void k_canon5(uint32_t* canon, uint8_t* conn) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= kCodes5) return;
+    canon[c] = minimal_relabelling<5>(c);
+    conn[c] = weakly_connected<5>(c) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kTableThreads) void k_ids5(const uint32_t* canon, const uint8_t* conn, uint16_t* cid,
+                                                        uint32_t* class_codes, int* num_classes) {
+    constexpr uint32_t PER = kCodes5 / kTableThreads;
+    __shared__ int scan[kTableThreads];
+    const int tid = threadIdx.x;
+    const uint32_t lo = tid * PER;
+    int mine = 0;
+    for (uint32_t c = lo; c < lo + PER; c++) mine += (canon[c] == c && conn[c]) ? 1 : 0;
+    scan[tid] = mine;
+    __syncthreads();
+    for (int s = 1; s < kTableThreads; s <<= 1) {   // inclusive Hillis-Steele scan
+        int v = tid >= s ? scan[tid - s] : 0;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    int next_id = scan[tid] - mine;
+    for (uint32_t c = lo; c < lo + PER; c++)
+        if (canon[c] == c && conn[c]) {
+            cid[c] = (uint16_t)next_id;
+            class_codes[next_id] = c;
+            next_id++;
+        }
+    if (tid == kTableThreads - 1) *num_classes = scan[tid];
+}
+
+__global__ __launch_bounds__(256) void k_table5(const uint32_t* canon, const uint8_t* conn, const uint16_t* cid,
+                                                uint16_t* table) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= kCodes5) return;
+    table[c] = conn[c] ? cid[canon[c]] : (uint16_t)0xFFFF;
+}
+
 std::mutex g_tables_mu;
 std::map<int, ClassTables*> g_tables;
+std::mutex g_tables5_mu;
+std::map<int, ClassTable5*> g_tables5;
 
 template <int K>
 void build_one(uint8_t* d_table, std::vector<uint8_t>& host, std::vector<uint16_t>& codes) {
@@ -226,17 +273,95 @@ const ClassTables& class_tables() {
     return *t;
 }
 
+const ClassTable5& class_table5() {
+    int dev = 0;
+    VDMC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_tables5_mu);
+    auto it = g_tables5.find(dev);
+    if (it != g_tables5.end()) return *it->second;
+    uint32_t *canon = nullptr, *codes = nullptr;
+    uint8_t* conn = nullptr;
+    uint16_t *cid = nullptr, *table = nullptr;
+    int* num = nullptr;
+    struct Free {
+        std::vector<void*> p;
+        ~Free() {
+            for (void* x : p) (void)hipFree(x);
+        }
+    } tmp;
+    VDMC_HIP(hipMalloc(&canon, kCodes5 * sizeof(uint32_t)));
+    tmp.p.push_back(canon);
+    VDMC_HIP(hipMalloc(&conn, kCodes5));
+    tmp.p.push_back(conn);
+    VDMC_HIP(hipMalloc(&cid, kCodes5 * sizeof(uint16_t)));
+    tmp.p.push_back(cid);
+    VDMC_HIP(hipMalloc(&codes, kClasses5 * sizeof(uint32_t)));
+    tmp.p.push_back(codes);
+    VDMC_HIP(hipMalloc(&num, sizeof(int)));
+    tmp.p.push_back(num);
+    VDMC_HIP(hipMalloc(&table, kCodes5 * sizeof(uint16_t)));
+    VDMC_HIP(hipMemset(cid, 0, kCodes5 * sizeof(uint16_t)));
+    hipLaunchKernelGGL(k_canon5, dim3(kCodes5 / 256), dim3(256), 0, 0, canon, conn);
+    VDMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ids5, dim3(1), dim3(kTableThreads), 0, 0, canon, conn, cid, codes, num);
+    VDMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_table5, dim3(kCodes5 / 256), dim3(256), 0, 0, canon, conn, cid, table);
+    VDMC_HIP(hipGetLastError());
+    int n = 0;
+    VDMC_HIP(hipMemcpy(&n, num, sizeof(int), hipMemcpyDeviceToHost));
+    if (n != kClasses5) {
+        (void)hipFree(table);
+        VDMC_REQUIRE(false, VDMC_ERR_DEVICE, "class table kernels produced " + std::to_string(n) + " classes for k=5");
+    }
+    auto* t = new ClassTable5();
+    t->table = table;
+    t->codes.resize(kClasses5);
+    VDMC_HIP(hipMemcpy(t->codes.data(), codes, kClasses5 * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    g_tables5[dev] = t;   // kept for the life of the process
+    return *t;
+}
+
 }  // namespace vdmc
 
 extern "C" {
 
 int32_t vdmc_num_classes(int32_t k) { return vdmc::num_classes(k); }
 
+vdmc_status vdmc_class_codes_u32(int32_t k, uint32_t* codes_out) {
+    return vdmc::guarded([&] {
+        VDMC_REQUIRE(codes_out != nullptr, VDMC_ERR_INVALID_ARG, "codes_out is NULL");
+        VDMC_REQUIRE(k >= 3 && k <= 5, VDMC_ERR_INVALID_ARG, "k must be 3, 4 or 5");
+        if (k == 5) {
+            const auto& c = vdmc::class_table5().codes;
+            std::copy(c.begin(), c.end(), codes_out);
+        } else {
+            const auto& t = vdmc::class_tables();
+            const auto& c = k == 3 ? t.codes3 : t.codes4;
+            std::copy(c.begin(), c.end(), codes_out);
+        }
+    });
+}
+
+vdmc_status vdmc_class_table_u16(int32_t k, uint16_t* table_out) {
+    return vdmc::guarded([&] {
+        VDMC_REQUIRE(table_out != nullptr, VDMC_ERR_INVALID_ARG, "table_out is NULL");
+        VDMC_REQUIRE(k >= 3 && k <= 5, VDMC_ERR_INVALID_ARG, "k must be 3, 4 or 5");
+        if (k == 5) {
+            VDMC_HIP(hipMemcpy(table_out, vdmc::class_table5().table, (size_t)vdmc::kCodes5 * sizeof(uint16_t),
+                               hipMemcpyDeviceToHost));
+        } else {
+            const auto& t = vdmc::class_tables();
+            const auto& h = k == 3 ? t.host3 : t.host4;
+            for (size_t i = 0; i < h.size(); i++) table_out[i] = h[i] == 0xFF ? (uint16_t)0xFFFF : h[i];
+        }
+    });
+}
+
 vdmc_status vdmc_class_codes(int32_t k, uint16_t* codes_out) {
     return vdmc::guarded([&] {
         VDMC_REQUIRE(codes_out != nullptr, VDMC_ERR_INVALID_ARG, "codes_out is NULL");
         VDMC_REQUIRE(k == 3 || k == 4, k == 5 ? VDMC_ERR_UNSUPPORTED : VDMC_ERR_INVALID_ARG,
-                     "k must be 3 or 4");
+                     k == 5 ? "5-vertex codes need 32 bits: vdmc_class_codes_u32" : "k must be 3 or 4");
         const auto& t = vdmc::class_tables();
         const auto& c = k == 3 ? t.codes3 : t.codes4;
         std::copy(c.begin(), c.end(), codes_out);
@@ -247,7 +372,7 @@ vdmc_status vdmc_class_table(int32_t k, uint8_t* table_out) {
     return vdmc::guarded([&] {
         VDMC_REQUIRE(table_out != nullptr, VDMC_ERR_INVALID_ARG, "table_out is NULL");
         VDMC_REQUIRE(k == 3 || k == 4, k == 5 ? VDMC_ERR_UNSUPPORTED : VDMC_ERR_INVALID_ARG,
-                     "k must be 3 or 4");
+                     k == 5 ? "5-vertex class ids need 16 bits: vdmc_class_table_u16" : "k must be 3 or 4");
         const auto& t = vdmc::class_tables();
         const auto& h = k == 3 ? t.host3 : t.host4;
         std::copy(h.begin(), h.end(), table_out);

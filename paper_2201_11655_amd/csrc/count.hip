@@ -511,14 +511,28 @@ extern "C" {
 vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream) {
     return vdmc::guarded([&] {
         VDMC_REQUIRE(g != nullptr, VDMC_ERR_INVALID_ARG, "graph is NULL");
-        VDMC_REQUIRE(k == 3 || k == 4, k == 5 ? VDMC_ERR_UNSUPPORTED : VDMC_ERR_INVALID_ARG,
-                     "k must be 3 or 4");
+        VDMC_REQUIRE(k >= 3 && k <= 5, VDMC_ERR_INVALID_ARG, "k must be 3, 4 or 5");
         VDMC_REQUIRE(out != nullptr || g->n == 0, VDMC_ERR_INVALID_ARG, "out is NULL");
         VDMC_HIP(hipSetDevice(g->device));
+        if (k == 5) {
+            VDMC_REQUIRE(vdmc::five_eligible(g->n, 2 * g->pairs), VDMC_ERR_UNSUPPORTED,
+                         "5-vertex counts take graphs held whole in LDS: n <= " + std::to_string(vdmc::kFiveMaxN) +
+                             " and the CSR plus a 2-bit arc matrix within one workgroup's LDS");
+            (void)vdmc::class_table5();
+            vdmc::GraphUse use(g, vdmc::as_stream(stream));
+            vdmc::launch_count5(g, out, vdmc::as_stream(stream));
+            return;
+        }
         vdmc::GraphUse use(g, vdmc::as_stream(stream));
         vdmc::launch_count(g, k == 3, k == 4, k == 3 ? out : nullptr, k == 4 ? out : nullptr,
                            vdmc::as_stream(stream));
     });
+}
+
+int32_t vdmc_count_supported(vdmc_graph g, int32_t k) {
+    if (g == nullptr || k < 3 || k > 5) return -1;
+    if (k == 5) return vdmc::five_eligible(g->n, 2 * g->pairs) ? 1 : 0;
+    return 1;
 }
 
 vdmc_status vdmc_set_hub_threshold(vdmc_graph g, int32_t min_higher) {

@@ -72,7 +72,11 @@ constexpr int kClasses4 = 199;
 constexpr int kShapes = 6;   // (1,1) (1,2) | (3,0,0) (2,1,0) (1,2,0) (1,1,1)
 constexpr int kStatSlots = 8;       // per graph: sets visited per shape (kShapes), then spare
 
-inline int num_classes(int k) { return k == 3 ? kClasses3 : (k == 4 ? kClasses4 : -1); }
+constexpr int kClasses5 = 9364;
+
+inline int num_classes(int k) {
+    return k == 3 ? kClasses3 : (k == 4 ? kClasses4 : (k == 5 ? kClasses5 : -1));
+}
 
 // Device-resident class tables of the current device: code -> class id (0xFF =
 // disconnected).  Built on first use by a kernel; cached per device.
@@ -96,6 +100,14 @@ struct ClassTables {
     std::vector<uint16_t> codes3, codes4;
 };
 const ClassTables& class_tables();   // for the current device
+
+// k = 5: code (20 bits) -> class id (0xFFFF = disconnected), 2 MiB in device memory;
+// built on the first 5-vertex count on a device and kept.
+struct ClassTable5 {
+    const uint16_t* table = nullptr;
+    std::vector<uint32_t> codes;   // class id -> minimal index
+};
+const ClassTable5& class_table5();   // for the current device
 
 // ----------------------------------------------------------------------------- graph
 
@@ -155,6 +167,7 @@ struct vdmc_graph_s {
     // end of the last call's device work on this graph (every call's work is ordered after
     // the previous call's, whatever the streams)
     std::shared_ptr<vdmc::DoneEvent> last;
+    unsigned* five_cursor = nullptr;   // work cursor of the 5-vertex kernel (allocated at the first such count)
 };
 
 namespace vdmc {
@@ -286,4 +299,11 @@ void launch_count_edges(vdmc_graph_s* g, int k, uint64_t* out, hipStream_t strea
 void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t stream,
                 uint32_t rank_lo = 0, uint32_t rank_hi = 0xFFFFFFFFu, const hipEvent_t* around = nullptr);
 void free_hub(vdmc_graph_s* g);
+// 5-vertex motifs (count5.hip): graphs held whole in one workgroup's LDS
+constexpr int64_t kFiveMaxN = 512;
+size_t five_lds_bytes(int64_t n, int64_t entries);
+bool five_eligible(int64_t n, int64_t entries);
+void launch_count5(vdmc_graph_s* g, uint64_t* out, hipStream_t stream);   // caller holds the graph (GraphUse)
+void count5_batch(const vdmc_graph_s* const* gs, int32_t num, uint64_t* const* outs, hipStream_t stream);
+void invalidate_five_plans(vdmc_graph_s* g);
 }  // namespace vdmc

@@ -17,8 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libvdmc.so")
 
 SYMBOLS = [
     "vdmc_last_error", "vdmc_num_classes", "vdmc_class_codes", "vdmc_class_table",
+    "vdmc_class_codes_u32", "vdmc_class_table_u16",
     "vdmc_build_graph", "vdmc_graph_info", "vdmc_graph_export", "vdmc_free_graph",
-    "vdmc_count", "vdmc_count_range", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters",
+    "vdmc_count", "vdmc_count_supported", "vdmc_count_range", "vdmc_count34", "vdmc_shape_counts", "vdmc_profile_counters",
     "vdmc_kernel_times", "vdmc_num_classes_undirected", "vdmc_undirected_classes", "vdmc_count_undirected",
     "vdmc_edge_list", "vdmc_count_edges",
     "vdmc_count_batch", "vdmc_tune", "vdmc_tuned_choice", "vdmc_set_hub_threshold",
@@ -60,11 +61,14 @@ def load():
         "vdmc_num_classes": ([i32], i32),
         "vdmc_class_codes": ([i32, p], i32),
         "vdmc_class_table": ([i32, p], i32),
+        "vdmc_class_codes_u32": ([i32, p], i32),
+        "vdmc_class_table_u16": ([i32, p], i32),
         "vdmc_build_graph": ([i64, i64, p, p, u32, p, p], i32),
         "vdmc_graph_info": ([p, p, p, p, p], i32),
         "vdmc_graph_export": ([p, p, p, p], i32),
         "vdmc_free_graph": ([p], i32),
         "vdmc_count": ([p, i32, p, p], i32),
+        "vdmc_count_supported": ([p, i32], i32),
         "vdmc_count34": ([p, p, p, p], i32),
         "vdmc_count_range": ([p, i32, p, i64, i64, u32, p], i32),
         "vdmc_shape_counts": ([p, p], i32),
@@ -125,15 +129,26 @@ def num_classes(k: int) -> int:
 
 
 def class_codes(k: int) -> np.ndarray:
+    """Minimal index of every class, by class id (uint16 for k = 3, 4; uint32 for k = 5)."""
     nc = num_classes(k)
     if nc < 0:
         raise VdmcError(1, f"k={k}")
+    if k == 5:
+        out = np.zeros(nc, np.uint32)
+        _check(load().vdmc_class_codes_u32(k, _np_ptr(out)))
+        return out
     out = np.zeros(nc, np.uint16)
     _check(load().vdmc_class_codes(k, _np_ptr(out)))
     return out
 
 
 def class_table(k: int) -> np.ndarray:
+    """Class id of every code (uint8, 0xFF = disconnected, for k = 3, 4; uint16, 0xFFFF,
+    for k = 5)."""
+    if k == 5:
+        out = np.zeros(1 << 20, np.uint16)
+        _check(load().vdmc_class_table_u16(k, _np_ptr(out)))
+        return out
     out = np.zeros(1 << (k * (k - 1)), np.uint8)
     _check(load().vdmc_class_table(k, _np_ptr(out)))
     return out
@@ -262,10 +277,17 @@ def count_edges(g: Graph, k: int, out=None, stream=None):
     return out
 
 
+def count_supported(g: Graph, k: int) -> bool:
+    """Whether vdmc_count can count g for this k (k = 5: graphs held whole in LDS)."""
+    return int(load().vdmc_count_supported(g.handle, int(k))) == 1
+
+
 def count(g: Graph, k: int, out=None, stream=None):
     """Per-vertex k-motif counts, int64[n, C] on the device (row = original id)."""
-    if k not in (3, 4):
+    if k not in (3, 4, 5):
         _check(load().vdmc_count(g.handle, int(k), None, _stream_handle(stream)))
+    if k == 5 and not count_supported(g, 5):
+        raise VdmcError(4, f"5-vertex counts take graphs held whole in LDS (n <= 512); n = {g.n}")
     out = _out_tensor(g.n, k, out)
     _check(load().vdmc_count(g.handle, int(k), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
@@ -293,6 +315,14 @@ def shape_counts(g: Graph) -> dict:
     return {s: int(v) for s, v in zip(SHAPES, out)}
 
 
+SHAPES5 = ("(4)", "(3,1)", "(2,2)", "(2,1,1)", "(1,3)", "(1,2,1)", "(1,1,2)", "(1,1,1,1)")
+
+
+def shape_counts5(g: Graph) -> dict:
+    """Sets visited per BFS layer shape by the last 5-vertex count on g."""
+    return {s: int(v) for s, v in zip(SHAPES5, profile_counters(g))}
+
+
 def profile_counters(g: Graph) -> np.ndarray:
     """Diagnostic counters of the last count (see vdmc_profile_counters in vdmc.h)."""
     out = np.zeros(8, np.uint64)
@@ -311,8 +341,12 @@ def kernel_times(g: Graph) -> tuple:
 def count_batch(graphs, k: int, outs=None, stream=None):
     """One batched launch over many graphs; returns the list of output tensors."""
     lib = load()
-    if k not in (3, 4):
+    if k not in (3, 4, 5):
         _check(lib.vdmc_count_batch(None, len(graphs), int(k), None, _stream_handle(stream)))
+    if k == 5:
+        for i, g in enumerate(graphs):
+            if not count_supported(g, 5):
+                raise VdmcError(4, f"graph {i}: 5-vertex counts take graphs held whole in LDS (n <= 512)")
     if outs is None:
         outs = [_out_tensor(g.n, k, None) for g in graphs]
     hs = (ctypes.c_void_p * max(1, len(graphs)))(*[g.handle.value for g in graphs])

@@ -19,7 +19,9 @@ static int fails = 0;
     } while (0)
 
 int main(void) {
-    if (vdmc_num_classes(3) != 13 || vdmc_num_classes(4) != 199 || vdmc_num_classes(5) != -1) fails++;
+    if (vdmc_num_classes(3) != 13 || vdmc_num_classes(4) != 199 || vdmc_num_classes(5) != 9364 ||
+        vdmc_num_classes(6) != -1)
+        fails++;
     if (vdmc_num_classes_undirected(3) != 2 || vdmc_num_classes_undirected(4) != 6) fails++;
     uint16_t codes[199];
     uint64_t u64[16];
@@ -40,7 +42,12 @@ int main(void) {
     EXPECT(vdmc_set_hub_threshold(NULL, 4), VDMC_ERR_INVALID_ARG);
     EXPECT(vdmc_free_graph(NULL), VDMC_OK);
     EXPECT(vdmc_count_batch(NULL, 1, 4, NULL, NULL), VDMC_ERR_INVALID_ARG);
-    EXPECT(vdmc_count_batch(NULL, 0, 5, NULL, NULL), VDMC_ERR_UNSUPPORTED);
+    EXPECT(vdmc_count_batch(NULL, 0, 5, NULL, NULL), VDMC_OK);
+    EXPECT(vdmc_count_batch(NULL, 0, 6, NULL, NULL), VDMC_ERR_INVALID_ARG);
+    EXPECT(vdmc_count(NULL, 5, NULL, NULL), VDMC_ERR_INVALID_ARG);
+    EXPECT(vdmc_count_supported(NULL, 5), -1);
+    EXPECT(vdmc_class_codes_u32(5, NULL), VDMC_ERR_INVALID_ARG);
+    EXPECT(vdmc_class_table_u16(7, NULL), VDMC_ERR_INVALID_ARG);
     EXPECT(vdmc_count_batch_noalloc(NULL, 9000, 4, NULL, NULL), VDMC_ERR_INVALID_ARG);
     EXPECT(vdmc_count_batch_noalloc(NULL, 0, 4, NULL, NULL), VDMC_OK);
     EXPECT(vdmc_tune(NULL, 0, 4, NULL), VDMC_ERR_INVALID_ARG);

@@ -35,8 +35,11 @@ def test_host_only_calls():
     from paper_2201_11655_amd import vdmc
     assert vdmc.num_classes(3) == 13
     assert vdmc.num_classes(4) == 199
-    assert vdmc.num_classes(5) == -1 and vdmc.num_classes(2) == -1
+    assert vdmc.num_classes(5) == 9364
+    assert vdmc.num_classes(2) == -1 and vdmc.num_classes(6) == -1
     lib = vdmc.load()
+    assert lib.vdmc_count_supported(None, 5) == -1   # NULL graph
+    assert lib.vdmc_class_codes_u32(6, None) == 1 and lib.vdmc_class_table_u16(5, None) == 1
     assert lib.vdmc_free_graph(None) == 0          # NULL is a no-op
     assert lib.vdmc_graph_info(None, None, None, None, None) == 1
     assert b"NULL" in lib.vdmc_last_error()
@@ -66,4 +69,4 @@ def test_serve_config_validation_without_device():
     assert lib.vdmc_serve_poll(None, 1, None) == 1
     assert lib.vdmc_count_batch(None, 1, 4, None, None) == 1   # NULL arrays
     assert lib.vdmc_count_batch(None, 0, 6, None, None) == 1   # bad k
-    assert lib.vdmc_count_batch(None, 0, 5, None, None) == 4   # k = 5 unsupported
+    assert lib.vdmc_count_batch(None, 0, 5, None, None) == 0   # k = 5, empty batch

@@ -260,8 +260,8 @@ def test_errors(v):
     G = v.Graph(g.n, g.src, g.dst)
     out = torch.zeros((20, 199), dtype=torch.int64, device="cuda")
     with pytest.raises(v.VdmcError) as e:
-        v.count(G, 5, out)
-    assert e.value.name == "UNSUPPORTED"
+        v.count(G, 6, out)
+    assert e.value.name == "INVALID_ARG"
     with pytest.raises(v.VdmcError) as e:
         v.count(G, 2, out)
     assert e.value.name == "INVALID_ARG"
