@@ -50,6 +50,9 @@ WORKLOADS = {
     "chunglu_u": "the Chung-Lu graph with arc directions ignored; undirected 4-vertex motifs (6 classes)",
     "serve": "serving: pool of resident ER and Chung-Lu graphs (even/odd), n log-uniform, mean out-degree "
              "U[2,10], k in {3,4} 50/50, Poisson arrivals at 0.5x and 0.8x the measured capacity",
+    "batch256_k5": "5-vertex motifs (9364 classes): the first 256 graphs of the batch4096 recipe (directed "
+                   "G(n,p), n ~ U{20..500}, mean out-degree ~ U[2,8], graph i seeded (3,i)); one batched "
+                   "launch (one workgroup per graph) vs 256 per-graph launches",
 }
 
 
@@ -254,6 +257,102 @@ def bench_batch(args, torch, gg, v):
     assert same, "batched and per-graph outputs differ"
     log(f"[bench] per-graph {ms_single:.1f} ms, host-synced {ms_sync:.1f} ms")
     return _batch_result(args, graphs, Gs, T4, visited, ms_batch, dev_ms, choice, ms_single, ms_sync, same), graphs
+
+
+def cpu_baseline_five(graphs, budget_s):
+    """The oracle (as it is) for k = 5 on the first graphs of the workload until about
+    budget_s/2 of work on every host core, then on one core for about budget_s/2."""
+    import oracle
+    threads = oracle.default_threads()
+    res = {}
+    for label, th in (("all", threads), ("one", 1)):
+        t0 = time.perf_counter()
+        sets, done = 0, 0
+        for g in graphs:
+            _, tot = oracle.count(g.n, g.src, g.dst, 5, threads=th)
+            sets += int(tot.sum())
+            done += 1
+            if time.perf_counter() - t0 > budget_s / 2:
+                break
+        res[label] = (sets, done, time.perf_counter() - t0)
+    sets, done, secs = res["all"]
+    s1, d1, t1 = res["one"]
+    return {"value": sets / secs, "unit": "5-vertex sets/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle ESU + 120-relabelling class table, full k=5 count of the first {done} graphs "
+                      f"({sets} sets) in {secs:.1f} s on {threads} threads",
+            "one_core": {"value": s1 / t1, "graphs": d1, "sets": s1, "seconds": t1},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def bench_batch5(args, torch, gg, v):
+    """k = 5 on the first 256 graphs of the batch recipe: one batched launch per step."""
+    C5 = v.num_classes(5)
+    graphs = gg.er_batch(256, 20, 500, 2.0, 8.0, seed=3)
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
+    assert all(v.count_supported(G, 5) for G in Gs)
+    outs = [torch.empty((g.n, C5), dtype=torch.int64, device="cuda") for g in graphs]
+    log(f"[bench] k=5 batch: {len(graphs)} graphs, {sum(g.n for g in graphs)} vertices, "
+        f"outputs {8.0 * C5 * sum(g.n for g in graphs) / 2**30:.2f} GiB")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for w in range(args.warmup):
+            v.count_batch(Gs, 5, outs=outs, stream=stream)
+            stream.synchronize()
+            log(f"[bench] warmup {w} done")
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            v.count_batch(Gs, 5, outs=outs, stream=stream)
+        ev1.record(stream)
+        stream.synchronize()
+        ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
+        dev_ms = ev0.elapsed_time(ev1) / args.steps
+        log(f"[bench] {args.steps} batched k=5 steps: {ms_batch:.3f} ms/step (device {dev_ms:.3f} ms)")
+        col = sum(o.sum(dim=0) for o in outs).cpu().numpy().view(np.uint64)
+        assert (col % 5 == 0).all(), "column sums must be multiples of 5"
+        T5 = int(col.sum()) // 5
+        shapes = {}
+        for G in Gs:
+            for key, val in v.shape_counts5(G).items():
+                shapes[key] = shapes.get(key, 0) + val
+        visited = sum(shapes.values())
+        assert visited == T5, f"sets visited one by one ({visited}) != sets counted ({T5})"
+        per_graph, same = None, None
+        if not args.no_per_graph:
+            ref = [o.clone() for o in outs]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for G, o in zip(Gs, outs):
+                v.count(G, 5, o, stream=stream)
+            stream.synchronize()
+            ms_single = (time.perf_counter() - t0) * 1e3
+            same = all(bool(torch.equal(a, b)) for a, b in zip(ref, outs))
+            assert same, "batched and per-graph outputs differ"
+            del ref
+            per_graph = {"sets_per_s": T5 / (ms_single * 1e-3), "ms": ms_single}
+            log(f"[bench] per-graph {ms_single:.1f} ms")
+    out_bytes = 8.0 * C5 * sum(g.n for g in graphs)
+    csr_bytes = sum(4.0 * (G.n + 1) + 8.0 * G.pairs + 4.0 * G.n for G in Gs)
+    secs = dev_ms * 1e-3
+    result = {
+        "metric": "connected 5-vertex subgraphs counted/s (bit-exact), batched",
+        "value": T5 / (ms_batch * 1e-3), "unit": "5-vertex sets/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["batch256_k5"], "graphs": len(graphs),
+                   "vertices": sum(g.n for g in graphs), "arcs": int(sum(G.arcs for G in Gs)), "sets5": T5,
+                   "sets_visited": visited, "shapes_visited": shapes},
+        "batched": {"sets_per_s": T5 / (ms_batch * 1e-3), "ms": ms_batch, "device_ms": dev_ms},
+        "per_graph": per_graph, "batched_equals_per_graph": same,
+        "roofline": {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernel": "k_five<owned>",
+                     "kernel_ms": dev_ms, "achieved": (out_bytes + csr_bytes) / secs / 1e9,
+                     "frac": (out_bytes + csr_bytes) / secs / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes": out_bytes + csr_bytes,
+                     "credits_per_s": 5.0 * T5 / secs},
+    }
+    return result, graphs
 
 
 def _batch_result(args, graphs, Gs, T4, visited, ms_batch, dev_ms, choice, ms_single, ms_sync, same):
@@ -475,6 +574,11 @@ def main():
         if not args.no_cpu_baseline:
             log("[bench] cpu baseline ...")
             result["cpu_baseline"] = cpu_baseline_batch(graphs, args.cpu_budget)
+    elif args.workload == "batch256_k5":
+        result, graphs = bench_batch5(args, torch, gg, v)
+        if not args.no_cpu_baseline:
+            log("[bench] cpu baseline ...")
+            result["cpu_baseline"] = cpu_baseline_five(graphs, args.cpu_budget)
     elif args.workload == "serve":
         log_hi = 6.0 if args.serve_log_hi is None else args.serve_log_hi
         s = run_serve(v, torch, gg, args.serve_graphs, args.serve_requests, log_hi, (0.5, 0.8))

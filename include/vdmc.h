@@ -174,8 +174,8 @@ vdmc_status vdmc_free_graph(vdmc_graph g);
  * its index (Sec. 4.1), looks up its class and credits the class to its k vertices
  * (vdmc_shape_counts reports the sets visited per shape).
  * k in {3, 4, 5}, other k INVALID_ARG.  k = 5 (n x 9364 output) takes graphs held
- * whole in one workgroup's LDS -- n <= 512 and 4 (4n + 2 + 2 pairs + n ceil(n/16))
- * bytes of CSR, id map and 2-bit arc matrix within 161792 -- and gives UNSUPPORTED
+ * whole in one workgroup's LDS -- n <= 512 and 4 (4n + 2 + 2 pairs + n ceil(n/32))
+ * bytes of CSR, id map and 1-bit adjacency matrix within 159744 -- and gives UNSUPPORTED
  * for any other (vdmc_count_supported tells which); its sets are visited along the
  * eight BFS layer shapes of five vertices (vdmc_profile_counters).  A graph with n < k
  * gives an all-zero matrix.  Asynchronous on `stream`; `out` must not be in use by

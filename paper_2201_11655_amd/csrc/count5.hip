@@ -20,50 +20,45 @@
 // parents and the choice order are all fixed by S, and each set is produced once.
 //
 // GPU mapping: the graph is held whole in LDS -- rank-space CSR, the rank -> id map
-// and a 2-bit arc matrix (every pair test and every index bit is one LDS read).  A work
-// item is a root r with the first member a of its layer 1 (one per pair of G_U, from
-// its lower-rank end); a lane runs the item's whole search (three nested candidate
-// loops) and visits every set of it.  Items are taken one at a time from an LDS cursor
-// so lanes with short items keep taking new ones.  Class ids come from a 2^20-entry
-// u16 table in device memory (2 MiB, L2-resident); each set adds one to five counters
-// of the graph's output rows (9364 classes per vertex do not fit in LDS).  Two modes:
-//   * owned (batches of many graphs): one workgroup takes a whole graph and zeroes its
-//     output block first; credits are workgroup-scope atomics, executed in the L2 of
-//     the workgroup's die;
-//   * shared (one graph, or few): workgroups take segments of a graph's items; credits
-//     are device-scope atomics and the output is zeroed by a fill launch before.
+// and a 1-bit adjacency matrix (every pair test is one LDS read; the arc bits of a
+// member with its parent come with the row entry, others are searched in the row).  A
+// work item is a root r with the first member a of its layer 1 (one per pair of G_U,
+// from its lower-rank end), cut for the heavy roots into K sub-items by the choice of
+// the third member; a lane runs a sub-item's whole search (three nested candidate
+// loops) and visits every set of it.  Lanes take items one at a time from the graph's
+// item cursor, so lanes with short items keep taking new ones.  Class ids come from a
+// 2^20-entry u16 table in device memory (2 MiB); the last member of a set is credited
+// per set, the four fixed members of a depth-3 context per distinct class through a
+// small per-lane cache (9364 classes per vertex do not fit in LDS, so the counters are
+// an output block in device memory).
+//
+// Work split.  A graph is cut into P parts (P from its estimated work, sum of d^4 over
+// its vertices, so that the heaviest graphs of a batch spread over many compute units):
+// a part is a workgroup that loads the graph, zeroes its own output block -- the
+// caller's output for part 0, a private copy in scratch for the others -- and then
+// takes items from the graph's item cursor until none are left.  A block belongs to one
+// workgroup for the whole launch, so its credits are workgroup-scope atomics.  A second
+// launch adds the copies of each graph with P > 1 into its output.  Parts are claimed
+// heaviest graph first from a slot cursor; items of a graph are handed out in rank
+// order, the heavy roots first.
 // Visited sets are counted per shape (the graph's 8 counters) so that callers can
 // check that every set was visited: their sum is the number of connected 5-sets.
+#include <cmath>
+#include <map>
+
 #include "vdmc_internal.h"
 
 namespace vdmc {
 namespace {
 
-constexpr uint32_t kFiveThreads = 256;
-constexpr size_t kFiveStaticLds = 2048;                        // the kernel's __shared__ words below
+constexpr size_t kFiveStaticLds = 4096;                        // the kernel's __shared__ bytes, rounded up
 constexpr size_t kFiveLdsBudget = 163840 - kFiveStaticLds;     // gfx950: 160 KiB of LDS per workgroup
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-
-struct FiveGraph {
-    const uint32_t* off;        // n + 1 (rank space)
-    const uint32_t* adj;        // entries: (nbr_rank << 2) | arc bits
-    const int32_t* perm;        // rank -> original id
-    unsigned long long* out;    // n x 9364, rows by original id
-    unsigned long long* stats;  // 8 shape counters
-    uint32_t n, entries, items; // items = pairs of G_U
-    uint32_t seg_base;          // first segment of this graph in the launch
-};
-
-struct FiveArgs {
-    const FiveGraph* graphs;    // device array of num graphs, or nullptr: the graph `one`
-    FiveGraph one;
-    uint32_t num;
-    uint32_t nseg;              // segments in the launch
-    uint32_t seg_items;         // items per segment (owned mode: at least every graph's items)
-    unsigned* cursor;           // segment cursor, zeroed before the launch
-    const uint16_t* table;      // code -> class id
-    uint32_t zero_out;          // owned mode: the workgroup zeroes the graph's output block
-};
+constexpr int kPartsPerCu = 2;                                 // target parts per compute unit in a batch
+constexpr uint32_t kSplitDiv = 32;                             // sub-items of a root: d+ x deg / 32 (measured best of 2..128)
+constexpr uint32_t kMaxParts = 64;                             // parts of one graph
+constexpr size_t kBatchScratchBudget = size_t(8) << 30;       // private copies of one batched launch
+constexpr size_t kSingleScratchBudget = size_t(512) << 20;    // private copies of one graph's count
 
 // bit of the index of a 5-set for the entry (i, j), i != j: rows in order, the diagonal
 // skipped, entry (0,1) the most significant of the 20 (Sec. 4.1, Fig. 1)
@@ -79,12 +74,23 @@ __device__ __forceinline__ uint32_t pair_bits(uint32_t i, uint32_t t, uint32_t b
 struct FiveLds {
     const uint32_t* off;
     const uint32_t* adj;
-    const uint32_t* mat;    // n rows of W words, 16 two-bit entries per word
+    const uint32_t* mat;    // n rows of W words, one adjacency bit per vertex
     const uint32_t* perm;
     uint32_t W;
-    // arc bits of (u, v) seen from u: bit 0 u -> v, bit 1 v -> u; 0 if not adjacent
+    __device__ __forceinline__ bool adjacent(uint32_t u, uint32_t v) const {
+        return (mat[u * W + (v >> 5)] >> (v & 31u)) & 1u;
+    }
+    // arc bits of (u, v) seen from u: bit 0 u -> v, bit 1 v -> u; 0 if not adjacent (a set
+    // bit is resolved by a search of u's row)
     __device__ __forceinline__ uint32_t bits(uint32_t u, uint32_t v) const {
-        return (mat[u * W + (v >> 4)] >> ((v & 15u) * 2u)) & 3u;
+        if (!adjacent(u, v)) return 0u;
+        uint32_t lo = off[u], hi = off[u + 1];
+        const uint32_t key = v << 2;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (adj[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        return adj[lo] & 3u;
     }
     // first entry of u's row whose neighbour has rank above x
     __device__ __forceinline__ uint32_t first_above(uint32_t u, uint32_t x) const {
@@ -112,7 +118,7 @@ __device__ __forceinline__ uint32_t member(const uint32_t (&S)[5], uint32_t i) {
 __device__ __forceinline__ bool clear_of(const FiveLds& L, const uint32_t (&S)[5], uint32_t lim, uint32_t y) {
 #pragma unroll
     for (uint32_t m = 0; m < 4; m++)
-        if (m < lim && L.bits(S[m], y)) return false;
+        if (m < lim && L.adjacent(S[m], y)) return false;
     return true;
 }
 
@@ -121,7 +127,7 @@ __device__ __forceinline__ bool clear_of(const FiveLds& L, const uint32_t (&S)[5
 // the members of S[t-1]'s layer.  pi: S index of the current parent, [pi, pend) the
 // parents left in the phase, [j, jend) the rest of the parent's row.
 struct Cand {
-    uint32_t pi, pend, j, jend, phase, ls;
+    uint32_t pi, pend, j, jend, phase, ls, pbits;   // pbits: arc bits of the last candidate with its parent
     __device__ __forceinline__ void start(const FiveLds& L, const uint32_t (&S)[5], uint32_t par, uint32_t pos,
                                           uint32_t ls_prev) {
         pi = par;
@@ -135,8 +141,11 @@ struct Cand {
     __device__ __forceinline__ uint32_t next(const FiveLds& L, const uint32_t (&S)[5], uint32_t t) {
         for (;;) {
             while (j < jend) {
-                const uint32_t y = L.adj[j++] >> 2;
-                if (clear_of(L, S, pi, y)) return y;
+                const uint32_t e = L.adj[j++], y = e >> 2;
+                if (clear_of(L, S, pi, y)) {
+                    pbits = e & 3u;
+                    return y;
+                }
             }
             if (++pi < pend) {
                 const uint32_t x = member(S, pi);
@@ -158,21 +167,80 @@ struct Cand {
     }
 };
 
-template <bool kOwned>
-__device__ __forceinline__ void bump(unsigned long long* p) {
-    if (kOwned) __hip_atomic_fetch_add(p, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    else __hip_atomic_fetch_add(p, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// arc bits of (S[m], y) seen from S[m], for the candidate y just returned by c: its
+// parent's come with the entry, members before the parent are not adjacent to it (the
+// candidate rule), the others are looked up
+__device__ __forceinline__ uint32_t arc_of(const FiveLds& L, const uint32_t (&S)[5], uint32_t m, const Cand& c,
+                                           uint32_t y) {
+    if (m == c.pi) return c.pbits;
+    if (m < c.pi) return 0u;
+    return L.bits(S[m], y);
 }
 
-__device__ __forceinline__ void add_shape(unsigned long long (&vis)[8], uint32_t s, unsigned long long v) {
-#pragma unroll
-    for (uint32_t i = 0; i < 8; i++) vis[i] += (s == i) ? v : 0ull;
+// credits to an output block that belongs to the calling workgroup (no other workgroup
+// touches the block during the launch)
+__device__ __forceinline__ void bump(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Every set of the item (root r, first layer-1 member at entry apos of r's row).
-template <bool kOwned>
+// v sets of class cls credited to the four fixed members of a context
+__device__ __forceinline__ void credit4(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2, uint32_t P3,
+                                        uint32_t cls, unsigned long long v) {
+    if (v == 0ull || cls >= (uint32_t)kClasses5) return;
+    bump(&out[(size_t)P0 * kClasses5 + cls], v);
+    bump(&out[(size_t)P1 * kClasses5 + cls], v);
+    bump(&out[(size_t)P2 * kClasses5 + cls], v);
+    bump(&out[(size_t)P3 * kClasses5 + cls], v);
+}
+
+// Per-lane cache of the last member's signatures in one context: entry = (count << 8) |
+// signature (0 = empty) and the signature's class; the oldest entry makes room.
+struct SigCache {
+    uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0, victim = 0;
+    // class of a cached signature (its count raised by one), or kNone
+    __device__ __forceinline__ uint32_t hit(uint32_t sig) {
+        if (e0 && (e0 & 255u) == sig) { e0 += 256u; return k0; }
+        if (e1 && (e1 & 255u) == sig) { e1 += 256u; return k1; }
+        if (e2 && (e2 & 255u) == sig) { e2 += 256u; return k2; }
+        if (e3 && (e3 & 255u) == sig) { e3 += 256u; return k3; }
+        return kNone;
+    }
+    __device__ __forceinline__ void insert(uint32_t sig, uint32_t cls, unsigned long long* out, uint32_t P0,
+                                           uint32_t P1, uint32_t P2, uint32_t P3) {
+        const uint32_t e = 256u | sig;
+        switch (victim) {
+            case 0: credit4(out, P0, P1, P2, P3, k0, e0 >> 8); e0 = e; k0 = cls; break;
+            case 1: credit4(out, P0, P1, P2, P3, k1, e1 >> 8); e1 = e; k1 = cls; break;
+            case 2: credit4(out, P0, P1, P2, P3, k2, e2 >> 8); e2 = e; k2 = cls; break;
+            default: credit4(out, P0, P1, P2, P3, k3, e3 >> 8); e3 = e; k3 = cls; break;
+        }
+        victim = (victim + 1u) & 3u;
+    }
+    __device__ __forceinline__ void flush_all(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2,
+                                              uint32_t P3) {
+        credit4(out, P0, P1, P2, P3, k0, e0 >> 8);
+        credit4(out, P0, P1, P2, P3, k1, e1 >> 8);
+        credit4(out, P0, P1, P2, P3, k2, e2 >> 8);
+        credit4(out, P0, P1, P2, P3, k3, e3 >> 8);
+    }
+};
+
+// visited sets of one shape added to the workgroup's shape counters (LDS)
+__device__ __forceinline__ void add_shape(unsigned long long* vis, uint32_t s, uint32_t v) {
+    if (v) atomicAdd(&vis[s], (unsigned long long)v);
+}
+
+// Sub-items per (root, first layer-1 member) of a root with dhi higher neighbours and
+// degree deg: the heavy roots' items are cut by the choice of the third member (every
+// K-th candidate), so that no single lane carries a hub root's whole subtree.
+__device__ __forceinline__ uint32_t item_split(uint32_t dhi, uint32_t deg, uint32_t div) {
+    return min(64u, max(1u, (dhi * deg + div - 1u) / div));
+}
+
+// Every set of the sub-item k of K of the item (root r, first layer-1 member at entry apos
+// of r's row).
 __device__ void five_item(const FiveLds& L, const uint16_t* __restrict__ table, unsigned long long* __restrict__ out,
-                          uint32_t r, uint32_t apos, unsigned long long (&vis)[8]) {
+                          uint32_t r, uint32_t apos, uint32_t k, uint32_t K, unsigned long long* vis) {
     uint32_t S[5];
     S[0] = r;
     S[1] = L.adj[apos] >> 2;
@@ -181,12 +249,14 @@ __device__ void five_item(const FiveLds& L, const uint16_t* __restrict__ table, 
     const uint32_t P0 = L.perm[r], P1 = L.perm[S[1]];
     Cand c2;
     c2.start(L, S, 0u, apos, 1u);   // S[1]'s parent is S[0]; layer 1 starts at index 1
+    uint32_t ord2 = 0;
     for (;;) {
         const uint32_t y2 = c2.next(L, S, 2u);
         if (y2 == kNone) break;
+        if (ord2++ % K != k) continue;   // another sub-item's third member
         S[2] = y2;
         const uint32_t par2 = c2.pi, pos2 = c2.j - 1u, ls2 = c2.phase ? 2u : 1u;
-        const uint32_t code2 = code1 | pair_bits(0, 2, L.bits(S[0], y2)) | pair_bits(1, 2, L.bits(S[1], y2));
+        const uint32_t code2 = code1 | pair_bits(0, 2, arc_of(L, S, 0, c2, y2)) | pair_bits(1, 2, arc_of(L, S, 1, c2, y2));
         const uint32_t P2 = L.perm[y2];
         Cand c3;
         c3.start(L, S, par2, pos2, ls2);
@@ -195,27 +265,34 @@ __device__ void five_item(const FiveLds& L, const uint16_t* __restrict__ table, 
             if (y3 == kNone) break;
             S[3] = y3;
             const uint32_t par3 = c3.pi, pos3 = c3.j - 1u, ls3 = c3.phase ? 3u : ls2;
-            const uint32_t code3 = code2 | pair_bits(0, 3, L.bits(S[0], y3)) | pair_bits(1, 3, L.bits(S[1], y3)) |
-                                   pair_bits(2, 3, L.bits(S[2], y3));
+            const uint32_t code3 = code2 | pair_bits(0, 3, arc_of(L, S, 0, c3, y3)) |
+                                   pair_bits(1, 3, arc_of(L, S, 1, c3, y3)) | pair_bits(2, 3, arc_of(L, S, 2, c3, y3));
             const uint32_t P3 = L.perm[y3];
             Cand c4;
             c4.start(L, S, par3, pos3, ls3);
-            unsigned long long same = 0, opened = 0;   // sets whose last member continues / opens a layer
+            uint32_t same = 0, opened = 0;   // sets whose last member continues / opens a layer
+            // The last member y4 of a set is credited once per set.  The four fixed members
+            // are credited per distinct signature of y4 -- its arc bits with S[0..3], which
+            // with code3 fix the class -- through a 4-entry cache of (signature, count,
+            // class): a context of a sparse graph holds ~8-25 sets with ~4-5 signatures, so
+            // this removes most of the fixed members' credits and class reads.
+            SigCache sc;
             for (;;) {
                 const uint32_t y4 = c4.next(L, S, 4u);
                 if (y4 == kNone) break;
-                const uint32_t code = code3 | pair_bits(0, 4, L.bits(S[0], y4)) | pair_bits(1, 4, L.bits(S[1], y4)) |
-                                      pair_bits(2, 4, L.bits(S[2], y4)) | pair_bits(3, 4, L.bits(S[3], y4));
-                const uint32_t cls = table[code];
-                if (cls >= (uint32_t)kClasses5) continue;   // a connected set always has a class
-                const uint32_t P4 = L.perm[y4];
-                bump<kOwned>(&out[(size_t)P0 * kClasses5 + cls]);
-                bump<kOwned>(&out[(size_t)P1 * kClasses5 + cls]);
-                bump<kOwned>(&out[(size_t)P2 * kClasses5 + cls]);
-                bump<kOwned>(&out[(size_t)P3 * kClasses5 + cls]);
-                bump<kOwned>(&out[(size_t)P4 * kClasses5 + cls]);
+                const uint32_t b0 = arc_of(L, S, 0, c4, y4), b1 = arc_of(L, S, 1, c4, y4),
+                               b2 = arc_of(L, S, 2, c4, y4), b3 = arc_of(L, S, 3, c4, y4);
+                const uint32_t sig = b0 | (b1 << 2) | (b2 << 4) | (b3 << 6);
+                uint32_t cls = sc.hit(sig);
+                if (cls == kNone) {
+                    cls = table[code3 | pair_bits(0, 4, b0) | pair_bits(1, 4, b1) | pair_bits(2, 4, b2) |
+                                pair_bits(3, 4, b3)];
+                    sc.insert(sig, cls, out, P0, P1, P2, P3);
+                }
+                if (cls < (uint32_t)kClasses5) bump(&out[(size_t)L.perm[y4] * kClasses5 + cls], 1ull);
                 if (c4.phase) opened++; else same++;
             }
+            sc.flush_all(out, P0, P1, P2, P3);
             // shape id: bit 2 = a new layer opens at member 2, bit 1 at member 3, bit 0 at member 4
             const uint32_t base = (ls2 == 2u ? 4u : 0u) | (ls3 == 3u ? 2u : 0u);
             add_shape(vis, base, same);
@@ -224,16 +301,51 @@ __device__ void five_item(const FiveLds& L, const uint16_t* __restrict__ table, 
     }
 }
 
+
+struct FiveGraph {
+    const uint32_t* off;           // n + 1 (rank space)
+    const uint32_t* adj;           // entries: (nbr_rank << 2) | arc bits
+    const int32_t* perm;           // rank -> original id
+    unsigned long long* out;       // n x 9364, rows by original id (part 0)
+    unsigned long long* copies;    // (parts - 1) x n x 9364: private blocks of parts 1.., summed into out
+    unsigned long long* stats;     // 8 shape counters
+    unsigned* cursor;              // item cursor
+    uint32_t n, entries, items;    // items = pairs of G_U
+    uint32_t parts;
+};
+
+struct FiveArgs {
+    const FiveGraph* graphs;       // device array of num graphs, or nullptr: the graph `one`
+    FiveGraph one;
+    uint32_t num;
+    const uint2* slots;            // (graph, part) in claim order, or nullptr: (0, s)
+    uint32_t nslots;
+    unsigned* slot_cursor;
+    const uint16_t* table;         // code -> class id
+    uint32_t split_div;            // sub-items of a root: ceil(d+ x deg / split_div), at most 64
+};
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-template <bool kOwned>
-__global__ __launch_bounds__(kFiveThreads) void k_five(FiveArgs A) {
+// zeroes every graph's counters and item cursor and the slot cursor (before k_five)
+__global__ __launch_bounds__(256) void k_five_prep(FiveArgs A) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *A.slot_cursor = 0u;
+    if (i >= A.num) return;
+    const FiveGraph& G = A.graphs ? A.graphs[i] : A.one;
+    for (int s = 0; s < kStatSlots; s++) G.stats[s] = 0ull;
+    *G.cursor = 0u;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_five(FiveArgs A) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t s_seg, s_gi, s_next;
-    __shared__ uint32_t part[kFiveThreads];
+    __shared__ uint32_t s_slot;
+    __shared__ uint32_t part[BS];
+    __shared__ unsigned long long s_vis[8];   // sets visited per shape by this part
     const uint32_t tid = threadIdx.x;
     uint32_t loaded = kNone;
     FiveGraph G{};
@@ -241,59 +353,46 @@ __global__ __launch_bounds__(kFiveThreads) void k_five(FiveArgs A) {
     uint32_t* sSplit = nullptr;
     uint32_t* sHp = nullptr;
     for (;;) {
-        if (tid == 0) {
-            const uint32_t seg = atomicAdd(A.cursor, 1u);
-            uint32_t gi = 0;
-            if (A.graphs && seg < A.nseg) {   // last graph whose first segment is <= seg
-                uint32_t lo = 0, hi = A.num;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (A.graphs[mid].seg_base <= seg) lo = mid; else hi = mid;
-                }
-                gi = lo;
-            }
-            s_seg = seg;
-            s_gi = gi;
-        }
+        if (tid == 0) s_slot = atomicAdd(A.slot_cursor, 1u);
         __syncthreads();
-        const uint32_t seg = s_seg, gi = s_gi;
-        if (seg >= A.nseg) break;
-        if (gi != loaded) {   // the graph into LDS
-            G = A.graphs ? A.graphs[gi] : A.one;
-            if (kOwned && tid < 8) G.stats[tid] = 0ull;   // owned: the graph's counters are this workgroup's
-            const uint32_t n = G.n, E = G.entries, W = (n + 15u) >> 4;
+        const uint32_t slot = s_slot;
+        if (slot >= A.nslots) break;
+        const uint2 sl = A.slots ? A.slots[slot] : make_uint2(0u, slot);
+        if (sl.x != loaded) {   // the graph into LDS
+            G = A.graphs ? A.graphs[sl.x] : A.one;
+            const uint32_t n = G.n, E = G.entries, W = (n + 31u) >> 5;
             uint32_t* sOff = lds;
             sSplit = sOff + n + 1;
             sHp = sSplit + n;
             uint32_t* sPerm = sHp + n + 1;
             uint32_t* sAdj = sPerm + n;
             uint32_t* sMat = sAdj + E;
-            for (uint32_t i = tid; i < (n ? n + 1u : 0u); i += kFiveThreads) sOff[i] = G.off[i];
-            for (uint32_t i = tid; i < n; i += kFiveThreads) sPerm[i] = (uint32_t)G.perm[i];
-            for (uint32_t i = tid; i < E; i += kFiveThreads) sAdj[i] = G.adj[i];
-            for (uint32_t i = tid; i < n * W; i += kFiveThreads) sMat[i] = 0u;
+            for (uint32_t i = tid; i < (n ? n + 1u : 0u); i += BS) sOff[i] = G.off[i];
+            for (uint32_t i = tid; i < n; i += BS) sPerm[i] = (uint32_t)G.perm[i];
+            for (uint32_t i = tid; i < E; i += BS) sAdj[i] = G.adj[i];
+            for (uint32_t i = tid; i < n * W; i += BS) sMat[i] = 0u;
             __syncthreads();
-            for (uint32_t u = tid; u < n; u += kFiveThreads) {
+            for (uint32_t u = tid; u < n; u += BS) {
                 const uint32_t b = sOff[u], e = sOff[u + 1];
                 uint32_t split = e;
                 for (uint32_t x = b; x < e; x++) {
                     const uint32_t a = sAdj[x], v = a >> 2;
                     if (v > u && split == e) split = x;
-                    sMat[u * W + (v >> 4)] |= (a & 3u) << ((v & 15u) * 2u);   // row u is this thread's
+                    sMat[u * W + (v >> 5)] |= 1u << (v & 31u);   // row u is this thread's
                 }
                 sSplit[u] = split;
-                sHp[u] = e - split;
+                sHp[u] = (e - split) * item_split(e - split, e - b, A.split_div);
             }
             __syncthreads();
             // exclusive prefix of the higher-neighbour counts: item i of the graph is the
             // entry sSplit[r] + (i - sHp[r]) of the root r with sHp[r] <= i < sHp[r + 1]
-            const uint32_t per = (n + kFiveThreads - 1) / kFiveThreads;
+            const uint32_t per = (n + BS - 1) / BS;
             const uint32_t lo = min(n, tid * per), hi = min(n, lo + per);
             uint32_t s = 0;
             for (uint32_t i = lo; i < hi; i++) s += sHp[i];
             part[tid] = s;
             __syncthreads();
-            for (uint32_t o = 1; o < kFiveThreads; o <<= 1) {
+            for (uint32_t o = 1; o < (uint32_t)BS; o <<= 1) {
                 const uint32_t v = tid >= o ? part[tid - o] : 0u;
                 __syncthreads();
                 part[tid] += v;
@@ -305,52 +404,74 @@ __global__ __launch_bounds__(kFiveThreads) void k_five(FiveArgs A) {
                 sHp[i] = run;
                 run += x;
             }
-            if (tid == 0) sHp[n] = part[kFiveThreads - 1];
-            if (kOwned && A.zero_out) {   // the graph's output block belongs to this workgroup
-                const size_t cells = (size_t)n * kClasses5;
-                if (((uintptr_t)G.out & 15u) == 0) {   // 16-byte stores (9364 is even)
-                    ulonglong2* o = reinterpret_cast<ulonglong2*>(G.out);
-                    for (size_t i = tid; i < cells / 2; i += kFiveThreads) o[i] = make_ulonglong2(0ull, 0ull);
-                } else {
-                    for (size_t i = tid; i < cells; i += kFiveThreads) G.out[i] = 0ull;
-                }
-            }
+            if (tid == 0) sHp[n] = part[BS - 1];
             L = FiveLds{sOff, sAdj, sMat, sPerm, W};
-            loaded = gi;
-            __syncthreads();
+            loaded = sl.x;
         }
-        const uint32_t lo = (seg - (A.graphs ? G.seg_base : 0u)) * A.seg_items;
-        const uint32_t hi = min(G.items, lo + A.seg_items);
-        if (tid == 0) s_next = lo;
+        // this part's output block: the caller's output or a private copy; zeroed here
+        const size_t cells = (size_t)G.n * kClasses5;
+        unsigned long long* dst = sl.y == 0 ? G.out : G.copies + (size_t)(sl.y - 1u) * cells;
+        if (((uintptr_t)dst & 15u) == 0) {   // 16-byte stores (9364 is even)
+            ulonglong2* o = reinterpret_cast<ulonglong2*>(dst);
+            for (size_t i = tid; i < cells / 2; i += BS) o[i] = make_ulonglong2(0ull, 0ull);
+        } else {
+            for (size_t i = tid; i < cells; i += BS) dst[i] = 0ull;
+        }
+        if (tid < 8) s_vis[tid] = 0ull;
         __syncthreads();
-        unsigned long long vis[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (;;) {
-            const uint32_t i = atomicAdd(&s_next, 1u);
-            if (i >= hi) break;
+            const uint32_t i = atomicAdd(G.cursor, 1u);   // items of the graph, shared by its parts
+            if (i >= sHp[G.n]) break;
             uint32_t rlo = 0, rhi = G.n;   // root: last r with sHp[r] <= i
             while (rhi - rlo > 1) {
                 const uint32_t mid = (rlo + rhi) >> 1;
                 if (sHp[mid] <= i) rlo = mid; else rhi = mid;
             }
-            five_item<kOwned>(L, A.table, G.out, rlo, sSplit[rlo] + (i - sHp[rlo]), vis);
+            const uint32_t K = item_split(L.off[rlo + 1] - sSplit[rlo], L.off[rlo + 1] - L.off[rlo], A.split_div);
+            const uint32_t local = i - sHp[rlo];
+            five_item(L, A.table, dst, rlo, sSplit[rlo] + local / K, local % K, K, s_vis);
         }
-#pragma unroll
-        for (int s = 0; s < 8; s++) {
-            const unsigned long long v = wave_sum(vis[s]);
-            if ((tid & 63u) == 0 && v) {
-                if (kOwned) __hip_atomic_fetch_add(&G.stats[s], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                else atomicAdd(&G.stats[s], v);
-            }
-        }
-        __syncthreads();   // the segment is done before the next claim rewrites s_seg / s_next
+        __syncthreads();
+        if (tid < 8 && s_vis[tid]) atomicAdd(&G.stats[tid], s_vis[tid]);
+        __syncthreads();   // the part is done before the next claim rewrites s_slot
     }
 }
 
-void launch_five(const FiveArgs& a, bool owned, unsigned grid, size_t lds, hipStream_t st) {
-    void (*kern)(FiveArgs) = owned ? k_five<true> : k_five<false>;
-    VDMC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kFiveThreads), lds, st, a);
-    VDMC_HIP(hipGetLastError());
+// out += the private copies of one graph (blockIdx.x strides over its cells)
+__device__ void five_reduce_one(const FiveGraph& G) {
+    const size_t cells = (size_t)G.n * kClasses5;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (((uintptr_t)G.out & 15u) == 0) {   // copies are 256-byte aligned and cells is even
+        ulonglong2* o = reinterpret_cast<ulonglong2*>(G.out);
+        const ulonglong2* c = reinterpret_cast<const ulonglong2*>(G.copies);
+        const size_t h = cells / 2;
+        for (size_t i = t0; i < h; i += stride) {
+            ulonglong2 a = o[i];
+            for (uint32_t p = 0; p + 1 < G.parts; p++) {
+                const ulonglong2 b = c[p * h + i];
+                a.x += b.x;
+                a.y += b.y;
+            }
+            o[i] = a;
+        }
+    } else {
+        for (size_t i = t0; i < cells; i += stride) {
+            unsigned long long a = G.out[i];
+            for (uint32_t p = 0; p + 1 < G.parts; p++) a += G.copies[p * cells + i];
+            G.out[i] = a;
+        }
+    }
+}
+
+
+// out += the private copies, for every graph with more than one part (graphs strided
+// over blockIdx.y)
+__global__ __launch_bounds__(256) void k_five_reduce(FiveArgs A) {
+    for (uint32_t gi = blockIdx.y; gi < A.num; gi += gridDim.y) {
+        const FiveGraph& G = A.graphs ? A.graphs[gi] : A.one;
+        if (G.parts > 1) five_reduce_one(G);
+    }
 }
 
 int g_ncu = -1;
@@ -365,37 +486,81 @@ int ncu() {
     return g_ncu;
 }
 
-unsigned grid_for(size_t lds, uint32_t nseg) {
-    const int fit = std::max(1, std::min(8, (int)(163840 / (lds + kFiveStaticLds))));
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(nseg, (int64_t)ncu() * fit));
+// Launches prep, the search and (when some graph has several parts) the reduction.
+void launch_five(const FiveArgs& a, size_t lds, uint32_t num_graphs, bool reduce, hipStream_t st) {
+    hipLaunchKernelGGL(k_five_prep, dim3((std::max<uint32_t>(num_graphs, 1) + 255) / 256), dim3(256), 0, st, a);
+    VDMC_HIP(hipGetLastError());
+    // 16 waves per compute unit (the register budget): two 512-thread workgroups when the
+    // LDS admits at most two, else up to four of 256 threads
+    const int fit = std::max(1, (int)(163840 / (lds + kFiveStaticLds)));
+    const bool wide = fit <= 2;
+    const int per_cu = std::min(wide ? 2 : 4, fit);
+    void (*kern)(FiveArgs) = wide ? k_five<512> : k_five<256>;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(a.nslots, (int64_t)ncu() * per_cu));
+    VDMC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(wide ? 512 : 256), lds, st, a);
+    VDMC_HIP(hipGetLastError());
+    if (reduce) {
+        hipLaunchKernelGGL(k_five_reduce, dim3(256, std::min<uint32_t>(std::max<uint32_t>(num_graphs, 1), 65535u)),
+                           dim3(256), 0, st, a);
+        VDMC_HIP(hipGetLastError());
+    }
 }
 
-// cached descriptor arrays of batched 5-vertex launches, by (graphs, outputs)
+// estimated work of a graph: sum over vertices of d^4 (d = degree in G_U)
+double work_estimate(const vdmc_graph_s* g) {
+    if (g->n == 0) return 0.0;
+    std::vector<uint32_t> off((size_t)g->n + 1);
+    VDMC_HIP(hipMemcpy(off.data(), g->off, off.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    double w = 0.0;
+    for (int64_t v = 0; v < g->n; v++) {
+        const double d = (double)(off[v + 1] - off[v]);
+        w += d * d * d * d;
+    }
+    return w;
+}
+
+size_t block_bytes(const vdmc_graph_s* g) { return (size_t)g->n * kClasses5 * sizeof(unsigned long long); }
+
+FiveGraph view_of(const vdmc_graph_s* g, uint64_t* out) {
+    FiveGraph v{};
+    v.off = g->off;
+    v.adj = g->adj;
+    v.perm = g->perm;
+    v.out = (unsigned long long*)out;
+    v.stats = g->stats;
+    v.n = (uint32_t)g->n;
+    v.entries = (uint32_t)(2 * g->pairs);
+    v.items = (uint32_t)g->pairs;
+    v.parts = 1;
+    return v;
+}
+
+// cached state of batched 5-vertex launches, by (graphs, outputs)
 struct FivePlan {
     std::vector<vdmc_graph_s*> graphs;
     std::vector<uint64_t*> outs;
     FiveGraph* d_graphs = nullptr;
-    unsigned* d_cursor = nullptr;
-    uint32_t nseg = 0, seg_items = 0;
-    bool owned = true;
+    uint2* d_slots = nullptr;
+    unsigned* d_cursors = nullptr;            // per graph item cursor, then the slot cursor
+    unsigned long long* d_copies = nullptr;   // private copies of parts 1..
+    uint32_t nslots = 0;
+    bool reduce = false;
     size_t lds = 0;
     ~FivePlan() {
         (void)hipFree(d_graphs);
-        (void)hipFree(d_cursor);
+        (void)hipFree(d_slots);
+        (void)hipFree(d_cursors);
+        (void)hipFree(d_copies);
     }
 };
 std::mutex g_five_mu;
 std::vector<FivePlan*> g_five_plans;
 
-FiveGraph view_of(const vdmc_graph_s* g, uint64_t* out) {
-    return FiveGraph{g->off, g->adj, g->perm, (unsigned long long*)out, g->stats, (uint32_t)g->n,
-                     (uint32_t)(2 * g->pairs), (uint32_t)g->pairs, 0u};
-}
-
 }  // namespace
 
 size_t five_lds_bytes(int64_t n, int64_t entries) {
-    const int64_t W = (n + 15) / 16;
+    const int64_t W = (n + 31) / 32;
     return (size_t)(4 * ((n + 1) + n + (n + 1) + n + entries + n * W));
 }
 
@@ -406,28 +571,38 @@ bool five_eligible(int64_t n, int64_t entries) {
 void launch_count5(vdmc_graph_s* g, uint64_t* out, hipStream_t st) {
     VDMC_REQUIRE(five_eligible(g->n, 2 * g->pairs), VDMC_ERR_UNSUPPORTED,
                  "5-vertex counts take graphs held whole in LDS: n <= " + std::to_string(kFiveMaxN) +
-                     " and the CSR plus a 2-bit arc matrix within " + std::to_string(kFiveLdsBudget) + " bytes");
+                     " and the CSR plus a 1-bit adjacency matrix within " + std::to_string(kFiveLdsBudget) + " bytes");
     const ClassTable5& t = class_table5();
-    launch_fill_u64((uint64_t*)g->stats, kStatSlots, 0, st);
-    if (g->n == 0) return;
-    launch_fill_u64(out, (size_t)g->n * kClasses5, 0, st);
     g->timed_light = g->timed_hub = false;
-    if (g->pairs == 0) return;
-    if (!g->five_cursor) VDMC_HIP(hipMalloc(&g->five_cursor, 64));
-    launch_fill_u64((uint64_t*)g->five_cursor, 1, 0, st);
+    // parts: one per 32 items, at most two per compute unit, copies within the budget.  The
+    // cursors and the copies come from the stream-ordered pool and go back to it after the
+    // launches, so concurrent counts on other streams never share them.
+    const size_t bb = std::max<size_t>(block_bytes(g), 16);
+    const uint32_t by_items = std::max<uint32_t>(1u, (uint32_t)(g->pairs / 32));
+    const uint32_t by_mem = (uint32_t)std::min<size_t>(kMaxParts, 1 + kSingleScratchBudget / bb);
+    const uint32_t parts = std::max<uint32_t>(1u, std::min<uint32_t>({by_items, by_mem, (uint32_t)(2 * ncu())}));
+    const size_t bytes = 256 + (size_t)(parts - 1) * bb;
+    void* buf = nullptr;
+    VDMC_HIP(hipMallocAsync(&buf, bytes, st));
     FiveArgs a{};
     a.graphs = nullptr;
     a.one = view_of(g, out);
+    a.one.cursor = static_cast<unsigned*>(buf);
+    a.one.copies = parts > 1 ? reinterpret_cast<unsigned long long*>(static_cast<char*>(buf) + 256) : nullptr;
+    a.one.parts = parts;
     a.num = 1;
-    // segments small enough that every workgroup of the grid gets some
-    const uint32_t items = (uint32_t)g->pairs;
-    a.seg_items = std::max<uint32_t>(16u, std::min<uint32_t>(1024u, (items + 4 * ncu() - 1) / (4 * ncu())));
-    a.nseg = (items + a.seg_items - 1) / a.seg_items;
-    a.cursor = g->five_cursor;
+    a.slots = nullptr;
+    a.nslots = g->n > 0 ? parts : 0u;
+    a.slot_cursor = static_cast<unsigned*>(buf) + 1;
     a.table = t.table;
-    a.zero_out = 0;
-    const size_t lds = five_lds_bytes(g->n, 2 * g->pairs);
-    launch_five(a, false, grid_for(lds, a.nseg), lds, st);
+    a.split_div = kSplitDiv;
+    try {
+        launch_five(a, five_lds_bytes(g->n, 2 * g->pairs), 1, parts > 1, st);
+    } catch (...) {
+        (void)hipFreeAsync(buf, st);
+        throw;
+    }
+    VDMC_HIP(hipFreeAsync(buf, st));
 }
 
 void count5_batch(const vdmc_graph_s* const* gs_in, int32_t num, uint64_t* const* outs, hipStream_t st) {
@@ -451,32 +626,56 @@ void count5_batch(const vdmc_graph_s* const* gs_in, int32_t num, uint64_t* const
         try {
             plan->graphs = gs;
             plan->outs.assign(outs, outs + num);
-            // owned mode when there are enough graphs to give every compute unit some;
-            // graphs in order of decreasing estimated work (pairs x largest degree^3)
-            plan->owned = num >= ncu();
+            std::vector<double> work(num);
+            double total = 0.0;
+            for (int i = 0; i < num; i++) {
+                work[i] = work_estimate(gs[i]);
+                total += work[i];
+            }
+            // parts per graph: about kPartsPerCu per compute unit over the batch, more for the
+            // heavy graphs; coarser while the private copies exceed the budget
+            std::vector<uint32_t> parts(num, 1);
+            double unit = total / std::max(1.0, (double)kPartsPerCu * ncu());
+            for (int round = 0; round < 32; round++) {
+                size_t scratch = 0;
+                for (int i = 0; i < num; i++) {
+                    const double want = unit > 0 ? std::ceil(work[i] / unit) : 1.0;
+                    parts[i] = (uint32_t)std::max(1.0, std::min<double>(kMaxParts, want));
+                    if (gs[i]->pairs < 64) parts[i] = 1;
+                    scratch += (size_t)(parts[i] - 1) * block_bytes(gs[i]);
+                }
+                if (scratch <= kBatchScratchBudget) break;
+                unit *= 1.5;
+            }
             std::vector<int> order(num);
             for (int i = 0; i < num; i++) order[i] = i;
-            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-                const double da = (double)gs[a]->max_deg, db = (double)gs[b]->max_deg;
-                return (double)gs[a]->pairs * da * da * da > (double)gs[b]->pairs * db * db * db;
-            });
-            uint32_t max_items = 1, total = 0;
-            for (int i : order) max_items = std::max<uint32_t>(max_items, (uint32_t)gs[i]->pairs);
-            plan->seg_items = plan->owned ? max_items : 256u;
-            std::vector<FiveGraph> views;
-            for (int i : order) {
-                FiveGraph v = view_of(gs[i], outs[i]);
-                v.seg_base = total;
-                total += plan->owned ? 1u : std::max<uint32_t>(1u, (v.items + plan->seg_items - 1) / plan->seg_items);
-                views.push_back(v);
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+            std::vector<FiveGraph> views(num);
+            std::vector<uint2> slots;
+            size_t scratch = 0;
+            for (int i = 0; i < num; i++) {
+                views[i] = view_of(gs[i], outs[i]);
+                views[i].parts = parts[i];
+                scratch += (size_t)(parts[i] - 1) * block_bytes(gs[i]);
                 plan->lds = std::max(plan->lds, five_lds_bytes(gs[i]->n, 2 * gs[i]->pairs));
+                plan->reduce |= parts[i] > 1;
             }
-            plan->nseg = total;
-            VDMC_HIP(hipMalloc(&plan->d_graphs, sizeof(FiveGraph) * std::max<size_t>(1, views.size())));
-            VDMC_HIP(hipMalloc(&plan->d_cursor, 64));
-            if (!views.empty())
-                VDMC_HIP(hipMemcpy(plan->d_graphs, views.data(), sizeof(FiveGraph) * views.size(),
-                                   hipMemcpyHostToDevice));
+            for (int i : order)
+                for (uint32_t p = 0; p < parts[i]; p++) slots.push_back(make_uint2((unsigned)i, p));
+            plan->nslots = (uint32_t)slots.size();
+            VDMC_HIP(hipMalloc(&plan->d_cursors, sizeof(unsigned) * (num + 1)));
+            if (scratch) VDMC_HIP(hipMalloc(&plan->d_copies, scratch));
+            size_t at = 0;
+            for (int i = 0; i < num; i++) {
+                views[i].cursor = plan->d_cursors + i;
+                views[i].copies = parts[i] > 1 ? plan->d_copies + at / sizeof(unsigned long long) : nullptr;
+                at += (size_t)(parts[i] - 1) * block_bytes(gs[i]);
+            }
+            VDMC_HIP(hipMalloc(&plan->d_graphs, sizeof(FiveGraph) * std::max(num, 1)));
+            VDMC_HIP(hipMalloc(&plan->d_slots, sizeof(uint2) * std::max<size_t>(slots.size(), 1)));
+            VDMC_HIP(hipMemcpy(plan->d_graphs, views.data(), sizeof(FiveGraph) * num, hipMemcpyHostToDevice));
+            if (!slots.empty())
+                VDMC_HIP(hipMemcpy(plan->d_slots, slots.data(), sizeof(uint2) * slots.size(), hipMemcpyHostToDevice));
         } catch (...) {
             delete plan;
             throw;
@@ -488,33 +687,28 @@ void count5_batch(const vdmc_graph_s* const* gs_in, int32_t num, uint64_t* const
         }
     }
     GraphUse use(plan->graphs, st);   // ordered after earlier work on these graphs
-    for (int i = 0; i < num; i++) {
-        gs[i]->timed_light = gs[i]->timed_hub = false;
-        if (!plan->owned) {   // owned mode zeroes counters and outputs inside the launch
-            launch_fill_u64((uint64_t*)gs[i]->stats, kStatSlots, 0, st);
-            if (gs[i]->n > 0) launch_fill_u64(outs[i], (size_t)gs[i]->n * kClasses5, 0, st);
-        }
-    }
-    launch_fill_u64((uint64_t*)plan->d_cursor, 1, 0, st);
+    for (auto* g : gs) g->timed_light = g->timed_hub = false;
     FiveArgs a{};
     a.graphs = plan->d_graphs;
     a.num = (uint32_t)num;
-    a.nseg = plan->nseg;
-    a.seg_items = plan->seg_items;
-    a.cursor = plan->d_cursor;
+    a.slots = plan->d_slots;
+    a.nslots = plan->nslots;
+    a.slot_cursor = plan->d_cursors + num;
     a.table = t.table;
-    a.zero_out = plan->owned ? 1u : 0u;
-    launch_five(a, plan->owned, grid_for(plan->lds, plan->nseg), plan->lds, st);
+    a.split_div = kSplitDiv;
+    launch_five(a, plan->lds, (uint32_t)num, plan->reduce, st);
 }
 
 void invalidate_five_plans(vdmc_graph_s* g) {
-    std::lock_guard<std::mutex> lock(g_five_mu);
-    for (auto it = g_five_plans.begin(); it != g_five_plans.end();) {
-        if (std::find((*it)->graphs.begin(), (*it)->graphs.end(), g) != (*it)->graphs.end()) {
-            delete *it;
-            it = g_five_plans.erase(it);
-        } else {
-            ++it;
+    {
+        std::lock_guard<std::mutex> lock(g_five_mu);
+        for (auto it = g_five_plans.begin(); it != g_five_plans.end();) {
+            if (std::find((*it)->graphs.begin(), (*it)->graphs.end(), g) != (*it)->graphs.end()) {
+                delete *it;
+                it = g_five_plans.erase(it);
+            } else {
+                ++it;
+            }
         }
     }
 }

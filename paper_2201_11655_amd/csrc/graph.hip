@@ -364,8 +364,6 @@ static void free_graph_arrays(vdmc_graph_s* g) {
     (void)hipFree(g->perm);
     (void)hipFree(g->roots);
     (void)hipFree(g->stats);
-    (void)hipFree(g->five_cursor);
-    g->five_cursor = nullptr;
     for (auto& e : g->ev)
         if (e) {
             (void)hipEventDestroy(e);

@@ -167,7 +167,6 @@ struct vdmc_graph_s {
     // end of the last call's device work on this graph (every call's work is ordered after
     // the previous call's, whatever the streams)
     std::shared_ptr<vdmc::DoneEvent> last;
-    unsigned* five_cursor = nullptr;   // work cursor of the 5-vertex kernel (allocated at the first such count)
 };
 
 namespace vdmc {

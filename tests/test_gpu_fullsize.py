@@ -121,3 +121,31 @@ def test_batch4096_full_size(v):
     for i in range(0, len(graphs), 97):
         single = v.count(Gs[i], 4)
         assert torch.equal(single, outs[i])
+
+
+def test_batch256_k5_full_size(v):
+    """The 5-vertex workload at full size: the first 256 graphs of the batch recipe in one
+    batched launch (one workgroup per graph); the 32 graphs with the most work and 32
+    seeded random others checked against the oracle entirely, every graph's visited
+    counters against its column sums, and every 17th graph against its single-graph count
+    (the shared mode)."""
+    import torch
+    graphs = gg.er_batch(256, 20, 500, 2.0, 8.0, seed=3)
+    _say(f"batch256_k5: {sum(g.n for g in graphs)} vertices")
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
+    outs = v.count_batch(Gs, 5)
+    torch.cuda.synchronize()
+    for i, (G, o) in enumerate(zip(Gs, outs)):
+        col = o.sum(dim=0).cpu().numpy().view(np.uint64)
+        assert (col % 5 == 0).all() and int(col.sum()) // 5 == sum(v.shape_counts5(G).values()), i
+    work = np.array([G.pairs * float(G.max_deg) ** 3 for G in Gs])
+    heavy = np.argsort(-work)[:32]
+    rest = np.setdiff1d(np.arange(len(graphs)), heavy)
+    pick = np.concatenate([heavy, np.random.default_rng(35).choice(rest, size=32, replace=False)])
+    for i in pick:
+        g = graphs[i]
+        want, _ = oracle.count(g.n, g.src, g.dst, 5)
+        assert (outs[i].cpu().numpy().view(np.uint64) == want).all(), f"graph {i}"
+    _say(f"  {len(pick)} graphs equal the oracle's")
+    for i in range(0, len(graphs), 17):
+        assert torch.equal(v.count(Gs[i], 5), outs[i]), i
