@@ -38,7 +38,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E, GB/s
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12    # 32-bit VALU lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
-MODEL_OPS_PER_SET = 40                      # lower end of the per-set integer work of the method
+MODEL_OPS_PER_SET = 40                      # per-set integer work of the method, k = 3, 4 (lower end)
+MODEL_OPS_PER_SET5 = 60                     # k = 5: 20-bit index, 4 pair tests, lookup, 5 credits
 
 WORKLOADS = {
     "batch4096": "4096 directed G(n,p) graphs, n ~ U{20..500}, mean out-degree ~ U[2,8], graph i seeded (3,i); "
@@ -74,15 +75,24 @@ def cpu_model():
 # ---------------------------------------------------------------------------------------------
 # counters from committed rocprofv3 runs (profiles/), keyed by a hash of the kernel sources
 
-COUNTER_SOURCES = ["paper_2201_11655_amd/csrc/small.hip", "paper_2201_11655_amd/csrc/count.hip",
-                   "paper_2201_11655_amd/csrc/count_hub.hip", "paper_2201_11655_amd/csrc/motif_device.h",
-                   "paper_2201_11655_amd/csrc/vdmc_internal.h"]
+_CS = "paper_2201_11655_amd/csrc/"
+# kernel sources behind each workload's counters: a change to any of them voids the
+# committed counters of that workload
+COUNTER_SOURCES = {
+    "batch4096": [_CS + "small.hip", _CS + "count.hip", _CS + "batch.hip", _CS + "motif_device.h",
+                  _CS + "vdmc_internal.h"],
+    "chunglu": [_CS + "count.hip", _CS + "count_hub.hip", _CS + "motif_device.h", _CS + "vdmc_internal.h"],
+    "batch256_k5": [_CS + "count5.hip", _CS + "vdmc_internal.h"],
+}
+COUNTER_SOURCES["rmat22"] = COUNTER_SOURCES["chunglu"]
+COUNTER_SOURCES["chunglu_u"] = COUNTER_SOURCES["chunglu"]
+COUNTER_SOURCES["er1000"] = COUNTER_SOURCES["chunglu"]
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0   # FETCH_SIZE / WRITE_SIZE of a 1 GiB copy read 0.5x / 1.0x its bytes
 
 
-def sources_sha256():
+def sources_sha256(workload):
     h = hashlib.sha256()
-    for f in COUNTER_SOURCES:
+    for f in COUNTER_SOURCES.get(workload, []):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -97,37 +107,39 @@ def load_counters(workload):
             rec = json.load(f).get(workload)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("sources_sha256") != sources_sha256():
+    if not rec or rec.get("sources_sha256") != sources_sha256(workload):
         return None
     return rec
 
 
-def roofline(workload, sets, kernel_ms, kernel_name, compulsory_bytes):
-    """ALU roofline of the dominant kernel: VALU lane-ops per launch from the committed
-    SQ_INSTS_VALU counters (x 64 lanes) over the launch time measured live; the method's
-    per-set model (MODEL_OPS_PER_SET) beside it; HBM bytes from FETCH_SIZE/WRITE_SIZE."""
-    rec = load_counters(workload)
-    out = {"bound": "alu", "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "kernel": kernel_name,
-           "kernel_ms": kernel_ms, "sets_per_launch": sets}
+def roofline(workload, sets, kernel_ms, kernel_name, compulsory_bytes, ops_per_set=MODEL_OPS_PER_SET):
+    """ALU roofline of the dominant kernel(s).  achieved = the method's per-set work (ops_per_set
+    32-bit lane-ops: index assembly, edge tests, class lookup, k credits) x the sets one launch
+    visits, over the launch time measured live; peak = the VALU lane-op rate of the chip.
+    From the committed counters of the same kernel sources (profiles/counters.json): the HBM
+    traffic per launch (FETCH_SIZE x 2 + WRITE_SIZE, the copy-calibrated factors), the issued
+    VALU lane-ops, and the memory-side atomics."""
     secs = kernel_ms * 1e-3
-    if rec is not None and rec.get("valu_insts"):
-        lane_ops = 64.0 * rec["valu_insts"]
-        out["achieved"] = lane_ops / secs / 1e12
-        out["valu_lane_ops_per_set"] = lane_ops / max(sets, 1)
-        out["traffic"] = 1024.0 * (FETCH_FACTOR * rec["fetch_kib"] + WRITE_FACTOR * rec["write_kib"]) \
-            if rec.get("fetch_kib") is not None else None
-        out["counters"] = {k: rec[k] for k in rec if k not in ("sources_sha256",)}
-    else:
-        out["achieved"] = MODEL_OPS_PER_SET * sets / secs / 1e12
-        out["traffic"] = None
-        out["note"] = "no counters for these kernel sources: achieved from the per-set model"
-    out["frac"] = out["achieved"] / VALU_PEAK_TOPS
-    out["model_ops_per_set"] = MODEL_OPS_PER_SET
-    out["model_frac"] = MODEL_OPS_PER_SET * sets / secs / 1e12 / VALU_PEAK_TOPS
-    out["hbm_compulsory_bytes"] = compulsory_bytes
-    out["hbm_compulsory_frac"] = compulsory_bytes / secs / 1e9 / HBM_PEAK_GBS
-    if out.get("traffic"):
-        out["hbm_traffic_frac"] = out["traffic"] / secs / 1e9 / HBM_PEAK_GBS
+    achieved = ops_per_set * sets / secs / 1e12
+    out = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+           "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": kernel_name, "kernel_ms": kernel_ms,
+           "sets_per_launch": sets, "ops_per_set": ops_per_set,
+           "hbm_compulsory_bytes": compulsory_bytes,
+           "hbm_compulsory_frac": compulsory_bytes / secs / 1e9 / HBM_PEAK_GBS}
+    rec = load_counters(workload)
+    if rec is None:
+        out["note"] = "no committed counters for these kernel sources: traffic unmeasured"
+        return out
+    traffic = 1024.0 * (FETCH_FACTOR * rec["fetch_kib"] + WRITE_FACTOR * rec["write_kib"])
+    out["traffic"] = traffic
+    out["traffic_frac_of_hbm"] = traffic / secs / 1e9 / HBM_PEAK_GBS
+    lane_ops = 64.0 * rec["valu_insts"]
+    out["measured"] = {
+        "valu_lane_ops_per_s": lane_ops / secs / 1e12, "valu_frac": lane_ops / secs / 1e12 / VALU_PEAK_TOPS,
+        "valu_lane_slots_per_set": lane_ops / max(sets, 1),
+        "memory_side_atomics": rec["tcc_ea0_atomic"], "atomics_per_s": rec["tcc_ea0_atomic"] / secs,
+        "counter_kernel_ms": rec.get("trace_ms"),
+    }
     return out
 
 
@@ -207,8 +219,10 @@ def bench_batch(args, torch, gg, v):
     Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
     outs = [torch.empty((g.n, 199), dtype=torch.int64, device="cuda") for g in graphs]
     t0 = time.perf_counter()
-    v.tune(Gs, 4)
     choice = v.tuned_choice(Gs, 4)
+    if not choice.get("tuned"):   # no choice for this batch shape in VDMC_TUNE_CACHE: tune now
+        v.tune(Gs, 4, args.tune_cache)
+        choice = v.tuned_choice(Gs, 4)
     log(f"[bench] tuned in {time.perf_counter() - t0:.1f}s: {choice}")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -346,11 +360,8 @@ def bench_batch5(args, torch, gg, v):
                    "sets_visited": visited, "shapes_visited": shapes},
         "batched": {"sets_per_s": T5 / (ms_batch * 1e-3), "ms": ms_batch, "device_ms": dev_ms},
         "per_graph": per_graph, "batched_equals_per_graph": same,
-        "roofline": {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernel": "k_five<owned>",
-                     "kernel_ms": dev_ms, "achieved": (out_bytes + csr_bytes) / secs / 1e9,
-                     "frac": (out_bytes + csr_bytes) / secs / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes": out_bytes + csr_bytes,
-                     "credits_per_s": 5.0 * T5 / secs},
+        "roofline": roofline("batch256_k5", T5, dev_ms, "k_five (layered search) + k_five_prep + k_five_reduce",
+                             out_bytes + csr_bytes, ops_per_set=MODEL_OPS_PER_SET5),
     }
     return result, graphs
 
@@ -552,6 +563,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--only-calibrate-copy", action="store_true",
+                    help="run the 1 GiB reference copy alone (for the HBM byte counters) and exit")
+    ap.add_argument("--tune-cache", default=None,
+                    help="file the autotuner appends its choice to (read back through VDMC_TUNE_CACHE)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -565,6 +580,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.only_calibrate_copy:
+        calibrate_copy(torch)
+        return
     v.load()
     if args.workload == "batch4096":
         result, graphs = bench_batch(args, torch, gg, v)
