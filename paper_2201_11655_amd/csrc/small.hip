@@ -18,14 +18,19 @@
 //   * every set is visited once by one lane: its index is assembled from the arc bits
 //     (Sec. 4.1), its class read from the table in LDS, and each of its k vertices
 //     credited (Sec. 4.2).  Credits go to LDS counters (k = 3: all 13 classes; k = 4:
-//     the 25 tree classes, which hold ~96% of the 4-sets of sparse graphs); the other
-//     classes go straight to the graph's output with workgroup-scope atomics (the
-//     output block of a graph belongs to one workgroup for the whole launch).  Members
-//     that all lanes of a wave step share (the root, the depth-1 vertex of a run of
-//     depth-2 items, the loop's current vertex) are credited once per class present in
-//     the step, grouped by ballots, instead of once per lane.
-// The LDS counters are added to the output once per graph.  u32 counters cannot
-// overflow: a vertex of a graph with n <= kSmallMaxN lies in fewer than 2^32 k-sets.
+//     the 25 tree classes, which hold ~96% of the 4-sets of sparse graphs), one LDS
+//     atomic per member and set; the other classes go straight to the graph's output
+//     with workgroup-scope atomics (the output block of a graph belongs to one
+//     workgroup for the whole launch), and there members that all lanes of a wave step
+//     share (the root, the depth-1 vertex of a run of depth-2 items, the loop's current
+//     vertex) are credited once per class present in the step, grouped by ballots;
+//   * in the k = 4 loops three members are fixed and the lane walks the fourth; a set
+//     whose fourth member has no arc to the fixed members other than the one the shape
+//     implies has its class fixed by that arc's code (a tree class): the fourth member
+//     is credited per set and the three fixed ones once per arc code after the loop.
+// The LDS counters are stored to the output once per graph (their classes never reach
+// the output otherwise).  u32 counters cannot overflow: a vertex of a graph with
+// n <= kSmallMaxN lies in fewer than 2^32 k-sets.
 #include "motif_device.h"
 #include "vdmc_internal.h"
 
@@ -127,33 +132,50 @@ struct SmallCredit {
         if (s < NC) atomicAdd(&cnt[v * NC + s], n);
         else out_add(&out[(size_t)perm[v] * C + cls], (unsigned long long)n);
     }
+    // n sets of class cls credited to three members (nothing when n = 0)
+    __device__ __forceinline__ void add3(uint32_t u, uint32_t v, uint32_t w, uint32_t cls, uint32_t n) const {
+        if (!n) return;
+        add_n(u, cls, n);
+        add_n(v, cls, n);
+        add_n(w, cls, n);
+    }
     // One set per active lane, of class cls, credited to the NS members in sv, which the
-    // lanes often share (the root, and the members fixed by the wave's loop position): a
-    // member common to all active lanes gets each class present once, with the lanes'
-    // count; a member that differs between lanes is added lane by lane.
+    // lanes often share (the root, and the members fixed by the wave's loop position).
+    // A class with an LDS counter (every k = 3 class, the 25 tree classes of k = 4) is
+    // added lane by lane: an LDS atomic is cheap, and lanes that share a member and a
+    // class only meet in the LDS unit.  The other classes go to the output, where every
+    // atomic is a memory-side operation: a member common to all such lanes gets each of
+    // their classes once, with the lanes' count; a member that differs is added lane by
+    // lane.
     template <int NS>
     __device__ __forceinline__ void shared(uint32_t cls, const uint32_t (&sv)[NS], bool active) const {
-        const unsigned long long act = __ballot(active);
+        const uint32_t s = active ? slot(cls) : NC;
+        if (active && s < NC)
+            for (int i = 0; i < NS; i++) atomicAdd(&cnt[sv[i] * NC + s], 1u);
+        if (K == 3) return;
+        const bool far = active && s >= NC;
+        const unsigned long long act = __ballot(far);
         if (!act) return;
         const int first = __ffsll((long long)act) - 1;
-        uint32_t common = 0;   // wave-uniform bit mask of the members all active lanes share
+        uint32_t common = 0;   // wave-uniform bit mask of the members all such lanes share
         for (int i = 0; i < NS; i++)
-            if (__ballot(active && sv[i] != (uint32_t)__shfl((int)sv[i], first, 64)) == 0ull) common |= 1u << i;
+            if (__ballot(far && sv[i] != (uint32_t)__shfl((int)sv[i], first, 64)) == 0ull) common |= 1u << i;
         if (common) {
             unsigned long long m = act;
             while (m) {
                 const uint32_t leader = (uint32_t)(__ffsll((long long)m) - 1);
                 const uint32_t k0 = (uint32_t)__shfl((int)cls, (int)leader, 64);
-                const unsigned long long grp = __ballot(active && cls == k0) & m;
+                const unsigned long long grp = __ballot(far && cls == k0) & m;
                 if (lane_of() == leader)
                     for (int i = 0; i < NS; i++)
-                        if ((common >> i) & 1u) add_n(sv[i], k0, (uint32_t)__popcll(grp));
+                        if ((common >> i) & 1u)
+                            out_add(&out[(size_t)perm[sv[i]] * C + k0], (unsigned long long)__popcll(grp));
                 m &= ~grp;
             }
         }
-        if (active)
+        if (far)
             for (int i = 0; i < NS; i++)
-                if (!((common >> i) & 1u)) add_n(sv[i], cls, 1u);
+                if (!((common >> i) & 1u)) out_add(&out[(size_t)perm[sv[i]] * C + cls], 1ull);
     }
 };
 
@@ -248,14 +270,32 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 cr.add_n(a, cls, 1u);
                 shp[0]++;
             } else {
+                // (3,0,0): r, a, b fixed, lanes' loops over c.  A set whose c is adjacent to
+                // neither a nor b has its class fixed by c's arc with r: those sets credit c
+                // one by one and r, a, b once per arc code after the loop.
+                const uint32_t p1 = sTable[motif_index4(ra, rb, 1u, ab, 0u, 0u)];
+                const uint32_t p2 = sTable[motif_index4(ra, rb, 2u, ab, 0u, 0u)];
+                const uint32_t p3 = sTable[motif_index4(ra, rb, 3u, ab, 0u, 0u)];
+                uint32_t n1 = 0, n2 = 0, n3 = 0;
                 for (uint32_t l = j + 1; l < d; l++) {
                     const uint32_t c = P[l] >> 2, rc = P[l] & 3u;
-                    const uint32_t cls = sTable[motif_index4(ra, rb, rc, ab, L.code(a, c), L.code(b, c))];
-                    const uint32_t sv[3] = {r, b, c};   // lanes share j, hence b and c
-                    cr.shared(cls, sv, true);
-                    cr.add_n(a, cls, 1u);
+                    const uint32_t ac = L.code(a, c), bc = L.code(b, c);
+                    if (ac | bc) {
+                        const uint32_t cls = sTable[motif_index4(ra, rb, rc, ab, ac, bc)];
+                        const uint32_t sv[3] = {r, b, c};   // lanes share j, hence b and c
+                        cr.shared(cls, sv, true);
+                        cr.add_n(a, cls, 1u);
+                    } else {
+                        cr.add_n(c, rc == 1u ? p1 : (rc == 2u ? p2 : p3), 1u);
+                        n1 += rc == 1u;
+                        n2 += rc == 2u;
+                        n3 += rc == 3u;
+                    }
                     shp[0]++;
                 }
+                cr.add3(r, a, b, p1, n1);
+                cr.add3(r, a, b, p2, n2);
+                cr.add3(r, a, b, p3, n3);
             }
         }
         // ---- depth-2 entries (r, a, c)
@@ -277,49 +317,96 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 shp[1]++;
                 continue;
             }
-            // (2,1,0): a second depth-1 vertex b; c hangs under the lower-rank parent
-            for (uint32_t jb = 0; jb < d; jb++) {
-                if (jb == ia) continue;
-                const uint32_t b = P[jb] >> 2, rb = P[jb] & 3u;
-                const uint32_t bc = L.code(b, c);
-                if (bc && jb < ia) continue;
-                const uint32_t cls = sTable[motif_index4(ra, rb, 0u, L.code(a, b), ac, bc)];
-                const uint32_t sv[3] = {r, a, b};   // lanes share (r, a) and the loop position
-                cr.shared(cls, sv, true);
-                cr.add_n(c, cls, 1u);
-                shp[1]++;
+            // (2,1,0): a second depth-1 vertex b; c hangs under the lower-rank parent.  r, a,
+            // c are fixed for the lane's loop; a set whose b is adjacent to neither a nor c
+            // has its class fixed by b's arc with r: b is credited per set, r, a, c once per
+            // arc code after the loop.  The same holds below for (1,2,0) (c2 not adjacent to
+            // c: class by a's arc with c2) and for every (1,1,1) set (class by c's arc with e).
+            {
+                const uint32_t q1 = sTable[motif_index4(ra, 1u, 0u, 0u, ac, 0u)];
+                const uint32_t q2 = sTable[motif_index4(ra, 2u, 0u, 0u, ac, 0u)];
+                const uint32_t q3 = sTable[motif_index4(ra, 3u, 0u, 0u, ac, 0u)];
+                uint32_t n1 = 0, n2 = 0, n3 = 0;
+                for (uint32_t jb = 0; jb < d; jb++) {
+                    if (jb == ia) continue;
+                    const uint32_t b = P[jb] >> 2, rb = P[jb] & 3u;
+                    const uint32_t bc = L.code(b, c);
+                    if (bc && jb < ia) continue;
+                    const uint32_t ab = L.code(a, b);
+                    if (ab | bc) {
+                        const uint32_t cls = sTable[motif_index4(ra, rb, 0u, ab, ac, bc)];
+                        const uint32_t sv[3] = {r, a, b};   // lanes share (r, a) and the loop position
+                        cr.shared(cls, sv, true);
+                        cr.add_n(c, cls, 1u);
+                    } else {
+                        cr.add_n(b, rb == 1u ? q1 : (rb == 2u ? q2 : q3), 1u);
+                        n1 += rb == 1u;
+                        n2 += rb == 2u;
+                        n3 += rb == 3u;
+                    }
+                    shp[1]++;
+                }
+                cr.add3(r, a, c, q1, n1);
+                cr.add3(r, a, c, q2, n2);
+                cr.add3(r, a, c, q3, n3);
             }
             // (1,2,0): a second child c2 > c of a, not adjacent to r
-            for (uint32_t t2 = t + 1; t2 < sOff[a + 1]; t2++) {
-                const uint32_t c2 = sAdj[t2] >> 2, ac2 = sAdj[t2] & 3u;
-                if (L.adjacent(r, c2)) continue;
-                const uint32_t cls = sTable[motif_index4(ra, 0u, 0u, ac, ac2, L.code(c, c2))];
-                const uint32_t sv[2] = {r, a};
-                cr.shared(cls, sv, true);
-                cr.add_n(c, cls, 1u);
-                cr.add_n(c2, cls, 1u);
-                shp[2]++;
+            {
+                const uint32_t u1 = sTable[motif_index4(ra, 0u, 0u, ac, 1u, 0u)];
+                const uint32_t u2 = sTable[motif_index4(ra, 0u, 0u, ac, 2u, 0u)];
+                const uint32_t u3 = sTable[motif_index4(ra, 0u, 0u, ac, 3u, 0u)];
+                uint32_t n1 = 0, n2 = 0, n3 = 0;
+                for (uint32_t t2 = t + 1; t2 < sOff[a + 1]; t2++) {
+                    const uint32_t c2 = sAdj[t2] >> 2, ac2 = sAdj[t2] & 3u;
+                    if (L.adjacent(r, c2)) continue;
+                    const uint32_t cc2 = L.code(c, c2);
+                    if (cc2) {
+                        const uint32_t cls = sTable[motif_index4(ra, 0u, 0u, ac, ac2, cc2)];
+                        const uint32_t sv[2] = {r, a};
+                        cr.shared(cls, sv, true);
+                        cr.add_n(c, cls, 1u);
+                        cr.add_n(c2, cls, 1u);
+                    } else {
+                        cr.add_n(c2, ac2 == 1u ? u1 : (ac2 == 2u ? u2 : u3), 1u);
+                        n1 += ac2 == 1u;
+                        n2 += ac2 == 2u;
+                        n3 += ac2 == 3u;
+                    }
+                    shp[2]++;
+                }
+                cr.add3(r, a, c, u1, n1);
+                cr.add3(r, a, c, u2, n2);
+                cr.add3(r, a, c, u3, n3);
             }
             // (1,1,1): path r - a - c - e, e not adjacent to r (nor equal to a) nor to a
-            for (uint32_t te = L.first_above(c, r); te < sOff[c + 1]; te++) {
-                const uint32_t e = sAdj[te] >> 2, ce = sAdj[te] & 3u;
-                if (L.adjacent(r, e) || L.adjacent(a, e)) continue;
-                const uint32_t cls = sTable[motif_index4(ra, 0u, 0u, ac, 0u, ce)];
-                const uint32_t sv[2] = {r, a};
-                cr.shared(cls, sv, true);
-                cr.add_n(c, cls, 1u);
-                cr.add_n(e, cls, 1u);
-                shp[3]++;
+            {
+                const uint32_t w1 = sTable[motif_index4(ra, 0u, 0u, ac, 0u, 1u)];
+                const uint32_t w2 = sTable[motif_index4(ra, 0u, 0u, ac, 0u, 2u)];
+                const uint32_t w3 = sTable[motif_index4(ra, 0u, 0u, ac, 0u, 3u)];
+                uint32_t n1 = 0, n2 = 0, n3 = 0;
+                for (uint32_t te = L.first_above(c, r); te < sOff[c + 1]; te++) {
+                    const uint32_t e = sAdj[te] >> 2, ce = sAdj[te] & 3u;
+                    if (L.adjacent(r, e) || L.adjacent(a, e)) continue;
+                    cr.add_n(e, ce == 1u ? w1 : (ce == 2u ? w2 : w3), 1u);
+                    n1 += ce == 1u;
+                    n2 += ce == 2u;
+                    n3 += ce == 3u;
+                    shp[3]++;
+                }
+                cr.add3(r, a, c, w1, n1);
+                cr.add3(r, a, c, w2, n2);
+                cr.add3(r, a, c, w3, n3);
             }
         }
         __syncthreads();
-        // ---- counters -> output (workgroup-owned rows)
+        // ---- counters -> output.  The block is this workgroup's and was zeroed above; an
+        // LDS-counted class never reaches the output otherwise, so its cells are stored.
         for (uint32_t i = tid; i < n * NC; i += BS) {
             const uint32_t x = sCnt[i];
             if (!x) continue;
             const uint32_t v = i / NC, s = i - v * NC;
             const uint32_t cls = K == 3 ? s : A.comp_cls[s];
-            out_add(&G.out[(size_t)G.perm[v] * C + cls], (unsigned long long)x);
+            G.out[(size_t)G.perm[v] * C + cls] = (unsigned long long)x;
         }
         // visited-set counters per shape: k = 3 -> (1,1), (1,2); k = 4 -> the four shapes
         for (int s = 0; s < 4; s++) {
