@@ -91,6 +91,17 @@ struct SmallLds {
     __device__ __forceinline__ bool adjacent(uint32_t u, uint32_t v) const {
         return (bits[u * W + (v >> 5)] >> (v & 31u)) & 1u;
     }
+    // arc bits of (u, v) seen from u for a pair whose adjacency bit is already read
+    __device__ __forceinline__ uint32_t code_if(bool is_adj, uint32_t u, uint32_t v) const {
+        if (!is_adj) return 0u;
+        uint32_t lo = off[u], hi = off[u + 1];
+        const uint32_t key = v << 2;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (adj[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        return adj[lo] & 3u;
+    }
     // arc bits of (u, v) seen from u, 0 if not adjacent
     __device__ __forceinline__ uint32_t code(uint32_t u, uint32_t v) const {
         if (!adjacent(u, v)) return 0u;
@@ -132,6 +143,8 @@ struct SmallCredit {
         if (s < NC) atomicAdd(&cnt[v * NC + s], n);
         else out_add(&out[(size_t)perm[v] * C + cls], (unsigned long long)n);
     }
+    // n sets of a class whose counter slot s (< NC) is already known
+    __device__ __forceinline__ void add_s(uint32_t v, uint32_t s, uint32_t n) const { atomicAdd(&cnt[v * NC + s], n); }
     // n sets of class cls credited to three members (nothing when n = 0)
     __device__ __forceinline__ void add3(uint32_t u, uint32_t v, uint32_t w, uint32_t cls, uint32_t n) const {
         if (!n) return;
@@ -279,7 +292,8 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 uint32_t n1 = 0, n2 = 0, n3 = 0;
                 for (uint32_t l = j + 1; l < d; l++) {
                     const uint32_t c = P[l] >> 2, rc = P[l] & 3u;
-                    const uint32_t ac = L.code(a, c), bc = L.code(b, c);
+                    const bool xa = L.adjacent(a, c), xb = L.adjacent(b, c);   // both reads in flight
+                    const uint32_t ac = L.code_if(xa, a, c), bc = L.code_if(xb, b, c);
                     if (ac | bc) {
                         const uint32_t cls = sTable[motif_index4(ra, rb, rc, ab, ac, bc)];
                         const uint32_t sv[3] = {r, b, c};   // lanes share j, hence b and c
@@ -326,20 +340,21 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t q1 = sTable[motif_index4(ra, 1u, 0u, 0u, ac, 0u)];
                 const uint32_t q2 = sTable[motif_index4(ra, 2u, 0u, 0u, ac, 0u)];
                 const uint32_t q3 = sTable[motif_index4(ra, 3u, 0u, 0u, ac, 0u)];
+                const uint32_t s1 = cr.slot(q1), s2 = cr.slot(q2), s3 = cr.slot(q3);   // 4-path classes: tree slots
                 uint32_t n1 = 0, n2 = 0, n3 = 0;
                 for (uint32_t jb = 0; jb < d; jb++) {
                     if (jb == ia) continue;
                     const uint32_t b = P[jb] >> 2, rb = P[jb] & 3u;
-                    const uint32_t bc = L.code(b, c);
-                    if (bc && jb < ia) continue;
-                    const uint32_t ab = L.code(a, b);
+                    const bool xbc = L.adjacent(b, c), xab = L.adjacent(a, b);   // both reads in flight
+                    if (xbc && jb < ia) continue;
+                    const uint32_t bc = L.code_if(xbc, b, c), ab = L.code_if(xab, a, b);
                     if (ab | bc) {
                         const uint32_t cls = sTable[motif_index4(ra, rb, 0u, ab, ac, bc)];
                         const uint32_t sv[3] = {r, a, b};   // lanes share (r, a) and the loop position
                         cr.shared(cls, sv, true);
                         cr.add_n(c, cls, 1u);
                     } else {
-                        cr.add_n(b, rb == 1u ? q1 : (rb == 2u ? q2 : q3), 1u);
+                        cr.add_s(b, rb == 1u ? s1 : (rb == 2u ? s2 : s3), 1u);
                         n1 += rb == 1u;
                         n2 += rb == 2u;
                         n3 += rb == 3u;
@@ -355,11 +370,13 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t u1 = sTable[motif_index4(ra, 0u, 0u, ac, 1u, 0u)];
                 const uint32_t u2 = sTable[motif_index4(ra, 0u, 0u, ac, 2u, 0u)];
                 const uint32_t u3 = sTable[motif_index4(ra, 0u, 0u, ac, 3u, 0u)];
+                const uint32_t s1 = cr.slot(u1), s2 = cr.slot(u2), s3 = cr.slot(u3);   // 3-star classes: tree slots
                 uint32_t n1 = 0, n2 = 0, n3 = 0;
                 for (uint32_t t2 = t + 1; t2 < sOff[a + 1]; t2++) {
                     const uint32_t c2 = sAdj[t2] >> 2, ac2 = sAdj[t2] & 3u;
-                    if (L.adjacent(r, c2)) continue;
-                    const uint32_t cc2 = L.code(c, c2);
+                    const bool xr = L.adjacent(r, c2), xc = L.adjacent(c, c2);   // both reads in flight
+                    if (xr) continue;
+                    const uint32_t cc2 = L.code_if(xc, c, c2);
                     if (cc2) {
                         const uint32_t cls = sTable[motif_index4(ra, 0u, 0u, ac, ac2, cc2)];
                         const uint32_t sv[2] = {r, a};
@@ -367,7 +384,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                         cr.add_n(c, cls, 1u);
                         cr.add_n(c2, cls, 1u);
                     } else {
-                        cr.add_n(c2, ac2 == 1u ? u1 : (ac2 == 2u ? u2 : u3), 1u);
+                        cr.add_s(c2, ac2 == 1u ? s1 : (ac2 == 2u ? s2 : s3), 1u);
                         n1 += ac2 == 1u;
                         n2 += ac2 == 2u;
                         n3 += ac2 == 3u;
@@ -383,11 +400,12 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t w1 = sTable[motif_index4(ra, 0u, 0u, ac, 0u, 1u)];
                 const uint32_t w2 = sTable[motif_index4(ra, 0u, 0u, ac, 0u, 2u)];
                 const uint32_t w3 = sTable[motif_index4(ra, 0u, 0u, ac, 0u, 3u)];
+                const uint32_t s1 = cr.slot(w1), s2 = cr.slot(w2), s3 = cr.slot(w3);   // 4-path classes: tree slots
                 uint32_t n1 = 0, n2 = 0, n3 = 0;
                 for (uint32_t te = L.first_above(c, r); te < sOff[c + 1]; te++) {
                     const uint32_t e = sAdj[te] >> 2, ce = sAdj[te] & 3u;
-                    if (L.adjacent(r, e) || L.adjacent(a, e)) continue;
-                    cr.add_n(e, ce == 1u ? w1 : (ce == 2u ? w2 : w3), 1u);
+                    if (L.adjacent(r, e) | L.adjacent(a, e)) continue;   // both reads in flight
+                    cr.add_s(e, ce == 1u ? s1 : (ce == 2u ? s2 : s3), 1u);
                     n1 += ce == 1u;
                     n2 += ce == 2u;
                     n3 += ce == 3u;
