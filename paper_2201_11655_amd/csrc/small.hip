@@ -223,6 +223,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
         uint32_t* sCnt = sBits + n * W;       // n * NC
         uint32_t* sAdj = sCnt + n * NC;       // E
         uint32_t* sPre2 = sAdj + E;           // E / 2 + 1: depth-2 candidates before each upper entry
+        uint16_t* sRootOf = reinterpret_cast<uint16_t*>(sPre2 + E / 2 + 1);   // E / 2: root of each upper entry
         // ---- stage the graph, clear bitmap, counters and the output block
         for (uint32_t i = tid; i <= n; i += BS) sOff[i] = G.off[i];
         for (uint32_t i = tid; i < E; i += BS) sAdj[i] = G.adj[i];
@@ -257,6 +258,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
             for (uint32_t t = sSplit[r]; t < sOff[r + 1]; t++) {
                 const uint32_t a = sAdj[t] >> 2;
                 sPre2[sPreD[r] + (t - sSplit[r])] = sOff[a + 1] - L.first_above(a, r);
+                sRootOf[sPreD[r] + (t - sSplit[r])] = (uint16_t)r;
             }
         if (tid == 0) sPre2[U] = 0u;
         __syncthreads();
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
         // ---- depth-2 entries (r, a, c)
         for (uint32_t q = tid; q < N2; q += BS) {
             const uint32_t u = upper_idx(sPre2, U + 1, q);
-            const uint32_t r = upper_idx(sPreD, n + 1, u);
+            const uint32_t r = sRootOf[u];
             const uint32_t* P = sAdj + sSplit[r];
             const uint32_t d = sOff[r + 1] - sSplit[r];
             const uint32_t ia = u - sPreD[r];
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
 size_t small_lds_bytes(int64_t n, int64_t entries, int k) {
     const int64_t W = (n + 31) / 32;
     const int64_t nc = k == 3 ? kClasses3 : kCompact4;
-    const int64_t words = (n + 1) * 3 + n + n * W + n * nc + entries + entries / 2 + 1;
+    const int64_t words = (n + 1) * 3 + n + n * W + n * nc + entries + entries / 2 + 1 + (entries / 2 + 1) / 2;
     return (size_t)words * sizeof(uint32_t);
 }
 
