@@ -173,12 +173,14 @@ vdmc_status vdmc_free_graph(vdmc_graph g);
  * along the BFS shapes of Lemma 2 under the rules of Lemmas 3-4: one lane assembles
  * its index (Sec. 4.1), looks up its class and credits the class to its k vertices
  * (vdmc_shape_counts reports the sets visited per shape).
- * k in {3, 4, 5}, other k INVALID_ARG.  k = 5 (n x 9364 output) takes graphs held
- * whole in one workgroup's LDS -- n <= 512 and 4 (4n + 2 + 2 pairs + n ceil(n/32))
- * bytes of CSR, id map and 1-bit adjacency matrix within 159744 -- and gives UNSUPPORTED
- * for any other (vdmc_count_supported tells which); its sets are visited along the
- * eight BFS layer shapes of five vertices (vdmc_profile_counters).  A graph with n < k
- * gives an all-zero matrix.  Asynchronous on `stream`; `out` must not be in use by
+ * k in {3, 4, 5}, other k INVALID_ARG.  k = 5 (n x 9364 output; n < 229,338): a graph
+ * held whole in one workgroup's LDS -- n <= 512 and 4 (4n + 2 + 2 pairs + n ceil(n/32))
+ * bytes of CSR, id map and 1-bit adjacency matrix within 159744 -- is counted there;
+ * any other is counted in device memory, which at its first 5-vertex count builds the
+ * graph's edge hash (2^ceil(log2(4 pairs)) 8-byte slots) and an (n + 2) x 8-byte item
+ * table, kept with the graph and synchronising `stream` once.  Its sets are visited
+ * along the eight BFS layer shapes of five vertices (vdmc_profile_counters).  A graph
+ * with n < k gives an all-zero matrix.  Asynchronous on `stream`; `out` must not be in use by
  * another call.  The first count on a graph (and the first after a change of its hub
  * threshold) bins its roots and synchronises `stream`; the hub path's scratch is
  * allocated then and kept with the graph.  Roots with at most 2048 higher neighbours
@@ -188,7 +190,7 @@ vdmc_status vdmc_free_graph(vdmc_graph g);
 vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream);
 
 /* 1 if vdmc_count(g, k, ...) and vdmc_count_batch with g can run (k = 3, 4: any graph;
- * k = 5: the LDS bound above), 0 if they give UNSUPPORTED, -1 for a NULL graph or a k
+ * k = 5: n x 9364 below 2^31), 0 if they give UNSUPPORTED, -1 for a NULL graph or a k
  * outside 3..5.  Lets a caller skip allocating an n x 9364 output it cannot use. */
 int32_t vdmc_count_supported(vdmc_graph g, int32_t k);
 
@@ -242,9 +244,9 @@ vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out, int32_t n);
  * persistent launch whose work tiles come from a device-side cursor; the launch is
  * captured in a HIP graph the first time a batch signature (same graphs, same
  * outputs, same k) is seen and replayed afterwards.  Asynchronous on `stream`.
- * k = 5: every graph must satisfy vdmc_count_supported (else UNSUPPORTED); with at
- * least one graph per compute unit each graph is counted whole by one workgroup, else
- * the graphs' items are split over the grid; the launch is not captured.
+ * k = 5: every graph must satisfy vdmc_count_supported (else UNSUPPORTED).  The graphs
+ * that LDS holds are counted by one launch (graphs cut into parts with private blocks,
+ * summed afterwards), the others one by one in device memory after it; not captured.
  */
 vdmc_status vdmc_count_batch(const vdmc_graph* gs, int32_t num, int32_t k,
                              uint64_t* const* outs, void* stream);

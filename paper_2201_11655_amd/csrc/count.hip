@@ -515,9 +515,8 @@ vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream) {
         VDMC_REQUIRE(out != nullptr || g->n == 0, VDMC_ERR_INVALID_ARG, "out is NULL");
         VDMC_HIP(hipSetDevice(g->device));
         if (k == 5) {
-            VDMC_REQUIRE(vdmc::five_eligible(g->n, 2 * g->pairs), VDMC_ERR_UNSUPPORTED,
-                         "5-vertex counts take graphs held whole in LDS: n <= " + std::to_string(vdmc::kFiveMaxN) +
-                             " and the CSR plus a 2-bit arc matrix within one workgroup's LDS");
+            VDMC_REQUIRE(g->n < ((int64_t)1 << 31) / vdmc::kClasses5, VDMC_ERR_UNSUPPORTED,
+                         "5-vertex counts: n x 9364 must stay below 2^31 counters per row index");
             (void)vdmc::class_table5();
             vdmc::GraphUse use(g, vdmc::as_stream(stream));
             vdmc::launch_count5(g, out, vdmc::as_stream(stream));
@@ -531,7 +530,7 @@ vdmc_status vdmc_count(vdmc_graph g, int32_t k, uint64_t* out, void* stream) {
 
 int32_t vdmc_count_supported(vdmc_graph g, int32_t k) {
     if (g == nullptr || k < 3 || k > 5) return -1;
-    if (k == 5) return vdmc::five_eligible(g->n, 2 * g->pairs) ? 1 : 0;
+    if (k == 5) return g->n < ((int64_t)1 << 31) / vdmc::kClasses5 ? 1 : 0;
     return 1;
 }
 

@@ -41,11 +41,17 @@
 // launch adds the copies of each graph with P > 1 into its output.  Parts are claimed
 // heaviest graph first from a slot cursor; items of a graph are handed out in rank
 // order, the heavy roots first.
+// Graphs that LDS does not hold take the same search over the graph in device memory
+// (k_five_global): pair tests from the graph's edge hash, rows searched in place, one
+// item cursor for the whole grid and device-scope credits to the caller's output.
 // Visited sets are counted per shape (the graph's 8 counters) so that callers can
 // check that every set was visited: their sum is the number of connected 5-sets.
 #include <cmath>
 #include <map>
 
+#include <hipcub/hipcub.hpp>
+
+#include "motif_device.h"
 #include "vdmc_internal.h"
 
 namespace vdmc {
@@ -104,6 +110,28 @@ struct FiveLds {
     }
 };
 
+// The same interface over a graph in device memory, for graphs that LDS does not hold:
+// pair tests and arc bits from the graph's edge hash (one probe sequence), rows searched
+// in place.
+struct FiveGlobal {
+    const uint32_t* off;
+    const uint32_t* adj;
+    const uint32_t* perm;
+    const unsigned long long* eh;
+    uint32_t ebits;
+    __device__ __forceinline__ bool adjacent(uint32_t u, uint32_t v) const { return edge_code(eh, ebits, u, v) != 0u; }
+    __device__ __forceinline__ uint32_t bits(uint32_t u, uint32_t v) const { return edge_code(eh, ebits, u, v); }
+    __device__ __forceinline__ uint32_t first_above(uint32_t u, uint32_t x) const {
+        uint32_t lo = off[u], hi = off[u + 1];
+        const uint32_t key = (x + 1u) << 2;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (adj[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    }
+};
+
 // member i of S (i < 5 is not a compile-time constant where this is called)
 __device__ __forceinline__ uint32_t member(const uint32_t (&S)[5], uint32_t i) {
     uint32_t v = S[0];
@@ -115,7 +143,8 @@ __device__ __forceinline__ uint32_t member(const uint32_t (&S)[5], uint32_t i) {
 }
 
 // y adjacent to none of S[0..lim)
-__device__ __forceinline__ bool clear_of(const FiveLds& L, const uint32_t (&S)[5], uint32_t lim, uint32_t y) {
+template <class V>
+__device__ __forceinline__ bool clear_of(const V& L, const uint32_t (&S)[5], uint32_t lim, uint32_t y) {
 #pragma unroll
     for (uint32_t m = 0; m < 4; m++)
         if (m < lim && L.adjacent(S[m], y)) return false;
@@ -128,7 +157,8 @@ __device__ __forceinline__ bool clear_of(const FiveLds& L, const uint32_t (&S)[5
 // parents left in the phase, [j, jend) the rest of the parent's row.
 struct Cand {
     uint32_t pi, pend, j, jend, phase, ls, pbits;   // pbits: arc bits of the last candidate with its parent
-    __device__ __forceinline__ void start(const FiveLds& L, const uint32_t (&S)[5], uint32_t par, uint32_t pos,
+    template <class V>
+    __device__ __forceinline__ void start(const V& L, const uint32_t (&S)[5], uint32_t par, uint32_t pos,
                                           uint32_t ls_prev) {
         pi = par;
         pend = ls_prev;
@@ -138,7 +168,8 @@ struct Cand {
         ls = ls_prev;
     }
     // next candidate vertex, or kNone; t = the S index being chosen
-    __device__ __forceinline__ uint32_t next(const FiveLds& L, const uint32_t (&S)[5], uint32_t t) {
+    template <class V>
+    __device__ __forceinline__ uint32_t next(const V& L, const uint32_t (&S)[5], uint32_t t) {
         for (;;) {
             while (j < jend) {
                 const uint32_t e = L.adj[j++], y = e >> 2;
@@ -170,27 +201,32 @@ struct Cand {
 // arc bits of (S[m], y) seen from S[m], for the candidate y just returned by c: its
 // parent's come with the entry, members before the parent are not adjacent to it (the
 // candidate rule), the others are looked up
-__device__ __forceinline__ uint32_t arc_of(const FiveLds& L, const uint32_t (&S)[5], uint32_t m, const Cand& c,
+template <class V>
+__device__ __forceinline__ uint32_t arc_of(const V& L, const uint32_t (&S)[5], uint32_t m, const Cand& c,
                                            uint32_t y) {
     if (m == c.pi) return c.pbits;
     if (m < c.pi) return 0u;
     return L.bits(S[m], y);
 }
 
-// credits to an output block that belongs to the calling workgroup (no other workgroup
-// touches the block during the launch)
+// credits: workgroup scope to an output block that belongs to the calling workgroup (no
+// other workgroup touches it during the launch), device scope to an output all
+// workgroups share (kDev)
+template <bool kDev>
 __device__ __forceinline__ void bump(unsigned long long* p, unsigned long long v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (kDev) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // v sets of class cls credited to the four fixed members of a context
+template <bool kDev>
 __device__ __forceinline__ void credit4(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2, uint32_t P3,
                                         uint32_t cls, unsigned long long v) {
     if (v == 0ull || cls >= (uint32_t)kClasses5) return;
-    bump(&out[(size_t)P0 * kClasses5 + cls], v);
-    bump(&out[(size_t)P1 * kClasses5 + cls], v);
-    bump(&out[(size_t)P2 * kClasses5 + cls], v);
-    bump(&out[(size_t)P3 * kClasses5 + cls], v);
+    bump<kDev>(&out[(size_t)P0 * kClasses5 + cls], v);
+    bump<kDev>(&out[(size_t)P1 * kClasses5 + cls], v);
+    bump<kDev>(&out[(size_t)P2 * kClasses5 + cls], v);
+    bump<kDev>(&out[(size_t)P3 * kClasses5 + cls], v);
 }
 
 // Per-lane cache of the last member's signatures in one context: entry = (count << 8) |
@@ -205,23 +241,25 @@ struct SigCache {
         if (e3 && (e3 & 255u) == sig) { e3 += 256u; return k3; }
         return kNone;
     }
+    template <bool kDev>
     __device__ __forceinline__ void insert(uint32_t sig, uint32_t cls, unsigned long long* out, uint32_t P0,
                                            uint32_t P1, uint32_t P2, uint32_t P3) {
         const uint32_t e = 256u | sig;
         switch (victim) {
-            case 0: credit4(out, P0, P1, P2, P3, k0, e0 >> 8); e0 = e; k0 = cls; break;
-            case 1: credit4(out, P0, P1, P2, P3, k1, e1 >> 8); e1 = e; k1 = cls; break;
-            case 2: credit4(out, P0, P1, P2, P3, k2, e2 >> 8); e2 = e; k2 = cls; break;
-            default: credit4(out, P0, P1, P2, P3, k3, e3 >> 8); e3 = e; k3 = cls; break;
+            case 0: credit4<kDev>(out, P0, P1, P2, P3, k0, e0 >> 8); e0 = e; k0 = cls; break;
+            case 1: credit4<kDev>(out, P0, P1, P2, P3, k1, e1 >> 8); e1 = e; k1 = cls; break;
+            case 2: credit4<kDev>(out, P0, P1, P2, P3, k2, e2 >> 8); e2 = e; k2 = cls; break;
+            default: credit4<kDev>(out, P0, P1, P2, P3, k3, e3 >> 8); e3 = e; k3 = cls; break;
         }
         victim = (victim + 1u) & 3u;
     }
+    template <bool kDev>
     __device__ __forceinline__ void flush_all(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2,
                                               uint32_t P3) {
-        credit4(out, P0, P1, P2, P3, k0, e0 >> 8);
-        credit4(out, P0, P1, P2, P3, k1, e1 >> 8);
-        credit4(out, P0, P1, P2, P3, k2, e2 >> 8);
-        credit4(out, P0, P1, P2, P3, k3, e3 >> 8);
+        credit4<kDev>(out, P0, P1, P2, P3, k0, e0 >> 8);
+        credit4<kDev>(out, P0, P1, P2, P3, k1, e1 >> 8);
+        credit4<kDev>(out, P0, P1, P2, P3, k2, e2 >> 8);
+        credit4<kDev>(out, P0, P1, P2, P3, k3, e3 >> 8);
     }
 };
 
@@ -239,7 +277,8 @@ __device__ __forceinline__ uint32_t item_split(uint32_t dhi, uint32_t deg, uint3
 
 // Every set of the sub-item k of K of the item (root r, first layer-1 member at entry apos
 // of r's row).
-__device__ void five_item(const FiveLds& L, const uint16_t* __restrict__ table, unsigned long long* __restrict__ out,
+template <class V, bool kDev>
+__device__ void five_item(const V& L, const uint16_t* __restrict__ table, unsigned long long* __restrict__ out,
                           uint32_t r, uint32_t apos, uint32_t k, uint32_t K, unsigned long long* vis) {
     uint32_t S[5];
     S[0] = r;
@@ -287,12 +326,12 @@ __device__ void five_item(const FiveLds& L, const uint16_t* __restrict__ table, 
                 if (cls == kNone) {
                     cls = table[code3 | pair_bits(0, 4, b0) | pair_bits(1, 4, b1) | pair_bits(2, 4, b2) |
                                 pair_bits(3, 4, b3)];
-                    sc.insert(sig, cls, out, P0, P1, P2, P3);
+                    sc.insert<kDev>(sig, cls, out, P0, P1, P2, P3);
                 }
-                if (cls < (uint32_t)kClasses5) bump(&out[(size_t)L.perm[y4] * kClasses5 + cls], 1ull);
+                if (cls < (uint32_t)kClasses5) bump<kDev>(&out[(size_t)L.perm[y4] * kClasses5 + cls], 1ull);
                 if (c4.phase) opened++; else same++;
             }
-            sc.flush_all(out, P0, P1, P2, P3);
+            sc.flush_all<kDev>(out, P0, P1, P2, P3);
             // shape id: bit 2 = a new layer opens at member 2, bit 1 at member 3, bit 0 at member 4
             const uint32_t base = (ls2 == 2u ? 4u : 0u) | (ls3 == 3u ? 2u : 0u);
             add_shape(vis, base, same);
@@ -429,7 +468,7 @@ __global__ __launch_bounds__(BS) void k_five(FiveArgs A) {
             }
             const uint32_t K = item_split(L.off[rlo + 1] - sSplit[rlo], L.off[rlo + 1] - L.off[rlo], A.split_div);
             const uint32_t local = i - sHp[rlo];
-            five_item(L, A.table, dst, rlo, sSplit[rlo] + local / K, local % K, K, s_vis);
+            five_item<FiveLds, false>(L, A.table, dst, rlo, sSplit[rlo] + local / K, local % K, K, s_vis);
         }
         __syncthreads();
         if (tid < 8 && s_vis[tid]) atomicAdd(&G.stats[tid], s_vis[tid]);
@@ -472,6 +511,57 @@ __global__ __launch_bounds__(256) void k_five_reduce(FiveArgs A) {
         const FiveGraph& G = A.graphs ? A.graphs[gi] : A.one;
         if (G.parts > 1) five_reduce_one(G);
     }
+}
+
+// ----------------------------------------------------------------------------- graphs in device memory
+
+struct FiveGlobalArgs {
+    FiveGlobal L;
+    const uint32_t* split;
+    const unsigned long long* hp;   // n + 1: items (sub-items) before each root
+    uint32_t n;
+    unsigned long long total;
+    unsigned long long* out;        // n x 9364, shared by every workgroup
+    unsigned long long* stats;
+    unsigned long long* cursor;     // item cursor, zeroed before the launch
+    const uint16_t* table;
+    uint32_t split_div;
+};
+
+// items of each root: d+(r) x K(r); cnt[n] = 0 so that an exclusive scan over n + 1 gives the total
+__global__ void k_five_counts(const uint32_t* off, const uint32_t* split, uint32_t n, uint32_t div,
+                              unsigned long long* cnt) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    if (r == n) {
+        cnt[n] = 0ull;
+        return;
+    }
+    const uint32_t dhi = off[r + 1] - split[r];
+    cnt[r] = (unsigned long long)dhi * item_split(dhi, off[r + 1] - off[r], div);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_five_global(FiveGlobalArgs A) {
+    __shared__ unsigned long long s_vis[8];
+    const uint32_t tid = threadIdx.x;
+    if (tid < 8) s_vis[tid] = 0ull;
+    __syncthreads();
+    for (;;) {
+        const unsigned long long i = atomicAdd(A.cursor, 1ull);
+        if (i >= A.total) break;
+        uint32_t lo = 0, hi = A.n;   // root: last r with hp[r] <= i
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (A.hp[mid] <= i) lo = mid; else hi = mid;
+        }
+        const uint32_t r = lo, e = A.L.off[r + 1], sp = A.split[r];
+        const uint32_t K = item_split(e - sp, e - A.L.off[r], A.split_div);
+        const uint32_t local = (uint32_t)(i - A.hp[r]);
+        five_item<FiveGlobal, true>(A.L, A.table, A.out, r, sp + local / K, local % K, K, s_vis);
+    }
+    __syncthreads();
+    if (tid < 8 && s_vis[tid]) atomicAdd(&A.stats[tid], s_vis[tid]);
 }
 
 int g_ncu = -1;
@@ -568,12 +658,73 @@ bool five_eligible(int64_t n, int64_t entries) {
     return n <= kFiveMaxN && five_lds_bytes(n, entries) <= kFiveLdsBudget;
 }
 
-void launch_count5(vdmc_graph_s* g, uint64_t* out, hipStream_t st) {
-    VDMC_REQUIRE(five_eligible(g->n, 2 * g->pairs), VDMC_ERR_UNSUPPORTED,
-                 "5-vertex counts take graphs held whole in LDS: n <= " + std::to_string(kFiveMaxN) +
-                     " and the CSR plus a 1-bit adjacency matrix within " + std::to_string(kFiveLdsBudget) + " bytes");
+namespace {
+
+// 5-vertex counts of a graph that LDS does not hold: every workgroup of the grid takes
+// sub-items from one cursor and credits the caller's output with device-scope atomics.
+// Needs the graph's edge hash and its item prefix (both built at the first such count
+// and kept with the graph).
+void launch_count5_global(vdmc_graph_s* g, uint64_t* out, hipStream_t st) {
     const ClassTable5& t = class_table5();
+    launch_fill_u64((uint64_t*)g->stats, kStatSlots, 0, st);
+    if (g->n == 0) return;
+    launch_fill_u64(out, (size_t)g->n * kClasses5, 0, st);
+    if (g->pairs == 0) return;
+    ensure_edge_hash(g, st);
+    if (!g->five_hp) {
+        const uint32_t n = (uint32_t)g->n;
+        unsigned long long *cnt = nullptr, *hp = nullptr;
+        VDMC_HIP(hipMalloc(&hp, sizeof(unsigned long long) * (n + 2)));   // prefix, then the item cursor
+        VDMC_HIP(hipMalloc(&cnt, sizeof(unsigned long long) * (n + 1)));
+        struct Free {
+            void* p;
+            ~Free() { (void)hipFree(p); }
+        } fcnt{cnt};
+        hipLaunchKernelGGL(k_five_counts, dim3((n + 256) / 256), dim3(256), 0, st, g->off, g->split, n, kSplitDiv, cnt);
+        VDMC_HIP(hipGetLastError());
+        size_t tmp_bytes = 0;
+        VDMC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, hp, n + 1, st));
+        void* tmp = nullptr;
+        VDMC_HIP(hipMalloc(&tmp, tmp_bytes ? tmp_bytes : 16));
+        struct Free2 {
+            void* p;
+            ~Free2() { (void)hipFree(p); }
+        } ftmp{tmp};
+        VDMC_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, hp, n + 1, st));
+        unsigned long long total = 0;
+        VDMC_HIP(hipMemcpyAsync(&total, hp + n, sizeof(total), hipMemcpyDeviceToHost, st));
+        VDMC_HIP(hipStreamSynchronize(st));
+        g->five_hp = hp;
+        g->five_items = total;
+    }
+    unsigned long long* cursor = g->five_hp + g->n + 1;
+    launch_fill_u64((uint64_t*)cursor, 1, 0, st);
+    FiveGlobalArgs a{};
+    a.L = FiveGlobal{g->off, g->adj, reinterpret_cast<const uint32_t*>(g->perm), g->ehash, g->ehash_bits};
+    a.split = g->split;
+    a.hp = g->five_hp;
+    a.n = (uint32_t)g->n;
+    a.total = g->five_items;
+    a.out = (unsigned long long*)out;
+    a.stats = g->stats;
+    a.cursor = cursor;
+    a.table = t.table;
+    a.split_div = kSplitDiv;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu() * 4,
+                                                                           (int64_t)((g->five_items + 255) / 256)));
+    hipLaunchKernelGGL(k_five_global<256>, dim3(grid), dim3(256), 0, st, a);
+    VDMC_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void launch_count5(vdmc_graph_s* g, uint64_t* out, hipStream_t st) {
     g->timed_light = g->timed_hub = false;
+    if (!five_eligible(g->n, 2 * g->pairs)) {
+        launch_count5_global(g, out, st);
+        return;
+    }
+    const ClassTable5& t = class_table5();
     // parts: one per 32 items, at most two per compute unit, copies within the budget.  The
     // cursors and the copies come from the stream-ordered pool and go back to it after the
     // launches, so concurrent counts on other streams never share them.
@@ -605,14 +756,16 @@ void launch_count5(vdmc_graph_s* g, uint64_t* out, hipStream_t st) {
     VDMC_HIP(hipFreeAsync(buf, st));
 }
 
-void count5_batch(const vdmc_graph_s* const* gs_in, int32_t num, uint64_t* const* outs, hipStream_t st) {
-    std::vector<vdmc_graph_s*> gs(num);
-    for (int i = 0; i < num; i++) {
-        gs[i] = const_cast<vdmc_graph_s*>(gs_in[i]);
-        VDMC_REQUIRE(five_eligible(gs[i]->n, 2 * gs[i]->pairs), VDMC_ERR_UNSUPPORTED,
-                     "graph " + std::to_string(i) + ": 5-vertex counts take graphs held whole in LDS (n <= " +
-                         std::to_string(kFiveMaxN) + ")");
-    }
+void free_five(vdmc_graph_s* g) {
+    (void)hipFree(g->five_hp);
+    g->five_hp = nullptr;
+    g->five_items = 0;
+}
+
+void count5_batch_lds(std::vector<vdmc_graph_s*>& gs, std::vector<uint64_t*>& outv, hipStream_t st) {
+    const int32_t num = (int32_t)gs.size();
+    if (num == 0) return;
+    uint64_t* const* outs = outv.data();
     const ClassTable5& t = class_table5();
     std::lock_guard<std::mutex> lock(g_five_mu);
     FivePlan* plan = nullptr;
@@ -697,6 +850,28 @@ void count5_batch(const vdmc_graph_s* const* gs_in, int32_t num, uint64_t* const
     a.table = t.table;
     a.split_div = kSplitDiv;
     launch_five(a, plan->lds, (uint32_t)num, plan->reduce, st);
+}
+
+void count5_batch(const vdmc_graph_s* const* gs_in, int32_t num, uint64_t* const* outs_in, hipStream_t st) {
+    // graphs that LDS holds go into one batched launch; the others are counted one by one
+    // in device memory after it
+    std::vector<vdmc_graph_s*> gs;
+    std::vector<uint64_t*> outv;
+    for (int i = 0; i < num; i++) {
+        vdmc_graph_s* g = const_cast<vdmc_graph_s*>(gs_in[i]);
+        if (five_eligible(g->n, 2 * g->pairs)) {
+            gs.push_back(g);
+            outv.push_back(outs_in[i]);
+        }
+    }
+    count5_batch_lds(gs, outv, st);
+    for (int i = 0; i < num; i++) {
+        vdmc_graph_s* g = const_cast<vdmc_graph_s*>(gs_in[i]);
+        if (!five_eligible(g->n, 2 * g->pairs)) {
+            GraphUse use(g, st);
+            launch_count5_global(g, outs_in[i], st);
+        }
+    }
 }
 
 void invalidate_five_plans(vdmc_graph_s* g) {

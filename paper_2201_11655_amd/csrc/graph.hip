@@ -348,6 +348,7 @@ static void build_graph(int64_t n, int64_t m, const int32_t* src, const int32_t*
 
 static void free_graph_arrays(vdmc_graph_s* g) {
     free_hub(g);
+    free_five(g);
     (void)hipFree(g->utmp);
     (void)hipFree(g->ehash);
     (void)hipFree(g->epid);

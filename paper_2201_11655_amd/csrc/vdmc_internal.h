@@ -167,6 +167,10 @@ struct vdmc_graph_s {
     // end of the last call's device work on this graph (every call's work is ordered after
     // the previous call's, whatever the streams)
     std::shared_ptr<vdmc::DoneEvent> last;
+    // 5-vertex counts in device memory (graphs that LDS does not hold): items before each
+    // root, then the item cursor; built at the first such count
+    unsigned long long* five_hp = nullptr;
+    unsigned long long five_items = 0;
 };
 
 namespace vdmc {
@@ -298,11 +302,13 @@ void launch_count_edges(vdmc_graph_s* g, int k, uint64_t* out, hipStream_t strea
 void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4, hipStream_t stream,
                 uint32_t rank_lo = 0, uint32_t rank_hi = 0xFFFFFFFFu, const hipEvent_t* around = nullptr);
 void free_hub(vdmc_graph_s* g);
-// 5-vertex motifs (count5.hip): graphs held whole in one workgroup's LDS
+// 5-vertex motifs (count5.hip): graphs held whole in one workgroup's LDS, others in device memory
 constexpr int64_t kFiveMaxN = 512;
 size_t five_lds_bytes(int64_t n, int64_t entries);
 bool five_eligible(int64_t n, int64_t entries);
 void launch_count5(vdmc_graph_s* g, uint64_t* out, hipStream_t stream);   // caller holds the graph (GraphUse)
+void count5_batch_lds(std::vector<vdmc_graph_s*>& gs, std::vector<uint64_t*>& outs, hipStream_t stream);
 void count5_batch(const vdmc_graph_s* const* gs, int32_t num, uint64_t* const* outs, hipStream_t stream);
 void invalidate_five_plans(vdmc_graph_s* g);
+void free_five(vdmc_graph_s* g);   // the graph's 5-vertex state; caller makes sure no count runs
 }  // namespace vdmc

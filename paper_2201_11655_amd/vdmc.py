@@ -278,7 +278,7 @@ def count_edges(g: Graph, k: int, out=None, stream=None):
 
 
 def count_supported(g: Graph, k: int) -> bool:
-    """Whether vdmc_count can count g for this k (k = 5: graphs held whole in LDS)."""
+    """Whether vdmc_count can count g for this k (k = 5: n x 9364 below 2^31)."""
     return int(load().vdmc_count_supported(g.handle, int(k))) == 1
 
 
@@ -287,7 +287,7 @@ def count(g: Graph, k: int, out=None, stream=None):
     if k not in (3, 4, 5):
         _check(load().vdmc_count(g.handle, int(k), None, _stream_handle(stream)))
     if k == 5 and not count_supported(g, 5):
-        raise VdmcError(4, f"5-vertex counts take graphs held whole in LDS (n <= 512); n = {g.n}")
+        raise VdmcError(4, f"5-vertex counts need n x 9364 below 2^31; n = {g.n}")
     out = _out_tensor(g.n, k, out)
     _check(load().vdmc_count(g.handle, int(k), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
@@ -346,7 +346,7 @@ def count_batch(graphs, k: int, outs=None, stream=None):
     if k == 5:
         for i, g in enumerate(graphs):
             if not count_supported(g, 5):
-                raise VdmcError(4, f"graph {i}: 5-vertex counts take graphs held whole in LDS (n <= 512)")
+                raise VdmcError(4, f"graph {i}: 5-vertex counts need n x 9364 below 2^31")
     if outs is None:
         outs = [_out_tensor(g.n, k, None) for g in graphs]
     hs = (ctypes.c_void_p * max(1, len(graphs)))(*[g.handle.value for g in graphs])

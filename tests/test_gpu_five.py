@@ -4,8 +4,9 @@ against the CPU oracle, every uint64 entry equal.
 Covers the class table (2^20 codes, 9364 classes), single-graph counts (workgroups
 sharing one graph's items, device-scope credits), batched counts in both modes (one
 workgroup per graph when there are at least as many graphs as compute units, shared
-otherwise), the visited-set counters per BFS layer shape, the degenerate cases (n < 5,
-no arcs, self-loops, isolated vertices) and the size limit of the LDS-resident kernel.
+otherwise), graphs too large for LDS (counted in device memory), mixed batches, the
+visited-set counters per BFS layer shape and the degenerate cases (n < 5, no arcs,
+self-loops, isolated vertices).
 """
 import math
 import sys
@@ -145,24 +146,48 @@ def test_batch_shared_mode(v):
         assert (_np(o) == want).all(), i
 
 
-def test_size_limit_and_errors(v):
-    import torch
-    big = gg.er_directed(513, 0.01, (94, 1))
-    G = v.Graph(big.n, big.src, big.dst)
-    assert not v.count_supported(G, 5) and v.count_supported(G, 4)
-    out = torch.zeros((513, C5), dtype=torch.int64, device="cuda")
-    with pytest.raises(v.VdmcError) as e:
-        v.count(G, 5, out)
-    assert e.value.name == "UNSUPPORTED"
+@pytest.mark.parametrize("case", [("er", 1200, 0.004, 1), ("er", 3000, 0.0015, 2),
+                                  ("chunglu", 800, 3200, 40.0), ("chunglu", 1500, 4500, 30.0)])
+def test_parity_device_memory_path(v, case):
+    """Graphs that one workgroup's LDS does not hold (n > 512): the search runs over the
+    graph in device memory (edge-hash pair tests, one shared item cursor, device-scope
+    credits)."""
+    if case[0] == "er":
+        _, n, p, seed = case
+        g = gg.er_directed(n, p, (95, seed))
+    else:
+        _, n, m, wcap = case
+        g = gg.chung_lu(n, m, 2.1, wcap, 0.2, int(2 * wcap), (96, n))
+    G, sc = _check(v, g.n, g.src, g.dst, f"{case[0]}({g.n}) in device memory")
+    assert G.n > 512
+
+
+def test_batch_mixed_lds_and_device_memory(v):
+    """A batch whose graphs are partly too large for LDS: the LDS ones in the batched
+    launch, the others counted in device memory after it; all equal to the oracle."""
+    gs = gg.er_batch(12, 30, 300, 2.0, 5.0, seed=97)
+    gs[2] = gg.er_directed(900, 0.005, (97, 2))
+    gs[7] = gg.er_directed(700, 0.006, (97, 7))
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in gs]
+    outs = v.count_batch(Gs, 5)
+    for i, (g, G, o) in enumerate(zip(gs, Gs, outs)):
+        want, tot = oracle.count(g.n, g.src, g.dst, 5)
+        assert (_np(o) == want).all(), i
+        assert sum(v.shape_counts5(G).values()) == int(tot.sum()), i
+
+
+def test_limits_and_errors(v):
     import ctypes
     lib = v.load()
-    rc = lib.vdmc_count(G.handle, 5, ctypes.c_void_p(out.data_ptr()), None)
-    assert rc == 4   # UNSUPPORTED from the library itself, not only from the binding
-    ok = v.Graph(512, np.zeros(0, np.int32), np.zeros(0, np.int32))
-    assert v.count_supported(ok, 5)
+    g = gg.er_directed(40, 0.1, (94, 1))
+    G = v.Graph(g.n, g.src, g.dst)
+    assert v.count_supported(G, 5) and v.count_supported(G, 4)
+    assert lib.vdmc_count_supported(G.handle, 6) == -1
     with pytest.raises(v.VdmcError) as e:
-        v.count_batch([ok, G], 5)
-    assert e.value.name == "UNSUPPORTED"
-    with pytest.raises(v.VdmcError) as e:
-        v.count(ok, 6)
+        v.count(G, 6)
     assert e.value.name == "INVALID_ARG"
+    rc = lib.vdmc_count(G.handle, 5, None, None)
+    assert rc == 1   # NULL output
+    empty = v.Graph(600, np.zeros(0, np.int32), np.zeros(0, np.int32))   # device-memory path, no arcs
+    o = v.count(empty, 5)
+    assert int(_np(o).sum()) == 0 and sum(v.shape_counts5(empty).values()) == 0
