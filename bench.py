@@ -51,6 +51,8 @@ WORKLOADS = {
     "chunglu_u": "the Chung-Lu graph with arc directions ignored; undirected 4-vertex motifs (6 classes)",
     "serve": "serving: pool of resident ER and Chung-Lu graphs (even/odd), n log-uniform, mean out-degree "
              "U[2,10], k in {3,4} 50/50, Poisson arrivals at 0.5x and 0.8x the measured capacity",
+    "chunglu5000_k5": "5-vertex motifs of one Chung-Lu graph too large for LDS (n = 5000, the chunglu recipe "
+                      "scaled down: ~50k arcs, max degree 141), counted in device memory",
     "batch256_k5": "5-vertex motifs (9364 classes): the first 256 graphs of the batch4096 recipe (directed "
                    "G(n,p), n ~ U{20..500}, mean out-degree ~ U[2,8], graph i seeded (3,i)); one batched "
                    "launch (one workgroup per graph) vs 256 per-graph launches",
@@ -83,6 +85,7 @@ COUNTER_SOURCES = {
                   _CS + "vdmc_internal.h"],
     "chunglu": [_CS + "count.hip", _CS + "count_hub.hip", _CS + "motif_device.h", _CS + "vdmc_internal.h"],
     "batch256_k5": [_CS + "count5.hip", _CS + "vdmc_internal.h"],
+    "chunglu5000_k5": [_CS + "count5.hip", _CS + "motif_device.h", _CS + "vdmc_internal.h"],
 }
 COUNTER_SOURCES["rmat22"] = COUNTER_SOURCES["chunglu"]
 COUNTER_SOURCES["chunglu_u"] = COUNTER_SOURCES["chunglu"]
@@ -182,7 +185,7 @@ def cpu_baseline_batch(graphs, budget_s):
     }
 
 
-def cpu_baseline_rows(g, budget_s):
+def cpu_baseline_rows(g, budget_s, k=4):
     """Large graphs: the oracle's per-vertex mode on seeded random vertices of the graph
     until about budget_s of work, as (vertex, set) incidences per second; a full count is
     out of reach on the host (extrapolation = sets / rate)."""
@@ -195,11 +198,11 @@ def cpu_baseline_rows(g, budget_s):
     while used < budget_s and rows < cand.size:
         pick = rng.choice(cand, size=threads, replace=False).astype(np.int32)
         t0 = time.perf_counter()
-        out = oracle.count_rows(g.n, g.src, g.dst, 4, pick, threads=threads)
+        out = oracle.count_rows(g.n, g.src, g.dst, k, pick, threads=threads)
         used += time.perf_counter() - t0
         sets += int(out.sum())
         rows += threads
-    return {"value": sets / used if used > 0 else None, "unit": "(vertex, 4-set) incidences/s", "cores": threads,
+    return {"value": sets / used if used > 0 else None, "unit": f"(vertex, {k}-set) incidences/s", "cores": threads,
             "kind": "oracle", "sample": f"oracle per-vertex mode on {rows} seeded random non-isolated vertices: "
                                         f"{sets} incidences in {used:.1f} s",
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
@@ -364,6 +367,49 @@ def bench_batch5(args, torch, gg, v):
                              out_bytes + csr_bytes, ops_per_set=MODEL_OPS_PER_SET5),
     }
     return result, graphs
+
+
+def bench_graph5(args, torch, gg, v):
+    """k = 5 on one graph that one workgroup's LDS does not hold: one count per step."""
+    g = gg.config_graph("chunglu_5000")
+    G = v.Graph(g.n, g.src, g.dst)
+    out = torch.empty((g.n, v.num_classes(5)), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for w in range(args.warmup):
+            v.count(G, 5, out, stream=stream)
+            stream.synchronize()
+            log(f"[bench] warmup {w} done")
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            v.count(G, 5, out, stream=stream)
+        ev1.record(stream)
+        stream.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        dev_ms = ev0.elapsed_time(ev1) / args.steps
+    col = out.sum(dim=0).cpu().numpy().view(np.uint64)
+    assert (col % 5 == 0).all()
+    T5 = int(col.sum()) // 5
+    shapes = v.shape_counts5(G)
+    assert sum(shapes.values()) == T5, "sets visited one by one != sets counted"
+    log(f"[bench] {args.steps} steps: {ms:.1f} ms/step, T5={T5}")
+    result = {
+        "metric": "connected 5-vertex subgraphs counted/s (bit-exact)", "value": T5 / (ms * 1e-3),
+        "unit": "5-vertex sets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["chunglu5000_k5"], "n": g.n, "arcs": G.arcs, "pairs": G.pairs,
+                   "max_degree": G.max_deg, "sets5": T5, "shapes_visited": shapes},
+        "roofline": roofline("chunglu5000_k5", T5, dev_ms, "k_five_global (layered search in device memory)",
+                             4.0 * (g.n + 1) + 8.0 * G.pairs + 8.0 * g.n * v.num_classes(5),
+                             ops_per_set=MODEL_OPS_PER_SET5),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline ...")
+        result["cpu_baseline"] = cpu_baseline_rows(g, args.cpu_budget, k=5)
+    return result
 
 
 def _batch_result(args, graphs, Gs, T4, visited, ms_batch, dev_ms, choice, ms_single, ms_sync, same):
@@ -597,6 +643,8 @@ def main():
         if not args.no_cpu_baseline:
             log("[bench] cpu baseline ...")
             result["cpu_baseline"] = cpu_baseline_five(graphs, args.cpu_budget)
+    elif args.workload == "chunglu5000_k5":
+        result = bench_graph5(args, torch, gg, v)
     elif args.workload == "serve":
         log_hi = 6.0 if args.serve_log_hi is None else args.serve_log_hi
         s = run_serve(v, torch, gg, args.serve_graphs, args.serve_requests, log_hi, (0.5, 0.8))
