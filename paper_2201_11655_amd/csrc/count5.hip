@@ -349,7 +349,7 @@ struct FiveGraph {
     unsigned long long* copies;    // (parts - 1) x n x 9364: private blocks of parts 1.., summed into out
     unsigned long long* stats;     // 8 shape counters
     unsigned* cursor;              // item cursor
-    uint32_t n, entries, items;    // items = pairs of G_U
+    uint32_t n, entries;
     uint32_t parts;
 };
 
@@ -621,7 +621,6 @@ FiveGraph view_of(const vdmc_graph_s* g, uint64_t* out) {
     v.stats = g->stats;
     v.n = (uint32_t)g->n;
     v.entries = (uint32_t)(2 * g->pairs);
-    v.items = (uint32_t)g->pairs;
     v.parts = 1;
     return v;
 }
