@@ -322,7 +322,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
             const uint32_t d = sOff[r + 1] - sSplit[r];
             const uint32_t ia = u - sPreD[r];
             const uint32_t a = P[ia] >> 2, ra = P[ia] & 3u;
-            const uint32_t t = L.first_above(a, r) + (q - sPre2[u]);
+            const uint32_t t0 = L.first_above(a, r), t = t0 + (q - sPre2[u]);
             const uint32_t c = sAdj[t] >> 2, ac = sAdj[t] & 3u;
             if (L.adjacent(r, c)) continue;   // c adjacent to r: depth 1, not 2
             if (K == 3) {
@@ -367,14 +367,21 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 cr.add3(r, a, c, q2, n2);
                 cr.add3(r, a, c, q3, n3);
             }
-            // (1,2,0): a second child c2 > c of a, not adjacent to r
+            // (1,2,0): a second child c2 of a, not adjacent to r.  Every pair {c, c2} of a's
+            // children is taken once, by the member from which the other lies less than half
+            // of a's row (above r) ahead, circularly: the lanes of one (r, a) then have equal
+            // loop lengths, (L - 1) / 2 or L / 2, instead of L - 1 down to 0.
             {
                 const uint32_t u1 = sTable[motif_index4(ra, 0u, 0u, ac, 1u, 0u)];
                 const uint32_t u2 = sTable[motif_index4(ra, 0u, 0u, ac, 2u, 0u)];
                 const uint32_t u3 = sTable[motif_index4(ra, 0u, 0u, ac, 3u, 0u)];
                 const uint32_t s1 = cr.slot(u1), s2 = cr.slot(u2), s3 = cr.slot(u3);   // 3-star classes: tree slots
                 uint32_t n1 = 0, n2 = 0, n3 = 0;
-                for (uint32_t t2 = t + 1; t2 < sOff[a + 1]; t2++) {
+                const uint32_t Lr = sOff[a + 1] - t0, pos = t - t0;
+                const uint32_t nd = (Lr - 1u) / 2u + ((Lr % 2u == 0u && pos < Lr / 2u) ? 1u : 0u);
+                for (uint32_t dlt = 1; dlt <= nd; dlt++) {
+                    const uint32_t p2 = pos + dlt < Lr ? pos + dlt : pos + dlt - Lr;
+                    const uint32_t t2 = t0 + p2;
                     const uint32_t c2 = sAdj[t2] >> 2, ac2 = sAdj[t2] & 3u;
                     const bool xr = L.adjacent(r, c2), xc = L.adjacent(c, c2);   // both reads in flight
                     if (xr) continue;
