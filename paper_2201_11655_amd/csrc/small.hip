@@ -12,7 +12,8 @@
 //         sets (3,0,0) that add a third higher neighbour c > b (Lemma 2);
 //       - depth-2 entries (r, a, c): a in N+(r), c in N(a), c > r, c not in N(r): the
 //         k = 3 set (1,2) and, for k = 4, the sets (2,1,0) (second depth-1 vertex b; c
-//         hangs under its lower-rank parent), (1,2,0) (a second child c' > c of a) and
+//         hangs under its lower-rank parent), (1,2,0) (a second child c' of a, each pair
+//         of children once) and
 //         (1,1,1) (an end vertex e of c's row, not adjacent to r or to a: the Lemma-4
 //         rule) (Lemmas 2-4);
 //   * every set is visited once by one lane: its index is assembled from the arc bits
