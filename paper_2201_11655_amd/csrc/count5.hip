@@ -346,9 +346,9 @@ struct FiveGraph {
     const uint32_t* adj;           // entries: (nbr_rank << 2) | arc bits
     const int32_t* perm;           // rank -> original id
     unsigned long long* out;       // n x 9364, rows by original id (part 0)
-    unsigned long long* copies;    // (parts - 1) x n x 9364: private blocks of parts 1.., summed into out
+    size_t copies_off;             // first element of its (parts - 1) x n x 9364 private blocks in the
+                                   // call's copies (parts 1.., summed into out)
     unsigned long long* stats;     // 8 shape counters
-    unsigned* cursor;              // item cursor
     uint32_t n, entries;
     uint32_t parts;
 };
@@ -359,7 +359,8 @@ struct FiveArgs {
     uint32_t num;
     const uint2* slots;            // (graph, part) in claim order, or nullptr: (0, s)
     uint32_t nslots;
-    unsigned* slot_cursor;
+    unsigned* cursors;             // num item cursors (one per graph), then the slot cursor
+    unsigned long long* copies;    // private blocks of every graph's parts 1.., or nullptr
     const uint16_t* table;         // code -> class id
     uint32_t split_div;            // sub-items of a root: ceil(d+ x deg / split_div), at most 64
 };
@@ -372,11 +373,11 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 // zeroes every graph's counters and item cursor and the slot cursor (before k_five)
 __global__ __launch_bounds__(256) void k_five_prep(FiveArgs A) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *A.slot_cursor = 0u;
+    if (i == 0) A.cursors[A.num] = 0u;
     if (i >= A.num) return;
     const FiveGraph& G = A.graphs ? A.graphs[i] : A.one;
     for (int s = 0; s < kStatSlots; s++) G.stats[s] = 0ull;
-    *G.cursor = 0u;
+    A.cursors[i] = 0u;
 }
 
 template <int BS>
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(BS) void k_five(FiveArgs A) {
     uint32_t* sSplit = nullptr;
     uint32_t* sHp = nullptr;
     for (;;) {
-        if (tid == 0) s_slot = atomicAdd(A.slot_cursor, 1u);
+        if (tid == 0) s_slot = atomicAdd(A.cursors + A.num, 1u);
         __syncthreads();
         const uint32_t slot = s_slot;
         if (slot >= A.nslots) break;
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(BS) void k_five(FiveArgs A) {
         }
         // this part's output block: the caller's output or a private copy; zeroed here
         const size_t cells = (size_t)G.n * kClasses5;
-        unsigned long long* dst = sl.y == 0 ? G.out : G.copies + (size_t)(sl.y - 1u) * cells;
+        unsigned long long* dst = sl.y == 0 ? G.out : A.copies + G.copies_off + (size_t)(sl.y - 1u) * cells;
         if (((uintptr_t)dst & 15u) == 0) {   // 16-byte stores (9364 is even)
             ulonglong2* o = reinterpret_cast<ulonglong2*>(dst);
             for (size_t i = tid; i < cells / 2; i += BS) o[i] = make_ulonglong2(0ull, 0ull);
@@ -459,7 +460,7 @@ __global__ __launch_bounds__(BS) void k_five(FiveArgs A) {
         if (tid < 8) s_vis[tid] = 0ull;
         __syncthreads();
         for (;;) {
-            const uint32_t i = atomicAdd(G.cursor, 1u);   // items of the graph, shared by its parts
+            const uint32_t i = atomicAdd(A.cursors + sl.x, 1u);   // items of the graph, shared by its parts
             if (i >= sHp[G.n]) break;
             uint32_t rlo = 0, rhi = G.n;   // root: last r with sHp[r] <= i
             while (rhi - rlo > 1) {
@@ -477,13 +478,13 @@ __global__ __launch_bounds__(BS) void k_five(FiveArgs A) {
 }
 
 // out += the private copies of one graph (blockIdx.x strides over its cells)
-__device__ void five_reduce_one(const FiveGraph& G) {
+__device__ void five_reduce_one(const FiveGraph& G, const unsigned long long* copies) {
     const size_t cells = (size_t)G.n * kClasses5;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (((uintptr_t)G.out & 15u) == 0) {   // copies are 256-byte aligned and cells is even
         ulonglong2* o = reinterpret_cast<ulonglong2*>(G.out);
-        const ulonglong2* c = reinterpret_cast<const ulonglong2*>(G.copies);
+        const ulonglong2* c = reinterpret_cast<const ulonglong2*>(copies);
         const size_t h = cells / 2;
         for (size_t i = t0; i < h; i += stride) {
             ulonglong2 a = o[i];
@@ -497,7 +498,7 @@ __device__ void five_reduce_one(const FiveGraph& G) {
     } else {
         for (size_t i = t0; i < cells; i += stride) {
             unsigned long long a = G.out[i];
-            for (uint32_t p = 0; p + 1 < G.parts; p++) a += G.copies[p * cells + i];
+            for (uint32_t p = 0; p + 1 < G.parts; p++) a += copies[p * cells + i];
             G.out[i] = a;
         }
     }
@@ -509,7 +510,7 @@ __device__ void five_reduce_one(const FiveGraph& G) {
 __global__ __launch_bounds__(256) void k_five_reduce(FiveArgs A) {
     for (uint32_t gi = blockIdx.y; gi < A.num; gi += gridDim.y) {
         const FiveGraph& G = A.graphs ? A.graphs[gi] : A.one;
-        if (G.parts > 1) five_reduce_one(G);
+        if (G.parts > 1) five_reduce_one(G, A.copies + G.copies_off);
     }
 }
 
@@ -625,26 +626,42 @@ FiveGraph view_of(const vdmc_graph_s* g, uint64_t* out) {
     return v;
 }
 
-// cached state of batched 5-vertex launches, by (graphs, outputs)
+// cached descriptors of batched 5-vertex launches, by (graphs, outputs).  Only the
+// read-only graph views and the slot order are kept; the cursors and the private copies
+// are taken from the stream-ordered pool for each call.
 struct FivePlan {
     std::vector<vdmc_graph_s*> graphs;
     std::vector<uint64_t*> outs;
     FiveGraph* d_graphs = nullptr;
     uint2* d_slots = nullptr;
-    unsigned* d_cursors = nullptr;            // per graph item cursor, then the slot cursor
-    unsigned long long* d_copies = nullptr;   // private copies of parts 1..
     uint32_t nslots = 0;
+    size_t scratch = 0;   // bytes of private copies of parts 1..
     bool reduce = false;
     size_t lds = 0;
     ~FivePlan() {
         (void)hipFree(d_graphs);
         (void)hipFree(d_slots);
-        (void)hipFree(d_cursors);
-        (void)hipFree(d_copies);
     }
 };
 std::mutex g_five_mu;
 std::vector<FivePlan*> g_five_plans;
+
+// The private copies come from the device's default stream-ordered pool.  It keeps up to one
+// batched launch's budget after the frees, so repeated counts reuse the same pages instead
+// of mapping them anew; what lies above that goes back to the device at synchronisation.
+std::mutex g_pool_mu;
+uint64_t g_pool_set = 0;   // devices whose pool threshold is set (bit per device id < 64)
+void keep_scratch_pool() {
+    int dev = 0;
+    VDMC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (dev < 64 && (g_pool_set >> dev) & 1u) return;
+    hipMemPool_t pool;
+    VDMC_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t keep = kBatchScratchBudget + (size_t(256) << 20);
+    VDMC_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    if (dev < 64) g_pool_set |= uint64_t(1) << dev;
+}
 
 }  // namespace
 
@@ -732,18 +749,19 @@ void launch_count5(vdmc_graph_s* g, uint64_t* out, hipStream_t st) {
     const uint32_t by_mem = (uint32_t)std::min<size_t>(kMaxParts, 1 + kSingleScratchBudget / bb);
     const uint32_t parts = std::max<uint32_t>(1u, std::min<uint32_t>({by_items, by_mem, (uint32_t)(2 * ncu())}));
     const size_t bytes = 256 + (size_t)(parts - 1) * bb;
+    keep_scratch_pool();
     void* buf = nullptr;
     VDMC_HIP(hipMallocAsync(&buf, bytes, st));
     FiveArgs a{};
     a.graphs = nullptr;
     a.one = view_of(g, out);
-    a.one.cursor = static_cast<unsigned*>(buf);
-    a.one.copies = parts > 1 ? reinterpret_cast<unsigned long long*>(static_cast<char*>(buf) + 256) : nullptr;
+    a.one.copies_off = 0;
     a.one.parts = parts;
     a.num = 1;
     a.slots = nullptr;
     a.nslots = g->n > 0 ? parts : 0u;
-    a.slot_cursor = static_cast<unsigned*>(buf) + 1;
+    a.cursors = static_cast<unsigned*>(buf);
+    a.copies = parts > 1 ? reinterpret_cast<unsigned long long*>(static_cast<char*>(buf) + 256) : nullptr;
     a.table = t.table;
     a.split_div = kSplitDiv;
     try {
@@ -815,12 +833,10 @@ void count5_batch_lds(std::vector<vdmc_graph_s*>& gs, std::vector<uint64_t*>& ou
             for (int i : order)
                 for (uint32_t p = 0; p < parts[i]; p++) slots.push_back(make_uint2((unsigned)i, p));
             plan->nslots = (uint32_t)slots.size();
-            VDMC_HIP(hipMalloc(&plan->d_cursors, sizeof(unsigned) * (num + 1)));
-            if (scratch) VDMC_HIP(hipMalloc(&plan->d_copies, scratch));
+            plan->scratch = scratch;
             size_t at = 0;
             for (int i = 0; i < num; i++) {
-                views[i].cursor = plan->d_cursors + i;
-                views[i].copies = parts[i] > 1 ? plan->d_copies + at / sizeof(unsigned long long) : nullptr;
+                views[i].copies_off = at / sizeof(unsigned long long);
                 at += (size_t)(parts[i] - 1) * block_bytes(gs[i]);
             }
             VDMC_HIP(hipMalloc(&plan->d_graphs, sizeof(FiveGraph) * std::max(num, 1)));
@@ -845,10 +861,23 @@ void count5_batch_lds(std::vector<vdmc_graph_s*>& gs, std::vector<uint64_t*>& ou
     a.num = (uint32_t)num;
     a.slots = plan->d_slots;
     a.nslots = plan->nslots;
-    a.slot_cursor = plan->d_cursors + num;
     a.table = t.table;
     a.split_div = kSplitDiv;
-    launch_five(a, plan->lds, (uint32_t)num, plan->reduce, st);
+    // cursors and copies for this call only: concurrent counts of other batches on other
+    // streams never share them, and no cached plan holds copies between calls
+    const size_t head = (sizeof(unsigned) * ((size_t)num + 1) + 255) / 256 * 256;
+    keep_scratch_pool();
+    void* buf = nullptr;
+    VDMC_HIP(hipMallocAsync(&buf, head + plan->scratch, st));
+    a.cursors = static_cast<unsigned*>(buf);
+    a.copies = plan->scratch ? reinterpret_cast<unsigned long long*>(static_cast<char*>(buf) + head) : nullptr;
+    try {
+        launch_five(a, plan->lds, (uint32_t)num, plan->reduce, st);
+    } catch (...) {
+        (void)hipFreeAsync(buf, st);
+        throw;
+    }
+    VDMC_HIP(hipFreeAsync(buf, st));
 }
 
 void count5_batch(const vdmc_graph_s* const* gs_in, int32_t num, uint64_t* const* outs_in, hipStream_t st) {
