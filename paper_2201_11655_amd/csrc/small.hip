@@ -92,6 +92,9 @@ struct SmallLds {
     __device__ __forceinline__ bool adjacent(uint32_t u, uint32_t v) const {
         return (bits[u * W + (v >> 5)] >> (v & 31u)) & 1u;
     }
+    // the bitmap word of row u that holds v's bit, and the bit itself
+    __device__ __forceinline__ uint32_t word(uint32_t u, uint32_t v) const { return bits[u * W + (v >> 5)]; }
+    static __device__ __forceinline__ bool bit(uint32_t w, uint32_t v) { return (w >> (v & 31u)) & 1u; }
     // arc bits of (u, v) seen from u for a pair whose adjacency bit is already read
     __device__ __forceinline__ uint32_t code_if(bool is_adj, uint32_t u, uint32_t v) const {
         if (!is_adj) return 0u;
@@ -293,9 +296,21 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t p2 = sTable[motif_index4(ra, rb, 2u, ab, 0u, 0u)];
                 const uint32_t p3 = sTable[motif_index4(ra, rb, 3u, ab, 0u, 0u)];
                 uint32_t n1 = 0, n2 = 0, n3 = 0;
+                // software pipeline: the entry two candidates ahead and the bitmap words of
+                // the next one are read before this candidate's credits (LDS atomics, which
+                // later reads could not otherwise pass)
+                const uint32_t dm = d - 1u;
+                uint32_t e0 = P[min(j + 1u, dm)], e1 = P[min(j + 2u, dm)];
+                uint32_t wa0 = L.word(a, e0 >> 2), wb0 = L.word(b, e0 >> 2);
                 for (uint32_t l = j + 1; l < d; l++) {
-                    const uint32_t c = P[l] >> 2, rc = P[l] & 3u;
-                    const bool xa = L.adjacent(a, c), xb = L.adjacent(b, c);   // both reads in flight
+                    const uint32_t e2 = P[min(l + 2u, dm)];
+                    const uint32_t wa1 = L.word(a, e1 >> 2), wb1 = L.word(b, e1 >> 2);
+                    const uint32_t c = e0 >> 2, rc = e0 & 3u;
+                    const bool xa = SmallLds::bit(wa0, c), xb = SmallLds::bit(wb0, c);
+                    e0 = e1;
+                    e1 = e2;
+                    wa0 = wa1;
+                    wb0 = wb1;
                     const uint32_t ac = L.code_if(xa, a, c), bc = L.code_if(xb, b, c);
                     if (ac | bc) {
                         const uint32_t cls = sTable[motif_index4(ra, rb, rc, ab, ac, bc)];
@@ -345,10 +360,22 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t q3 = sTable[motif_index4(ra, 3u, 0u, 0u, ac, 0u)];
                 const uint32_t s1 = cr.slot(q1), s2 = cr.slot(q2), s3 = cr.slot(q3);   // 4-path classes: tree slots
                 uint32_t n1 = 0, n2 = 0, n3 = 0;
-                for (uint32_t jb = 0; jb < d; jb++) {
-                    if (jb == ia) continue;
-                    const uint32_t b = P[jb] >> 2, rb = P[jb] & 3u;
-                    const bool xbc = L.adjacent(b, c), xab = L.adjacent(a, b);   // both reads in flight
+                // pipelined as the (3,0,0) loop; jb runs over r's row without a's entry ia
+                const uint32_t dm = d - 1u;
+                uint32_t jb = ia == 0u ? 1u : 0u;
+                uint32_t j1 = jb + 1u == ia ? jb + 2u : jb + 1u;
+                uint32_t e0 = P[min(jb, dm)], e1 = P[min(j1, dm)];
+                uint32_t wc0 = L.word(e0 >> 2, c), wa0 = L.word(a, e0 >> 2);
+                for (; jb < d; jb = j1, j1 = j1 + 1u == ia ? j1 + 2u : j1 + 1u) {
+                    const uint32_t j2 = j1 + 1u == ia ? j1 + 2u : j1 + 1u;
+                    const uint32_t e2 = P[min(j2, dm)];
+                    const uint32_t wc1 = L.word(e1 >> 2, c), wa1 = L.word(a, e1 >> 2);
+                    const uint32_t b = e0 >> 2, rb = e0 & 3u;
+                    const bool xbc = SmallLds::bit(wc0, c), xab = SmallLds::bit(wa0, b);
+                    e0 = e1;
+                    e1 = e2;
+                    wc0 = wc1;
+                    wa0 = wa1;
                     if (xbc && jb < ia) continue;
                     const uint32_t bc = L.code_if(xbc, b, c), ab = L.code_if(xab, a, b);
                     if (ab | bc) {
@@ -380,11 +407,22 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 uint32_t n1 = 0, n2 = 0, n3 = 0;
                 const uint32_t Lr = sOff[a + 1] - t0, pos = t - t0;
                 const uint32_t nd = (Lr - 1u) / 2u + ((Lr % 2u == 0u && pos < Lr / 2u) ? 1u : 0u);
+                // pipelined as the (3,0,0) loop over the circular positions pos + 1 .. pos + nd
+                const auto at = [&](uint32_t dl) {
+                    const uint32_t p2 = pos + dl < Lr ? pos + dl : pos + dl - Lr;
+                    return sAdj[t0 + (p2 < Lr ? p2 : 0u)];
+                };
+                uint32_t e0 = at(1u), e1 = at(2u);
+                uint32_t wr0 = L.word(r, e0 >> 2), wc0 = L.word(c, e0 >> 2);
                 for (uint32_t dlt = 1; dlt <= nd; dlt++) {
-                    const uint32_t p2 = pos + dlt < Lr ? pos + dlt : pos + dlt - Lr;
-                    const uint32_t t2 = t0 + p2;
-                    const uint32_t c2 = sAdj[t2] >> 2, ac2 = sAdj[t2] & 3u;
-                    const bool xr = L.adjacent(r, c2), xc = L.adjacent(c, c2);   // both reads in flight
+                    const uint32_t e2 = at(dlt + 2u);
+                    const uint32_t wr1 = L.word(r, e1 >> 2), wc1 = L.word(c, e1 >> 2);
+                    const uint32_t c2 = e0 >> 2, ac2 = e0 & 3u;
+                    const bool xr = SmallLds::bit(wr0, c2), xc = SmallLds::bit(wc0, c2);
+                    e0 = e1;
+                    e1 = e2;
+                    wr0 = wr1;
+                    wc0 = wc1;
                     if (xr) continue;
                     const uint32_t cc2 = L.code_if(xc, c, c2);
                     if (cc2) {
@@ -412,9 +450,21 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t w3 = sTable[motif_index4(ra, 0u, 0u, ac, 0u, 3u)];
                 const uint32_t s1 = cr.slot(w1), s2 = cr.slot(w2), s3 = cr.slot(w3);   // 4-path classes: tree slots
                 uint32_t n1 = 0, n2 = 0, n3 = 0;
-                for (uint32_t te = L.first_above(c, r); te < sOff[c + 1]; te++) {
-                    const uint32_t e = sAdj[te] >> 2, ce = sAdj[te] & 3u;
-                    if (L.adjacent(r, e) | L.adjacent(a, e)) continue;   // both reads in flight
+                // pipelined as the (3,0,0) loop
+                const uint32_t tb = L.first_above(c, r), tend = sOff[c + 1];
+                const uint32_t tm = tend - 1u;   // read only when the row part is not empty
+                uint32_t e0 = tend > tb ? sAdj[tb] : 0u, e1 = tend > tb ? sAdj[min(tb + 1u, tm)] : 0u;
+                uint32_t wr0 = L.word(r, e0 >> 2), wa0 = L.word(a, e0 >> 2);
+                for (uint32_t te = tb; te < tend; te++) {
+                    const uint32_t e2 = sAdj[min(te + 2u, tm)];   // te < tend: in the row
+                    const uint32_t wr1 = L.word(r, e1 >> 2), wa1 = L.word(a, e1 >> 2);
+                    const uint32_t e = e0 >> 2, ce = e0 & 3u;
+                    const bool skip = SmallLds::bit(wr0, e) | SmallLds::bit(wa0, e);
+                    e0 = e1;
+                    e1 = e2;
+                    wr0 = wr1;
+                    wa0 = wa1;
+                    if (skip) continue;
                     cr.add_s(e, ce == 1u ? s1 : (ce == 2u ? s2 : s3), 1u);
                     n1 += ce == 1u;
                     n2 += ce == 2u;
