@@ -132,19 +132,19 @@ struct FiveGlobal {
     }
 };
 
-// member i of S (i < 5 is not a compile-time constant where this is called)
-__device__ __forceinline__ uint32_t member(const uint32_t (&S)[5], uint32_t i) {
-    uint32_t v = S[0];
-    v = i == 1u ? S[1] : v;
-    v = i == 2u ? S[2] : v;
-    v = i == 3u ? S[3] : v;
-    v = i == 4u ? S[4] : v;
-    return v;
-}
+// The members S[0..3] of the set being built (the fifth is the innermost loop's
+// candidate).  Named fields rather than an array: a member picked by an index that is not
+// a compile-time constant is a select, where an array would be placed in scratch memory.
+struct Members {
+    uint32_t v0, v1, v2, v3;
+    __device__ __forceinline__ uint32_t operator[](uint32_t i) const {
+        return i == 0u ? v0 : (i == 1u ? v1 : (i == 2u ? v2 : v3));
+    }
+};
 
 // y adjacent to none of S[0..lim)
 template <class V>
-__device__ __forceinline__ bool clear_of(const V& L, const uint32_t (&S)[5], uint32_t lim, uint32_t y) {
+__device__ __forceinline__ bool clear_of(const V& L, const Members& S, uint32_t lim, uint32_t y) {
 #pragma unroll
     for (uint32_t m = 0; m < 4; m++)
         if (m < lim && L.adjacent(S[m], y)) return false;
@@ -158,18 +158,18 @@ __device__ __forceinline__ bool clear_of(const V& L, const uint32_t (&S)[5], uin
 struct Cand {
     uint32_t pi, pend, j, jend, phase, ls, pbits;   // pbits: arc bits of the last candidate with its parent
     template <class V>
-    __device__ __forceinline__ void start(const V& L, const uint32_t (&S)[5], uint32_t par, uint32_t pos,
+    __device__ __forceinline__ void start(const V& L, const Members& S, uint32_t par, uint32_t pos,
                                           uint32_t ls_prev) {
         pi = par;
         pend = ls_prev;
         j = pos + 1u;
-        jend = L.off[member(S, par) + 1u];
+        jend = L.off[S[par] + 1u];
         phase = 0u;
         ls = ls_prev;
     }
     // next candidate vertex, or kNone; t = the S index being chosen
     template <class V>
-    __device__ __forceinline__ uint32_t next(const V& L, const uint32_t (&S)[5], uint32_t t) {
+    __device__ __forceinline__ uint32_t next(const V& L, const Members& S, uint32_t t) {
         for (;;) {
             while (j < jend) {
                 const uint32_t e = L.adj[j++], y = e >> 2;
@@ -179,7 +179,7 @@ struct Cand {
                 }
             }
             if (++pi < pend) {
-                const uint32_t x = member(S, pi);
+                const uint32_t x = S[pi];
                 j = L.first_above(x, S[0]);
                 jend = L.off[x + 1u];
                 continue;
@@ -188,7 +188,7 @@ struct Cand {
                 phase = 1u;
                 pi = ls;
                 pend = t;
-                const uint32_t x = member(S, pi);
+                const uint32_t x = S[pi];
                 j = L.first_above(x, S[0]);
                 jend = L.off[x + 1u];
                 continue;
@@ -202,7 +202,7 @@ struct Cand {
 // parent's come with the entry, members before the parent are not adjacent to it (the
 // candidate rule), the others are looked up
 template <class V>
-__device__ __forceinline__ uint32_t arc_of(const V& L, const uint32_t (&S)[5], uint32_t m, const Cand& c,
+__device__ __forceinline__ uint32_t arc_of(const V& L, const Members& S, uint32_t m, const Cand& c,
                                            uint32_t y) {
     if (m == c.pi) return c.pbits;
     if (m < c.pi) return 0u;
@@ -218,48 +218,113 @@ __device__ __forceinline__ void bump(unsigned long long* p, unsigned long long v
     else __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// v sets of class cls credited to the four fixed members of a context
+// v sets of class cls credited to the three members fixed over a depth-2 loop
 template <bool kDev>
-__device__ __forceinline__ void credit4(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2, uint32_t P3,
-                                        uint32_t cls, unsigned long long v) {
-    if (v == 0ull || cls >= (uint32_t)kClasses5) return;
+__device__ __forceinline__ void credit3(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2, uint32_t cls,
+                                        unsigned long long v) {
     bump<kDev>(&out[(size_t)P0 * kClasses5 + cls], v);
     bump<kDev>(&out[(size_t)P1 * kClasses5 + cls], v);
     bump<kDev>(&out[(size_t)P2 * kClasses5 + cls], v);
-    bump<kDev>(&out[(size_t)P3 * kClasses5 + cls], v);
 }
 
-// Per-lane cache of the last member's signatures in one context: entry = (count << 8) |
-// signature (0 = empty) and the signature's class; the oldest entry makes room.
+// Per-lane cache of the classes credited to S[0], S[1], S[2] over one depth-2 loop (all
+// fourth members under one third member): entry = (count << 14) | class, 0 = empty; the
+// oldest entry makes room.  A count stays below 2^18: an entry about to pass it takes a
+// new slot instead.
+struct ClassCache {
+    uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0, e4 = 0, e5 = 0, e6 = 0, e7 = 0, victim = 0;
+    static __device__ __forceinline__ bool take(uint32_t& e, uint32_t cls, uint32_t v) {
+        if (e == 0u || (e & 0x3FFFu) != cls || (e >> 14) + v >= (1u << 18)) return false;
+        e += v << 14;
+        return true;
+    }
+    template <bool kDev>
+    __device__ __forceinline__ void add(uint32_t cls, uint32_t v, unsigned long long* out, uint32_t P0, uint32_t P1,
+                                        uint32_t P2) {
+        if (take(e0, cls, v) || take(e1, cls, v) || take(e2, cls, v) || take(e3, cls, v) || take(e4, cls, v) ||
+            take(e5, cls, v) || take(e6, cls, v) || take(e7, cls, v))
+            return;
+        const uint32_t e = (v << 14) | cls;
+        uint32_t old;
+        switch (victim) {
+            case 0: old = e0; e0 = e; break;
+            case 1: old = e1; e1 = e; break;
+            case 2: old = e2; e2 = e; break;
+            case 3: old = e3; e3 = e; break;
+            case 4: old = e4; e4 = e; break;
+            case 5: old = e5; e5 = e; break;
+            case 6: old = e6; e6 = e; break;
+            default: old = e7; e7 = e; break;
+        }
+        victim = (victim + 1u) & 7u;
+        if (old) credit3<kDev>(out, P0, P1, P2, old & 0x3FFFu, old >> 14);
+    }
+    template <bool kDev>
+    __device__ __forceinline__ void flush_all(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2) {
+        if (e0) credit3<kDev>(out, P0, P1, P2, e0 & 0x3FFFu, e0 >> 14);
+        if (e1) credit3<kDev>(out, P0, P1, P2, e1 & 0x3FFFu, e1 >> 14);
+        if (e2) credit3<kDev>(out, P0, P1, P2, e2 & 0x3FFFu, e2 >> 14);
+        if (e3) credit3<kDev>(out, P0, P1, P2, e3 & 0x3FFFu, e3 >> 14);
+        if (e4) credit3<kDev>(out, P0, P1, P2, e4 & 0x3FFFu, e4 >> 14);
+        if (e5) credit3<kDev>(out, P0, P1, P2, e5 & 0x3FFFu, e5 >> 14);
+        if (e6) credit3<kDev>(out, P0, P1, P2, e6 & 0x3FFFu, e6 >> 14);
+        if (e7) credit3<kDev>(out, P0, P1, P2, e7 & 0x3FFFu, e7 >> 14);
+        e0 = e1 = e2 = e3 = e4 = e5 = e6 = e7 = 0u;
+        victim = 0u;
+    }
+};
+
+// v sets of class cls of one context: the fourth member credited now, the three before it
+// through the class cache
+template <bool kDev>
+__device__ __forceinline__ void credit_ctx(unsigned long long* out, ClassCache& cc, uint32_t P0, uint32_t P1,
+                                           uint32_t P2, uint32_t P3, uint32_t cls, uint32_t v) {
+    if (v == 0u || cls >= (uint32_t)kClasses5) return;
+    bump<kDev>(&out[(size_t)P3 * kClasses5 + cls], (unsigned long long)v);
+    cc.add<kDev>(cls, v, out, P0, P1, P2);
+}
+
+// Per-lane cache of the last member's signatures in one context: entry = (count << 22) |
+// (class << 8) | signature, 0 = empty (a signature is never 0: the last member has an
+// arc to its parent); the oldest entry makes room.  A count stays below 1023: a signature
+// whose entry is full takes a new one.
 struct SigCache {
-    uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0, victim = 0;
+    uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0, victim = 0;
+    static __device__ __forceinline__ bool take(uint32_t& e, uint32_t sig) {
+        if ((e & 255u) != sig || (e >> 22) >= 1023u) return false;
+        e += 1u << 22;
+        return true;
+    }
+    static __device__ __forceinline__ uint32_t cls_of(uint32_t e) { return (e >> 8) & 0x3FFFu; }
     // class of a cached signature (its count raised by one), or kNone
     __device__ __forceinline__ uint32_t hit(uint32_t sig) {
-        if (e0 && (e0 & 255u) == sig) { e0 += 256u; return k0; }
-        if (e1 && (e1 & 255u) == sig) { e1 += 256u; return k1; }
-        if (e2 && (e2 & 255u) == sig) { e2 += 256u; return k2; }
-        if (e3 && (e3 & 255u) == sig) { e3 += 256u; return k3; }
+        if (take(e0, sig)) return cls_of(e0);
+        if (take(e1, sig)) return cls_of(e1);
+        if (take(e2, sig)) return cls_of(e2);
+        if (take(e3, sig)) return cls_of(e3);
         return kNone;
     }
     template <bool kDev>
-    __device__ __forceinline__ void insert(uint32_t sig, uint32_t cls, unsigned long long* out, uint32_t P0,
-                                           uint32_t P1, uint32_t P2, uint32_t P3) {
-        const uint32_t e = 256u | sig;
+    __device__ __forceinline__ void insert(uint32_t sig, uint32_t cls, unsigned long long* out, ClassCache& cc,
+                                           uint32_t P0, uint32_t P1, uint32_t P2, uint32_t P3) {
+        const uint32_t e = (1u << 22) | ((cls & 0x3FFFu) << 8) | sig;
+        uint32_t old;
         switch (victim) {
-            case 0: credit4<kDev>(out, P0, P1, P2, P3, k0, e0 >> 8); e0 = e; k0 = cls; break;
-            case 1: credit4<kDev>(out, P0, P1, P2, P3, k1, e1 >> 8); e1 = e; k1 = cls; break;
-            case 2: credit4<kDev>(out, P0, P1, P2, P3, k2, e2 >> 8); e2 = e; k2 = cls; break;
-            default: credit4<kDev>(out, P0, P1, P2, P3, k3, e3 >> 8); e3 = e; k3 = cls; break;
+            case 0: old = e0; e0 = e; break;
+            case 1: old = e1; e1 = e; break;
+            case 2: old = e2; e2 = e; break;
+            default: old = e3; e3 = e; break;
         }
         victim = (victim + 1u) & 3u;
+        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(old), old >> 22);
     }
     template <bool kDev>
-    __device__ __forceinline__ void flush_all(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2,
-                                              uint32_t P3) {
-        credit4<kDev>(out, P0, P1, P2, P3, k0, e0 >> 8);
-        credit4<kDev>(out, P0, P1, P2, P3, k1, e1 >> 8);
-        credit4<kDev>(out, P0, P1, P2, P3, k2, e2 >> 8);
-        credit4<kDev>(out, P0, P1, P2, P3, k3, e3 >> 8);
+    __device__ __forceinline__ void flush_all(unsigned long long* out, ClassCache& cc, uint32_t P0, uint32_t P1,
+                                              uint32_t P2, uint32_t P3) {
+        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(e0), e0 >> 22);
+        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(e1), e1 >> 22);
+        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(e2), e2 >> 22);
+        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(e3), e3 >> 22);
     }
 };
 
@@ -280,10 +345,7 @@ __device__ __forceinline__ uint32_t item_split(uint32_t dhi, uint32_t deg, uint3
 template <class V, bool kDev>
 __device__ void five_item(const V& L, const uint16_t* __restrict__ table, unsigned long long* __restrict__ out,
                           uint32_t r, uint32_t apos, uint32_t k, uint32_t K, unsigned long long* vis) {
-    uint32_t S[5];
-    S[0] = r;
-    S[1] = L.adj[apos] >> 2;
-    S[2] = S[3] = S[4] = 0u;
+    Members S{r, L.adj[apos] >> 2, 0u, 0u};
     const uint32_t code1 = pair_bits(0, 1, L.adj[apos] & 3u);
     const uint32_t P0 = L.perm[r], P1 = L.perm[S[1]];
     Cand c2;
@@ -293,16 +355,17 @@ __device__ void five_item(const V& L, const uint16_t* __restrict__ table, unsign
         const uint32_t y2 = c2.next(L, S, 2u);
         if (y2 == kNone) break;
         if (ord2++ % K != k) continue;   // another sub-item's third member
-        S[2] = y2;
+        S.v2 = y2;
         const uint32_t par2 = c2.pi, pos2 = c2.j - 1u, ls2 = c2.phase ? 2u : 1u;
         const uint32_t code2 = code1 | pair_bits(0, 2, arc_of(L, S, 0, c2, y2)) | pair_bits(1, 2, arc_of(L, S, 1, c2, y2));
         const uint32_t P2 = L.perm[y2];
+        ClassCache cc;
         Cand c3;
         c3.start(L, S, par2, pos2, ls2);
         for (;;) {
             const uint32_t y3 = c3.next(L, S, 3u);
             if (y3 == kNone) break;
-            S[3] = y3;
+            S.v3 = y3;
             const uint32_t par3 = c3.pi, pos3 = c3.j - 1u, ls3 = c3.phase ? 3u : ls2;
             const uint32_t code3 = code2 | pair_bits(0, 3, arc_of(L, S, 0, c3, y3)) |
                                    pair_bits(1, 3, arc_of(L, S, 1, c3, y3)) | pair_bits(2, 3, arc_of(L, S, 2, c3, y3));
@@ -326,17 +389,18 @@ __device__ void five_item(const V& L, const uint16_t* __restrict__ table, unsign
                 if (cls == kNone) {
                     cls = table[code3 | pair_bits(0, 4, b0) | pair_bits(1, 4, b1) | pair_bits(2, 4, b2) |
                                 pair_bits(3, 4, b3)];
-                    sc.insert<kDev>(sig, cls, out, P0, P1, P2, P3);
+                    sc.insert<kDev>(sig, cls, out, cc, P0, P1, P2, P3);
                 }
                 if (cls < (uint32_t)kClasses5) bump<kDev>(&out[(size_t)L.perm[y4] * kClasses5 + cls], 1ull);
                 if (c4.phase) opened++; else same++;
             }
-            sc.flush_all<kDev>(out, P0, P1, P2, P3);
+            sc.flush_all<kDev>(out, cc, P0, P1, P2, P3);
             // shape id: bit 2 = a new layer opens at member 2, bit 1 at member 3, bit 0 at member 4
             const uint32_t base = (ls2 == 2u ? 4u : 0u) | (ls3 == 3u ? 2u : 0u);
             add_shape(vis, base, same);
             add_shape(vis, base | 1u, opened);
         }
+        cc.flush_all<kDev>(out, P0, P1, P2);
     }
 }
 
@@ -381,7 +445,7 @@ __global__ __launch_bounds__(256) void k_five_prep(FiveArgs A) {
 }
 
 template <int BS>
-__global__ __launch_bounds__(BS) void k_five(FiveArgs A) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_five(FiveArgs A) {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_slot;
     __shared__ uint32_t part[BS];
