@@ -27,10 +27,11 @@
 // the third member; a lane runs a sub-item's whole search (three nested candidate
 // loops) and visits every set of it.  Lanes take items one at a time from the graph's
 // item cursor, so lanes with short items keep taking new ones.  Class ids come from a
-// 2^20-entry u16 table in device memory (2 MiB); the last member of a set is credited
-// per set, the four fixed members of a depth-3 context per distinct class through a
-// small per-lane cache (9364 classes per vertex do not fit in LDS, so the counters are
-// an output block in device memory).
+// 2^20-entry u16 table in device memory (2 MiB).  Credits go to an output block in
+// device memory (9364 classes per vertex do not fit in LDS): the last member of a set is
+// credited per set, the fourth member per distinct signature of the last one in its
+// context (a 4-entry per-lane cache), and the first three per class over the whole loop
+// under one third member (an 8-entry per-lane cache of (class, count)).
 //
 // Work split.  A graph is cut into P parts (P from its estimated work, sum of d^4 over
 // its vertices, so that the heaviest graphs of a batch spread over many compute units):
@@ -373,11 +374,12 @@ __device__ void five_item(const V& L, const uint16_t* __restrict__ table, unsign
             Cand c4;
             c4.start(L, S, par3, pos3, ls3);
             uint32_t same = 0, opened = 0;   // sets whose last member continues / opens a layer
-            // The last member y4 of a set is credited once per set.  The four fixed members
-            // are credited per distinct signature of y4 -- its arc bits with S[0..3], which
-            // with code3 fix the class -- through a 4-entry cache of (signature, count,
-            // class): a context of a sparse graph holds ~8-25 sets with ~4-5 signatures, so
-            // this removes most of the fixed members' credits and class reads.
+            // The last member y4 of a set is credited once per set.  The fixed members are
+            // credited per distinct signature of y4 -- its arc bits with S[0..3], which with
+            // code3 fix the class -- through a 4-entry cache of (signature, count, class): a
+            // context of a sparse graph holds ~8-25 sets with ~4-5 signatures, so this
+            // removes most of the fixed members' credits and class reads.  An evicted entry
+            // credits S[3] and passes its class and count on to the class cache of S[0..2].
             SigCache sc;
             for (;;) {
                 const uint32_t y4 = c4.next(L, S, 4u);
