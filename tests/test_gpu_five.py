@@ -106,6 +106,27 @@ def test_closed_forms(v, name):
         assert (got.sum(axis=1) == 5).all() and sum(sc.values()) == n
 
 
+def test_star_past_cache_limits(v):
+    """An out-star on 1030 vertices (device-memory path): one context holds 1026 last
+    members of one signature and one depth-2 loop over 5e5 sets of one class, past the
+    count limits of both per-lane credit caches (1023 and 2^18), so their overflow paths
+    run.  Closed form: the hub lies in C(n-1, 4) sets, a leaf in C(n-2, 3), all of the
+    out-star class (read from the oracle's count of a 6-vertex out-star)."""
+    n = 1030
+    g = gg.special_graph("outstar", n)
+    small = gg.special_graph("outstar", 6)
+    want6, _ = oracle.count(6, small.src, small.dst, 5)
+    cls = int(np.flatnonzero(want6[0])[0])
+    _say(f"k=5 out-star n={n}: {math.comb(n - 1, 4)} sets")
+    G = v.Graph(n, g.src, g.dst)
+    got = _np(v.count(G, 5))
+    exp = np.zeros((n, C5), np.uint64)
+    exp[0, cls] = math.comb(n - 1, 4)
+    exp[1:, cls] = math.comb(n - 2, 3)
+    assert (got == exp).all()
+    assert sum(v.shape_counts5(G).values()) == math.comb(n - 1, 4)
+
+
 def test_degenerate(v):
     for n, src, dst, label in [
         (4, [0, 1, 2], [1, 2, 3], "n<5"),
