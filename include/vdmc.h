@@ -179,7 +179,13 @@ vdmc_status vdmc_free_graph(vdmc_graph g);
  * any other is counted in device memory, which at its first 5-vertex count builds the
  * graph's edge hash (2^ceil(log2(4 pairs)) 8-byte slots) and an (n + 2) x 8-byte item
  * table, kept with the graph and synchronising `stream` once.  Its sets are visited
- * along the eight BFS layer shapes of five vertices (vdmc_profile_counters).  A graph
+ * along the eight BFS layer shapes of five vertices (vdmc_profile_counters).  An LDS
+ * count of a graph with at least 64 pairs splits it into up to 64 parts whose extra
+ * private n x 9364 blocks (at most 512 MiB) and item cursors are taken from the
+ * device's default stream-ordered pool (hipMallocAsync on `stream`) and returned to it
+ * after the launches; the library raises that pool's release threshold to 8.25 GiB so
+ * that repeated counts reuse the pages (other users of the default pool keep that
+ * much too).  A graph
  * with n < k gives an all-zero matrix.  Asynchronous on `stream`; `out` must not be in use by
  * another call.  The first count on a graph (and the first after a change of its hub
  * threshold) bins its roots and synchronises `stream`; the hub path's scratch is
@@ -246,7 +252,8 @@ vdmc_status vdmc_kernel_times(vdmc_graph g, float* ms_out, int32_t n);
  * outputs, same k) is seen and replayed afterwards.  Asynchronous on `stream`.
  * k = 5: every graph must satisfy vdmc_count_supported (else UNSUPPORTED).  The graphs
  * that LDS holds are counted by one launch (graphs cut into parts with private blocks,
- * summed afterwards), the others one by one in device memory after it; not captured.
+ * summed afterwards: at most 8 GiB per call, from the default stream-ordered pool as
+ * for vdmc_count), the others one by one in device memory after it; not captured.
  */
 vdmc_status vdmc_count_batch(const vdmc_graph* gs, int32_t num, int32_t k,
                              uint64_t* const* outs, void* stream);
