@@ -3,9 +3,9 @@
 // For graphs of a few hundred vertices (the batched workload, small served requests)
 // a per-root launch leaves most of a workgroup idle: a root of such a graph has a
 // handful of higher neighbours.  Here one workgroup takes a whole graph:
-//   * its rank-space CSR, a 1-bit adjacency matrix (so that almost every pair test is
-//     one LDS read; a set bit is resolved to its arc bits by a search of the LDS row)
-//     and per-vertex counters live in LDS;
+//   * its rank-space CSR (16-bit row entries), a 1-bit adjacency matrix (so that almost
+//     every pair test is one LDS read; a set bit is resolved to its arc bits by a search
+//     of the LDS row) and per-vertex counters live in LDS;
 //   * the work of all roots is flattened into two item lists, so that threads never
 //     wait at per-root barriers:
 //       - pairs {a < b} of N+(r) for every root r: the k = 3 set (1,1) and the k = 4
@@ -19,12 +19,14 @@
 //   * every set is visited once by one lane: its index is assembled from the arc bits
 //     (Sec. 4.1), its class read from the table in LDS, and each of its k vertices
 //     credited (Sec. 4.2).  Credits go to LDS counters (k = 3: all 13 classes; k = 4:
-//     the 25 tree classes, which hold ~96% of the 4-sets of sparse graphs), one LDS
-//     atomic per member and set; the other classes go straight to the graph's output
-//     with workgroup-scope atomics (the output block of a graph belongs to one
-//     workgroup for the whole launch), and there members that all lanes of a wave step
-//     share (the root, the depth-1 vertex of a run of depth-2 items, the loop's current
-//     vertex) are credited once per class present in the step, grouped by ballots;
+//     the 25 tree classes and the 12 single-arc 4-pair classes, which hold ~99.6% of the
+//     credits of sparse graphs), one LDS atomic per member and set; the other classes
+//     go straight to the graph's output with workgroup-scope atomics (the output block
+//     of a graph belongs to one workgroup for the whole launch; every such atomic is a
+//     memory-side operation, so they are kept rare), and there members that all lanes of
+//     a wave step share (the root, the depth-1 vertex of a run of depth-2 items, the
+//     loop's current vertex) are credited once per class present in the step, grouped
+//     by ballots;
 //   * in the k = 4 loops three members are fixed and the lane walks the fourth; a set
 //     whose fourth member has no arc to the fixed members other than the one the shape
 //     implies has its class fixed by that arc's code (a tree class): the fourth member
@@ -40,35 +42,61 @@ namespace {
 
 __device__ __forceinline__ uint32_t lane_of() { return threadIdx.x & 63u; }
 
+// LDS counter slots per vertex for k = 4: the 25 tree classes, then the 12 classes whose
+// four joined pairs are all single arcs (directed 4-cycles and tailed triangles without a
+// reciprocal pair).  In a sparse digraph these are the next most frequent after the trees
+// (each further arc or reciprocation costs another factor of p): together they hold ~99.6%
+// of the credits of the batch workload, and only the rest goes to the output with
+// memory-side atomics.
+constexpr uint32_t kSingleArc4 = 12;
+constexpr uint32_t kSlots4 = (uint32_t)kCompact4 + kSingleArc4;
+
+// bit of the 4-vertex index for the entry (i, j), i != j: rows in order, the diagonal
+// skipped, entry (0,1) the most significant of the 12 (Sec. 4.1)
+__device__ __forceinline__ uint32_t bit4(uint32_t code, uint32_t i, uint32_t j) {
+    return (code >> (11u - (3u * i + (j < i ? j : j - 1u)))) & 1u;
+}
+
 // wg-scope atomic add on a graph's output (the block is owned by this workgroup)
 __device__ __forceinline__ void out_add(unsigned long long* p, unsigned long long v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // exclusive prefix sum of a[0..len) in place (LDS), returns the total; every thread of
-// the workgroup must call it.  part: BS words of LDS scratch.
+// the workgroup must call it.  Each thread sums a contiguous chunk; the chunk sums are
+// scanned within each wave by shuffles and across the BS / 64 waves by the first wave.
+// part: BS / 64 words of LDS scratch.
 template <int BS>
 __device__ uint32_t block_exclusive_scan(uint32_t* a, uint32_t len, uint32_t* part) {
-    const uint32_t tid = threadIdx.x;
+    constexpr uint32_t NWV = BS / 64;
+    const uint32_t tid = threadIdx.x, lane = lane_of(), wave = tid >> 6;
     const uint32_t per = (len + BS - 1) / BS;
     const uint32_t lo = min(len, tid * per), hi = min(len, lo + per);
     uint32_t s = 0;
     for (uint32_t i = lo; i < hi; i++) s += a[i];
-    part[tid] = s;
+    uint32_t x = s;   // inclusive scan of the chunk sums within the wave
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) part[wave] = x;
     __syncthreads();
-    for (uint32_t off = 1; off < BS; off <<= 1) {   // inclusive Hillis-Steele over the parts
-        const uint32_t v = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    if (tid < 64) {   // inclusive scan of the wave totals
+        uint32_t w = tid < NWV ? part[tid] : 0u;
+        for (uint32_t o = 1; o < NWV; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)w, o, 64);
+            if (lane >= o) w += y;
+        }
+        if (tid < NWV) part[tid] = w;
     }
-    uint32_t run = part[tid] - s;
+    __syncthreads();
+    uint32_t run = (wave ? part[wave - 1] : 0u) + x - s;
     for (uint32_t i = lo; i < hi; i++) {
-        const uint32_t x = a[i];
+        const uint32_t v = a[i];
         a[i] = run;
-        run += x;
+        run += v;
     }
-    const uint32_t total = part[BS - 1];
+    const uint32_t total = part[NWV - 1];
     __syncthreads();
     return total;
 }
@@ -85,7 +113,7 @@ __device__ __forceinline__ uint32_t upper_idx(const uint32_t* pre, uint32_t len,
 
 struct SmallLds {
     const uint32_t* off;
-    const uint32_t* adj;
+    const uint16_t* adj;   // entries (nbr_rank << 2) | arc bits; ranks below 1024 fit 16 bits
     const uint32_t* split;
     const uint32_t* bits;
     uint32_t W;
@@ -130,10 +158,10 @@ struct SmallLds {
 
 template <int K>
 struct SmallCredit {
-    static constexpr uint32_t NC = K == 3 ? (uint32_t)kClasses3 : (uint32_t)kCompact4;
+    static constexpr uint32_t NC = K == 3 ? (uint32_t)kClasses3 : kSlots4;
     static constexpr uint32_t C = K == 3 ? (uint32_t)kClasses3 : (uint32_t)kClasses4;
     uint32_t* cnt;            // n x NC (LDS)
-    const uint8_t* comp;      // k = 4: class -> tree slot or 0xFF (LDS)
+    const uint8_t* comp;      // k = 4: class -> counter slot or 0xFF (LDS)
     const int32_t* perm;
     unsigned long long* out;
     // slot of cls in the LDS counters, or NC when the class is credited to the output
@@ -201,14 +229,43 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
     extern __shared__ uint32_t dyn[];
     __shared__ uint8_t sTable[K == 3 ? 64 : 4096];
     __shared__ uint8_t sComp[256];
-    __shared__ uint32_t sPart[BS];
+    __shared__ uint8_t sSlotCls[64];
+    __shared__ uint32_t sMask[8];   // k = 4: 256-bit mask of the single-arc 4-pair classes
+    __shared__ uint32_t sPart[BS / 64];
     __shared__ uint32_t sGraph;
     constexpr uint32_t NC = SmallCredit<K>::NC;
     constexpr uint32_t C = SmallCredit<K>::C;
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < (K == 3 ? 64u : 4096u); i += BS) sTable[i] = A.table[i];
-    if (K == 4)
+    if (K == 4) {
+        // counter slots: the tree classes' from the class tables, then the single-arc
+        // 4-pair classes in ascending class id (each found from any of its codes)
         for (uint32_t i = tid; i < 256u; i += BS) sComp[i] = A.comp_of[i];
+        for (uint32_t i = tid; i < (uint32_t)kCompact4; i += BS) sSlotCls[i] = A.comp_cls[i];
+        if (tid < 8) sMask[tid] = 0u;
+        __syncthreads();
+        for (uint32_t code = tid; code < 4096u; code += BS) {
+            uint32_t joined = 0, recip = 0;
+            for (uint32_t i = 0; i < 4; i++)
+                for (uint32_t j = i + 1; j < 4; j++) {
+                    const uint32_t x = bit4(code, i, j), y = bit4(code, j, i);
+                    joined += x | y;
+                    recip += x & y;
+                }
+            const uint32_t cls = sTable[code];
+            if (joined == 4u && recip == 0u && cls != 0xFFu) atomicOr(&sMask[cls >> 5], 1u << (cls & 31u));
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t k = 0;
+            for (uint32_t c = 0; c < 256u; c++)
+                if (((sMask[c >> 5] >> (c & 31u)) & 1u) && sComp[c] == 0xFFu && k < kSingleArc4) {
+                    sComp[c] = (uint8_t)(kCompact4 + k);
+                    sSlotCls[kCompact4 + k] = (uint8_t)c;
+                    k++;
+                }
+        }
+    }
 
     for (uint32_t round = 0;; round++) {
         __syncthreads();
@@ -225,12 +282,12 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
         uint32_t* sPre1 = sPreD + n + 1;      // n + 1: pair items before root r
         uint32_t* sBits = sPre1 + n + 1;      // n * W
         uint32_t* sCnt = sBits + n * W;       // n * NC
-        uint32_t* sAdj = sCnt + n * NC;       // E
-        uint32_t* sPre2 = sAdj + E;           // E / 2 + 1: depth-2 candidates before each upper entry
-        uint16_t* sRootOf = reinterpret_cast<uint16_t*>(sPre2 + E / 2 + 1);   // E / 2: root of each upper entry
+        uint32_t* sPre2 = sCnt + n * NC;      // E / 2 + 1: depth-2 candidates before each upper entry
+        uint16_t* sAdj = reinterpret_cast<uint16_t*>(sPre2 + E / 2 + 1);   // E (u16)
+        uint16_t* sRootOf = sAdj + E;         // E / 2 (u16): root of each upper entry
         // ---- stage the graph, clear bitmap, counters and the output block
         for (uint32_t i = tid; i <= n; i += BS) sOff[i] = G.off[i];
-        for (uint32_t i = tid; i < E; i += BS) sAdj[i] = G.adj[i];
+        for (uint32_t i = tid; i < E; i += BS) sAdj[i] = (uint16_t)G.adj[i];
         for (uint32_t i = tid; i < n * W; i += BS) sBits[i] = 0u;
         for (uint32_t i = tid; i < n * NC; i += BS) sCnt[i] = 0u;
         for (size_t i = tid; i < (size_t)n * C; i += BS) G.out[i] = 0ull;
@@ -278,7 +335,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
             while (j * (j - 1u) / 2u > idx) j--;
             while ((j + 1u) * j / 2u <= idx) j++;
             const uint32_t i = idx - j * (j - 1u) / 2u;
-            const uint32_t* P = sAdj + sSplit[r];
+            const uint16_t* P = sAdj + sSplit[r];
             const uint32_t d = sOff[r + 1] - sSplit[r];
             const uint32_t a = P[i] >> 2, ra = P[i] & 3u, b = P[j] >> 2, rb = P[j] & 3u;
             const uint32_t ab = L.code(a, b);
@@ -334,7 +391,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
         for (uint32_t q = tid; q < N2; q += BS) {
             const uint32_t u = upper_idx(sPre2, U + 1, q);
             const uint32_t r = sRootOf[u];
-            const uint32_t* P = sAdj + sSplit[r];
+            const uint16_t* P = sAdj + sSplit[r];
             const uint32_t d = sOff[r + 1] - sSplit[r];
             const uint32_t ia = u - sPreD[r];
             const uint32_t a = P[ia] >> 2, ra = P[ia] & 3u;
@@ -483,7 +540,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
             const uint32_t x = sCnt[i];
             if (!x) continue;
             const uint32_t v = i / NC, s = i - v * NC;
-            const uint32_t cls = K == 3 ? s : A.comp_cls[s];
+            const uint32_t cls = K == 3 ? s : sSlotCls[s];
             G.out[(size_t)G.perm[v] * C + cls] = (unsigned long long)x;
         }
         // visited-set counters per shape: k = 3 -> (1,1), (1,2); k = 4 -> the four shapes
@@ -508,8 +565,9 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
 
 size_t small_lds_bytes(int64_t n, int64_t entries, int k) {
     const int64_t W = (n + 31) / 32;
-    const int64_t nc = k == 3 ? kClasses3 : kCompact4;
-    const int64_t words = (n + 1) * 3 + n + n * W + n * nc + entries + entries / 2 + 1 + (entries / 2 + 1) / 2;
+    const int64_t nc = k == 3 ? kClasses3 : kSlots4;
+    // u32 arrays, then the row entries and the roots of the upper entries (u16)
+    const int64_t words = (n + 1) * 3 + n + n * W + n * nc + entries / 2 + 1 + (entries + entries / 2 + 1) / 2;
     return (size_t)words * sizeof(uint32_t);
 }
 
