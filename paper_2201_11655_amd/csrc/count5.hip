@@ -58,7 +58,13 @@
 namespace vdmc {
 namespace {
 
-constexpr size_t kFiveStaticLds = 4096;                        // the kernel's __shared__ bytes, rounded up
+constexpr size_t kFiveStaticLds = 14336;                       // the kernel's __shared__ bytes, rounded up
+// LDS counter slots per vertex: the 27 classes of 5-sets whose induced subgraph is a tree
+// with single arcs (oriented paths, stars and forks without a reciprocal pair), which in a
+// sparse digraph hold most of the sets (~84% of the batch workload's credits); the other
+// classes are credited to the output block
+constexpr uint32_t kTreeSlots5 = 27;
+constexpr uint32_t kClassPad = 9376;                           // 9364 classes, padded to 16 bytes
 constexpr size_t kFiveLdsBudget = 163840 - kFiveStaticLds;     // gfx950: 160 KiB of LDS per workgroup
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kPartsPerCu = 2;                                 // target parts per compute unit in a batch
@@ -69,7 +75,7 @@ constexpr size_t kSingleScratchBudget = size_t(512) << 20;    // private copies 
 
 // bit of the index of a 5-set for the entry (i, j), i != j: rows in order, the diagonal
 // skipped, entry (0,1) the most significant of the 20 (Sec. 4.1, Fig. 1)
-__device__ __forceinline__ constexpr uint32_t shift5(uint32_t i, uint32_t j) {
+__host__ __device__ __forceinline__ constexpr uint32_t shift5(uint32_t i, uint32_t j) {
     return 19u - (i * 4u + (j < i ? j : j - 1u));
 }
 // index bits of the pair (i, t), i < t, from the arc bits b seen from member i
@@ -219,13 +225,35 @@ __device__ __forceinline__ void bump(unsigned long long* p, unsigned long long v
     else __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// v sets of class cls credited to the three members fixed over a depth-2 loop
+// Where a credit of v sets of class cls to vertex P (original id) goes.  GlobalSink: to
+// the output (device scope when kDev).  LdsSink: a class with an LDS counter slot (the
+// single-arc tree classes) to the workgroup's LDS counters, any other to its output
+// block.
 template <bool kDev>
-__device__ __forceinline__ void credit3(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2, uint32_t cls,
-                                        unsigned long long v) {
-    bump<kDev>(&out[(size_t)P0 * kClasses5 + cls], v);
-    bump<kDev>(&out[(size_t)P1 * kClasses5 + cls], v);
-    bump<kDev>(&out[(size_t)P2 * kClasses5 + cls], v);
+struct GlobalSink {
+    unsigned long long* out;
+    __device__ __forceinline__ void add(uint32_t P, uint32_t cls, uint32_t v) const {
+        bump<kDev>(&out[(size_t)P * kClasses5 + cls], (unsigned long long)v);
+    }
+};
+struct LdsSink {
+    unsigned long long* out;
+    uint32_t* cnt;            // n x kTreeSlots5 (LDS), rows by original id
+    const uint8_t* slot_of;   // class -> counter slot or 0xFF (LDS)
+    __device__ __forceinline__ void add(uint32_t P, uint32_t cls, uint32_t v) const {
+        const uint32_t sl = slot_of[cls];
+        if (sl < kTreeSlots5) atomicAdd(&cnt[P * kTreeSlots5 + sl], v);
+        else bump<false>(&out[(size_t)P * kClasses5 + cls], (unsigned long long)v);
+    }
+};
+
+// v sets of class cls credited to the three members fixed over a depth-2 loop
+template <class Sk>
+__device__ __forceinline__ void credit3(const Sk& sk, uint32_t P0, uint32_t P1, uint32_t P2, uint32_t cls,
+                                        uint32_t v) {
+    sk.add(P0, cls, v);
+    sk.add(P1, cls, v);
+    sk.add(P2, cls, v);
 }
 
 // Per-lane cache of the classes credited to S[0], S[1], S[2] over one depth-2 loop (all
@@ -239,8 +267,8 @@ struct ClassCache {
         e += v << 14;
         return true;
     }
-    template <bool kDev>
-    __device__ __forceinline__ void add(uint32_t cls, uint32_t v, unsigned long long* out, uint32_t P0, uint32_t P1,
+    template <class Sk>
+    __device__ __forceinline__ void add(uint32_t cls, uint32_t v, const Sk& sk, uint32_t P0, uint32_t P1,
                                         uint32_t P2) {
         if (take(e0, cls, v) || take(e1, cls, v) || take(e2, cls, v) || take(e3, cls, v) || take(e4, cls, v) ||
             take(e5, cls, v) || take(e6, cls, v) || take(e7, cls, v))
@@ -258,18 +286,18 @@ struct ClassCache {
             default: old = e7; e7 = e; break;
         }
         victim = (victim + 1u) & 7u;
-        if (old) credit3<kDev>(out, P0, P1, P2, old & 0x3FFFu, old >> 14);
+        if (old) credit3(sk, P0, P1, P2, old & 0x3FFFu, old >> 14);
     }
-    template <bool kDev>
-    __device__ __forceinline__ void flush_all(unsigned long long* out, uint32_t P0, uint32_t P1, uint32_t P2) {
-        if (e0) credit3<kDev>(out, P0, P1, P2, e0 & 0x3FFFu, e0 >> 14);
-        if (e1) credit3<kDev>(out, P0, P1, P2, e1 & 0x3FFFu, e1 >> 14);
-        if (e2) credit3<kDev>(out, P0, P1, P2, e2 & 0x3FFFu, e2 >> 14);
-        if (e3) credit3<kDev>(out, P0, P1, P2, e3 & 0x3FFFu, e3 >> 14);
-        if (e4) credit3<kDev>(out, P0, P1, P2, e4 & 0x3FFFu, e4 >> 14);
-        if (e5) credit3<kDev>(out, P0, P1, P2, e5 & 0x3FFFu, e5 >> 14);
-        if (e6) credit3<kDev>(out, P0, P1, P2, e6 & 0x3FFFu, e6 >> 14);
-        if (e7) credit3<kDev>(out, P0, P1, P2, e7 & 0x3FFFu, e7 >> 14);
+    template <class Sk>
+    __device__ __forceinline__ void flush_all(const Sk& sk, uint32_t P0, uint32_t P1, uint32_t P2) {
+        if (e0) credit3(sk, P0, P1, P2, e0 & 0x3FFFu, e0 >> 14);
+        if (e1) credit3(sk, P0, P1, P2, e1 & 0x3FFFu, e1 >> 14);
+        if (e2) credit3(sk, P0, P1, P2, e2 & 0x3FFFu, e2 >> 14);
+        if (e3) credit3(sk, P0, P1, P2, e3 & 0x3FFFu, e3 >> 14);
+        if (e4) credit3(sk, P0, P1, P2, e4 & 0x3FFFu, e4 >> 14);
+        if (e5) credit3(sk, P0, P1, P2, e5 & 0x3FFFu, e5 >> 14);
+        if (e6) credit3(sk, P0, P1, P2, e6 & 0x3FFFu, e6 >> 14);
+        if (e7) credit3(sk, P0, P1, P2, e7 & 0x3FFFu, e7 >> 14);
         e0 = e1 = e2 = e3 = e4 = e5 = e6 = e7 = 0u;
         victim = 0u;
     }
@@ -277,12 +305,12 @@ struct ClassCache {
 
 // v sets of class cls of one context: the fourth member credited now, the three before it
 // through the class cache
-template <bool kDev>
-__device__ __forceinline__ void credit_ctx(unsigned long long* out, ClassCache& cc, uint32_t P0, uint32_t P1,
-                                           uint32_t P2, uint32_t P3, uint32_t cls, uint32_t v) {
+template <class Sk>
+__device__ __forceinline__ void credit_ctx(const Sk& sk, ClassCache& cc, uint32_t P0, uint32_t P1, uint32_t P2,
+                                           uint32_t P3, uint32_t cls, uint32_t v) {
     if (v == 0u || cls >= (uint32_t)kClasses5) return;
-    bump<kDev>(&out[(size_t)P3 * kClasses5 + cls], (unsigned long long)v);
-    cc.add<kDev>(cls, v, out, P0, P1, P2);
+    sk.add(P3, cls, v);
+    cc.add(cls, v, sk, P0, P1, P2);
 }
 
 // Per-lane cache of the last member's signatures in one context: entry = (count << 22) |
@@ -305,9 +333,9 @@ struct SigCache {
         if (take(e3, sig)) return cls_of(e3);
         return kNone;
     }
-    template <bool kDev>
-    __device__ __forceinline__ void insert(uint32_t sig, uint32_t cls, unsigned long long* out, ClassCache& cc,
-                                           uint32_t P0, uint32_t P1, uint32_t P2, uint32_t P3) {
+    template <class Sk>
+    __device__ __forceinline__ void insert(uint32_t sig, uint32_t cls, const Sk& sk, ClassCache& cc, uint32_t P0,
+                                           uint32_t P1, uint32_t P2, uint32_t P3) {
         const uint32_t e = (1u << 22) | ((cls & 0x3FFFu) << 8) | sig;
         uint32_t old;
         switch (victim) {
@@ -317,15 +345,15 @@ struct SigCache {
             default: old = e3; e3 = e; break;
         }
         victim = (victim + 1u) & 3u;
-        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(old), old >> 22);
+        credit_ctx(sk, cc, P0, P1, P2, P3, cls_of(old), old >> 22);
     }
-    template <bool kDev>
-    __device__ __forceinline__ void flush_all(unsigned long long* out, ClassCache& cc, uint32_t P0, uint32_t P1,
-                                              uint32_t P2, uint32_t P3) {
-        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(e0), e0 >> 22);
-        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(e1), e1 >> 22);
-        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(e2), e2 >> 22);
-        credit_ctx<kDev>(out, cc, P0, P1, P2, P3, cls_of(e3), e3 >> 22);
+    template <class Sk>
+    __device__ __forceinline__ void flush_all(const Sk& sk, ClassCache& cc, uint32_t P0, uint32_t P1, uint32_t P2,
+                                              uint32_t P3) {
+        credit_ctx(sk, cc, P0, P1, P2, P3, cls_of(e0), e0 >> 22);
+        credit_ctx(sk, cc, P0, P1, P2, P3, cls_of(e1), e1 >> 22);
+        credit_ctx(sk, cc, P0, P1, P2, P3, cls_of(e2), e2 >> 22);
+        credit_ctx(sk, cc, P0, P1, P2, P3, cls_of(e3), e3 >> 22);
     }
 };
 
@@ -343,8 +371,8 @@ __device__ __forceinline__ uint32_t item_split(uint32_t dhi, uint32_t deg, uint3
 
 // Every set of the sub-item k of K of the item (root r, first layer-1 member at entry apos
 // of r's row).
-template <class V, bool kDev>
-__device__ void five_item(const V& L, const uint16_t* __restrict__ table, unsigned long long* __restrict__ out,
+template <class V, class Sk>
+__device__ void five_item(const V& L, const uint16_t* __restrict__ table, const Sk& sk,
                           uint32_t r, uint32_t apos, uint32_t k, uint32_t K, unsigned long long* vis) {
     Members S{r, L.adj[apos] >> 2, 0u, 0u};
     const uint32_t code1 = pair_bits(0, 1, L.adj[apos] & 3u);
@@ -391,18 +419,18 @@ __device__ void five_item(const V& L, const uint16_t* __restrict__ table, unsign
                 if (cls == kNone) {
                     cls = table[code3 | pair_bits(0, 4, b0) | pair_bits(1, 4, b1) | pair_bits(2, 4, b2) |
                                 pair_bits(3, 4, b3)];
-                    sc.insert<kDev>(sig, cls, out, cc, P0, P1, P2, P3);
+                    sc.insert(sig, cls, sk, cc, P0, P1, P2, P3);
                 }
-                if (cls < (uint32_t)kClasses5) bump<kDev>(&out[(size_t)L.perm[y4] * kClasses5 + cls], 1ull);
+                if (cls < (uint32_t)kClasses5) sk.add(L.perm[y4], cls, 1u);
                 if (c4.phase) opened++; else same++;
             }
-            sc.flush_all<kDev>(out, cc, P0, P1, P2, P3);
+            sc.flush_all(sk, cc, P0, P1, P2, P3);
             // shape id: bit 2 = a new layer opens at member 2, bit 1 at member 3, bit 0 at member 4
             const uint32_t base = (ls2 == 2u ? 4u : 0u) | (ls3 == 3u ? 2u : 0u);
             add_shape(vis, base, same);
             add_shape(vis, base | 1u, opened);
         }
-        cc.flush_all<kDev>(out, P0, P1, P2);
+        cc.flush_all(sk, P0, P1, P2);
     }
 }
 
@@ -428,6 +456,8 @@ struct FiveArgs {
     unsigned* cursors;             // num item cursors (one per graph), then the slot cursor
     unsigned long long* copies;    // private blocks of every graph's parts 1.., or nullptr
     const uint16_t* table;         // code -> class id
+    const uint8_t* slot_of;        // class -> LDS counter slot or 0xFF (kClassPad entries)
+    const uint16_t* slot_cls;      // LDS counter slot -> class (kTreeSlots5 entries)
     uint32_t split_div;            // sub-items of a root: ceil(d+ x deg / split_div), at most 64
 };
 
@@ -452,12 +482,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ uint32_t s_slot;
     __shared__ uint32_t part[BS];
     __shared__ unsigned long long s_vis[8];   // sets visited per shape by this part
+    __shared__ uint8_t sSlotOf[kClassPad];
+    __shared__ uint16_t sSlotCls[32];
     const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < (uint32_t)kClassPad; i += BS) sSlotOf[i] = A.slot_of[i];
+    if (tid < kTreeSlots5) sSlotCls[tid] = A.slot_cls[tid];
     uint32_t loaded = kNone;
     FiveGraph G{};
     FiveLds L{};
     uint32_t* sSplit = nullptr;
     uint32_t* sHp = nullptr;
+    uint32_t* sCnt = nullptr;
     for (;;) {
         if (tid == 0) s_slot = atomicAdd(A.cursors + A.num, 1u);
         __syncthreads();
@@ -473,6 +508,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
             uint32_t* sPerm = sHp + n + 1;
             uint32_t* sAdj = sPerm + n;
             uint32_t* sMat = sAdj + E;
+            sCnt = sMat + n * W;   // n x kTreeSlots5 counters of the part, rows by original id
             for (uint32_t i = tid; i < (n ? n + 1u : 0u); i += BS) sOff[i] = G.off[i];
             for (uint32_t i = tid; i < n; i += BS) sPerm[i] = (uint32_t)G.perm[i];
             for (uint32_t i = tid; i < E; i += BS) sAdj[i] = G.adj[i];
@@ -523,6 +559,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
         } else {
             for (size_t i = tid; i < cells; i += BS) dst[i] = 0ull;
         }
+        for (uint32_t i = tid; i < G.n * kTreeSlots5; i += BS) sCnt[i] = 0u;
         if (tid < 8) s_vis[tid] = 0ull;
         __syncthreads();
         for (;;) {
@@ -535,9 +572,16 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
             }
             const uint32_t K = item_split(L.off[rlo + 1] - sSplit[rlo], L.off[rlo + 1] - L.off[rlo], A.split_div);
             const uint32_t local = i - sHp[rlo];
-            five_item<FiveLds, false>(L, A.table, dst, rlo, sSplit[rlo] + local / K, local % K, K, s_vis);
+            five_item(L, A.table, LdsSink{dst, sCnt, sSlotOf}, rlo, sSplit[rlo] + local / K, local % K, K, s_vis);
         }
         __syncthreads();
+        // the part's LDS counters into its block (which only this workgroup writes)
+        for (uint32_t i = tid; i < G.n * kTreeSlots5; i += BS) {
+            const uint32_t x = sCnt[i];
+            if (!x) continue;
+            const uint32_t v = i / kTreeSlots5, sl2 = i - v * kTreeSlots5;
+            bump<false>(&dst[(size_t)v * kClasses5 + sSlotCls[sl2]], (unsigned long long)x);
+        }
         if (tid < 8 && s_vis[tid]) atomicAdd(&G.stats[tid], s_vis[tid]);
         __syncthreads();   // the part is done before the next claim rewrites s_slot
     }
@@ -625,10 +669,54 @@ __global__ __launch_bounds__(BS) void k_five_global(FiveGlobalArgs A) {
         const uint32_t r = lo, e = A.L.off[r + 1], sp = A.split[r];
         const uint32_t K = item_split(e - sp, e - A.L.off[r], A.split_div);
         const uint32_t local = (uint32_t)(i - A.hp[r]);
-        five_item<FiveGlobal, true>(A.L, A.table, A.out, r, sp + local / K, local % K, K, s_vis);
+        five_item(A.L, A.table, GlobalSink<true>{A.out}, r, sp + local / K, local % K, K, s_vis);
     }
     __syncthreads();
     if (tid < 8 && s_vis[tid]) atomicAdd(&A.stats[tid], s_vis[tid]);
+}
+
+// Per-device LDS counter slots: the single-arc tree classes found from each class's
+// minimal index (four joined pairs, none reciprocal), in ascending class id.
+struct FiveSlots {
+    uint8_t* slot_of = nullptr;    // kClassPad entries: class -> slot or 0xFF
+    uint16_t* slot_cls = nullptr;  // 32 entries: slot -> class
+};
+std::mutex g_slots_mu;
+std::map<int, FiveSlots> g_slots;
+const FiveSlots& five_slots() {
+    int dev = 0;
+    VDMC_HIP(hipGetDevice(&dev));
+    const ClassTable5& t = class_table5();
+    std::lock_guard<std::mutex> lock(g_slots_mu);
+    auto it = g_slots.find(dev);
+    if (it != g_slots.end()) return it->second;
+    std::vector<uint8_t> slot_of(kClassPad, 0xFF);
+    std::vector<uint16_t> slot_cls(32, 0);
+    uint32_t k = 0;
+    for (uint32_t c = 0; c < (uint32_t)kClasses5; c++) {
+        const uint32_t code = t.codes[c];
+        uint32_t joined = 0, recip = 0;
+        for (uint32_t i = 0; i < 5; i++)
+            for (uint32_t j = i + 1; j < 5; j++) {
+                const uint32_t x = (code >> shift5(i, j)) & 1u, y = (code >> shift5(j, i)) & 1u;
+                joined += x | y;
+                recip += x & y;
+            }
+        if (joined == 4u && recip == 0u) {
+            VDMC_REQUIRE(k < kTreeSlots5, VDMC_ERR_DEVICE, "more single-arc 5-vertex tree classes than slots");
+            slot_of[c] = (uint8_t)k;
+            slot_cls[k] = (uint16_t)c;
+            k++;
+        }
+    }
+    VDMC_REQUIRE(k == kTreeSlots5, VDMC_ERR_DEVICE,
+                 "expected 27 single-arc 5-vertex tree classes, found " + std::to_string(k));
+    FiveSlots fs;
+    VDMC_HIP(hipMalloc(&fs.slot_of, kClassPad));
+    VDMC_HIP(hipMalloc(&fs.slot_cls, 32 * sizeof(uint16_t)));
+    VDMC_HIP(hipMemcpy(fs.slot_of, slot_of.data(), kClassPad, hipMemcpyHostToDevice));
+    VDMC_HIP(hipMemcpy(fs.slot_cls, slot_cls.data(), 32 * sizeof(uint16_t), hipMemcpyHostToDevice));
+    return g_slots.emplace(dev, fs).first->second;   // kept for the life of the process
 }
 
 int g_ncu = -1;
@@ -647,15 +735,15 @@ int ncu() {
 void launch_five(const FiveArgs& a, size_t lds, uint32_t num_graphs, bool reduce, hipStream_t st) {
     hipLaunchKernelGGL(k_five_prep, dim3((std::max<uint32_t>(num_graphs, 1) + 255) / 256), dim3(256), 0, st, a);
     VDMC_HIP(hipGetLastError());
-    // 16 waves per compute unit (the register budget): two 512-thread workgroups when the
-    // LDS admits at most two, else up to four of 256 threads
+    // 16 waves per compute unit (the register budget): one 1024-thread workgroup when the
+    // LDS admits one, two of 512 threads when it admits two or three, else four of 256
     const int fit = std::max(1, (int)(163840 / (lds + kFiveStaticLds)));
-    const bool wide = fit <= 2;
-    const int per_cu = std::min(wide ? 2 : 4, fit);
-    void (*kern)(FiveArgs) = wide ? k_five<512> : k_five<256>;
+    const int bs = fit == 1 ? 1024 : (fit <= 3 ? 512 : 256);
+    const int per_cu = 1024 / bs;
+    void (*kern)(FiveArgs) = bs == 1024 ? k_five<1024> : (bs == 512 ? k_five<512> : k_five<256>);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(a.nslots, (int64_t)ncu() * per_cu));
     VDMC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(wide ? 512 : 256), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(bs), lds, st, a);
     VDMC_HIP(hipGetLastError());
     if (reduce) {
         hipLaunchKernelGGL(k_five_reduce, dim3(256, std::min<uint32_t>(std::max<uint32_t>(num_graphs, 1), 65535u)),
@@ -733,7 +821,7 @@ void keep_scratch_pool() {
 
 size_t five_lds_bytes(int64_t n, int64_t entries) {
     const int64_t W = (n + 31) / 32;
-    return (size_t)(4 * ((n + 1) + n + (n + 1) + n + entries + n * W));
+    return (size_t)(4 * ((n + 1) + n + (n + 1) + n + entries + n * W + n * (int64_t)kTreeSlots5));
 }
 
 bool five_eligible(int64_t n, int64_t entries) {
@@ -829,6 +917,9 @@ void launch_count5(vdmc_graph_s* g, uint64_t* out, hipStream_t st) {
     a.cursors = static_cast<unsigned*>(buf);
     a.copies = parts > 1 ? reinterpret_cast<unsigned long long*>(static_cast<char*>(buf) + 256) : nullptr;
     a.table = t.table;
+    const FiveSlots& fs = five_slots();
+    a.slot_of = fs.slot_of;
+    a.slot_cls = fs.slot_cls;
     a.split_div = kSplitDiv;
     try {
         launch_five(a, five_lds_bytes(g->n, 2 * g->pairs), 1, parts > 1, st);
@@ -928,6 +1019,9 @@ void count5_batch_lds(std::vector<vdmc_graph_s*>& gs, std::vector<uint64_t*>& ou
     a.slots = plan->d_slots;
     a.nslots = plan->nslots;
     a.table = t.table;
+    const FiveSlots& fs = five_slots();
+    a.slot_of = fs.slot_of;
+    a.slot_cls = fs.slot_cls;
     a.split_div = kSplitDiv;
     // cursors and copies for this call only: concurrent counts of other batches on other
     // streams never share them, and no cached plan holds copies between calls
