@@ -27,11 +27,14 @@
 // the third member; a lane runs a sub-item's whole search (three nested candidate
 // loops) and visits every set of it.  Lanes take items one at a time from the graph's
 // item cursor, so lanes with short items keep taking new ones.  Class ids come from a
-// 2^20-entry u16 table in device memory (2 MiB).  Credits go to an output block in
-// device memory (9364 classes per vertex do not fit in LDS): the last member of a set is
-// credited per set, the fourth member per distinct signature of the last one in its
-// context (a 4-entry per-lane cache), and the first three per class over the whole loop
-// under one third member (an 8-entry per-lane cache of (class, count)).
+// 2^20-entry u16 table in device memory (2 MiB).  9364 classes per vertex do not fit in
+// LDS; the 27 single-arc tree classes, which hold most sets of a sparse digraph, have
+// per-vertex LDS counters (added to the output block when the part ends), and the other
+// classes are credited to the output block in device memory.  The last member of a set
+// is credited per set, the four fixed members per distinct signature of the last one in
+// their context (a 4-entry per-lane cache).  Over a graph in device memory (no LDS
+// counters) the first three members' credits are further added up per class over the
+// whole loop under one third member (an 8-entry per-lane cache of (class, count)).
 //
 // Work split.  A graph is cut into P parts (P from its estimated work, sum of d^4 over
 // its vertices, so that the heaviest graphs of a batch spread over many compute units):
@@ -231,12 +234,14 @@ __device__ __forceinline__ void bump(unsigned long long* p, unsigned long long v
 // block.
 template <bool kDev>
 struct GlobalSink {
+    static constexpr bool kClassCache = true;
     unsigned long long* out;
     __device__ __forceinline__ void add(uint32_t P, uint32_t cls, uint32_t v) const {
         bump<kDev>(&out[(size_t)P * kClasses5 + cls], (unsigned long long)v);
     }
 };
 struct LdsSink {
+    static constexpr bool kClassCache = false;
     unsigned long long* out;
     uint32_t* cnt;            // n x kTreeSlots5 (LDS), rows by original id
     const uint8_t* slot_of;   // class -> counter slot or 0xFF (LDS)
@@ -259,7 +264,8 @@ __device__ __forceinline__ void credit3(const Sk& sk, uint32_t P0, uint32_t P1, 
 // Per-lane cache of the classes credited to S[0], S[1], S[2] over one depth-2 loop (all
 // fourth members under one third member): entry = (count << 14) | class, 0 = empty; the
 // oldest entry makes room.  A count stays below 2^18: an entry about to pass it takes a
-// new slot instead.
+// new slot instead.  Used where every credit is a memory-side atomic (GlobalSink); with
+// LDS counters the three credits are cheaper than the cache's registers.
 struct ClassCache {
     uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0, e4 = 0, e5 = 0, e6 = 0, e7 = 0, victim = 0;
     static __device__ __forceinline__ bool take(uint32_t& e, uint32_t cls, uint32_t v) {
@@ -310,7 +316,8 @@ __device__ __forceinline__ void credit_ctx(const Sk& sk, ClassCache& cc, uint32_
                                            uint32_t P3, uint32_t cls, uint32_t v) {
     if (v == 0u || cls >= (uint32_t)kClasses5) return;
     sk.add(P3, cls, v);
-    cc.add(cls, v, sk, P0, P1, P2);
+    if constexpr (Sk::kClassCache) cc.add(cls, v, sk, P0, P1, P2);
+    else credit3(sk, P0, P1, P2, cls, v);
 }
 
 // Per-lane cache of the last member's signatures in one context: entry = (count << 22) |
@@ -407,7 +414,7 @@ __device__ void five_item(const V& L, const uint16_t* __restrict__ table, const 
             // code3 fix the class -- through a 4-entry cache of (signature, count, class): a
             // context of a sparse graph holds ~8-25 sets with ~4-5 signatures, so this
             // removes most of the fixed members' credits and class reads.  An evicted entry
-            // credits S[3] and passes its class and count on to the class cache of S[0..2].
+            // credits S[3], and S[0..2] directly or through the class cache (sink's choice).
             SigCache sc;
             for (;;) {
                 const uint32_t y4 = c4.next(L, S, 4u);
@@ -430,7 +437,7 @@ __device__ void five_item(const V& L, const uint16_t* __restrict__ table, const 
             add_shape(vis, base, same);
             add_shape(vis, base | 1u, opened);
         }
-        cc.flush_all(sk, P0, P1, P2);
+        if constexpr (Sk::kClassCache) cc.flush_all(sk, P0, P1, P2);
     }
 }
 
