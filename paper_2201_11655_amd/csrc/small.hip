@@ -186,7 +186,7 @@ struct SmallCredit {
     }
     // One set per active lane, of class cls, credited to the NS members in sv, which the
     // lanes often share (the root, and the members fixed by the wave's loop position).
-    // A class with an LDS counter (every k = 3 class, the 25 tree classes of k = 4) is
+    // A class with an LDS counter (every k = 3 class, the 37 slot classes of k = 4) is
     // added lane by lane: an LDS atomic is cheap, and lanes that share a member and a
     // class only meet in the LDS unit.  The other classes go to the output, where every
     // atomic is a memory-side operation: a member common to all such lanes gets each of
@@ -290,7 +290,14 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
         for (uint32_t i = tid; i < E; i += BS) sAdj[i] = (uint16_t)G.adj[i];
         for (uint32_t i = tid; i < n * W; i += BS) sBits[i] = 0u;
         for (uint32_t i = tid; i < n * NC; i += BS) sCnt[i] = 0u;
-        for (size_t i = tid; i < (size_t)n * C; i += BS) G.out[i] = 0ull;
+        if (((uintptr_t)G.out & 15u) == 0) {   // 16-byte stores, then the odd last cell
+            const size_t cells = (size_t)n * C;
+            ulonglong2* o = reinterpret_cast<ulonglong2*>(G.out);
+            for (size_t i = tid; i < cells / 2; i += BS) o[i] = make_ulonglong2(0ull, 0ull);
+            if ((cells & 1u) && tid == 0) G.out[cells - 1] = 0ull;
+        } else {
+            for (size_t i = tid; i < (size_t)n * C; i += BS) G.out[i] = 0ull;
+        }
         if (tid < (uint32_t)kShapes) G.stats[tid] = 0ull;   // this launch's visit counters of the graph
         __syncthreads();
         for (uint32_t r = tid; r < n; r += BS) {
@@ -352,7 +359,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t p1 = sTable[motif_index4(ra, rb, 1u, ab, 0u, 0u)];
                 const uint32_t p2 = sTable[motif_index4(ra, rb, 2u, ab, 0u, 0u)];
                 const uint32_t p3 = sTable[motif_index4(ra, rb, 3u, ab, 0u, 0u)];
-                uint32_t n1 = 0, n2 = 0, n3 = 0;
+                uint32_t np = 0;   // sets by arc code 1, 2, 3: 10-bit fields (every loop runs < 1024 times)
                 // software pipeline: the entry two candidates ahead and the bitmap words of
                 // the next one are read before this candidate's credits (LDS atomics, which
                 // later reads could not otherwise pass)
@@ -376,15 +383,13 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                         cr.add_n(a, cls, 1u);
                     } else {
                         cr.add_n(c, rc == 1u ? p1 : (rc == 2u ? p2 : p3), 1u);
-                        n1 += rc == 1u;
-                        n2 += rc == 2u;
-                        n3 += rc == 3u;
+                        np += 1u << (10u * rc - 10u);
                     }
                     shp[0]++;
                 }
-                cr.add3(r, a, b, p1, n1);
-                cr.add3(r, a, b, p2, n2);
-                cr.add3(r, a, b, p3, n3);
+                cr.add3(r, a, b, p1, np & 1023u);
+                cr.add3(r, a, b, p2, (np >> 10) & 1023u);
+                cr.add3(r, a, b, p3, np >> 20);
             }
         }
         // ---- depth-2 entries (r, a, c)
@@ -416,7 +421,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t q2 = sTable[motif_index4(ra, 2u, 0u, 0u, ac, 0u)];
                 const uint32_t q3 = sTable[motif_index4(ra, 3u, 0u, 0u, ac, 0u)];
                 const uint32_t s1 = cr.slot(q1), s2 = cr.slot(q2), s3 = cr.slot(q3);   // 4-path classes: tree slots
-                uint32_t n1 = 0, n2 = 0, n3 = 0;
+                uint32_t np = 0;   // sets by arc code 1, 2, 3: 10-bit fields (every loop runs < 1024 times)
                 // pipelined as the (3,0,0) loop; jb runs over r's row without a's entry ia
                 const uint32_t dm = d - 1u;
                 uint32_t jb = ia == 0u ? 1u : 0u;
@@ -442,15 +447,13 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                         cr.add_n(c, cls, 1u);
                     } else {
                         cr.add_s(b, rb == 1u ? s1 : (rb == 2u ? s2 : s3), 1u);
-                        n1 += rb == 1u;
-                        n2 += rb == 2u;
-                        n3 += rb == 3u;
+                        np += 1u << (10u * rb - 10u);
                     }
                     shp[1]++;
                 }
-                cr.add3(r, a, c, q1, n1);
-                cr.add3(r, a, c, q2, n2);
-                cr.add3(r, a, c, q3, n3);
+                cr.add3(r, a, c, q1, np & 1023u);
+                cr.add3(r, a, c, q2, (np >> 10) & 1023u);
+                cr.add3(r, a, c, q3, np >> 20);
             }
             // (1,2,0): a second child c2 of a, not adjacent to r.  Every pair {c, c2} of a's
             // children is taken once, by the member from which the other lies less than half
@@ -461,7 +464,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t u2 = sTable[motif_index4(ra, 0u, 0u, ac, 2u, 0u)];
                 const uint32_t u3 = sTable[motif_index4(ra, 0u, 0u, ac, 3u, 0u)];
                 const uint32_t s1 = cr.slot(u1), s2 = cr.slot(u2), s3 = cr.slot(u3);   // 3-star classes: tree slots
-                uint32_t n1 = 0, n2 = 0, n3 = 0;
+                uint32_t np = 0;   // sets by arc code 1, 2, 3: 10-bit fields (every loop runs < 1024 times)
                 const uint32_t Lr = sOff[a + 1] - t0, pos = t - t0;
                 const uint32_t nd = (Lr - 1u) / 2u + ((Lr % 2u == 0u && pos < Lr / 2u) ? 1u : 0u);
                 // pipelined as the (3,0,0) loop over the circular positions pos + 1 .. pos + nd
@@ -490,15 +493,13 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                         cr.add_n(c2, cls, 1u);
                     } else {
                         cr.add_s(c2, ac2 == 1u ? s1 : (ac2 == 2u ? s2 : s3), 1u);
-                        n1 += ac2 == 1u;
-                        n2 += ac2 == 2u;
-                        n3 += ac2 == 3u;
+                        np += 1u << (10u * ac2 - 10u);
                     }
                     shp[2]++;
                 }
-                cr.add3(r, a, c, u1, n1);
-                cr.add3(r, a, c, u2, n2);
-                cr.add3(r, a, c, u3, n3);
+                cr.add3(r, a, c, u1, np & 1023u);
+                cr.add3(r, a, c, u2, (np >> 10) & 1023u);
+                cr.add3(r, a, c, u3, np >> 20);
             }
             // (1,1,1): path r - a - c - e, e not adjacent to r (nor equal to a) nor to a
             {
@@ -506,7 +507,7 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                 const uint32_t w2 = sTable[motif_index4(ra, 0u, 0u, ac, 0u, 2u)];
                 const uint32_t w3 = sTable[motif_index4(ra, 0u, 0u, ac, 0u, 3u)];
                 const uint32_t s1 = cr.slot(w1), s2 = cr.slot(w2), s3 = cr.slot(w3);   // 4-path classes: tree slots
-                uint32_t n1 = 0, n2 = 0, n3 = 0;
+                uint32_t np = 0;   // sets by arc code 1, 2, 3: 10-bit fields (every loop runs < 1024 times)
                 // pipelined as the (3,0,0) loop
                 const uint32_t tb = L.first_above(c, r), tend = sOff[c + 1];
                 const uint32_t tm = tend - 1u;   // read only when the row part is not empty
@@ -523,14 +524,12 @@ __global__ __launch_bounds__(BS) void k_small(SmallArgs A) {
                     wa0 = wa1;
                     if (skip) continue;
                     cr.add_s(e, ce == 1u ? s1 : (ce == 2u ? s2 : s3), 1u);
-                    n1 += ce == 1u;
-                    n2 += ce == 2u;
-                    n3 += ce == 3u;
+                    np += 1u << (10u * ce - 10u);
                     shp[3]++;
                 }
-                cr.add3(r, a, c, w1, n1);
-                cr.add3(r, a, c, w2, n2);
-                cr.add3(r, a, c, w3, n3);
+                cr.add3(r, a, c, w1, np & 1023u);
+                cr.add3(r, a, c, w2, (np >> 10) & 1023u);
+                cr.add3(r, a, c, w3, np >> 20);
             }
         }
         __syncthreads();
