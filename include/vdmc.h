@@ -177,8 +177,9 @@ vdmc_status vdmc_free_graph(vdmc_graph g);
  * held whole in one workgroup's LDS -- n <= 512 and 4 (4n + 2 + 2 pairs + n ceil(n/32))
  * bytes of CSR, id map and 1-bit adjacency matrix within 159744 -- is counted there;
  * any other is counted in device memory, which at its first 5-vertex count builds the
- * graph's edge hash (2^ceil(log2(4 pairs)) 8-byte slots) and an (n + 2) x 8-byte item
- * table, kept with the graph and synchronising `stream` once.  Its sets are visited
+ * graph's edge hash (2^ceil(log2(4 pairs)) 8-byte slots), an (n + 2) x 8-byte item
+ * table and, for n <= 16384, a 1-bit adjacency matrix (n x ceil(n/32) x 4 bytes, at
+ * most 32 MiB), kept with the graph and synchronising `stream` once.  Its sets are visited
  * along the eight BFS layer shapes of five vertices (vdmc_profile_counters).  An LDS
  * count of a graph with at least 64 pairs splits it into up to 64 parts whose extra
  * private n x 9364 blocks (at most 512 MiB) and item cursors are taken from the

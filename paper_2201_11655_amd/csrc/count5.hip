@@ -68,6 +68,7 @@ constexpr size_t kFiveStaticLds = 14336;                       // the kernel's _
 // classes are credited to the output block
 constexpr uint32_t kTreeSlots5 = 27;
 constexpr uint32_t kClassPad = 9376;                           // 9364 classes, padded to 16 bytes
+constexpr int64_t kFiveMatMaxN = 16384;                        // device-memory graphs up to this get a bit matrix (32 MiB)
 constexpr size_t kFiveLdsBudget = 163840 - kFiveStaticLds;     // gfx950: 160 KiB of LDS per workgroup
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kPartsPerCu = 2;                                 // target parts per compute unit in a batch
@@ -121,16 +122,25 @@ struct FiveLds {
 };
 
 // The same interface over a graph in device memory, for graphs that LDS does not hold:
-// pair tests and arc bits from the graph's edge hash (one probe sequence), rows searched
-// in place.
+// pair tests from a 1-bit adjacency matrix in device memory when the graph has one (one
+// cached load), else from the edge hash; arc bits of an adjacent pair from the edge hash
+// (one probe sequence); rows searched in place.
 struct FiveGlobal {
     const uint32_t* off;
     const uint32_t* adj;
     const uint32_t* perm;
     const unsigned long long* eh;
     uint32_t ebits;
-    __device__ __forceinline__ bool adjacent(uint32_t u, uint32_t v) const { return edge_code(eh, ebits, u, v) != 0u; }
-    __device__ __forceinline__ uint32_t bits(uint32_t u, uint32_t v) const { return edge_code(eh, ebits, u, v); }
+    const uint32_t* mat;   // n rows of W words, or nullptr
+    uint32_t W;
+    __device__ __forceinline__ bool adjacent(uint32_t u, uint32_t v) const {
+        if (mat) return (mat[(size_t)u * W + (v >> 5)] >> (v & 31u)) & 1u;
+        return edge_code(eh, ebits, u, v) != 0u;
+    }
+    __device__ __forceinline__ uint32_t bits(uint32_t u, uint32_t v) const {
+        if (mat && !((mat[(size_t)u * W + (v >> 5)] >> (v & 31u)) & 1u)) return 0u;
+        return edge_code(eh, ebits, u, v);
+    }
     __device__ __forceinline__ uint32_t first_above(uint32_t u, uint32_t x) const {
         uint32_t lo = off[u], hi = off[u + 1];
         const uint32_t key = (x + 1u) << 2;
@@ -726,6 +736,23 @@ const FiveSlots& five_slots() {
     return g_slots.emplace(dev, fs).first->second;   // kept for the life of the process
 }
 
+// 1-bit adjacency matrix (rank space) of a graph counted in device memory: row u set by
+// thread u from its CSR row (zeroed before)
+__global__ __launch_bounds__(256) void k_five_mat(const uint32_t* off, const uint32_t* adj, uint32_t n, uint32_t W,
+                                                   uint32_t* mat) {
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    uint32_t* row = mat + (size_t)u * W;
+    for (uint32_t x = off[u]; x < off[u + 1]; x++) {
+        const uint32_t v = adj[x] >> 2;
+        row[v >> 5] |= 1u << (v & 31u);
+    }
+}
+
+// the matrices, kept with their graphs until free_five
+std::mutex g_mat_mu;
+std::map<const vdmc_graph_s*, uint32_t*> g_five_mat;
+
 int g_ncu = -1;
 int ncu() {
     if (g_ncu < 0) {
@@ -874,10 +901,27 @@ void launch_count5_global(vdmc_graph_s* g, uint64_t* out, hipStream_t st) {
         g->five_hp = hp;
         g->five_items = total;
     }
+    const uint32_t W = (uint32_t)((g->n + 31) / 32);
+    uint32_t* mat = nullptr;
+    if (g->n <= kFiveMatMaxN) {
+        std::lock_guard<std::mutex> lock(g_mat_mu);
+        auto it = g_five_mat.find(g);
+        if (it != g_five_mat.end()) {
+            mat = it->second;
+        } else {
+            const size_t words = ((size_t)g->n * W + 1) & ~(size_t)1;   // even: zeroed as u64
+            VDMC_HIP(hipMalloc(&mat, words * sizeof(uint32_t)));
+            launch_fill_u64(reinterpret_cast<uint64_t*>(mat), words / 2, 0, st);
+            hipLaunchKernelGGL(k_five_mat, dim3((uint32_t)((g->n + 255) / 256)), dim3(256), 0, st, g->off, g->adj,
+                               (uint32_t)g->n, W, mat);
+            VDMC_HIP(hipGetLastError());
+            g_five_mat[g] = mat;
+        }
+    }
     unsigned long long* cursor = g->five_hp + g->n + 1;
     launch_fill_u64((uint64_t*)cursor, 1, 0, st);
     FiveGlobalArgs a{};
-    a.L = FiveGlobal{g->off, g->adj, reinterpret_cast<const uint32_t*>(g->perm), g->ehash, g->ehash_bits};
+    a.L = FiveGlobal{g->off, g->adj, reinterpret_cast<const uint32_t*>(g->perm), g->ehash, g->ehash_bits, mat, W};
     a.split = g->split;
     a.hp = g->five_hp;
     a.n = (uint32_t)g->n;
@@ -941,6 +985,12 @@ void free_five(vdmc_graph_s* g) {
     (void)hipFree(g->five_hp);
     g->five_hp = nullptr;
     g->five_items = 0;
+    std::lock_guard<std::mutex> lock(g_mat_mu);
+    auto it = g_five_mat.find(g);
+    if (it != g_five_mat.end()) {
+        (void)hipFree(it->second);
+        g_five_mat.erase(it);
+    }
 }
 
 void count5_batch_lds(std::vector<vdmc_graph_s*>& gs, std::vector<uint64_t*>& outv, hipStream_t st) {
