@@ -66,6 +66,37 @@ def test_class_table_sizes_match_known_enumerations(k):
             assert codes[cls[c]] == canon[c]
 
 
+def _pairs_and_reciprocal(k, code):
+    A = np.array(ex.matrix_of(k, code), dtype=int)
+    U = (A + A.T) > 0
+    return int(U.sum() // 2), int(((A + A.T) == 2).sum() // 2)
+
+
+def test_sparse_class_families():
+    """The class families the whole-graph kernels keep LDS counters for, counted in the
+    oracle's tables against counts fixed independently:
+    - classes whose underlying graph is a tree with single arcs = oriented trees on k
+      nodes, OEIS A000238 (1, 1, 3, 8, 27, ...): 3, 8, 27 for k = 3, 4, 5;
+    - k = 4 trees with any arc states: 3-stars are multisets of 3 leaf arcs over 3 states,
+      C(5, 3) = 10; 4-paths are arc triples up to reversal (which swaps each arc's
+      direction), (27 + 3) / 2 = 15 by Burnside; 25 in all;
+    - k = 4 classes with four joined pairs, all single arcs: oriented 4-cycles (4) and
+      oriented tailed triangles (2^4 / 2 = 8: the swap of the two unattached triangle
+      vertices reverses their arc, so it fixes no orientation); 12 in all."""
+    fam = {}
+    for k in (3, 4, 5):
+        _, _, codes = oracle.class_table(k)
+        pr = [_pairs_and_reciprocal(k, int(c)) for c in codes]
+        fam[k] = {
+            "single_arc_trees": sum(1 for e, r in pr if e == k - 1 and r == 0),
+            "trees": sum(1 for e, r in pr if e == k - 1),
+            "single_arc_4pair": sum(1 for e, r in pr if e == 4 and r == 0),
+        }
+    assert [fam[k]["single_arc_trees"] for k in (3, 4, 5)] == [3, 8, 27]
+    assert fam[4]["trees"] == 25
+    assert fam[4]["single_arc_4pair"] == 12
+
+
 def test_k3_class_structure_by_hand():
     """The 13 connected 3-vertex digraphs by number of arcs, counted by hand:
     2 arcs: out-star, in-star, path (3); 3 arcs: cycle, transitive triangle, a mutual
