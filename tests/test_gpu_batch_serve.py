@@ -80,6 +80,25 @@ def test_batch_small_graph_edge_cases(v, k):
         assert (_np(o) == want).all(), f"graph n={g.n} arcs={g.m}"
 
 
+@pytest.mark.parametrize("k", [3, 4])
+def test_batch_special_and_dense_graphs(v, k):
+    """Whole-graph counts of graphs whose sets fall almost all outside the LDS counter
+    slots (complete bidirected graph, transitive tournament, dense G(n,p) with many
+    reciprocal pairs) or all inside them (cycle, stars, path), in one batch."""
+    import torch
+    graphs = [gg.special_graph(kind, 13) for kind in ("complete", "tournament", "cycle", "outstar", "instar", "path")]
+    graphs += [gg.er_directed(64, 0.5, (62, 0)), gg.er_directed(40, 0.3, (62, 1)), gg.er_directed(90, 0.08, (62, 2))]
+    _say(f"batch special/dense k={k} n={[g.n for g in graphs]}")
+    Gs = [v.Graph(g.n, g.src, g.dst) for g in graphs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        outs = v.count_batch(Gs, k, stream=stream)
+        stream.synchronize()
+    for g, o in zip(graphs, outs):
+        want, _ = oracle.count(g.n, g.src, g.dst, k)
+        assert (_np(o) == want).all(), f"graph {g.name}"
+
+
 def test_batch_with_hub_graph_and_single_path(v, small_batch):
     import torch
     graphs = small_batch[:8] + [gg.config_graph("chunglu_2000")] + small_batch[8:12]
