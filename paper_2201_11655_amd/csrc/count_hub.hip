@@ -75,6 +75,7 @@ struct HubArgs {
     uint32_t s2cap, tcap;
     uint2* tasks;                // long-slot tasks: (hub index, the slot's entry in r's row)
     uint32_t task_cap;
+    uint32_t shares;             // workgroups per hub root (see k_hub)
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -214,11 +215,18 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     uint32_t* heads = keys + A.tcap;                             // tcap
     unsigned long long shp[kShapes] = {0, 0, 0, 0, 0, 0};
 
+    // A hub root is taken by A.shares workgroups when there are too few hub roots to fill
+    // the device.  Each stages the whole root (its slot hash, local lists and depth-2
+    // buckets live in its own scratch) and does the share of every phase's tasks that is
+    // its own: slots x with x % shares == share (phases B-C4, F) and depth-2 vertices c
+    // with c % shares == share (phase D, whose group order differs between workgroups).
+    // Its counters are partial sums, flushed with atomics like a whole root's.
+    const uint32_t G = A.shares;
     for (;;) {
         __syncthreads();
         if (tid == 0) sRoot = atomicAdd(&A.cursor[0], 1u);
         __syncthreads();
-        const uint32_t hi_idx = sRoot;
+        const uint32_t hi_idx = sRoot / G, share = sRoot - hi_idx * G;
         if (hi_idx >= A.nhub) break;
         const uint32_t r = A.hubs[hi_idx];
         if (r < A.rank_lo || r >= A.rank_hi) continue;   // uniform over the workgroup
@@ -281,12 +289,13 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         for (;;) {
             const uint32_t x = wave_task(&L.ctr[0]);
             if (x >= D) break;
+            const bool own = x % G == share;   // staging for every slot, credits for its own
             const uint32_t vx = L.P[x] >> 2, rx = L.P[x] & 3u;
             const uint32_t hi = A.off[vx + 1];
             const uint32_t base = locoff[x];
             const uint32_t lo = hi - (locoff[x + 1] - base);
             uint32_t nloc = 0;
-            if (A.k4 && hi - lo > SHORT && lane == 0) {
+            if (own && A.k4 && hi - lo > SHORT && lane == 0) {
                 const uint32_t t = atomicAdd(&A.cursor[1], 1u);
                 if (t < A.task_cap) A.tasks[t] = make_uint2(hi_idx, L.P[x]);
             }
@@ -306,11 +315,11 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
                 nloc += (uint32_t)__popcll(ml);
                 if (A.k3) {   // (1,2): r - x - e
                     const uint32_t cls = L.t3[motif_index3(rx, 0u, ec)];
-                    by_class(cls, d2, [&](uint32_t k, uint32_t n) {
+                    by_class(cls, own && d2, [&](uint32_t k, uint32_t n) {
                         atomicAdd(&L.root3[k], (unsigned long long)n);
                         atomicAdd(&R3[x * kClasses3 + k], n);
                     });
-                    if (d2) {
+                    if (own && d2) {
                         gadd(A.out3, A.perm, kClasses3, e, cls, 1ull);
                         shp[1]++;
                     }
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         if (A.k3) {
             uint32_t* rows = R3 + DMAX * kClasses3;   // per wave: one code row
             for (;;) {
-                const uint32_t a = wave_task(&L.ctr[3]);
+                const uint32_t a = wave_task(&L.ctr[3]) * G + share;
                 if (a + 1 >= D) break;
                 uint32_t* BA = rows + wid * CW;
                 build_row(BA, locnbr, locoff[a], L.locn[a]);
@@ -374,7 +383,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
         for (uint32_t i = tid; i < D * NSTAR; i += HT) R4[i] = 0u;
         __syncthreads();
         for (;;) {
-            const uint32_t a = wave_task(&L.ctr[4]);
+            const uint32_t a = wave_task(&L.ctr[4]) * G + share;
             if (a + 2 >= D) break;
             uint32_t* BA = rows4 + wid * 2 * CW;
             uint32_t* BB = BA + CW;
@@ -426,6 +435,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             if (gi >= ngroups) break;
             const uint32_t h = groups[gi];
             const uint32_t c = keys[h] - 1u;
+            if (c % G != share) continue;
             uint32_t* BC = rows5 + wid * 2 * CW;
             uint32_t* BX = BC + CW;
             uint32_t* ch = chist + wid * 16;
@@ -502,7 +512,7 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
             uint32_t* CC = CA + 4;
             uint32_t* AH = CC + 64 * NTREE;
             for (;;) {
-                const uint32_t a = wave_task(&L.ctr[6]);
+                const uint32_t a = wave_task(&L.ctr[6]) * G + share;
                 if (a >= D) break;
                 const uint32_t len = locoff[a + 1] - locoff[a];
                 if (len == 0 || len > SHORT) continue;
@@ -1078,8 +1088,11 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.tcap = (uint32_t)g->hub_layout[2];
     a.tasks = (uint2*)g->hub_tasks;
     a.task_cap = g->hub_task_cap;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 16);
     const int wgs = hub_workgroups();
+    // workgroups per hub root: fewer hub roots than twice the workgroups -> up to 8 per root
+    a.shares = g->nhub >= (int64_t)(2 * wgs) ? 1u
+                                              : (uint32_t)std::min<int64_t>(8, (2 * wgs + g->nhub - 1) / g->nhub);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 16);
     // around[0] and around[1] bracket the hub path, around[2] marks the end of k_hub
     if (around) VDMC_HIP(hipEventRecord(around[0], st));
     hipLaunchKernelGGL(k_hub, dim3(wgs), dim3(HT), 0, st, a);
