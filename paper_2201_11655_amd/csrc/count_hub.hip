@@ -75,7 +75,8 @@ struct HubArgs {
     uint32_t s2cap, tcap;
     uint2* tasks;                // long-slot tasks: (hub index, the slot's entry in r's row)
     uint32_t task_cap;
-    uint32_t shares;             // workgroups per hub root (see k_hub)
+    uint32_t split_roots;        // the first split_roots hub roots (the heaviest) ...
+    uint32_t shares;             // ... are each taken by this many workgroups (see k_hub)
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -215,18 +216,22 @@ __global__ __launch_bounds__(HT) void k_hub(HubArgs A) {
     uint32_t* heads = keys + A.tcap;                             // tcap
     unsigned long long shp[kShapes] = {0, 0, 0, 0, 0, 0};
 
-    // A hub root is taken by A.shares workgroups when there are too few hub roots to fill
-    // the device.  Each stages the whole root (its slot hash, local lists and depth-2
-    // buckets live in its own scratch) and does the share of every phase's tasks that is
-    // its own: slots x with x % shares == share (phases B-C4, F) and depth-2 vertices c
-    // with c % shares == share (phase D, whose group order differs between workgroups).
-    // Its counters are partial sums, flushed with atomics like a whole root's.
-    const uint32_t G = A.shares;
+    // The heaviest hub roots (the first A.split_roots of the queue) are each taken by
+    // A.shares workgroups, so that no single root's workgroup is the critical path.  Each
+    // stages the whole root (its slot hash, local lists and depth-2 buckets live in its own
+    // scratch) and does the share of every phase's tasks that is its own: slots x with
+    // x % G == share (phases B-C4, F) and depth-2 vertices c with c % G == share (phase D,
+    // whose group order differs between workgroups).  Its counters are partial sums,
+    // flushed with atomics like a whole root's.  Later roots are taken whole (G = 1).
+    const uint32_t split_tasks = A.split_roots * A.shares;
     for (;;) {
         __syncthreads();
         if (tid == 0) sRoot = atomicAdd(&A.cursor[0], 1u);
         __syncthreads();
-        const uint32_t hi_idx = sRoot / G, share = sRoot - hi_idx * G;
+        const uint32_t vi = sRoot;
+        const uint32_t G = vi < split_tasks ? A.shares : 1u;
+        const uint32_t hi_idx = vi < split_tasks ? vi / G : A.split_roots + (vi - split_tasks);
+        const uint32_t share = vi < split_tasks ? vi - hi_idx * G : 0u;
         if (hi_idx >= A.nhub) break;
         const uint32_t r = A.hubs[hi_idx];
         if (r < A.rank_lo || r >= A.rank_hi) continue;   // uniform over the workgroup
@@ -670,6 +675,10 @@ __global__ __launch_bounds__(HT) void k_long_slots(HubArgs A) {
     for (uint32_t i = tid; i < 256; i += HT) L.tree_of[i] = A.maps[512 + i];
     if (tid == 0) L.root = 0xFFFFFFFFu;
     const uint32_t ntask = min(A.cursor[1], A.task_cap);
+    // workgroups per task when there are fewer tasks than twice the workgroups (up to 8):
+    // each stages the task and walks the children i with i % G == share (the child list is
+    // a stable compaction of a's row, the same in every workgroup)
+    const uint32_t G = ntask >= 2u * gridDim.x ? 1u : min(8u, (2u * gridDim.x + ntask - 1u) / max(ntask, 1u));
     unsigned long long shp[kShapes] = {0, 0, 0, 0, 0, 0};
     auto cc_add = [&](uint32_t pos, uint32_t s, uint32_t n) {
         atomicAdd(&L.CC[pos * CTW + (s >> 1)], n << ((s & 1u) << 4));
@@ -678,7 +687,7 @@ __global__ __launch_bounds__(HT) void k_long_slots(HubArgs A) {
         __syncthreads();
         if (tid == 0) sTask = atomicAdd(&A.cursor[2], 1u);
         __syncthreads();
-        const uint32_t t = sTask;
+        const uint32_t t = sTask / G, share = sTask - t * G;
         if (t >= ntask) break;
         const uint2 task = A.tasks[t];
         const uint32_t r = A.hubs[task.x];
@@ -735,7 +744,7 @@ __global__ __launch_bounds__(HT) void k_long_slots(HubArgs A) {
         __syncthreads();
         uint32_t* CA = L.CA + wid * CW;
         for (;;) {
-            const uint32_t i = wave_task(&L.ctr[0]);
+            const uint32_t i = wave_task(&L.ctr[0]) * G + share;
             if (i >= m) break;
             const uint32_t vc = L.CL[i] >> 2, ac = L.CL[i] & 3u;
             const uint32_t chi = A.off[vc + 1];
@@ -983,6 +992,7 @@ void ensure_bins(vdmc_graph_s* g, hipStream_t st) {
     unsigned* d_maxhi = (unsigned*)(d_max + 1);
     unsigned long long* d_dsum = d_max + 2;
     int64_t nhub = 0, nlight = 0;
+    std::vector<unsigned long long> hub_keys;   // sorted work keys of the hub roots (~work)
     unsigned long long max_s2 = 0;
     unsigned maxhi = 0;
     if (nr > 0) {
@@ -1016,8 +1026,26 @@ void ensure_bins(vdmc_graph_s* g, hipStream_t st) {
             void* t2 = alloc(sb);
             VDMC_HIP(hipcub::DeviceRadixSort::SortPairs(t2, sb, wkey, wkey_s, g->roots, roots_s, ni, 0, 64, st));
             VDMC_HIP(hipMemcpyAsync(g->hubs, roots_s, nhub * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+            hub_keys.resize((size_t)nhub);
+            VDMC_HIP(hipMemcpyAsync(hub_keys.data(), wkey_s, nhub * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                    st));
         }
         VDMC_HIP(hipStreamSynchronize(st));
+        // Hub roots whose estimated work exceeds a fair share of the device (the total over
+        // twice the workgroups) would each be the critical path on one workgroup: the
+        // leading ones of the queue (largest first) are shared by G workgroups, G from the
+        // heaviest root's excess, at most 8.  hub_layout[3] = how many, hub_layout[4] = G.
+        if (nhub > 0) {
+            double total = 0.0;
+            for (unsigned long long k : hub_keys) total += (double)(~k);
+            const double fair = total / (2.0 * hub_workgroups());
+            size_t h = 0;
+            while (h < hub_keys.size() && h < 4096 && (double)(~hub_keys[h]) > fair) h++;
+            const double top = (double)(~hub_keys[0]);
+            const uint32_t shares = fair > 0.0 ? (uint32_t)std::min(8.0, std::ceil(top / fair)) : 1u;
+            g->hub_layout[3] = shares >= 2 ? h : 0;
+            g->hub_layout[4] = shares >= 2 ? shares : 1;
+        }
     } else {
         VDMC_HIP(hipMalloc(&g->light, sizeof(uint32_t)));
         VDMC_HIP(hipMalloc(&g->hubs, sizeof(uint32_t)));
@@ -1089,9 +1117,8 @@ void launch_hub(vdmc_graph_s* g, int k3, int k4, uint64_t* out3, uint64_t* out4,
     a.tasks = (uint2*)g->hub_tasks;
     a.task_cap = g->hub_task_cap;
     const int wgs = hub_workgroups();
-    // workgroups per hub root: fewer hub roots than twice the workgroups -> up to 8 per root
-    a.shares = g->nhub >= (int64_t)(2 * wgs) ? 1u
-                                              : (uint32_t)std::min<int64_t>(8, (2 * wgs + g->nhub - 1) / g->nhub);
+    a.split_roots = (uint32_t)g->hub_layout[3];   // the heaviest hub roots, shared (set at binning)
+    a.shares = (uint32_t)std::max<size_t>(1, g->hub_layout[4]);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->hub_queue, 16);
     // around[0] and around[1] bracket the hub path, around[2] marks the end of k_hub
     if (around) VDMC_HIP(hipEventRecord(around[0], st));
