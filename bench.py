@@ -55,7 +55,7 @@ WORKLOADS = {
                       "scaled down: ~50k arcs, max degree 141), counted in device memory",
     "batch256_k5": "5-vertex motifs (9364 classes): the first 256 graphs of the batch4096 recipe (directed "
                    "G(n,p), n ~ U{20..500}, mean out-degree ~ U[2,8], graph i seeded (3,i)); one batched "
-                   "launch (one workgroup per graph) vs 256 per-graph launches",
+                   "launch (graphs cut into parts by estimated work) vs 256 per-graph launches",
 }
 
 
