@@ -125,7 +125,7 @@ def test_batch4096_full_size(v):
 
 def test_batch256_k5_full_size(v):
     """The 5-vertex workload at full size: the first 256 graphs of the batch recipe in one
-    batched launch (one workgroup per graph); the 32 graphs with the most work and 32
+    batched launch (graphs cut into parts); the 32 graphs with the most work and 32
     seeded random others checked against the oracle entirely, every graph's visited
     counters against its column sums, and every 17th graph against its single-graph count
     (the shared mode)."""
