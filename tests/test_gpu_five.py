@@ -1,12 +1,12 @@
 """GPU parity for 5-vertex motifs (the Sec. 11 extension): the HIP path through the C ABI
 against the CPU oracle, every uint64 entry equal.
 
-Covers the class table (2^20 codes, 9364 classes), single-graph counts (workgroups
-sharing one graph's items, device-scope credits), batched counts in both modes (one
-workgroup per graph when there are at least as many graphs as compute units, shared
-otherwise), graphs too large for LDS (counted in device memory), mixed batches, the
-visited-set counters per BFS layer shape and the degenerate cases (n < 5, no arcs,
-self-loops, isolated vertices).
+Covers the class table (2^20 codes, 9364 classes), single-graph counts (parts of one
+graph sharing its items, each with its own LDS counters and output block), batched counts
+with many small graphs (most of them one part each) and with few larger ones (many parts
+each), graphs too large for LDS (counted in device memory, device-scope credits), mixed
+batches, the count limits of the per-lane credit caches, the visited-set counters per BFS
+layer shape and the degenerate cases (n < 5, no arcs, self-loops, isolated vertices).
 """
 import math
 import sys
@@ -140,7 +140,8 @@ def test_degenerate(v):
 
 
 def test_batch_owned_mode(v):
-    """At least one graph per compute unit: each graph counted whole by one workgroup."""
+    """More graphs than compute units, most of them small: parts are few per graph (one for
+    graphs with fewer than 64 pairs)."""
     import torch
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     gs = gg.er_batch(ncu + 20, 5, 120, 1.0, 5.0, seed=92)
@@ -157,7 +158,7 @@ def test_batch_owned_mode(v):
 
 
 def test_batch_shared_mode(v):
-    """Fewer graphs than compute units: the graphs' items are spread over the grid."""
+    """Fewer graphs than compute units: each graph cut into many parts over the grid."""
     gs = gg.er_batch(9, 30, 400, 2.0, 6.0, seed=93)
     _say(f"k=5 batch shared: {len(gs)} graphs")
     Gs = [v.Graph(g.n, g.src, g.dst) for g in gs]
