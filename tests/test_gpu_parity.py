@@ -215,6 +215,17 @@ def test_hub_root_over_1024(v, path):
     assert G.max_deg >= 1100
 
 
+def test_heavy_hubs_shared_by_workgroups(v):
+    """A serving-pool graph whose work sits in a few heavy hub roots (n = 5624, largest
+    degree 1144): under the default hub threshold its heaviest roots exceed the device's
+    fair share and are each taken by several workgroups (every task of such a root by
+    exactly one of them); every row equals the oracle's, k = 3 and k = 4."""
+    g = gg.serve_pool(70, 2.0, 4.5, 2.0, 10.0, seed=5)[69]
+    assert g.n == 5624
+    _check_graph(v, g.n, g.src, g.dst, ks=(3,), label="serve pool[69]")
+    _check_graph(v, g.n, g.src, g.dst, ks=(4,), label="serve pool[69]")
+
+
 def test_root_over_2048_takes_per_root_kernel(v):
     """A root with 2,100 higher neighbours (more than the hub path stages) goes through the
     per-root kernel: k = 3 in full against the oracle; k = 4 against the closed form of an
