@@ -490,8 +490,15 @@ def run_serve(v, torch, gg, pool_graphs, requests, log_hi, rates, seed=5):
                      "deferred_by_memory": st.get("deferred_by_memory")})
         log(f"[bench] serve at {frac}x capacity: p50 {st['p50_us'] / 1e3:.2f} ms, p99 {st['p99_us'] / 1e3:.2f} ms, "
             f"{st['sets'] / wall:.3e} sets/s over {wall:.1f}s")
+    # the same quantiles of the requests' alone service times (each (graph, k) weighted by its
+    # number of requests): the part of the served latency that the request mix itself fixes
+    order = np.argsort(service)
+    cum = np.cumsum(weights[order]) / weights.sum()
+    alone_q = {q: float(np.asarray(service)[order][min(int(np.searchsorted(cum, q)), len(order) - 1)]) * 1e3
+               for q in (0.5, 0.99)}
     return {"workload": WORKLOADS["serve"], "pool_graphs": len(pool), "n_log10_range": [2.0, log_hi],
-            "requests": requests, "mean_alone_service_ms": mean_service * 1e3, "runs": runs}
+            "requests": requests, "mean_alone_service_ms": mean_service * 1e3,
+            "alone_p50_ms": alone_q[0.5], "alone_p99_ms": alone_q[0.99], "runs": runs}
 
 
 def bench_graph(args, torch, gg, v):
